@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X Pi_MatMul path; prints one JSON line.
+
+Workload: one BERT-base-shaped layer of private linear products at sequence
+128 (QKV 768x2304, attn-out 768x768, FFN 768x3072 and 3072x768), RNS-BFV with
+N = 4096, two 50-bit primes, t = 2^37, W = floor(N(0, 0.02) * 2^12), client
+share X uniform over Z_{2^37}; fewest-wire block plan.  Synthetic seeded
+inputs (workloads.py).  The server's weight cache (pi_A blocks in NTT form) is
+built once at weight-load time, outside the timed region.
+
+A step is one pass of the whole protocol over the layer: for each of the four
+products encode (client), encrypt (client), ciphertext-plaintext product with
+accumulation (server), re-randomise + mask + sparse reply (server), decrypt
+and decode (client).  value = useful multiply-accumulates (seq * d_in * d_out
+summed over the four products) per second of wall time over the timed steps.
+
+roofline: the dominant kernel is the slot-wise modular product ("mac"); its
+algorithmic bytes per launch are the weight-cache words it must stream
+(Wb * L * N * 8) plus the transformed inputs it reads once (I * 2 * L * N * 8)
+plus the accumulators it writes (O * 2 * L * N * 8), divided by its average
+launch duration from HIP events recorded on its stream during the timed steps.
+
+cpu_baseline: the oracle (plain C + Python big integers, OpenMP) on a bounded
+sample: the 768x768 product at sequence 128, output ciphertexts taken in
+chunks until about --cpu-seconds have passed, encryption of all inputs counted
+pro rata.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ct-pt MatMul int-MAC/s and layer-stack p50/p99 latency, batched vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(seconds: float):
+    import numpy as np
+
+    from oracle import oracle as orc
+    from paper_2305_18396_amd import workloads
+
+    wl = workloads.bert_base_layer(128)[1]  # attn-out 768x768
+    n, r, m = wl.shape
+    pyp = orc.Params(4096, 2, 37, 12)
+    plan = orc.plan_comm(4096, n, r, m)
+    cseed, sseed = workloads.seed("client", 900), workloads.seed("server", 900)
+    s, pk = orc.keygen(pyp, cseed)
+    ptA = orc.encode_weights(plan, wl.W)
+    t0 = time.perf_counter()
+    pt = orc.encode_input(plan, wl.X)
+    ct = orc.encrypt(pyp, s, cseed, 0, pt)
+    t_enc = time.perf_counter() - t0
+    threads = orc.max_threads()
+    done, t_out = 0, 0.0
+    macs = 0
+    while done < plan.O and t_out + t_enc < seconds:
+        outs = np.arange(done, min(plan.O, done + threads), dtype=np.uint32)
+        t1 = time.perf_counter()
+        acc = orc.matmul(pyp, plan, ptA, ct, outs)
+        acc = orc.rerandomize(pyp, pk, sseed, 0, acc, outs)
+        c1, c0s, sm = orc.mask_extract(pyp, plan, sseed, 0, acc, outs)
+        orc.decrypt(pyp, plan, s, c1, c0s, outs)
+        t_out += time.perf_counter() - t1
+        for y in outs.tolist():
+            ib, kb = divmod(y, plan.K)
+            rows = min(plan.nb, n - kb * plan.nb)
+            cols = min(plan.mb, m - ib * plan.mb)
+            macs += rows * cols * r
+        done += len(outs)
+    elapsed = t_out + t_enc * done / plan.O
+    return {"value": macs / elapsed, "unit": "int-MAC/s", "cores": threads, "kind": "oracle",
+            "sample": f"768x768 product at seq 128 (N=4096, 2 primes): {done} of {plan.O} output "
+                      f"ciphertexts through product, re-randomisation, mask and decryption, "
+                      f"encryption of all {plan.I} inputs counted pro rata; {elapsed:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seq", type=int, default=128)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "sharding of Pi_MatMul is a design note, not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2305_18396_amd import pimm, workloads
+
+    dev = torch.device("cuda", 0)
+    N, L, ell, f = 4096, 2, 37, 12
+    ctx = pimm.Context(N, L, ell, f, rerandomize=True, device=0)
+    ops = workloads.bert_base_layer(args.seq)
+    cseed, sseed = workloads.seed("client", 1), workloads.seed("server", 1)
+    sk, pk = pimm.keygen(ctx, cseed)
+    state = []
+    useful = 0
+    mac_bytes = 0
+    for i, wl in enumerate(ops):
+        n, r, m = wl.shape
+        plan = pimm.Plan(ctx, n, r, m)
+        w = pimm.Weights(plan, pimm.to_device_u64(wl.W))
+        fi = plan.info
+        st = dict(
+            plan=plan, w=w, X=pimm.to_device_u64(wl.X),
+            pt=torch.empty((fi.I, N), dtype=torch.int64, device=dev),
+            ct=torch.empty((fi.I, 2, L, N), dtype=torch.int64, device=dev),
+            acc=torch.empty((fi.O, 2, L, N), dtype=torch.int64, device=dev),
+            c1=torch.empty((fi.O, L, N), dtype=torch.int64, device=dev),
+            c0s=torch.empty((fi.O, L, fi.mb * fi.nb), dtype=torch.int64, device=dev),
+            y0=torch.empty((n, m), dtype=torch.int64, device=dev),
+            y1=torch.empty((n, m), dtype=torch.int64, device=dev),
+            ws=plan.workspace(), op=i)
+        state.append(st)
+        useful += n * r * m
+        mac_bytes += (fi.Wb + 2 * fi.I + 2 * fi.O) * L * N * 8
+        log(f"{wl.name}: plan ({fi.mb},{fi.rb},{fi.nb}) I={fi.I} O={fi.O} Wb={fi.Wb} "
+            f"weights {fi.weights_bytes / 1e9:.2f} GB")
+    torch.cuda.synchronize()
+
+    def step(k):
+        for st in state:
+            p = st["plan"]
+            pimm.encode_input(p, st["X"], st["pt"])
+            pimm.encrypt(p, sk, cseed, k * 8 + st["op"], st["pt"], st["ct"], st["ws"])
+            pimm.matmul(p, st["w"], st["ct"], st["acc"], st["ws"])
+            pimm.mask_share(p, pk, sseed, k * 8 + st["op"], st["acc"], st["c1"], st["c0s"],
+                            st["y1"], st["ws"])
+            pimm.decrypt(p, sk, st["c1"], st["c0s"], st["y0"], st["ws"])
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps)")
+    for kname in ("mac", "ntt_fwd", "ntt_inv", "sample", "encode", "decode", "mask_extract"):
+        pimm.profile_read(kname)
+    pimm.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(args.warmup + k)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pimm.profile_enable(False)
+    elapsed = t1 - t0
+    kernels = {}
+    for kname in ("mac", "ntt_fwd", "ntt_inv", "sample", "encode", "decode", "mask_extract"):
+        cnt, ms = pimm.profile_read(kname)
+        kernels[kname] = {"launches": cnt, "ms_total": round(ms, 3),
+                          "ms_per_step": round(ms / args.steps, 4)}
+    log(f"timed {args.steps} steps in {elapsed:.4f} s")
+
+    # Per-step latency of the layer (each step synchronised), for p50/p99.
+    lat = []
+    for k in range(max(5, min(30, args.steps * 2))):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        step(10_000 + k)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - a) * 1e3)
+    lat = np.array(lat)
+
+    mac = kernels["mac"]
+    mac_avg_s = mac["ms_total"] / 1e3 / max(1, mac["launches"])
+    bytes_per_launch = mac_bytes / len(state)
+    achieved = bytes_per_launch / mac_avg_s / 1e9 if mac["launches"] else 0.0
+    value = useful * args.steps / elapsed
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "int-MAC/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"BERT-base-shaped linear layer, seq {args.seq}: QKV 768x2304, "
+                        "attn-out 768x768, FFN 768x3072 and 3072x768; RNS-BFV N=4096, "
+                        "2x50-bit primes, t=2^37, 12 fractional bits; fewest-wire plan; "
+                        "weight cache built at load",
+            "global_batch": 1, "seq_len": args.seq, "parallelism": "single GPU",
+            "plans": [[s["plan"].mb, s["plan"].rb, s["plan"].nb] for s in state],
+            "useful_macs_per_step": useful,
+        },
+        "layer_latency_ms": {"p50": float(np.percentile(lat, 50)),
+                             "p99": float(np.percentile(lat, 99)), "samples": len(lat)},
+        "kernels": kernels,
+        "roofline": {
+            "kernel": "mac (k_mac)", "bound": "hbm", "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "alg_bytes_per_launch": bytes_per_launch,
+            "avg_launch_ms": mac_avg_s * 1e3,
+        },
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,236 @@
+/*
+ * pimm.h -- C ABI of libpimm, an MI355X (gfx950) implementation of the
+ * private matrix-multiplication protocol Pi_MatMul of Liu & Liu, "LLMs Can
+ * Understand Encrypted Prompt: Towards Privacy-Computing Friendly
+ * Transformers" (arXiv 2305.18396), Algorithm 1 (section 3.1.1), over RNS-BFV
+ * (section 2.2), with the sparse reply of section 3.1.3.
+ *
+ * Problem (Algorithm 1, inputs and outputs): the server holds A (m x r), the
+ * client holds B (r x n); the parties end with additive shares of C = AB over
+ * Z_t, t = 2^l.  For a linear layer Y = X W (section 3.1.1, fully connected
+ * layer, and the transposed form in the footnote of the attention paragraph)
+ * the library takes A = W^T and B = X^T, so the user-level contract is
+ *
+ *     client_share + server_share = X W   (mod 2^l), elementwise over [n][m].
+ *
+ * Conventions for every call:
+ *   - Return value: PIMM_OK (0) or a negative PIMM_E_* code.  No exception or
+ *     longjmp crosses the ABI.  pimm_last_error() gives a thread-local message.
+ *   - Bulk buffers are caller-owned DEVICE pointers on the context's device
+ *     (for example torch tensor data pointers), row-major, with the sizes that
+ *     pimm_plan_query() reports.  Handles (context, plan, key, weights) are
+ *     created and destroyed by the library; a key and a weight cache hold
+ *     device memory that the library allocates.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls enqueue work and return; errors of the work itself surface at
+ *     pimm_sync() or at a later call.  Calls that take a workspace use the
+ *     caller's buffer `ws` of `ws_bytes` bytes (at least
+ *     pimm_plan_info.workspace_bytes) and allocate nothing.
+ *   - Contexts, plans, keys and weight caches are immutable after creation,
+ *     so calls on different streams may share them; two calls in flight must
+ *     not share a workspace or an output buffer.
+ *   - Output bytes depend only on (parameters, plan, inputs, seeds, op_id),
+ *     never on batching, stream or launch order.
+ *   - Residues are canonical integers in [0, q_l), stored as uint64.  Shares
+ *     are integers in [0, 2^l), stored as uint64.
+ *
+ * Randomness (encryption noise and masks): ChaCha20 (RFC 8439, section 2.3)
+ * keyed by the caller's 32-byte seed, nonce (tag | prime << 8, op_id,
+ * object index), block counter from 0; the 64-bit draw j is keystream bytes
+ * [8j, 8j+8) and the 128-bit draw j bytes [16j, 16j+16), little-endian.
+ */
+#ifndef PIMM_H
+#define PIMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIMM_OK 0
+#define PIMM_E_ARG (-1)         /* NULL pointer or out-of-range argument */
+#define PIMM_E_SHAPE (-2)       /* matrix shape or block plan that does not fit */
+#define PIMM_E_PARAMS (-3)      /* N not a power of two in [4096, 8192], L not in [1, 4], ... */
+#define PIMM_E_NOISE (-4)       /* weights whose worst-case noise breaks decryption */
+#define PIMM_E_OOM (-5)         /* device allocation failed */
+#define PIMM_E_DEVICE (-6)      /* HIP runtime error */
+#define PIMM_E_UNSUPPORTED (-7) /* valid request this build does not implement */
+#define PIMM_E_WORKSPACE (-8)   /* workspace missing or smaller than required */
+
+typedef struct pimm_ctx pimm_ctx;
+typedef struct pimm_plan pimm_plan;
+typedef struct pimm_sk pimm_sk;
+typedef struct pimm_weights pimm_weights;
+
+/* RNS-BFV parameters (section 2.2: N a power of two, plaintext modulus t = 2^l,
+ * ciphertext modulus q a product of L word-size primes).
+ *   N           ring degree, 4096 or 8192
+ *   L           number of RNS primes, 1..4
+ *   log2_t      l, 2..48 (t = 2^l; shares live in Z_{2^l})
+ *   frac_bits   f, fixed-point fractional bits of W (section 2.2); informational
+ *   prime_bits  must be 50: the primes are the L largest primes q < 2^50 with
+ *               q = 1 (mod 2N), in descending order
+ *   rerandomize 1: pimm_mask_share adds a fresh public-key encryption of zero
+ *               to each reply ciphertext before masking; 0: it does not. */
+typedef struct {
+    uint32_t N, L, log2_t, frac_bits, prime_bits, rerandomize;
+} pimm_params;
+
+/* Block plan and buffer sizes of one product Y[n][m] = X[n][r] W[r][m].
+ * Blocks are (mb, rb, nb) with mb*rb*nb <= N; M = ceil(m/mb), R = ceil(r/rb),
+ * K = ceil(n/nb); I = R*K input ciphertexts (index x = jb*K + kb), O = M*K
+ * output ciphertexts (index y = ib*K + kb), Wb = M*R weight blocks, P = M*R*K
+ * block products.  Byte sizes are of the caller-owned buffers:
+ *   pt        [I][N]          uint64  encoded client plaintexts
+ *   ct        [I][2][L][N]    uint64  input ciphertexts (c0, c1), coefficient form
+ *   acc       [O][2][L][N]    uint64  products before masking, coefficient form
+ *   c1        [O][L][N]       uint64  reply, full c1
+ *   c0s       [O][L][mb*nb]   uint64  reply, c0 at the decoded positions only,
+ *                                     entry k*mb + i for position k*mb*rb + i*rb + rb-1
+ *   share     [n][m]          uint64  one party's share of Y
+ *   weights   device bytes held by a weight cache for this plan
+ *   workspace bytes of scratch that encrypt, matmul, mask_share and decrypt need */
+typedef struct {
+    uint32_t n, r, m, mb, rb, nb, M, R, K, I, O, Wb;
+    uint64_t P;
+    uint64_t pt_bytes, ct_bytes, acc_bytes, c1_bytes, c0s_bytes, share_bytes;
+    uint64_t weights_bytes, workspace_bytes;
+} pimm_plan_info;
+
+/* ---- context -------------------------------------------------------------- */
+
+/* Create a context on HIP device `device`: finds the primes, builds the NTT
+ * tables and the decryption constants on that device. */
+int pimm_ctx_create(const pimm_params *params, int device, pimm_ctx **out);
+int pimm_ctx_destroy(pimm_ctx *ctx);
+/* q_out[L]: the RNS primes. */
+int pimm_ctx_primes(const pimm_ctx *ctx, uint64_t *q_out);
+/* cdt_out[19]: the cumulative table of the error sampler (width 3.2, |e| <= 19),
+ * T[k] = floor(2^63 P(|e| <= k)). */
+int pimm_ctx_cdt(const pimm_ctx *ctx, uint64_t *cdt_out);
+
+/* ---- host-only queries (no device needed) --------------------------------------- */
+
+/* Validate params and write the L primes to q_out[L] (same rule as the context). */
+int pimm_params_primes(const pimm_params *params, uint64_t *q_out);
+/* cdt_out[19]: the error sampler's cumulative table (as pimm_ctx_cdt). */
+int pimm_cdt(uint64_t *cdt_out);
+/* The plan pimm_plan_create would make, without a context or a device. */
+int pimm_plan_rule(const pimm_params *params, uint32_t n, uint32_t r, uint32_t m, uint32_t mb,
+                   uint32_t rb, uint32_t nb, uint32_t d_fix, pimm_plan_info *info);
+/* 1 if weights with max |W| = wmax pass the noise check of pimm_weights_create for
+ * this plan, 0 if not, <0 on error.  The worst-case noise of a decoded reply
+ * coefficient is E = R*D*wmax*19 + (q mod t)(r*wmax + 1) [+ 2*N*19 + 19 with
+ * re-randomisation], D = mb*rb, and decryption is correct when 2 t (E + (q mod t)) < q. */
+int pimm_noise_ok(const pimm_params *params, const pimm_plan_info *info, uint64_t wmax);
+
+/* ---- plan ------------------------------------------------------------------ */
+
+/* Plan Y[n][m] = X[n][r] W[r][m].  The paper leaves the block split open
+ * (section 3.1.1 says only that larger matrices are split into blocks):
+ *   mb, rb, nb all > 0   use that block shape (mb*rb*nb <= N);
+ *   d_fix > 0            mb*rb = d_fix (a power of two <= N), split to minimise
+ *                        ceil(r/rb) + ceil(m/mb), ties to larger mb; nb = min(n, N/d_fix);
+ *   otherwise            fewest ciphertexts on the wire: minimise
+ *                        (ceil(r/rb) + ceil(m/mb)) * ceil(n/nb) over powers of two
+ *                        mb <= nextpow2(m), rb <= nextpow2(r), mb*rb <= N,
+ *                        nb = min(n, N/(mb rb)); ties to larger nb, then larger mb. */
+int pimm_plan_create(pimm_ctx *ctx, uint32_t n, uint32_t r, uint32_t m, uint32_t mb, uint32_t rb,
+                     uint32_t nb, uint32_t d_fix, pimm_plan **out);
+int pimm_plan_destroy(pimm_plan *plan);
+int pimm_plan_query(const pimm_plan *plan, pimm_plan_info *info);
+
+/* ---- client ---------------------------------------------------------------- */
+
+/* Key generation.  s ternary from stream tag 1; with re-randomisation on and
+ * pk_out not NULL, also pk = ([-a' s + e']_q, a') (a' uniform per prime from
+ * tag 2, e' Gaussian from tag 3), written to pk_out [2][L][N] (device).
+ * The key stays on the device inside the returned handle. */
+int pimm_keygen(pimm_ctx *ctx, const uint8_t seed[32], pimm_sk **sk, uint64_t *pk_out,
+                void *stream);
+int pimm_sk_destroy(pimm_sk *sk);
+
+/* Algorithm 1 step 1, client side: pi_B per block,
+ * pt[jb*K + kb][k*mb*rb + j] = X[kb*nb + k][jb*rb + j], zero elsewhere.
+ * X: [n][r] values < 2^l (device). */
+int pimm_encode_input(const pimm_plan *plan, const uint64_t *X, uint64_t *pt, void *stream);
+
+/* Algorithm 1 step 2: symmetric BFV encryption of every pt row x:
+ * c1_l = a_l (uniform mod q_l, stream tag 4, prime l, op_id, x),
+ * c0_l = [Delta_l pt + e - a_l s]_{q_l} (e Gaussian, tag 5, op_id, x),
+ * Delta = floor(q / t).  ct: [I][2][L][N] (device). */
+int pimm_encrypt(const pimm_plan *plan, const pimm_sk *sk, const uint8_t seed[32], uint32_t op_id,
+                 const uint64_t *pt, uint64_t *ct, void *ws, size_t ws_bytes, void *stream);
+
+/* Algorithm 1 step 4, client side: decrypt the decoded coefficients
+ * (section 3.1.3: coefficient i of c0 + c1 s needs (c0)_i and all of c1),
+ * x = CRT, v = floor((t x + floor(q/2)) / q) mod t, and place them by pi_C^{-1}:
+ * client_share[kb*nb + k][ib*mb + i] = v.  Rows and columns past n, m are dropped. */
+int pimm_decrypt(const pimm_plan *plan, const pimm_sk *sk, const uint64_t *c1, const uint64_t *c0s,
+                 uint64_t *client_share, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- server ---------------------------------------------------------------- */
+
+/* Algorithm 1 step 1, server side, plus the transform the product needs:
+ * pi_A per block, a[ib*R + jb][i*rb + rb-1-j] = W[jb*rb + j][ib*mb + i], lifted
+ * centred (w < 0 -> q_l - |w|), kept on the device in NTT form.
+ * W: [r][m] signed fixed-point integers (device).  Fails with PIMM_E_NOISE when
+ * the worst-case noise bound of the reply breaks decryption.  Synchronises
+ * `stream` (it reads max |W| back). */
+int pimm_weights_create(const pimm_plan *plan, const int64_t *W, pimm_weights **out, void *stream);
+int pimm_weights_destroy(pimm_weights *w);
+
+/* Algorithm 1 step 3, [[c]] = a [[b]], accumulated over the inner blocks:
+ * acc[y = ib*K + kb][comp][l] = sum_jb a[ib*R + jb] * ct[jb*K + kb][comp][l]
+ * mod (X^N + 1, q_l), coefficient form. */
+int pimm_matmul(const pimm_plan *plan, const pimm_weights *w, const uint64_t *ct, uint64_t *acc,
+                void *ws, size_t ws_bytes, void *stream);
+
+/* Algorithm 1 step 3, [[c]] - s, with the sparse reply of section 3.1.3, in place
+ * on acc.  With re-randomisation on (pk must then be given, [2][L][N]):
+ * acc0 += u pk0 + e1, acc1 += u pk1 + e2 (u ternary tag 6, e1 tag 7, e2 tag 8,
+ * object y).  Then the mask s_y over Z_t (tag 9, object y, draw index = the
+ * coefficient index) at each decoded position pos = k*mb*rb + i*rb + rb-1:
+ * c0s[y][l][k*mb + i] = [acc0[pos] - Delta_l s_y[pos]]_{q_l},
+ * server_share[kb*nb + k][ib*mb + i] = s_y[pos]; c1[y] = acc1. */
+int pimm_mask_share(const pimm_plan *plan, const uint64_t *pk, const uint8_t seed[32],
+                    uint32_t op_id, uint64_t *acc, uint64_t *c1, uint64_t *c0s,
+                    uint64_t *server_share, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- primitives exposed for checking ----------------------------------------- */
+
+/* c = a * b mod (X^N + 1, q_l) for count pairs of polynomials laid out
+ * [count][L][N] (canonical residues, device).  The ring product that
+ * ciphertext-plaintext multiplication is made of (section 3.1.3 footnote). */
+int pimm_poly_mul(pimm_ctx *ctx, const uint64_t *a, const uint64_t *b, uint64_t *c, uint32_t count,
+                  void *ws, size_t ws_bytes, void *stream);
+/* Workspace bytes pimm_poly_mul needs for `count` pairs. */
+uint64_t pimm_poly_mul_workspace(const pimm_ctx *ctx, uint32_t count);
+
+/* Sample one polynomial of N coefficients from stream (tag, prime, op_id, obj):
+ * kind 0 uniform mod q_prime (uint64), 1 ternary (int64), 2 Gaussian (int64),
+ * 3 mask mod 2^l (uint64).  out: [N] (device). */
+int pimm_sample_poly(pimm_ctx *ctx, int kind, const uint8_t seed[32], uint32_t tag, uint32_t prime,
+                     uint32_t op_id, uint32_t obj, void *out, void *stream);
+
+/* ---- tracing ----------------------------------------------------------------- */
+
+/* on != 0: from now on bracket every kernel launch of the library with two HIP
+ * events recorded on the launch's stream, filed under the kernel class
+ * ("ntt_fwd", "ntt_inv", "mac", "sample", "encode", "decode", "mask_extract"). */
+int pimm_profile_enable(int on);
+/* Wait for the events recorded for `kernel`, report how many launches they cover
+ * and their summed duration in milliseconds, and forget them. */
+int pimm_profile_read(const char *kernel, uint64_t *count, double *total_ms);
+
+/* ---- misc ------------------------------------------------------------------ */
+
+int pimm_sync(void *stream);
+const char *pimm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIMM_H */

@@ -298,18 +298,11 @@ def encode_input(plan: Plan, X: np.ndarray) -> np.ndarray:
     X = np.asarray(X, dtype=np.uint64)
     assert X.shape == (plan.n, plan.r)
     pt = np.zeros((plan.I, plan.N), dtype=np.uint64)
-    for jb in range(plan.R):
-        for kb in range(plan.K):
-            x = jb * plan.K + kb
-            for k in range(plan.nb):
-                row = kb * plan.nb + k
-                if row >= plan.n:
-                    break
-                for j in range(plan.rb):
-                    col = jb * plan.rb + j
-                    if col >= plan.r:
-                        break
-                    pt[x, k * plan.mb * plan.rb + j] = X[row, col]
+    # Every (row, col) of X lands in exactly one block and one coefficient.
+    row, col = np.meshgrid(np.arange(plan.n), np.arange(plan.r), indexing="ij")
+    kb, k = np.divmod(row, plan.nb)
+    jb, j = np.divmod(col, plan.rb)
+    pt[jb * plan.K + kb, k * plan.mb * plan.rb + j] = X[row, col]
     return pt
 
 
@@ -319,18 +312,10 @@ def encode_weights(plan: Plan, W: np.ndarray) -> np.ndarray:
     W = np.asarray(W, dtype=np.int64)
     assert W.shape == (plan.r, plan.m)
     pa = np.zeros((plan.Wb, plan.N), dtype=np.int64)
-    for ib in range(plan.M):
-        for jb in range(plan.R):
-            w = ib * plan.R + jb
-            for i in range(plan.mb):
-                col = ib * plan.mb + i
-                if col >= plan.m:
-                    break
-                for j in range(plan.rb):
-                    row = jb * plan.rb + j
-                    if row >= plan.r:
-                        break
-                    pa[w, i * plan.rb + plan.rb - 1 - j] = W[row, col]
+    row, col = np.meshgrid(np.arange(plan.r), np.arange(plan.m), indexing="ij")
+    jb, j = np.divmod(row, plan.rb)
+    ib, i = np.divmod(col, plan.mb)
+    pa[ib * plan.R + jb, i * plan.rb + plan.rb - 1 - j] = W[row, col]
     return pa
 
 

@@ -1,0 +1,281 @@
+// client.hip -- the client's side of Pi_MatMul (Algorithm 1 steps 1, 2 and 4).
+#include "common.h"
+#include "ntt.h"
+
+namespace pimm {
+
+int launch_sample(const Ctx &c, int kind, const Key &key, uint32_t tag, uint32_t op, uint32_t obj0,
+                  int nobj, int prime0, int nprime, void *out, size_t obj_stride,
+                  size_t prime_stride, hipStream_t s);
+
+// ---- encode (Algorithm 1 step 1, pi_B) -------------------------------------------
+
+// One thread per plaintext coefficient; every coefficient is written (zeros included).
+__global__ void k_encode_input(const uint64_t *X, uint64_t *pt, pimm_plan_info f, int logn)
+{
+    const size_t N = (size_t)1 << logn;
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (size_t)f.I * N) return;
+    const uint32_t x = (uint32_t)(gid >> logn);
+    const uint32_t jcoef = (uint32_t)(gid & (N - 1));
+    const uint32_t jb = x / f.K, kb = x % f.K;
+    const uint32_t D = f.mb * f.rb;
+    uint64_t v = 0;
+    const uint32_t k = jcoef / D, j = jcoef % D;
+    if (k < f.nb && j < f.rb) {
+        const uint32_t row = kb * f.nb + k, col = jb * f.rb + j;
+        if (row < f.n && col < f.r) v = X[(size_t)row * f.r + col];
+    }
+    pt[gid] = v;
+}
+
+// ---- encrypt (Algorithm 1 step 2) -----------------------------------------------
+
+// Component `comp` of [count][2][L][N] ciphertexts as [count*L] polynomials.
+struct LoadCtComp {
+    const uint64_t *ct;
+    int logn, L, comp;
+    __device__ double operator()(int poly, int l, int j, double, double) const
+    {
+        const size_t x = (size_t)(poly / L);
+        return (double)ct[(((x * 2 + comp) * L + l) << logn) + j];
+    }
+};
+
+// c0 = [Delta_l pt + e - a s]_{q_l} from the inverse NTT of a^ s^.
+// Delta_l travels by value inside the functor (kernel arguments are the only
+// host data a kernel may read).
+struct StoreEncC0 {
+    const uint64_t *pt;  // [I][N]
+    const int64_t *e;    // [I][N]
+    uint64_t *ct;        // [I][2][L][N]
+    uint64_t delta[kMaxL];
+    int logn, L;
+    __device__ void operator()(int poly, int l, int j, double v, double p, double pinv) const
+    {
+        const size_t x = (size_t)(poly / L);
+        const uint64_t q = (uint64_t)p;
+        const uint64_t as = to_canonical(v, p, pinv);
+        const uint64_t m = mul_mod(delta[l], pt[(x << logn) + j], p, pinv);
+        const uint64_t c0 = sub_mod(add_mod(m, lift_signed(e[(x << logn) + j], q), q), as, q);
+        ct[(((x * 2) * L + l) << logn) + j] = c0;
+    }
+};
+
+// ---- decrypt (Algorithm 1 step 4, section 3.1.3) ---------------------------------
+
+// (c1 s) at the decoded positions pos = k*mb*rb + i*rb + rb-1 -> cs[o][l][k*mb + i].
+struct StoreDecoded {
+    uint64_t *cs;
+    int logn;
+    uint32_t mb, rb, nb;
+    __device__ void operator()(int poly, int, int j, double v, double p, double pinv) const
+    {
+        const uint32_t uj = (uint32_t)j;
+        if (uj % rb != rb - 1) return;
+        const uint32_t i = (uj / rb) % mb, k = uj / (mb * rb);
+        if (k >= nb) return;
+        cs[(size_t)poly * mb * nb + k * mb + i] = to_canonical(v, p, pinv);
+    }
+};
+
+// Multi-limb helpers (little-endian uint64 limbs, W limbs).
+constexpr int W = kMaxL + 1;
+
+__device__ __forceinline__ void limbs_mul_add(uint64_t *x, uint64_t m, uint64_t a)
+{
+    unsigned __int128 carry = a;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        unsigned __int128 v = (unsigned __int128)x[i] * m + carry;
+        x[i] = (uint64_t)v;
+        carry = v >> 64;
+    }
+}
+
+// x -= y; returns the final borrow (1 if the true result is negative).
+__device__ __forceinline__ int limbs_sub(uint64_t *x, const uint64_t *y)
+{
+    uint64_t borrow = 0;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        const uint64_t yi = y[i] + borrow;
+        const uint64_t nb = (yi < borrow) || (x[i] < yi);
+        x[i] -= yi;
+        borrow = nb;
+    }
+    return (int)borrow;
+}
+
+__device__ __forceinline__ void limbs_add(uint64_t *x, const uint64_t *y)
+{
+    uint64_t carry = 0;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        const uint64_t s = x[i] + carry;
+        const uint64_t c1 = s < carry;
+        x[i] = s + y[i];
+        carry = c1 + (x[i] < y[i]);
+    }
+}
+
+// BFV decryption of one coefficient from its residues: x = CRT(res) in [0, q)
+// (mixed-radix / Garner form, so no reduction mod q is needed), then
+// v = floor((t x + floor(q/2)) / q) mod t.  The quotient is estimated in double
+// precision (error below 1/8 for t <= 2^48) and corrected exactly with limbs.
+__device__ uint64_t crt_round(const uint64_t *res, const DevParams &dp)
+{
+    uint64_t v[kMaxL];
+    for (int l = 0; l < dp.L; ++l) {
+        const double p = dp.p[l], pinv = dp.pinv[l];
+        const uint64_t q = dp.q[l];
+        uint64_t t = res[l];
+        for (int i = 0; i < l; ++i)
+            t = sub_mod(t, mul_mod(v[i] % q, (uint64_t)dp.garner_c[l][i], p, pinv), q);
+        v[l] = mul_mod(t, (uint64_t)dp.garner_inv[l], p, pinv);
+    }
+    uint64_t X[W] = {0, 0, 0, 0, 0};
+    for (int l = dp.L - 1; l >= 0; --l) {
+        if (l == dp.L - 1)
+            X[0] = v[l];
+        else
+            limbs_mul_add(X, dp.q[l], v[l]);
+    }
+    // num = X * 2^ell + floor(q/2)
+    uint64_t num[W];
+    const int s = dp.ell;
+#pragma unroll
+    for (int i = W - 1; i >= 0; --i) num[i] = (X[i] << s) | (i > 0 ? X[i - 1] >> (64 - s) : 0);
+    limbs_add(num, dp.halfQ);
+    double nd = 0.0;
+#pragma unroll
+    for (int i = W - 1; i >= 0; --i) nd = nd * 18446744073709551616.0 + (double)num[i];
+    uint64_t est = (uint64_t)__builtin_floor(nd / dp.Qd);
+    if (est > 0) est -= 1;  // start below the quotient, then step up exactly
+    uint64_t prod[W];
+#pragma unroll
+    for (int i = 0; i < W; ++i) prod[i] = dp.Q[i];
+    {
+        unsigned __int128 carry = 0;
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            unsigned __int128 t = (unsigned __int128)prod[i] * est + carry;
+            prod[i] = (uint64_t)t;
+            carry = t >> 64;
+        }
+    }
+    // rem = num - est*q >= 0; while rem >= q: rem -= q, est += 1 (at most three steps).
+    limbs_sub(num, prod);
+    for (int it = 0; it < 4; ++it) {
+        uint64_t tmp[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) tmp[i] = num[i];
+        if (limbs_sub(tmp, dp.Q)) break;
+#pragma unroll
+        for (int i = 0; i < W; ++i) num[i] = tmp[i];
+        est += 1;
+    }
+    return est & ((1ull << dp.ell) - 1);
+}
+
+// One thread per decoded coefficient of each output ciphertext.
+__global__ void k_decode(const uint64_t *c0s, const uint64_t *cs, uint64_t *share, pimm_plan_info f,
+                         DevParams dp)
+{
+    const uint32_t per = f.mb * f.nb;
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (size_t)f.O * per) return;
+    const uint32_t o = (uint32_t)(gid / per), idx = (uint32_t)(gid % per);
+    const uint32_t k = idx / f.mb, i = idx % f.mb;
+    const uint32_t ib = o / f.K, kb = o % f.K;
+    const uint32_t row = kb * f.nb + k, col = ib * f.mb + i;
+    if (row >= f.n || col >= f.m) return;
+    uint64_t res[kMaxL];
+    for (int l = 0; l < dp.L; ++l) {
+        const size_t at = ((size_t)o * dp.L + l) * per + idx;
+        res[l] = add_mod(c0s[at], cs[at], dp.q[l]);
+    }
+    share[(size_t)row * f.m + col] = crt_round(res, dp);
+}
+
+}  // namespace pimm
+
+using namespace pimm;
+
+extern "C" {
+
+int pimm_encode_input(const pimm_plan *plan, const uint64_t *X, uint64_t *pt, void *stream)
+{
+    if (!plan || !X || !pt) return set_error(PIMM_E_ARG, "pimm_encode_input: NULL argument");
+    const pimm_plan_info &f = plan->info;
+    const size_t total = (size_t)f.I << plan->ctx->dp.logN;
+    const int threads = 256;
+    ProfScope prof("encode", (hipStream_t)stream);
+    hipLaunchKernelGGL(k_encode_input, dim3((unsigned)((total + threads - 1) / threads)),
+                       dim3(threads), 0, (hipStream_t)stream, X, pt, f, plan->ctx->dp.logN);
+    return check_hip(hipGetLastError(), "encode_input launch");
+}
+
+// Workspace: a^ [I][L][N] doubles, then e [I][N] int64.
+int pimm_encrypt(const pimm_plan *plan, const pimm_sk *sk, const uint8_t seed[32], uint32_t op_id,
+                 const uint64_t *pt, uint64_t *ct, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!plan || !sk || !seed || !pt || !ct) return set_error(PIMM_E_ARG, "pimm_encrypt: NULL argument");
+    const Ctx &c = *plan->ctx;
+    if (sk->ctx != plan->ctx) return set_error(PIMM_E_ARG, "pimm_encrypt: key of another context");
+    const pimm_plan_info &f = plan->info;
+    const size_t N = c.params.N, L = c.params.L;
+    const size_t need = (size_t)f.I * N * 8 * (L + 1);
+    if (!ws || ws_bytes < need) return set_error(PIMM_E_WORKSPACE, "pimm_encrypt: workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    const int lg = c.dp.logN;
+    double *ah = (double *)ws;
+    int64_t *e = (int64_t *)(ah + (size_t)f.I * L * N);
+    const Key key = make_key(seed);
+    // c1 = a: uniform per prime, written straight into the ciphertexts.
+    int rc = launch_sample(c, 0, key, kTagEncA, op_id, 0, (int)f.I, 0, (int)L, ct + L * N, 2 * L * N,
+                           N, s);
+    if (!rc) rc = launch_sample(c, 2, key, kTagEncE, op_id, 0, (int)f.I, 0, 1, e, N, 0, s);
+    if (!rc)
+        rc = launch_fwd(c, LoadCtComp{ct, lg, (int)L, 1}, StoreSlots{ah, lg}, (int)(f.I * L), s);
+    if (!rc) {
+        StoreEncC0 st{pt, e, ct, {0, 0, 0, 0}, lg, (int)L};
+        for (size_t l = 0; l < L; ++l) st.delta[l] = c.dp.delta[l];
+        rc = launch_inv(c, LoadSlotsMul{ah, sk->d_s_hat, lg, (int)L}, st, (int)(f.I * L), s);
+    }
+    return rc;
+}
+
+// Workspace: c1^ [O][L][N] doubles, then cs [O][L][mb*nb] uint64.
+int pimm_decrypt(const pimm_plan *plan, const pimm_sk *sk, const uint64_t *c1, const uint64_t *c0s,
+                 uint64_t *client_share, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!plan || !sk || !c1 || !c0s || !client_share)
+        return set_error(PIMM_E_ARG, "pimm_decrypt: NULL argument");
+    const Ctx &c = *plan->ctx;
+    if (sk->ctx != plan->ctx) return set_error(PIMM_E_ARG, "pimm_decrypt: key of another context");
+    const pimm_plan_info &f = plan->info;
+    const size_t N = c.params.N, L = c.params.L;
+    const size_t per = (size_t)f.mb * f.nb;
+    const size_t need = (size_t)f.O * L * N * 8 + (size_t)f.O * L * per * 8;
+    if (!ws || ws_bytes < need) return set_error(PIMM_E_WORKSPACE, "pimm_decrypt: workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    const int lg = c.dp.logN;
+    double *ch = (double *)ws;
+    uint64_t *cs = (uint64_t *)(ch + (size_t)f.O * L * N);
+    int rc = launch_fwd(c, LoadU64{c1, lg}, StoreSlots{ch, lg}, (int)(f.O * L), s);
+    if (!rc)
+        rc = launch_inv(c, LoadSlotsMul{ch, sk->d_s_hat, lg, (int)L},
+                        StoreDecoded{cs, lg, f.mb, f.rb, f.nb}, (int)(f.O * L), s);
+    if (!rc) {
+        const size_t total = (size_t)f.O * per;
+        const int threads = 256;
+        ProfScope prof("decode", s);
+        hipLaunchKernelGGL(k_decode, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads),
+                           0, s, c0s, cs, client_share, f, c.dp);
+        rc = check_hip(hipGetLastError(), "decode launch");
+    }
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,259 @@
+// common.h -- internal types and device arithmetic of libpimm (gfx950).
+//
+// Residue arithmetic on the hot path runs on the FP64 vector unit, which on
+// CDNA4 issues one FMA per lane per clock while 32-bit integer multiplies run
+// at a quarter of that.  All primes are below 2^50, so residues and their
+// small multiples are exact doubles, and a product a*b (< 2^103) splits
+// exactly into h + l with h = RN(a*b) and l = fma(a, b, -h) (the
+// error-free product of Dekker / Ogita-Rump-Oishi).  The reduction estimates
+// the quotient k = rint(h / p) from a double reciprocal and forms
+// (h - k p) + l with one more fma; both steps are exact because the true
+// value is an integer far below 2^53 (the floating-point modular product of
+// van der Hoeven, Lecerf and Quintin, "Modular SIMD arithmetic in
+// Mathemagix", 2014).  Values are kept "balanced": any double of magnitude
+// below a few p stands for its residue; canonical [0, q) integers appear only
+// where data crosses the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pimm.h"
+
+namespace pimm {
+
+constexpr int kMaxL = 4;
+constexpr int kCdtLen = 19;
+constexpr int kMinLogN = 12;
+constexpr int kMaxLogN = 13;
+
+// Stream tags: which random object a ChaCha20 stream feeds.
+enum Tag : uint32_t {
+    kTagSK = 1,
+    kTagPkA = 2,
+    kTagPkE = 3,
+    kTagEncA = 4,
+    kTagEncE = 5,
+    kTagRrU = 6,
+    kTagRrE1 = 7,
+    kTagRrE2 = 8,
+    kTagMask = 9,
+};
+
+// Everything a kernel needs to know about the parameters, passed by value.
+struct DevParams {
+    int N, logN, L, ell;
+    double p[kMaxL], pinv[kMaxL];
+    uint64_t q[kMaxL];
+    uint64_t delta[kMaxL];           // floor(q / t) mod q_l
+    double n_inv[kMaxL];             // N^-1 mod q_l, balanced
+    double garner_inv[kMaxL];        // (q_0 ... q_{l-1})^-1 mod q_l
+    double garner_c[kMaxL][kMaxL];   // (q_0 ... q_{i-1}) mod q_l for i < l
+    uint64_t Q[kMaxL + 1];           // q, little-endian 64-bit limbs
+    uint64_t halfQ[kMaxL + 1];       // floor(q / 2)
+    double Qd;                       // q rounded to a double
+    uint64_t cdt[kCdtLen];
+    const double *tw_fwd;            // [L][N] psi^bitrev(k), balanced
+    const double *tw_inv;            // [L][N] psi^-bitrev(k), balanced
+};
+
+// 32-byte ChaCha20 key as little-endian words.
+struct Key {
+    uint32_t w[8];
+};
+
+// ---------------------------------------------------------------------------
+// FP64 residue arithmetic
+// ---------------------------------------------------------------------------
+
+// a*b - k*p for the k nearest a*b/p: exact; for |a| <= B p, |b| <= p/2 the result
+// lies within (0.5 + 0.1875 B) p of zero.
+__device__ __forceinline__ double mulmod(double a, double b, double p, double pinv)
+{
+    const double h = a * b;
+    const double l = __builtin_fma(a, b, -h);
+    const double k = __builtin_rint(h * pinv);
+    const double r = __builtin_fma(-k, p, h);
+    return r + l;
+}
+
+// x - k*p for the k nearest x/p: |result| <= p/2 (+ a few units) for |x| < 2^52.
+__device__ __forceinline__ double reduce(double x, double p, double pinv)
+{
+    return __builtin_fma(-__builtin_rint(x * pinv), p, x);
+}
+
+// Balanced double -> canonical residue in [0, p).
+__device__ __forceinline__ uint64_t to_canonical(double x, double p, double pinv)
+{
+    x = reduce(x, p, pinv);
+    if (x < 0.0) x += p;
+    if (x >= p) x -= p;
+    return (uint64_t)x;
+}
+
+// Canonical residues: exact add/sub for values < 2^63.
+__device__ __forceinline__ uint64_t add_mod(uint64_t a, uint64_t b, uint64_t q)
+{
+    uint64_t s = a + b;
+    return s >= q ? s - q : s;
+}
+__device__ __forceinline__ uint64_t sub_mod(uint64_t a, uint64_t b, uint64_t q)
+{
+    return a >= b ? a - b : a + q - b;
+}
+// Signed small integer -> canonical residue.
+__device__ __forceinline__ uint64_t lift_signed(int64_t x, uint64_t q)
+{
+    return x >= 0 ? (uint64_t)x % q : q - ((uint64_t)(-x) % q);
+}
+// Canonical product through the FP64 path.
+__device__ __forceinline__ uint64_t mul_mod(uint64_t a, uint64_t b, double p, double pinv)
+{
+    return to_canonical(mulmod((double)a, (double)b, p, pinv), p, pinv);
+}
+
+// ---------------------------------------------------------------------------
+// ChaCha20 block function (RFC 8439 section 2.3) and the samplers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t rotl(uint32_t v, int c) { return (v << c) | (v >> (32 - c)); }
+
+#define PIMM_QR(a, b, c, d)                  \
+    a += b; d ^= a; d = rotl(d, 16);         \
+    c += d; b ^= c; b = rotl(b, 12);         \
+    a += b; d ^= a; d = rotl(d, 8);          \
+    c += d; b ^= c; b = rotl(b, 7);
+
+__device__ __forceinline__ void chacha_block(const Key &k, uint32_t counter, uint32_t n0, uint32_t n1,
+                                             uint32_t n2, uint32_t out[16])
+{
+    const uint32_t s0 = 0x61707865u, s1 = 0x3320646eu, s2 = 0x79622d32u, s3 = 0x6b206574u;
+    uint32_t x0 = s0, x1 = s1, x2 = s2, x3 = s3;
+    uint32_t x4 = k.w[0], x5 = k.w[1], x6 = k.w[2], x7 = k.w[3];
+    uint32_t x8 = k.w[4], x9 = k.w[5], x10 = k.w[6], x11 = k.w[7];
+    uint32_t x12 = counter, x13 = n0, x14 = n1, x15 = n2;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        PIMM_QR(x0, x4, x8, x12)
+        PIMM_QR(x1, x5, x9, x13)
+        PIMM_QR(x2, x6, x10, x14)
+        PIMM_QR(x3, x7, x11, x15)
+        PIMM_QR(x0, x5, x10, x15)
+        PIMM_QR(x1, x6, x11, x12)
+        PIMM_QR(x2, x7, x8, x13)
+        PIMM_QR(x3, x4, x9, x14)
+    }
+    out[0] = x0 + s0; out[1] = x1 + s1; out[2] = x2 + s2; out[3] = x3 + s3;
+    out[4] = x4 + k.w[0]; out[5] = x5 + k.w[1]; out[6] = x6 + k.w[2]; out[7] = x7 + k.w[3];
+    out[8] = x8 + k.w[4]; out[9] = x9 + k.w[5]; out[10] = x10 + k.w[6]; out[11] = x11 + k.w[7];
+    out[12] = x12 + counter; out[13] = x13 + n0; out[14] = x14 + n1; out[15] = x15 + n2;
+}
+#undef PIMM_QR
+
+// Nonce word 0 of a stream.
+__device__ __forceinline__ uint32_t nonce0(uint32_t tag, uint32_t prime) { return tag | (prime << 8); }
+
+// (hi 2^64 + lo) mod q for q < 2^50: Horner over 32-bit words, each step
+// (r 2^32 + w) mod q with r 2^32 formed exactly as a double.
+__device__ __forceinline__ uint64_t mod_u128(uint64_t lo, uint64_t hi, uint64_t q, double p,
+                                             double pinv)
+{
+    const uint32_t w[4] = {(uint32_t)(hi >> 32), (uint32_t)hi, (uint32_t)(lo >> 32), (uint32_t)lo};
+    int64_t r = (int64_t)w[0];
+#pragma unroll
+    for (int i = 1; i < 4; ++i) {
+        const double h = (double)r * 4294967296.0;
+        int64_t t = (int64_t)reduce(h, p, pinv) + (int64_t)w[i];
+        if (t < 0) t += (int64_t)q;
+        if (t >= (int64_t)q) t -= (int64_t)q;
+        r = t;
+    }
+    return (uint64_t)r;
+}
+
+__device__ __forceinline__ int64_t ternary_of(uint64_t v) { return (int64_t)(v % 3u) - 1; }
+
+__device__ __forceinline__ int64_t gauss_of(uint64_t v, const uint64_t *cdt)
+{
+    const uint64_t u = v & 0x7fffffffffffffffull;
+    int64_t mag = 0;
+#pragma unroll
+    for (int k = 0; k < kCdtLen; ++k) mag += (u >= cdt[k]) ? 1 : 0;
+    return (v >> 63) ? -mag : mag;
+}
+
+__device__ __forceinline__ uint64_t mask_of(uint64_t v, int ell)
+{
+    return ell >= 64 ? v : (v & ((1ull << ell) - 1));
+}
+
+__device__ __forceinline__ uint64_t word64(const uint32_t b[16], int i)
+{
+    return (uint64_t)b[2 * i] | ((uint64_t)b[2 * i + 1] << 32);
+}
+
+// ---------------------------------------------------------------------------
+// Host-side objects
+// ---------------------------------------------------------------------------
+
+struct Ctx {
+    pimm_params params;
+    int device;
+    DevParams dp;             // with device table pointers
+    double *d_tw = nullptr;   // [2][L][N] device: forward then inverse twiddles
+    uint64_t q[kMaxL];
+    uint64_t psi[kMaxL];
+};
+
+struct Plan {
+    Ctx *ctx;
+    pimm_plan_info info;
+};
+
+struct SecretKey {
+    Ctx *ctx;
+    int64_t *d_s = nullptr;   // [N] ternary coefficients
+    double *d_s_hat = nullptr; // [L][N] NTT of s, balanced
+};
+
+struct Weights {
+    const Plan *plan;
+    double *d_w_hat = nullptr; // [Wb][L][N] NTT slots, balanced
+    int64_t wmax = 0;
+};
+
+// Error reporting (thread-local message).
+int set_error(int code, const char *fmt, ...);
+int check_hip(hipError_t e, const char *what);
+Key make_key(const uint8_t seed[32]);
+bool noise_ok(const Ctx &c, const pimm_plan_info &f, uint64_t wmax);
+
+// Brackets one kernel launch with HIP events when profiling is on.
+class ProfScope {
+  public:
+    ProfScope(const char *name, hipStream_t s);
+    ~ProfScope();
+
+  private:
+    const char *name_;
+    hipStream_t s_;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
+    bool active_ = false;
+};
+
+// Launch helpers implemented in the kernel translation units.
+int launch_ntt_fwd_u64(const Ctx &c, const uint64_t *in, double *out, int npoly, hipStream_t s);
+int launch_ntt_fwd_i64_shared(const Ctx &c, const int64_t *in, double *out, int nsrc,
+                              hipStream_t s);
+int launch_intt_mul_u64(const Ctx &c, const double *a, const double *b, int b_mod, uint64_t *out,
+                        int npoly, hipStream_t s);
+int launch_intt_u64(const Ctx &c, const double *in, uint64_t *out, int npoly, hipStream_t s);
+
+}  // namespace pimm
+
+// The C handle types are the internal objects.
+struct pimm_ctx : pimm::Ctx {};
+struct pimm_plan : pimm::Plan {};
+struct pimm_sk : pimm::SecretKey {};
+struct pimm_weights : pimm::Weights {};

@@ -1,0 +1,643 @@
+// context.hip -- parameters, plans, keys, sampling and the ring-product primitive.
+//
+// Parameters follow section 2.2 (BFV with RNS: N a power of two, t = 2^l,
+// q a product of word-size primes).  The paper fixes only N = 8192 and
+// q ~ 180 bits for its runs; the library takes N, L and l from the caller and
+// uses the L largest primes below 2^50 that are 1 mod 2N (so negacyclic NTTs
+// of length N exist and every residue is an exact double).
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+#include "common.h"
+#include "ntt.h"
+
+extern "C" int pimm_host_cdt(int len, uint64_t *out);
+
+namespace pimm {
+
+static thread_local char g_err[512] = "";
+
+int set_error(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int check_hip(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return PIMM_OK;
+    if (e == hipErrorOutOfMemory) return set_error(PIMM_E_OOM, "%s: %s", what, hipGetErrorString(e));
+    return set_error(PIMM_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+Key make_key(const uint8_t seed[32])
+{
+    Key k;
+    for (int i = 0; i < 8; ++i)
+        k.w[i] = (uint32_t)seed[4 * i] | ((uint32_t)seed[4 * i + 1] << 8) |
+                 ((uint32_t)seed[4 * i + 2] << 16) | ((uint32_t)seed[4 * i + 3] << 24);
+    return k;
+}
+
+// ---- host integer arithmetic -------------------------------------------------
+
+using u128 = unsigned __int128;
+
+static uint64_t h_mul(uint64_t a, uint64_t b, uint64_t q) { return (uint64_t)((u128)a * b % q); }
+
+static uint64_t h_pow(uint64_t a, uint64_t e, uint64_t q)
+{
+    uint64_t r = 1 % q;
+    a %= q;
+    while (e) {
+        if (e & 1) r = h_mul(r, a, q);
+        a = h_mul(a, a, q);
+        e >>= 1;
+    }
+    return r;
+}
+
+static uint64_t h_inv(uint64_t a, uint64_t q) { return h_pow(a, q - 2, q); }
+
+// Miller-Rabin with the first twelve prime bases: deterministic below 3.3e24.
+static bool h_is_prime(uint64_t n)
+{
+    static const uint64_t bases[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+    if (n < 2) return false;
+    for (uint64_t b : bases)
+        if (n % b == 0) return n == b;
+    uint64_t d = n - 1;
+    int s = 0;
+    while ((d & 1) == 0) {
+        d >>= 1;
+        ++s;
+    }
+    for (uint64_t a : bases) {
+        uint64_t x = h_pow(a, d, n);
+        if (x == 1 || x == n - 1) continue;
+        bool comp = true;
+        for (int i = 1; i < s; ++i) {
+            x = h_mul(x, x, n);
+            if (x == n - 1) {
+                comp = false;
+                break;
+            }
+        }
+        if (comp) return false;
+    }
+    return true;
+}
+
+static uint32_t bitrev(uint32_t x, int bits)
+{
+    uint32_t r = 0;
+    for (int i = 0; i < bits; ++i) r |= ((x >> i) & 1u) << (bits - 1 - i);
+    return r;
+}
+
+// Residue v in [0, q) as the balanced double in (-q/2, q/2].
+static double balanced(uint64_t v, uint64_t q)
+{
+    return v > q / 2 ? -(double)(q - v) : (double)v;
+}
+
+// Little-endian multi-limb helpers for q = prod q_l (at most 4 x 50 bits).
+static void limbs_mul_small(uint64_t *x, int n, uint64_t m)
+{
+    u128 carry = 0;
+    for (int i = 0; i < n; ++i) {
+        u128 v = (u128)x[i] * m + carry;
+        x[i] = (uint64_t)v;
+        carry = v >> 64;
+    }
+}
+
+static uint64_t limbs_mod_small(const uint64_t *x, int n, uint64_t q)
+{
+    uint64_t r = 0;
+    for (int i = n - 1; i >= 0; --i) r = (uint64_t)((((u128)r << 64) | x[i]) % q);
+    return r;
+}
+
+static void limbs_shr(const uint64_t *x, uint64_t *y, int n, int s)
+{
+    for (int i = 0; i < n; ++i) {
+        int w = i + s / 64, b = s % 64;
+        uint64_t lo = w < n ? x[w] >> b : 0;
+        uint64_t hi = (b && w + 1 < n) ? x[w + 1] << (64 - b) : 0;
+        y[i] = lo | hi;
+    }
+}
+
+// ---- context -----------------------------------------------------------------
+
+static int build_context(const pimm_params &prm, int device, Ctx *c, bool upload)
+{
+    if (prm.N < (1u << kMinLogN) || prm.N > (1u << kMaxLogN) || (prm.N & (prm.N - 1)))
+        return set_error(PIMM_E_PARAMS, "N = %u must be a power of two in [%d, %d]", prm.N,
+                         1 << kMinLogN, 1 << kMaxLogN);
+    if (prm.L < 1 || prm.L > (uint32_t)kMaxL)
+        return set_error(PIMM_E_PARAMS, "L = %u must be in [1, %d]", prm.L, kMaxL);
+    if (prm.log2_t < 2 || prm.log2_t > 48)
+        return set_error(PIMM_E_PARAMS, "log2_t = %u must be in [2, 48]", prm.log2_t);
+    if (prm.prime_bits != 50)
+        return set_error(PIMM_E_PARAMS, "prime_bits = %u: only 50-bit primes are supported",
+                         prm.prime_bits);
+    c->params = prm;
+    c->device = device;
+    const int N = (int)prm.N, L = (int)prm.L;
+    int logN = 0;
+    while ((1 << logN) < N) ++logN;
+
+    // Primes: the L largest q < 2^50 with q = 1 mod 2N, descending.
+    uint64_t k = ((1ull << 50) - 2) / (2ull * N);
+    for (int l = 0; l < L; --k) {
+        uint64_t cand = k * 2ull * N + 1;
+        if (cand < (1ull << 50) && h_is_prime(cand)) c->q[l++] = cand;
+    }
+    // psi: g^((q-1)/2N) for the first g with psi^N = -1 (then psi has order exactly 2N).
+    for (int l = 0; l < L; ++l) {
+        const uint64_t q = c->q[l];
+        c->psi[l] = 0;
+        for (uint64_t g = 2; g < 1000; ++g) {
+            uint64_t ps = h_pow(g, (q - 1) / (2ull * N), q);
+            if (h_pow(ps, N, q) == q - 1) {
+                c->psi[l] = ps;
+                break;
+            }
+        }
+        if (!c->psi[l]) return set_error(PIMM_E_PARAMS, "no 2N-th root of unity mod q_%d", l);
+    }
+
+    DevParams &d = c->dp;
+    memset(&d, 0, sizeof d);
+    d.N = N;
+    d.logN = logN;
+    d.L = L;
+    d.ell = (int)prm.log2_t;
+    for (int l = 0; l < L; ++l) {
+        d.q[l] = c->q[l];
+        d.p[l] = (double)c->q[l];
+        d.pinv[l] = 1.0 / (double)c->q[l];
+        d.n_inv[l] = balanced(h_inv((uint64_t)N, c->q[l]), c->q[l]);
+    }
+    // q as limbs, floor(q/2), Delta = floor(q / 2^l) mod q_l.
+    uint64_t Q[kMaxL + 1] = {1, 0, 0, 0, 0};
+    for (int l = 0; l < L; ++l) limbs_mul_small(Q, kMaxL + 1, c->q[l]);
+    memcpy(d.Q, Q, sizeof Q);
+    limbs_shr(Q, d.halfQ, kMaxL + 1, 1);
+    uint64_t Delta[kMaxL + 1];
+    limbs_shr(Q, Delta, kMaxL + 1, (int)prm.log2_t);
+    for (int l = 0; l < L; ++l) d.delta[l] = limbs_mod_small(Delta, kMaxL + 1, c->q[l]);
+    long double qd = 0.0L;
+    for (int i = kMaxL; i >= 0; --i) qd = qd * 18446744073709551616.0L + (long double)Q[i];
+    d.Qd = (double)qd;
+    // Garner constants for the mixed-radix CRT.
+    for (int l = 0; l < L; ++l) {
+        uint64_t prod = 1 % c->q[l];
+        for (int i = 0; i < l; ++i) {
+            d.garner_c[l][i] = (double)prod;
+            prod = h_mul(prod, c->q[i] % c->q[l], c->q[l]);
+        }
+        d.garner_inv[l] = (double)h_inv(prod, c->q[l]);
+    }
+    if (pimm_host_cdt(kCdtLen, d.cdt) != 0) return set_error(PIMM_E_PARAMS, "CDT table failed");
+
+    if (!upload) return PIMM_OK;
+    // Twiddles: forward psi^bitrev(k), inverse psi^-bitrev(k), balanced doubles.
+    std::vector<double> tw(2ull * L * N);
+    for (int l = 0; l < L; ++l) {
+        const uint64_t q = c->q[l], pinvv = h_inv(c->psi[l], q);
+        for (int i = 0; i < N; ++i) {
+            uint32_t e = bitrev((uint32_t)i, logN);
+            tw[(size_t)l * N + i] = balanced(h_pow(c->psi[l], e, q), q);
+            tw[((size_t)L + l) * N + i] = balanced(h_pow(pinvv, e, q), q);
+        }
+    }
+    int rc = check_hip(hipSetDevice(device), "hipSetDevice");
+    if (rc) return rc;
+    rc = check_hip(hipMalloc((void **)&c->d_tw, tw.size() * sizeof(double)), "hipMalloc twiddles");
+    if (rc) return rc;
+    rc = check_hip(hipMemcpy(c->d_tw, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice),
+                   "copy twiddles");
+    if (rc) return rc;
+    d.tw_fwd = c->d_tw;
+    d.tw_inv = c->d_tw + (size_t)L * N;
+    return PIMM_OK;
+}
+
+// ---- plans -------------------------------------------------------------------
+
+static uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+static uint64_t next_pow2(uint64_t x)
+{
+    uint64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+static void fill_info(const Ctx &c, pimm_plan_info &f)
+{
+    const uint64_t N = c.params.N, L = c.params.L;
+    f.M = (uint32_t)ceil_div(f.m, f.mb);
+    f.R = (uint32_t)ceil_div(f.r, f.rb);
+    f.K = (uint32_t)ceil_div(f.n, f.nb);
+    f.I = f.R * f.K;
+    f.O = f.M * f.K;
+    f.Wb = f.M * f.R;
+    f.P = (uint64_t)f.M * f.R * f.K;
+    f.pt_bytes = (uint64_t)f.I * N * 8;
+    f.ct_bytes = (uint64_t)f.I * 2 * L * N * 8;
+    f.acc_bytes = (uint64_t)f.O * 2 * L * N * 8;
+    f.c1_bytes = (uint64_t)f.O * L * N * 8;
+    f.c0s_bytes = (uint64_t)f.O * L * f.mb * f.nb * 8;
+    f.share_bytes = (uint64_t)f.n * f.m * 8;
+    f.weights_bytes = (uint64_t)f.Wb * L * N * 8;
+    // Scratch of each call (see the call's implementation for the layout).
+    const uint64_t enc = (uint64_t)f.I * N * 8 * (L + 1);
+    const uint64_t mm = ((uint64_t)f.I + f.O) * 2 * L * N * 8;
+    const uint64_t msk = 2 * L * N * 8 + (uint64_t)f.O * L * N * 8 + (uint64_t)f.O * 3 * N * 8;
+    const uint64_t dec = (uint64_t)f.O * L * N * 8 + (uint64_t)f.O * L * f.mb * f.nb * 8;
+    uint64_t ws = enc;
+    if (mm > ws) ws = mm;
+    if (msk > ws) ws = msk;
+    if (dec > ws) ws = dec;
+    f.workspace_bytes = ws;
+}
+
+static int plan_rule(const Ctx &c, uint32_t n, uint32_t r, uint32_t m, uint32_t mb, uint32_t rb,
+                     uint32_t nb, uint32_t d_fix, pimm_plan_info &f)
+{
+    const uint64_t N = c.params.N;
+    memset(&f, 0, sizeof f);
+    f.n = n;
+    f.r = r;
+    f.m = m;
+    if (mb && rb && nb) {
+        if ((uint64_t)mb * rb * nb > N)
+            return set_error(PIMM_E_SHAPE, "block %u x %u x %u exceeds N = %llu", mb, rb, nb,
+                             (unsigned long long)N);
+        f.mb = mb;
+        f.rb = rb;
+        f.nb = nb;
+    } else if (d_fix) {
+        if ((d_fix & (d_fix - 1)) || d_fix > N)
+            return set_error(PIMM_E_SHAPE, "d_fix = %u must be a power of two <= N", d_fix);
+        uint64_t best_cost = ~0ull, bm = 1;
+        for (uint64_t tm = 1; tm <= d_fix; tm *= 2) {
+            uint64_t cost = ceil_div(r, d_fix / tm) + ceil_div(m, tm);
+            if (cost < best_cost || (cost == best_cost && tm > bm)) {
+                best_cost = cost;
+                bm = tm;
+            }
+        }
+        f.mb = (uint32_t)bm;
+        f.rb = (uint32_t)(d_fix / bm);
+        f.nb = (uint32_t)(n < N / d_fix ? n : N / d_fix);
+    } else {
+        uint64_t best_cost = ~0ull, bnb = 0, bmb = 0, brb = 0;
+        for (uint64_t tm = 1; tm <= next_pow2(m) && tm <= N; tm *= 2)
+            for (uint64_t tr = 1; tr <= next_pow2(r) && tm * tr <= N; tr *= 2) {
+                uint64_t tn = N / (tm * tr);
+                if (tn > n) tn = n;
+                uint64_t cost = (ceil_div(r, tr) + ceil_div(m, tm)) * ceil_div(n, tn);
+                bool better = cost < best_cost || (cost == best_cost && tn > bnb) ||
+                              (cost == best_cost && tn == bnb && tm > bmb);
+                if (better) {
+                    best_cost = cost;
+                    bnb = tn;
+                    bmb = tm;
+                    brb = tr;
+                }
+            }
+        f.mb = (uint32_t)bmb;
+        f.rb = (uint32_t)brb;
+        f.nb = (uint32_t)bnb;
+    }
+    fill_info(c, f);
+    if ((uint64_t)f.Wb * c.params.L >= (1ull << 31) || (uint64_t)f.I * 2 * c.params.L >= (1ull << 31))
+        return set_error(PIMM_E_SHAPE, "plan has too many blocks for one launch");
+    return PIMM_OK;
+}
+
+// Worst-case decryption noise of a reply coefficient (exact, 128-bit):
+//   R*D*wmax*19           products a * e of every inner block (|e| <= 19),
+//   (q mod t)(r*wmax + 1) Delta*t = q - (q mod t): each multiple of t carried by
+//                         the integer product a*b and the mask's wrap past t,
+//   2*N*19 + 19           u*e' + e1 + e2*s of the re-randomisation (if on).
+// Decryption rounds correctly when 2 t (E + (q mod t)) < q.
+bool noise_ok(const Ctx &c, const pimm_plan_info &f, uint64_t wmax)
+{
+    using u128 = unsigned __int128;
+    const uint64_t t = 1ull << c.params.log2_t;
+    const uint64_t qt = c.dp.Q[0] & (t - 1);
+    const u128 D = (u128)f.mb * f.rb;
+    u128 E = (u128)f.R * D * wmax * kCdtLen + (u128)qt * ((u128)f.r * wmax + 1);
+    if (c.params.rerandomize) E += (u128)2 * c.params.N * kCdtLen + kCdtLen;
+    // lhs = 2 t (E + qt) as limbs; compare with q.
+    const u128 a = E + qt;
+    uint64_t lhs[kMaxL + 1] = {0, 0, 0, 0, 0};
+    const int sh = (int)c.params.log2_t + 1;  // 3 .. 49
+    // a < 2^110, so a << sh < 2^160 spans three limbs.
+    const u128 lo = a << sh;
+    lhs[0] = (uint64_t)lo;
+    lhs[1] = (uint64_t)(lo >> 64);
+    lhs[2] = (uint64_t)(a >> (128 - sh));
+    for (int i = kMaxL; i >= 0; --i) {
+        if (lhs[i] != c.dp.Q[i]) return lhs[i] < c.dp.Q[i];
+    }
+    return false;
+}
+
+// ---- sampling kernels --------------------------------------------------------
+
+// One thread per ChaCha20 block of stream (tag, prime, op, obj0 + o):
+// KIND 0 writes four uniform residues mod q_prime (uint64), 1 eight ternary
+// values (int64), 2 eight Gaussian values (int64), 3 eight Z_{2^l} values (uint64).
+template <int KIND>
+__global__ void k_sample(Key key, uint32_t tag, uint32_t op, uint32_t obj0, int nobj, int prime0,
+                         int nprime, void *out, size_t obj_stride, size_t prime_stride, DevParams dp)
+{
+    const int per = KIND == 0 ? 4 : 8;
+    const int nblk = dp.N / per;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (long)nblk * nprime * nobj) return;
+    const int b = (int)(gid % nblk);
+    const int li = (int)((gid / nblk) % nprime);
+    const int l = prime0 + li;
+    const int o = (int)(gid / ((long)nblk * nprime));
+    uint32_t w[16];
+    chacha_block(key, (uint32_t)b, nonce0(tag, KIND == 0 ? (uint32_t)l : 0u), op, obj0 + (uint32_t)o,
+                 w);
+    const size_t base = (size_t)o * obj_stride + (size_t)li * prime_stride + (size_t)b * per;
+    if (KIND == 0) {
+        uint64_t *dst = (uint64_t *)out + base;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            dst[i] = mod_u128(word64(w, 2 * i), word64(w, 2 * i + 1), dp.q[l], dp.p[l], dp.pinv[l]);
+    } else if (KIND == 1) {
+        int64_t *dst = (int64_t *)out + base;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) dst[i] = ternary_of(word64(w, i));
+    } else if (KIND == 2) {
+        int64_t *dst = (int64_t *)out + base;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) dst[i] = gauss_of(word64(w, i), dp.cdt);
+    } else {
+        uint64_t *dst = (uint64_t *)out + base;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) dst[i] = mask_of(word64(w, i), dp.ell);
+    }
+}
+
+int launch_sample(const Ctx &c, int kind, const Key &key, uint32_t tag, uint32_t op, uint32_t obj0,
+                  int nobj, int prime0, int nprime, void *out, size_t obj_stride,
+                  size_t prime_stride, hipStream_t s)
+{
+    if (nobj <= 0) return PIMM_OK;
+    const int per = kind == 0 ? 4 : 8;
+    const long total = (long)(c.dp.N / per) * nprime * nobj;
+    const int threads = 256;
+    const dim3 grid((unsigned)((total + threads - 1) / threads));
+    ProfScope prof("sample", s);
+    switch (kind) {
+    case 0:
+        hipLaunchKernelGGL(k_sample<0>, grid, dim3(threads), 0, s, key, tag, op, obj0, nobj, prime0,
+                           nprime, out, obj_stride, prime_stride, c.dp);
+        break;
+    case 1:
+        hipLaunchKernelGGL(k_sample<1>, grid, dim3(threads), 0, s, key, tag, op, obj0, nobj, prime0,
+                           nprime, out, obj_stride, prime_stride, c.dp);
+        break;
+    case 2:
+        hipLaunchKernelGGL(k_sample<2>, grid, dim3(threads), 0, s, key, tag, op, obj0, nobj, prime0,
+                           nprime, out, obj_stride, prime_stride, c.dp);
+        break;
+    default:
+        hipLaunchKernelGGL(k_sample<3>, grid, dim3(threads), 0, s, key, tag, op, obj0, nobj, prime0,
+                           nprime, out, obj_stride, prime_stride, c.dp);
+        break;
+    }
+    return check_hip(hipGetLastError(), "sample launch");
+}
+
+// pk0[l][j] = [e'_j - (a' s)_j]_{q_l}: storer of the inverse NTT of a'^ s^.
+struct StorePk0 {
+    const int64_t *e;
+    uint64_t *pk0;  // [L][N]
+    int logn;
+    __device__ void operator()(int poly, int l, int j, double v, double p, double pinv) const
+    {
+        const uint64_t q = (uint64_t)p;
+        const uint64_t as = to_canonical(v, p, pinv);
+        pk0[((size_t)poly << logn) + j] = sub_mod(lift_signed(e[j], q), as, q);
+    }
+};
+
+}  // namespace pimm
+
+using namespace pimm;
+
+// ---- C ABI -------------------------------------------------------------------
+
+extern "C" {
+
+const char *pimm_last_error(void) { return g_err; }
+
+int pimm_sync(void *stream)
+{
+    return check_hip(hipStreamSynchronize((hipStream_t)stream), "stream synchronize");
+}
+
+int pimm_ctx_create(const pimm_params *params, int device, pimm_ctx **out)
+{
+    if (!params || !out) return set_error(PIMM_E_ARG, "pimm_ctx_create: NULL argument");
+    pimm_ctx *c = new pimm_ctx();
+    int rc = build_context(*params, device, c, true);
+    if (rc) {
+        if (c->d_tw) (void)hipFree(c->d_tw);
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return PIMM_OK;
+}
+
+int pimm_ctx_destroy(pimm_ctx *ctx)
+{
+    if (!ctx) return PIMM_OK;
+    if (ctx->d_tw) (void)hipFree(ctx->d_tw);
+    delete ctx;
+    return PIMM_OK;
+}
+
+int pimm_ctx_primes(const pimm_ctx *ctx, uint64_t *q_out)
+{
+    if (!ctx || !q_out) return set_error(PIMM_E_ARG, "pimm_ctx_primes: NULL argument");
+    for (uint32_t l = 0; l < ctx->params.L; ++l) q_out[l] = ctx->q[l];
+    return PIMM_OK;
+}
+
+int pimm_ctx_cdt(const pimm_ctx *ctx, uint64_t *cdt_out)
+{
+    if (!ctx || !cdt_out) return set_error(PIMM_E_ARG, "pimm_ctx_cdt: NULL argument");
+    memcpy(cdt_out, ctx->dp.cdt, sizeof ctx->dp.cdt);
+    return PIMM_OK;
+}
+
+int pimm_params_primes(const pimm_params *params, uint64_t *q_out)
+{
+    if (!params || !q_out) return set_error(PIMM_E_ARG, "pimm_params_primes: NULL argument");
+    Ctx c;
+    int rc = build_context(*params, 0, &c, false);
+    if (rc) return rc;
+    for (uint32_t l = 0; l < params->L; ++l) q_out[l] = c.q[l];
+    return PIMM_OK;
+}
+
+int pimm_cdt(uint64_t *cdt_out)
+{
+    if (!cdt_out) return set_error(PIMM_E_ARG, "pimm_cdt: NULL argument");
+    if (pimm_host_cdt(kCdtLen, cdt_out) != 0) return set_error(PIMM_E_PARAMS, "CDT table failed");
+    return PIMM_OK;
+}
+
+int pimm_plan_rule(const pimm_params *params, uint32_t n, uint32_t r, uint32_t m, uint32_t mb,
+                   uint32_t rb, uint32_t nb, uint32_t d_fix, pimm_plan_info *info)
+{
+    if (!params || !info) return set_error(PIMM_E_ARG, "pimm_plan_rule: NULL argument");
+    if (!n || !r || !m) return set_error(PIMM_E_SHAPE, "empty matrix %u x %u x %u", n, r, m);
+    Ctx c;
+    int rc = build_context(*params, 0, &c, false);
+    if (rc) return rc;
+    return plan_rule(c, n, r, m, mb, rb, nb, d_fix, *info);
+}
+
+int pimm_noise_ok(const pimm_params *params, const pimm_plan_info *info, uint64_t wmax)
+{
+    if (!params || !info) return set_error(PIMM_E_ARG, "pimm_noise_ok: NULL argument");
+    Ctx c;
+    int rc = build_context(*params, 0, &c, false);
+    if (rc) return rc;
+    return noise_ok(c, *info, wmax) ? 1 : 0;
+}
+
+int pimm_plan_create(pimm_ctx *ctx, uint32_t n, uint32_t r, uint32_t m, uint32_t mb, uint32_t rb,
+                     uint32_t nb, uint32_t d_fix, pimm_plan **out)
+{
+    if (!ctx || !out) return set_error(PIMM_E_ARG, "pimm_plan_create: NULL argument");
+    if (!n || !r || !m) return set_error(PIMM_E_SHAPE, "empty matrix %u x %u x %u", n, r, m);
+    pimm_plan_info f;
+    int rc = plan_rule(*ctx, n, r, m, mb, rb, nb, d_fix, f);
+    if (rc) return rc;
+    pimm_plan *p = new pimm_plan();
+    p->ctx = ctx;
+    p->info = f;
+    *out = p;
+    return PIMM_OK;
+}
+
+int pimm_plan_destroy(pimm_plan *plan)
+{
+    delete plan;
+    return PIMM_OK;
+}
+
+int pimm_plan_query(const pimm_plan *plan, pimm_plan_info *info)
+{
+    if (!plan || !info) return set_error(PIMM_E_ARG, "pimm_plan_query: NULL argument");
+    *info = plan->info;
+    return PIMM_OK;
+}
+
+int pimm_sample_poly(pimm_ctx *ctx, int kind, const uint8_t seed[32], uint32_t tag, uint32_t prime,
+                     uint32_t op_id, uint32_t obj, void *out, void *stream)
+{
+    if (!ctx || !seed || !out) return set_error(PIMM_E_ARG, "pimm_sample_poly: NULL argument");
+    if (kind < 0 || kind > 3) return set_error(PIMM_E_ARG, "kind %d not in 0..3", kind);
+    if (kind == 0 && prime >= ctx->params.L)
+        return set_error(PIMM_E_ARG, "prime %u >= L", prime);
+    if (kind != 0 && prime != 0) return set_error(PIMM_E_ARG, "only uniform draws are per prime");
+    return launch_sample(*ctx, kind, make_key(seed), tag, op_id, obj, 1, (int)prime, 1, out, 0, 0,
+                         (hipStream_t)stream);
+}
+
+int pimm_keygen(pimm_ctx *ctx, const uint8_t seed[32], pimm_sk **sk_out, uint64_t *pk_out,
+                void *stream)
+{
+    if (!ctx || !seed || !sk_out) return set_error(PIMM_E_ARG, "pimm_keygen: NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    const int N = (int)ctx->params.N, L = (int)ctx->params.L;
+    int rc = check_hip(hipSetDevice(ctx->device), "hipSetDevice");
+    if (rc) return rc;
+    pimm_sk *sk = new pimm_sk();
+    sk->ctx = ctx;
+    Key key = make_key(seed);
+    double *tmp = nullptr;
+    int64_t *e = nullptr;
+    rc = check_hip(hipMalloc((void **)&sk->d_s, (size_t)N * 8), "hipMalloc sk");
+    if (!rc) rc = check_hip(hipMalloc((void **)&sk->d_s_hat, (size_t)L * N * 8), "hipMalloc sk");
+    if (!rc) rc = launch_sample(*ctx, 1, key, kTagSK, 0, 0, 1, 0, 1, sk->d_s, 0, 0, s);
+    if (!rc)
+        rc = launch_fwd(*ctx, LoadI64Shared{sk->d_s, ctx->dp.logN, L},
+                        StoreSlots{sk->d_s_hat, ctx->dp.logN}, L, s);
+    if (!rc && pk_out && ctx->params.rerandomize) {
+        uint64_t *pk1 = pk_out + (size_t)L * N;
+        rc = check_hip(hipMalloc((void **)&tmp, (size_t)L * N * 8), "hipMalloc keygen");
+        if (!rc) rc = check_hip(hipMalloc((void **)&e, (size_t)N * 8), "hipMalloc keygen");
+        if (!rc) rc = launch_sample(*ctx, 0, key, kTagPkA, 0, 0, 1, 0, L, pk1, 0, (size_t)N, s);
+        if (!rc) rc = launch_sample(*ctx, 2, key, kTagPkE, 0, 0, 1, 0, 1, e, 0, 0, s);
+        if (!rc) rc = launch_fwd(*ctx, LoadU64{pk1, ctx->dp.logN}, StoreSlots{tmp, ctx->dp.logN}, L, s);
+        if (!rc)
+            rc = launch_inv(*ctx, LoadSlotsMul{tmp, sk->d_s_hat, ctx->dp.logN, L},
+                            StorePk0{e, pk_out, ctx->dp.logN}, L, s);
+        if (!rc) rc = check_hip(hipStreamSynchronize(s), "keygen synchronize");
+    }
+    if (tmp) (void)hipFree(tmp);
+    if (e) (void)hipFree(e);
+    if (rc) {
+        pimm_sk_destroy(sk);
+        return rc;
+    }
+    *sk_out = sk;
+    return PIMM_OK;
+}
+
+int pimm_sk_destroy(pimm_sk *sk)
+{
+    if (!sk) return PIMM_OK;
+    if (sk->d_s) (void)hipFree(sk->d_s);
+    if (sk->d_s_hat) (void)hipFree(sk->d_s_hat);
+    delete sk;
+    return PIMM_OK;
+}
+
+uint64_t pimm_poly_mul_workspace(const pimm_ctx *ctx, uint32_t count)
+{
+    if (!ctx) return 0;
+    return 2ull * count * ctx->params.L * ctx->params.N * 8;
+}
+
+int pimm_poly_mul(pimm_ctx *ctx, const uint64_t *a, const uint64_t *b, uint64_t *c, uint32_t count,
+                  void *ws, size_t ws_bytes, void *stream)
+{
+    if (!ctx || !a || !b || !c) return set_error(PIMM_E_ARG, "pimm_poly_mul: NULL argument");
+    if (ws_bytes < pimm_poly_mul_workspace(ctx, count) || (!ws && count))
+        return set_error(PIMM_E_WORKSPACE, "pimm_poly_mul: workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    const int np = (int)(count * ctx->params.L);
+    const int lg = ctx->dp.logN;
+    double *ah = (double *)ws, *bh = ah + ((size_t)np << lg);
+    int rc = launch_fwd(*ctx, LoadU64{a, lg}, StoreSlots{ah, lg}, np, s);
+    if (!rc) rc = launch_fwd(*ctx, LoadU64{b, lg}, StoreSlots{bh, lg}, np, s);
+    if (!rc) rc = launch_inv(*ctx, LoadSlotsMul{ah, bh, lg, np}, StoreU64{c, lg}, np, s);
+    return rc;
+}
+
+}  // extern "C"

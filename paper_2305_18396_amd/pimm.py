@@ -1,0 +1,434 @@
+"""Thin ctypes binding of libpimm (Pi_MatMul, Algorithm 1 of arXiv 2305.18396).
+
+Argument marshalling only: every step of the protocol runs in the library's
+HIP kernels.  PyTorch provides device memory (tensors are int64 storage; the
+library reads and writes them as uint64) and the current stream.  The module
+refuses to work without the built library: there is no fallback.
+
+Call names match the C ABI in include/pimm.h (without the ``pimm_`` prefix on
+the Python side where a class method is more natural).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpimm.so")
+
+PIMM_OK = 0
+ERRORS = {-1: "PIMM_E_ARG", -2: "PIMM_E_SHAPE", -3: "PIMM_E_PARAMS", -4: "PIMM_E_NOISE",
+          -5: "PIMM_E_OOM", -6: "PIMM_E_DEVICE", -7: "PIMM_E_UNSUPPORTED",
+          -8: "PIMM_E_WORKSPACE"}
+
+# Stream tags of the randomness layout.
+TAG_SK, TAG_PK_A, TAG_PK_E, TAG_ENC_A, TAG_ENC_E = 1, 2, 3, 4, 5
+TAG_RR_U, TAG_RR_E1, TAG_RR_E2, TAG_MASK = 6, 7, 8, 9
+
+# Every function include/pimm.h declares.
+EXPORTS = [
+    "pimm_ctx_create", "pimm_ctx_destroy", "pimm_ctx_primes", "pimm_ctx_cdt",
+    "pimm_params_primes", "pimm_cdt", "pimm_plan_rule", "pimm_noise_ok",
+    "pimm_plan_create", "pimm_plan_destroy", "pimm_plan_query",
+    "pimm_keygen", "pimm_sk_destroy", "pimm_encode_input", "pimm_encrypt", "pimm_decrypt",
+    "pimm_weights_create", "pimm_weights_destroy", "pimm_matmul", "pimm_mask_share",
+    "pimm_poly_mul", "pimm_poly_mul_workspace", "pimm_sample_poly",
+    "pimm_profile_enable", "pimm_profile_read", "pimm_sync", "pimm_last_error",
+]
+
+
+class PimmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint32) for n in
+                ("N", "L", "log2_t", "frac_bits", "prime_bits", "rerandomize")]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = ([(n, ctypes.c_uint32) for n in
+                 ("n", "r", "m", "mb", "rb", "nb", "M", "R", "K", "I", "O", "Wb")] +
+                [(n, ctypes.c_uint64) for n in
+                 ("P", "pt_bytes", "ct_bytes", "acc_bytes", "c1_bytes", "c0s_bytes",
+                  "share_bytes", "weights_bytes", "workspace_bytes")])
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libpimm.so.  Raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                          "(python paper_2305_18396_amd/build.py)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    sig = {
+        "pimm_ctx_create": [vp, i32, vp],
+        "pimm_ctx_destroy": [vp],
+        "pimm_ctx_primes": [vp, vp],
+        "pimm_ctx_cdt": [vp, vp],
+        "pimm_params_primes": [vp, vp],
+        "pimm_cdt": [vp],
+        "pimm_plan_rule": [vp, u32, u32, u32, u32, u32, u32, u32, vp],
+        "pimm_noise_ok": [vp, vp, u64],
+        "pimm_plan_create": [vp, u32, u32, u32, u32, u32, u32, u32, vp],
+        "pimm_plan_destroy": [vp],
+        "pimm_plan_query": [vp, vp],
+        "pimm_keygen": [vp, vp, vp, vp, vp],
+        "pimm_sk_destroy": [vp],
+        "pimm_encode_input": [vp, vp, vp, vp],
+        "pimm_encrypt": [vp, vp, vp, u32, vp, vp, vp, ctypes.c_size_t, vp],
+        "pimm_decrypt": [vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp],
+        "pimm_weights_create": [vp, vp, vp, vp],
+        "pimm_weights_destroy": [vp],
+        "pimm_matmul": [vp, vp, vp, vp, vp, ctypes.c_size_t, vp],
+        "pimm_mask_share": [vp, vp, vp, u32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp],
+        "pimm_poly_mul": [vp, vp, vp, vp, u32, vp, ctypes.c_size_t, vp],
+        "pimm_poly_mul_workspace": [vp, u32],
+        "pimm_sample_poly": [vp, i32, vp, u32, u32, u32, u32, vp, vp],
+        "pimm_profile_enable": [i32],
+        "pimm_profile_read": [ctypes.c_char_p, vp, vp],
+        "pimm_sync": [vp],
+        "pimm_last_error": [],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    L.pimm_poly_mul_workspace.restype = ctypes.c_uint64
+    L.pimm_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc < 0:
+        raise PimmError(rc, lib().pimm_last_error().decode())
+    return rc
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    assert t.is_contiguous(), "libpimm buffers must be contiguous"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _seed(seed: bytes):
+    assert len(seed) == 32
+    return ctypes.create_string_buffer(bytes(seed), 32)
+
+
+def _words(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(1, (int(nbytes) + 7) // 8), dtype=torch.int64, device=device)
+
+
+def to_device_u64(a: np.ndarray, device="cuda") -> torch.Tensor:
+    """numpy uint64/int64 array -> device int64 tensor with the same bytes."""
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint64:
+        a = a.view(np.int64)
+    return torch.from_numpy(a.astype(np.int64, copy=False)).to(device)
+
+
+def to_host_u64(t: torch.Tensor) -> np.ndarray:
+    return t.detach().cpu().numpy().view(np.uint64)
+
+
+# ---------------------------------------------------------------------------
+# host-only queries
+# ---------------------------------------------------------------------------
+
+def make_params(N: int, L: int, log2_t: int, frac_bits: int, rerandomize: bool = True) -> Params:
+    return Params(N, L, log2_t, frac_bits, 50, 1 if rerandomize else 0)
+
+
+def params_primes(params: Params) -> list[int]:
+    q = (ctypes.c_uint64 * params.L)()
+    _check(lib().pimm_params_primes(ctypes.byref(params), q))
+    return list(q)
+
+
+def cdt() -> list[int]:
+    t = (ctypes.c_uint64 * 19)()
+    _check(lib().pimm_cdt(t))
+    return list(t)
+
+
+def plan_rule(params: Params, n, r, m, mb=0, rb=0, nb=0, d_fix=0) -> PlanInfo:
+    info = PlanInfo()
+    _check(lib().pimm_plan_rule(ctypes.byref(params), n, r, m, mb, rb, nb, d_fix,
+                                ctypes.byref(info)))
+    return info
+
+
+def noise_ok(params: Params, info: PlanInfo, wmax: int) -> bool:
+    return _check(lib().pimm_noise_ok(ctypes.byref(params), ctypes.byref(info), int(wmax))) == 1
+
+
+# ---------------------------------------------------------------------------
+# handles
+# ---------------------------------------------------------------------------
+
+class Context:
+    """pimm_ctx: parameters, primes and NTT tables on one device."""
+
+    def __init__(self, N: int, L: int, log2_t: int, frac_bits: int, rerandomize: bool = True,
+                 device: int = 0):
+        self.params = make_params(N, L, log2_t, frac_bits, rerandomize)
+        self.device = torch.device("cuda", device)
+        self.h = ctypes.c_void_p()
+        _check(lib().pimm_ctx_create(ctypes.byref(self.params), device, ctypes.byref(self.h)))
+
+    @property
+    def N(self):
+        return self.params.N
+
+    @property
+    def L(self):
+        return self.params.L
+
+    @property
+    def ell(self):
+        return self.params.log2_t
+
+    def primes(self) -> list[int]:
+        q = (ctypes.c_uint64 * self.params.L)()
+        _check(lib().pimm_ctx_primes(self.h, q))
+        return list(q)
+
+    def cdt(self) -> list[int]:
+        t = (ctypes.c_uint64 * 19)()
+        _check(lib().pimm_ctx_cdt(self.h, t))
+        return list(t)
+
+    def close(self):
+        if self.h:
+            lib().pimm_ctx_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """pimm_plan: block plan and buffer sizes of Y[n][m] = X[n][r] W[r][m]."""
+
+    def __init__(self, ctx: Context, n: int, r: int, m: int, mb=0, rb=0, nb=0, d_fix=0):
+        self.ctx = ctx
+        self.h = ctypes.c_void_p()
+        _check(lib().pimm_plan_create(ctx.h, n, r, m, mb, rb, nb, d_fix, ctypes.byref(self.h)))
+        info = PlanInfo()
+        _check(lib().pimm_plan_query(self.h, ctypes.byref(info)))
+        self.info = info
+        self._ws = None
+
+    def __getattr__(self, k):
+        info = self.__dict__.get("info")
+        if info is not None and k in dict(PlanInfo._fields_):
+            return getattr(info, k)
+        raise AttributeError(k)
+
+    def workspace(self) -> torch.Tensor:
+        """A workspace tensor of the plan's size, allocated once by torch."""
+        if self._ws is None:
+            self._ws = _words(self.info.workspace_bytes, self.ctx.device)
+        return self._ws
+
+    def close(self):
+        if self.h:
+            lib().pimm_plan_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SecretKey:
+    def __init__(self, ctx: Context, h):
+        self.ctx, self.h = ctx, h
+
+    def close(self):
+        if self.h:
+            lib().pimm_sk_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Weights:
+    """pimm_weights: the server's weight cache (pi_A blocks in NTT form) for one plan."""
+
+    def __init__(self, plan: Plan, W: torch.Tensor, stream=None):
+        assert W.dtype == torch.int64 and W.shape == (plan.info.r, plan.info.m)
+        self.plan = plan
+        self.h = ctypes.c_void_p()
+        _check(lib().pimm_weights_create(plan.h, _ptr(W), ctypes.byref(self.h), _stream(stream)))
+
+    def close(self):
+        if self.h:
+            lib().pimm_weights_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# protocol calls
+# ---------------------------------------------------------------------------
+
+def keygen(ctx: Context, seed: bytes, stream=None):
+    """-> (SecretKey, pk [2][L][N] or None)."""
+    h = ctypes.c_void_p()
+    pk = None
+    if ctx.params.rerandomize:
+        pk = torch.empty((2, ctx.L, ctx.N), dtype=torch.int64, device=ctx.device)
+    _check(lib().pimm_keygen(ctx.h, _seed(seed), ctypes.byref(h), _ptr(pk), _stream(stream)))
+    return SecretKey(ctx, h), pk
+
+
+def encode_input(plan: Plan, X: torch.Tensor, pt: torch.Tensor | None = None, stream=None):
+    f = plan.info
+    if pt is None:
+        pt = torch.empty((f.I, plan.ctx.N), dtype=torch.int64, device=plan.ctx.device)
+    _check(lib().pimm_encode_input(plan.h, _ptr(X), _ptr(pt), _stream(stream)))
+    return pt
+
+
+def encrypt(plan: Plan, sk: SecretKey, seed: bytes, op_id: int, pt: torch.Tensor,
+            ct: torch.Tensor | None = None, ws: torch.Tensor | None = None, stream=None):
+    f, c = plan.info, plan.ctx
+    if ct is None:
+        ct = torch.empty((f.I, 2, c.L, c.N), dtype=torch.int64, device=c.device)
+    ws = plan.workspace() if ws is None else ws
+    _check(lib().pimm_encrypt(plan.h, sk.h, _seed(seed), op_id, _ptr(pt), _ptr(ct), _ptr(ws),
+                              ws.numel() * 8, _stream(stream)))
+    return ct
+
+
+def matmul(plan: Plan, w: Weights, ct: torch.Tensor, acc: torch.Tensor | None = None,
+           ws: torch.Tensor | None = None, stream=None):
+    f, c = plan.info, plan.ctx
+    if acc is None:
+        acc = torch.empty((f.O, 2, c.L, c.N), dtype=torch.int64, device=c.device)
+    ws = plan.workspace() if ws is None else ws
+    _check(lib().pimm_matmul(plan.h, w.h, _ptr(ct), _ptr(acc), _ptr(ws), ws.numel() * 8,
+                             _stream(stream)))
+    return acc
+
+
+def mask_share(plan: Plan, pk: torch.Tensor | None, seed: bytes, op_id: int, acc: torch.Tensor,
+               c1=None, c0s=None, share=None, ws=None, stream=None):
+    """In place on acc.  -> (c1 [O][L][N], c0s [O][L][mb*nb], server_share [n][m])."""
+    f, c = plan.info, plan.ctx
+    dev = c.device
+    if c1 is None:
+        c1 = torch.empty((f.O, c.L, c.N), dtype=torch.int64, device=dev)
+    if c0s is None:
+        c0s = torch.empty((f.O, c.L, f.mb * f.nb), dtype=torch.int64, device=dev)
+    if share is None:
+        share = torch.empty((f.n, f.m), dtype=torch.int64, device=dev)
+    ws = plan.workspace() if ws is None else ws
+    _check(lib().pimm_mask_share(plan.h, _ptr(pk), _seed(seed), op_id, _ptr(acc), _ptr(c1),
+                                 _ptr(c0s), _ptr(share), _ptr(ws), ws.numel() * 8,
+                                 _stream(stream)))
+    return c1, c0s, share
+
+
+def decrypt(plan: Plan, sk: SecretKey, c1: torch.Tensor, c0s: torch.Tensor, share=None, ws=None,
+            stream=None):
+    f, c = plan.info, plan.ctx
+    if share is None:
+        share = torch.empty((f.n, f.m), dtype=torch.int64, device=c.device)
+    ws = plan.workspace() if ws is None else ws
+    _check(lib().pimm_decrypt(plan.h, sk.h, _ptr(c1), _ptr(c0s), _ptr(share), _ptr(ws),
+                              ws.numel() * 8, _stream(stream)))
+    return share
+
+
+def poly_mul(ctx: Context, a: torch.Tensor, b: torch.Tensor, stream=None):
+    """c = a * b mod (X^N + 1, q_l) for [count][L][N] residue tensors."""
+    count = a.shape[0]
+    c = torch.empty_like(a)
+    ws = _words(lib().pimm_poly_mul_workspace(ctx.h, count), ctx.device)
+    _check(lib().pimm_poly_mul(ctx.h, _ptr(a), _ptr(b), _ptr(c), count, _ptr(ws), ws.numel() * 8,
+                               _stream(stream)))
+    return c, ws
+
+
+def sample_poly(ctx: Context, kind: int, seed: bytes, tag: int, prime: int, op_id: int, obj: int,
+                stream=None):
+    out = torch.empty(ctx.N, dtype=torch.int64, device=ctx.device)
+    _check(lib().pimm_sample_poly(ctx.h, kind, _seed(seed), tag, prime, op_id, obj, _ptr(out),
+                                  _stream(stream)))
+    return out
+
+
+def profile_enable(on: bool = True):
+    _check(lib().pimm_profile_enable(1 if on else 0))
+
+
+def profile_read(kernel: str):
+    """-> (launches, total milliseconds) of one kernel class since the last read."""
+    cnt, ms = ctypes.c_uint64(), ctypes.c_double()
+    _check(lib().pimm_profile_read(kernel.encode(), ctypes.byref(cnt), ctypes.byref(ms)))
+    return cnt.value, ms.value
+
+
+def sync(stream=None):
+    _check(lib().pimm_sync(_stream(stream)))
+
+
+class Party:
+    """Both parties of one Pi_MatMul call in one process (the wire is device memory):
+    the client's key and the server's weight cache for a plan."""
+
+    def __init__(self, ctx: Context, plan: Plan, W: torch.Tensor, client_seed: bytes,
+                 keys=None):
+        self.ctx, self.plan = ctx, plan
+        self.sk, self.pk = keys if keys is not None else keygen(ctx, client_seed)
+        self.weights = Weights(plan, W)
+        self.client_seed = client_seed
+
+    def run(self, X: torch.Tensor, server_seed: bytes, op_id: int = 0, stream=None):
+        """The whole protocol for Y = X W: -> (client_share, server_share), both [n][m]."""
+        p = self.plan
+        pt = encode_input(p, X, stream=stream)
+        ct = encrypt(p, self.sk, self.client_seed, op_id, pt, stream=stream)
+        acc = matmul(p, self.weights, ct, stream=stream)
+        c1, c0s, y1 = mask_share(p, self.pk, server_seed, op_id, acc, stream=stream)
+        y0 = decrypt(p, self.sk, c1, c0s, stream=stream)
+        return y0, y1

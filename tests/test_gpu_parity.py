@@ -1,0 +1,293 @@
+"""GPU parity: libpimm (HIP, gfx950) against the CPU oracle, through the C ABI.
+
+All arithmetic is integer, so the bar is bit-exact equality of every buffer that
+crosses the ABI (public key, plaintexts, ciphertexts, accumulators, the sparse
+reply, both shares), plus the user-level contract Y0 + Y1 = X W (mod 2^l)
+against a plain integer matrix product.  Small cases span several blocks with
+ragged edges; the full-size cases run the BERT-shaped layers at their real
+shapes, in the launch configuration the benchmark uses, and compare sampled
+ciphertexts with the oracle.
+"""
+import zlib
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2305_18396_amd import pimm, workloads
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU-only machines
+    pytest.skip("no HIP device", allow_module_level=True)
+
+
+def log(msg):
+    print(f"[gpu-parity] {msg}", flush=True)
+
+
+def u64(t):
+    return pimm.to_host_u64(t)
+
+
+def xw_mod(X, W, ell):
+    Xu = np.asarray(X, dtype=np.uint64)
+    Wu = np.asarray(W, dtype=np.int64).astype(np.uint64)
+    return (Xu @ Wu) & np.uint64((1 << ell) - 1)
+
+
+def xw_sampled(X, W, ell, rows, cols):
+    Xu = np.asarray(X, dtype=np.uint64)[rows]
+    Wu = np.asarray(W, dtype=np.int64).astype(np.uint64)[:, cols].T
+    return (Xu * Wu).sum(axis=1, dtype=np.uint64) & np.uint64((1 << ell) - 1)
+
+
+_ctx_cache = {}
+
+
+def context(N, L, ell, f, rr):
+    key = (N, L, ell, f, rr)
+    if key not in _ctx_cache:
+        _ctx_cache[key] = pimm.Context(N, L, ell, f, rerandomize=rr)
+    return _ctx_cache[key]
+
+
+def test_context_tables(orc):
+    log("context tables")
+    for N, L in [(4096, 2), (8192, 3)]:
+        ctx = context(N, L, 37, 12, True)
+        assert ctx.primes() == orc.find_primes(N, L)
+        assert ctx.cdt() == orc.cdt_table()
+
+
+@pytest.mark.parametrize("kind,tag,prime", [(0, 4, 0), (0, 4, 1), (1, 1, 0), (2, 5, 0), (3, 9, 0)])
+def test_samplers_bitexact(orc, kind, tag, prime):
+    import ctypes
+    log(f"sampler kind={kind} tag={tag} prime={prime}")
+    ctx = context(4096, 2, 37, 12, True)
+    seed = workloads.seed("client", 77)
+    got = u64(pimm.sample_poly(ctx, kind, seed, tag, prime, 1234, 56))
+    pyp = orc.Params(4096, 2, 37, 12)
+    k = np.frombuffer(seed, np.uint8).copy()
+    want = np.zeros(4096, np.uint64 if kind in (0, 3) else np.int64)
+    cdt = pyp.cdt_arr
+    orc.lib().orc_sample_poly(kind, k.ctypes.data_as(ctypes.c_void_p), tag, prime, 1234, 56, 4096,
+                              pyp.q[prime], 37, cdt.ctypes.data_as(ctypes.c_void_p),
+                              want.ctypes.data_as(ctypes.c_void_p))
+    assert np.array_equal(got, want.view(np.uint64))
+
+
+@pytest.mark.parametrize("N,L", [(4096, 2), (8192, 3)])
+def test_poly_mul_bitexact(orc, N, L):
+    import ctypes
+    log(f"poly_mul N={N} L={L}")
+    ctx = context(N, L, 37, 12, True)
+    q = ctx.primes()
+    rng = np.random.default_rng(N + L)
+    count = 3
+    a = np.stack([np.stack([rng.integers(0, ql, N, dtype=np.uint64) for ql in q])
+                  for _ in range(count)])
+    b = np.stack([np.stack([rng.integers(0, ql, N, dtype=np.uint64) for ql in q])
+                  for _ in range(count)])
+    b[0, 0] = 0
+    b[0, 0, 1] = 1  # x * a: a negacyclic shift
+    c, _ = pimm.poly_mul(ctx, pimm.to_device_u64(a), pimm.to_device_u64(b))
+    got = u64(c)
+    pyp = orc.Params(N, L, 37, 12)
+    for i in range(count):
+        for l in range(L):
+            want = np.zeros(N, np.uint64)
+            ai, bi = np.ascontiguousarray(a[i, l]), np.ascontiguousarray(b[i, l])
+            orc.lib().orc_negacyclic_mul(ai.ctypes.data_as(ctypes.c_void_p),
+                                         bi.ctypes.data_as(ctypes.c_void_p),
+                                         want.ctypes.data_as(ctypes.c_void_p), N, pyp.q[l],
+                                         pyp.psi[l])
+            assert np.array_equal(got[i, l], want), (i, l)
+    shifted = np.concatenate([[(q[0] - a[0, 0, -1]) % q[0]], a[0, 0, :-1]]).astype(np.uint64)
+    assert np.array_equal(got[0, 0], shifted)
+
+
+def run_both(orc, N, L, ell, f, rr, X, W, plan_kw, tag):
+    """Run the protocol on the GPU and in the oracle; return both sets of buffers."""
+    ctx = context(N, L, ell, f, rr)
+    n, r = X.shape
+    m = W.shape[1]
+    plan = pimm.Plan(ctx, n, r, m, **plan_kw)
+    pyp = orc.Params(N, L, ell, f, rerandomize=rr)
+    oplan = orc.Plan(n, r, m, plan.mb, plan.rb, plan.nb, N)
+    cseed, sseed = workloads.seed("client", tag), workloads.seed("server", tag)
+    log(f"case {tag}: N={N} L={L} l={ell} rr={rr} n,r,m={n},{r},{m} "
+        f"plan=({plan.mb},{plan.rb},{plan.nb})")
+    sk, pk = pimm.keygen(ctx, cseed)
+    Xd, Wd = pimm.to_device_u64(X), pimm.to_device_u64(W.astype(np.int64))
+    pt = pimm.encode_input(plan, Xd)
+    ct = pimm.encrypt(plan, sk, cseed, tag, pt)
+    w = pimm.Weights(plan, Wd)
+    acc = pimm.matmul(plan, w, ct)
+    acc0 = u64(acc).copy()
+    c1, c0s, y1 = pimm.mask_share(plan, pk, sseed, tag, acc)
+    y0 = pimm.decrypt(plan, sk, c1, c0s)
+    pimm.sync()
+    gpu = dict(pk=None if pk is None else u64(pk), pt=u64(pt), ct=u64(ct), acc=acc0,
+               acc_rr=u64(acc), c1=u64(c1), c0s=u64(c0s), Y1=u64(y1), Y0=u64(y0))
+    ref = orc.pi_matmul(pyp, oplan, X, W, cseed, sseed, op_id=tag)
+    return gpu, ref, pyp
+
+
+CASES = {
+    "single": dict(N=4096, L=2, ell=37, f=12, rr=True, shape=(16, 64, 64), plan={}),
+    "single_norr": dict(N=4096, L=2, ell=37, f=12, rr=False, shape=(16, 64, 64), plan={}),
+    "ragged_explicit": dict(N=4096, L=2, ell=37, f=12, rr=True, shape=(19, 70, 45),
+                            plan=dict(mb=3, rb=5, nb=7)),
+    "fix256": dict(N=4096, L=2, ell=37, f=12, rr=True, shape=(40, 300, 200),
+                   plan=dict(d_fix=256)),
+    "n8192_l3": dict(N=8192, L=3, ell=41, f=14, rr=True, shape=(33, 100, 70), plan={}),
+    "n4096_l1": dict(N=4096, L=1, ell=20, f=8, rr=True, shape=(8, 24, 16), plan={}),
+    "scalar": dict(N=4096, L=2, ell=37, f=12, rr=True, shape=(1, 1, 1), plan={}),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_protocol_bitexact(orc, name):
+    c = CASES[name]
+    n, r, m = c["shape"]
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    X = workloads.share(rng, n, r, c["ell"])
+    W = workloads.weights(rng, r, m, c["f"])
+    tag = 10 + list(CASES).index(name)
+    gpu, ref, pyp = run_both(orc, c["N"], c["L"], c["ell"], c["f"], c["rr"], X, W, c["plan"], tag)
+    if c["rr"]:
+        assert np.array_equal(gpu["pk"], ref["pk"]), "public key"
+    for k in ("pt", "ct", "acc", "acc_rr", "c1", "c0s", "Y1", "Y0"):
+        want = ref[k].view(np.uint64) if ref[k].dtype != np.uint64 else ref[k]
+        assert np.array_equal(gpu[k], want), k
+    Y = (gpu["Y0"] + gpu["Y1"]) & np.uint64(pyp.t - 1)
+    assert np.array_equal(Y, xw_mod(X, W, c["ell"]))
+
+
+@pytest.mark.parametrize("case", ["zeroW", "zeroX", "identity", "maxX"])
+def test_protocol_special_inputs(orc, case):
+    n, r, m = 9, 32, 32
+    rng = np.random.default_rng(5)
+    X = workloads.share(rng, n, r, 37)
+    W = workloads.weights(rng, r, m, 12)
+    if case == "zeroW":
+        W[:] = 0
+    elif case == "zeroX":
+        X[:] = 0
+    elif case == "identity":
+        W = np.eye(r, m, dtype=np.int64)
+    else:
+        X[:] = (1 << 37) - 1
+    gpu, ref, pyp = run_both(orc, 4096, 2, 37, 12, True, X, W, {}, 40)
+    for k in ("ct", "acc_rr", "c1", "c0s", "Y1", "Y0"):
+        assert np.array_equal(gpu[k], ref[k].view(np.uint64)), k
+    Y = (gpu["Y0"] + gpu["Y1"]) & np.uint64(pyp.t - 1)
+    assert np.array_equal(Y, xw_mod(X, W, 37))
+
+
+def test_deterministic_and_stream_independent():
+    log("determinism")
+    ctx = context(4096, 2, 37, 12, True)
+    wl = workloads.single_matmul()
+    plan = pimm.Plan(ctx, *wl.shape)
+    party = pimm.Party(ctx, plan, pimm.to_device_u64(wl.W), workloads.seed("client", 3))
+    Xd = pimm.to_device_u64(wl.X)
+    a0, a1 = party.run(Xd, workloads.seed("server", 3), op_id=9)
+    # Calls in flight must not share a workspace: finish the first run before the
+    # same plan's workspace is used from another stream.
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b0, b1 = party.run(Xd, workloads.seed("server", 3), op_id=9, stream=s)
+    s.synchronize()
+    torch.cuda.synchronize()
+    assert torch.equal(a0, b0) and torch.equal(a1, b1)
+    c0, _ = party.run(Xd, workloads.seed("server", 3), op_id=10)
+    assert not torch.equal(a0, c0)
+
+
+def test_error_paths():
+    log("error paths")
+    ctx = context(4096, 2, 37, 12, True)
+    plan = pimm.Plan(ctx, 16, 64, 64)
+    with pytest.raises(pimm.PimmError, match="PIMM_E_NOISE"):
+        pimm.Weights(plan, torch.full((64, 64), 1 << 40, dtype=torch.int64, device="cuda"))
+    w = pimm.Weights(plan, torch.ones((64, 64), dtype=torch.int64, device="cuda"))
+    ct = torch.zeros((plan.I, 2, 2, 4096), dtype=torch.int64, device="cuda")
+    tiny = torch.empty(8, dtype=torch.int64, device="cuda")
+    with pytest.raises(pimm.PimmError, match="PIMM_E_WORKSPACE"):
+        pimm.matmul(plan, w, ct, ws=tiny)
+    other = pimm.Plan(ctx, 16, 64, 64, d_fix=64)
+    with pytest.raises(pimm.PimmError, match="PIMM_E_ARG"):
+        pimm.matmul(other, w, ct)
+    with pytest.raises(pimm.PimmError, match="PIMM_E_ARG"):
+        pimm.mask_share(plan, None, workloads.seed("server", 0), 0,
+                        torch.zeros((plan.O, 2, 2, 4096), dtype=torch.int64, device="cuda"))
+
+
+def check_layer_op(orc, ctx, pyp, wl, plan_kw, tag, nsample_out=2):
+    """One full-size product: the contract on every entry (or a sample) and bit-exact
+    ciphertexts / accumulators / reply for sampled output ciphertexts."""
+    n, r, m = wl.shape
+    plan = pimm.Plan(ctx, n, r, m, **plan_kw)
+    oplan = orc.Plan(n, r, m, plan.mb, plan.rb, plan.nb, ctx.N)
+    cseed, sseed = workloads.seed("client", tag), workloads.seed("server", tag)
+    log(f"full-size {wl.name}: plan=({plan.mb},{plan.rb},{plan.nb}) I={plan.I} O={plan.O}")
+    sk, pk = pimm.keygen(ctx, cseed)
+    s_ref, pk_ref = orc.keygen(pyp, cseed)
+    assert np.array_equal(u64(pk), pk_ref)
+    Xd = pimm.to_device_u64(wl.X)
+    pt = pimm.encode_input(plan, Xd)
+    ct = pimm.encrypt(plan, sk, cseed, tag, pt)
+    w = pimm.Weights(plan, pimm.to_device_u64(wl.W))
+    acc = pimm.matmul(plan, w, ct)
+    pimm.sync()
+    outs = sorted({0, plan.O // 2, plan.O - 1})[:nsample_out + 1]
+    acc_s = u64(acc[outs])
+    c1, c0s, y1 = pimm.mask_share(plan, pk, sseed, tag, acc)
+    y0 = pimm.decrypt(plan, sk, c1, c0s)
+    pimm.sync()
+    Y0, Y1 = u64(y0), u64(y1)
+    t = np.uint64((1 << wl.ell) - 1)
+    if n * r * m <= 400_000_000:
+        assert np.array_equal((Y0 + Y1) & t, xw_mod(wl.X, wl.W, wl.ell))
+    else:
+        rng = np.random.default_rng(tag)
+        rows = rng.integers(0, n, 4000)
+        cols = rng.integers(0, m, 4000)
+        assert np.array_equal((Y0[rows, cols] + Y1[rows, cols]) & t,
+                              xw_sampled(wl.X, wl.W, wl.ell, rows, cols))
+    # Sampled bit-exactness against the oracle.
+    pt_ref = orc.encode_input(oplan, wl.X)
+    assert np.array_equal(u64(pt), pt_ref)
+    ct_ref = orc.encrypt(pyp, s_ref, cseed, tag, pt_ref)
+    assert np.array_equal(u64(ct), ct_ref)
+    ptA = orc.encode_weights(oplan, wl.W)
+    acc_ref = orc.matmul(pyp, oplan, ptA, ct_ref, outs)
+    assert np.array_equal(acc_s, acc_ref)
+    acc_rr = orc.rerandomize(pyp, pk_ref, sseed, tag, acc_ref, outs)
+    c1_ref, c0s_ref, sm_ref = orc.mask_extract(pyp, oplan, sseed, tag, acc_rr, outs)
+    assert np.array_equal(u64(c1[outs]), c1_ref)
+    assert np.array_equal(u64(c0s[outs]), c0s_ref)
+    assert np.array_equal(Y1, orc.place_shares(oplan, sm_ref, outs, out=Y1.copy()))
+    y0_ref = orc.decrypt(pyp, oplan, s_ref, c1_ref, c0s_ref, outs)
+    sel = orc.place_shares(oplan, np.ones((len(outs), plan.mb * plan.nb), np.uint64), outs)
+    assert np.array_equal(Y0[sel == 1], y0_ref[sel == 1])
+
+
+def test_full_size_bert_base_layer(orc):
+    """One BERT-base-shaped layer at sequence 128 (the benchmark's workload), fewest-wire plan."""
+    ctx = context(4096, 2, 37, 12, True)
+    pyp = orc.Params(4096, 2, 37, 12)
+    for i, wl in enumerate(workloads.bert_base_layer(128)):
+        check_layer_op(orc, ctx, pyp, wl, {}, 100 + i)
+
+
+def test_full_size_bert_large_op(orc):
+    """The largest BERT-large-shaped product (FFN2 4096x1024, seq 512) with N = 8192, three
+    primes, t = 2^41, blocks of area 1024."""
+    ctx = context(8192, 3, 41, 14, True)
+    pyp = orc.Params(8192, 3, 41, 14)
+    wl = workloads.bert_large_layer(512)[3]
+    check_layer_op(orc, ctx, pyp, wl, dict(d_fix=1024), 200)
