@@ -63,6 +63,7 @@ typedef struct pimm_ctx pimm_ctx;
 typedef struct pimm_plan pimm_plan;
 typedef struct pimm_sk pimm_sk;
 typedef struct pimm_weights pimm_weights;
+typedef struct pimm_batch pimm_batch;
 
 /* RNS-BFV parameters (section 2.2: N a power of two, plaintext modulus t = 2^l,
  * ciphertext modulus q a product of L word-size primes).
@@ -198,6 +199,40 @@ int pimm_matmul(const pimm_plan *plan, const pimm_weights *w, const uint64_t *ct
 int pimm_mask_share(const pimm_plan *plan, const uint64_t *pk, const uint8_t seed[32],
                     uint32_t op_id, uint64_t *acc, uint64_t *c1, uint64_t *c0s,
                     uint64_t *server_share, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- batching: many products in one pass ----------------------------------------- */
+
+/* One product of a batch: a plan, a weight cache that fits it (same r, m, mb, rb),
+ * its input ciphertexts [I][2][L][N] and its accumulator output [O][2][L][N]. */
+typedef struct {
+    const pimm_plan *plan;
+    const pimm_weights *weights;
+    const uint64_t *ct;
+    uint64_t *acc;
+} pimm_batch_item;
+
+/* Build a batch of `count` products of any shapes and lengths on one context
+ * (uploads an item table to the device; the items' buffers must stay valid while
+ * the batch is used).  pimm_batch_matmul then computes, for every item, exactly
+ * what pimm_matmul computes for it. */
+int pimm_batch_create(const pimm_batch_item *items, uint32_t count, pimm_batch **out);
+int pimm_batch_destroy(pimm_batch *batch);
+/* Workspace bytes the batch needs and the useful multiply-accumulates it does
+ * (sum of n*r*m); either pointer may be NULL. */
+int pimm_batch_query(const pimm_batch *batch, uint64_t *workspace_bytes, uint64_t *useful_macs);
+/* Schedule: schedule 0 = three launches (all forward NTTs, all slot-wise products,
+ * all inverse NTTs); 1 = one persistent launch whose workgroups take units from an
+ * atomic queue in dependency order, with bounded waits.  mac_rows (4, 8 or 16) is
+ * the number of output rows a product thread owns; xcd_map != 0 places consecutive
+ * product tiles on one XCD; grid = persistent workgroups (0: fill the device). */
+int pimm_batch_set_schedule(pimm_batch *batch, int schedule, int mac_rows, int xcd_map,
+                            uint32_t grid);
+/* Run every product of the batch on `stream` (plain kernel launches only, so the
+ * call can be captured into a hipGraph and replayed; one run at a time per workspace). */
+int pimm_batch_matmul(const pimm_batch *batch, void *ws, size_t ws_bytes, void *stream);
+/* After a persistent run: synchronise `stream` and report PIMM_E_DEVICE if a
+ * dependency wait hit its bound (the outputs are then invalid). */
+int pimm_batch_status(const pimm_batch *batch, const void *ws, void *stream);
 
 /* ---- primitives exposed for checking ----------------------------------------- */
 

@@ -1,0 +1,451 @@
+// batch.hip -- many independent Pi_MatMul products in one pass over the device.
+//
+// A batch is a list of (plan, weight cache, input ciphertexts, accumulator)
+// items of any shapes and sequence lengths on one context.  Its work is the
+// union of three kinds of units:
+//   in   forward NTT of one input polynomial      (sum over items of I*2*L)
+//   mac  one slot-chunk x row-tile x column-block  (sum of (N/256)*L*ceil(M/G)*K)
+//   out  inverse NTT of one accumulator polynomial (sum of O*2*L)
+// Two schedules run them:
+//   PHASED      three launches (all in, all mac, all out), each over a flat
+//               list of units of every item;
+//   PERSISTENT  one launch of a resident grid that takes units from an atomic
+//               counter in dependency order (in, then mac, then out).  A mac
+//               unit waits until the 2R input NTTs of its column block and
+//               prime are done; an out unit waits until the N/256 slot chunks
+//               of its row tile are done.  Every unit it waits for was taken
+//               earlier by a running workgroup that itself only waits on
+//               earlier units, so the waits always end; each wait is also
+//               bounded (a spin limit sets an error flag and every later wait
+//               returns at once), so every wave exits.
+// The item table lives in device memory owned by the batch; the scratch (NTT
+// forms, accumulators, dependency counters) is the caller's workspace.  Both
+// schedules are plain kernel launches with no memset, so a stream capture of
+// pimm_batch_matmul can be replayed as a hipGraph.
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+#include "mac.h"
+#include "ntt.h"
+
+namespace pimm {
+
+struct BatchItemDev {
+    const uint64_t *ct;  // [I][2][L][N]
+    uint64_t *acc;       // [O][2][L][N]
+    const double *wh;    // [Wb][L][N]
+    uint64_t chat_off;   // doubles into the workspace: c^ [I][2][L][N]
+    uint64_t ahat_off;   // acc^ [O][2][L][N]
+    uint32_t M, R, K, I, O;
+    uint32_t mtiles;            // ceil(M / G)
+    uint32_t in0, mac0, out0;   // first unit of each kind
+    uint32_t dep_in0, dep_mac0; // first dependency counter of each kind
+};
+
+// Counter words at the start of the workspace (uint32).
+constexpr int kCtrQueue = 0;
+constexpr int kCtrError = 1;
+constexpr int kCtrFirstDep = 2;
+
+enum Schedule : int { kPhased = 0, kPersistent = 1 };
+
+__device__ __forceinline__ int find_item(const BatchItemDev *items, int n, uint32_t u, int which)
+{
+    // last item whose first unit of this kind is <= u
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const uint32_t s = which == 0 ? items[mid].in0 : (which == 1 ? items[mid].mac0 : items[mid].out0);
+        if (s <= u)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Position of workgroup b among the workgroups dispatched to its XCD, so that
+// consecutive tiles (which share input slices) land on one XCD's L2.
+__device__ __forceinline__ uint32_t xcd_local(uint32_t b, uint32_t nblocks)
+{
+    const uint32_t xcd = b % 8, k = b / 8;
+    const uint32_t per = nblocks / 8, rem = nblocks % 8;
+    return xcd * per + (xcd < rem ? xcd : rem) + k;
+}
+
+template <int LOGN>
+__device__ __forceinline__ void run_in(const BatchItemDev &it, int poly, double *ws,
+                                       const DevParams &dp, double *lds)
+{
+    ntt_fwd_block<LOGN>(LoadU64{it.ct, LOGN}, StoreSlots{ws + it.chat_off, LOGN}, dp, poly, lds);
+}
+
+template <int LOGN>
+__device__ __forceinline__ void run_out(const BatchItemDev &it, int poly, double *ws,
+                                        const DevParams &dp, double *lds)
+{
+    ntt_inv_block<LOGN>(LoadSlots{ws + it.ahat_off, LOGN}, StoreU64{it.acc, LOGN}, dp, poly, lds);
+}
+
+// mac unit t of an item -> (l, slot chunk, row tile, column block); row tiles vary fastest.
+struct MacCoord {
+    int l, zc, ibt, kb;
+};
+__device__ __forceinline__ MacCoord mac_coord(const BatchItemDev &it, uint32_t t, int chunks)
+{
+    MacCoord c;
+    c.ibt = (int)(t % it.mtiles);
+    t /= it.mtiles;
+    c.kb = (int)(t % it.K);
+    t /= it.K;
+    c.zc = (int)(t % chunks);
+    c.l = (int)(t / chunks);
+    return c;
+}
+
+template <int G>
+__device__ __forceinline__ void run_mac(const BatchItemDev &it, const MacCoord &c, double *ws,
+                                        const DevParams &dp)
+{
+    mac_tile<G>(it.wh, ws + it.chat_off, ws + it.ahat_off, (int)it.M, (int)it.R, (int)it.K, dp, c.l,
+                (c.zc << 8) + (int)threadIdx.x, c.ibt * G, c.kb);
+}
+
+// ---- phased schedule ---------------------------------------------------------------
+
+template <int LOGN>
+__global__ __launch_bounds__(kNttThreads) void k_batch_in(const BatchItemDev *items, int n,
+                                                          double *ws, DevParams dp)
+{
+    __shared__ double lds[NttPasses<LOGN>::LDS];
+    const uint32_t u = blockIdx.x;
+    const BatchItemDev &it = items[find_item(items, n, u, 0)];
+    run_in<LOGN>(it, (int)(u - it.in0), ws, dp, lds);
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_batch_mac(const BatchItemDev *items, int n, double *ws,
+                                                   int xcd_map, DevParams dp)
+{
+    const uint32_t u = xcd_map ? xcd_local(blockIdx.x, gridDim.x) : blockIdx.x;
+    const BatchItemDev &it = items[find_item(items, n, u, 1)];
+    run_mac<G>(it, mac_coord(it, u - it.mac0, dp.N >> 8), ws, dp);
+}
+
+template <int LOGN>
+__global__ __launch_bounds__(kNttThreads) void k_batch_out(const BatchItemDev *items, int n,
+                                                           double *ws, DevParams dp)
+{
+    __shared__ double lds[NttPasses<LOGN>::LDS];
+    const uint32_t u = blockIdx.x;
+    const BatchItemDev &it = items[find_item(items, n, u, 2)];
+    run_out<LOGN>(it, (int)(u - it.out0), ws, dp, lds);
+}
+
+// ---- persistent schedule -----------------------------------------------------------
+
+__global__ void k_batch_reset(uint32_t *ctr, uint32_t count)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+        ctr[i] = 0;
+}
+
+// Thread 0 waits until ctr[idx] >= target (acquire, device scope) or the batch
+// has failed; returns false on failure.  Bounded by spin_limit polls.
+__device__ __forceinline__ bool wait_for(uint32_t *ctr, uint32_t idx, uint32_t target,
+                                         uint32_t spin_limit)
+{
+    uint32_t spins = 0;
+    while (__hip_atomic_load(&ctr[idx], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (__hip_atomic_load(&ctr[kCtrError], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+            return false;
+        if (++spins > spin_limit) {
+            __hip_atomic_store(&ctr[kCtrError], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return true;
+}
+
+template <int LOGN, int G>
+__global__ __launch_bounds__(kNttThreads) void k_batch_fused(const BatchItemDev *items, int n,
+                                                             double *ws, uint32_t *ctr,
+                                                             uint32_t n_in, uint32_t n_mac,
+                                                             uint32_t n_out, uint32_t spin_limit,
+                                                             DevParams dp)
+{
+    __shared__ double lds[NttPasses<LOGN>::LDS];
+    __shared__ uint32_t s_unit;
+    __shared__ int s_ok;
+    const uint32_t total = n_in + n_mac + n_out;
+    const int chunks = dp.N >> 8, L = dp.L;
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_unit = __hip_atomic_fetch_add(&ctr[kCtrQueue], 1u, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const uint32_t u = s_unit;
+        __syncthreads();
+        if (u >= total) break;
+        uint32_t sig = 0xffffffffu;  // counter this unit bumps when done
+        if (u < n_in) {
+            const BatchItemDev &it = items[find_item(items, n, u, 0)];
+            const int poly = (int)(u - it.in0);
+            run_in<LOGN>(it, poly, ws, dp, lds);
+            const int x = poly / (2 * L), l = poly % L;
+            sig = it.dep_in0 + (uint32_t)((x % (int)it.K) * L + l);
+        } else if (u < n_in + n_mac) {
+            const uint32_t v = u - n_in;
+            const BatchItemDev &it = items[find_item(items, n, v, 1)];
+            const MacCoord c = mac_coord(it, v - it.mac0, chunks);
+            if (threadIdx.x == 0)
+                s_ok = wait_for(ctr, it.dep_in0 + (uint32_t)(c.kb * L + c.l), 2 * it.R, spin_limit);
+            __syncthreads();
+            __threadfence();
+            if (s_ok) run_mac<G>(it, c, ws, dp);
+            sig = it.dep_mac0 + (uint32_t)(((c.ibt * (int)it.K) + c.kb) * L + c.l);
+        } else {
+            const uint32_t v = u - n_in - n_mac;
+            const BatchItemDev &it = items[find_item(items, n, v, 2)];
+            const int poly = (int)(v - it.out0);
+            const int y = poly / (2 * L), l = poly % L;
+            const int ibt = (y / (int)it.K) / G, kb = y % (int)it.K;
+            if (threadIdx.x == 0)
+                s_ok = wait_for(ctr, it.dep_mac0 + (uint32_t)((ibt * (int)it.K + kb) * L + l),
+                                (uint32_t)chunks, spin_limit);
+            __syncthreads();
+            __threadfence();
+            if (s_ok) run_out<LOGN>(it, poly, ws, dp, lds);
+        }
+        if (sig != 0xffffffffu) {
+            __threadfence();
+            __syncthreads();
+            if (threadIdx.x == 0)
+                __hip_atomic_fetch_add(&ctr[sig], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace pimm
+
+using namespace pimm;
+
+struct pimm_batch {
+    Ctx *ctx = nullptr;
+    std::vector<pimm_batch_item> items;
+    int G = 8;
+    int schedule = kPhased;
+    int xcd_map = 1;
+    uint32_t grid = 0;          // persistent grid size (0: from occupancy)
+    uint32_t spin_limit = 1u << 22;
+    BatchItemDev *d_items = nullptr;
+    uint32_t n_in = 0, n_mac = 0, n_out = 0, n_dep = 0;
+    uint64_t ws_bytes = 0;
+    uint64_t useful_macs = 0;
+};
+
+namespace {
+
+int build_tables(pimm_batch *b)
+{
+    const Ctx &c = *b->ctx;
+    const uint64_t N = c.params.N, L = c.params.L;
+    const uint32_t chunks = (uint32_t)(N >> 8);
+    std::vector<BatchItemDev> t(b->items.size());
+    uint64_t off = 0;
+    uint32_t in0 = 0, mac0 = 0, out0 = 0, dep = kCtrFirstDep;
+    b->useful_macs = 0;
+    for (size_t i = 0; i < b->items.size(); ++i) {
+        const pimm_batch_item &it = b->items[i];
+        const pimm_plan_info &f = it.plan->info;
+        BatchItemDev &d = t[i];
+        d.ct = it.ct;
+        d.acc = it.acc;
+        d.wh = it.weights->d_w_hat;
+        d.M = f.M;
+        d.R = f.R;
+        d.K = f.K;
+        d.I = f.I;
+        d.O = f.O;
+        d.mtiles = (f.M + b->G - 1) / b->G;
+        d.in0 = in0;
+        d.mac0 = mac0;
+        d.out0 = out0;
+        d.dep_in0 = dep;
+        dep += f.K * (uint32_t)L;
+        d.dep_mac0 = dep;
+        dep += d.mtiles * f.K * (uint32_t)L;
+        in0 += f.I * 2 * (uint32_t)L;
+        mac0 += chunks * (uint32_t)L * d.mtiles * f.K;
+        out0 += f.O * 2 * (uint32_t)L;
+        b->useful_macs += (uint64_t)f.n * f.r * f.m;
+    }
+    // Counters first (rounded to 256 bytes), then each item's c^ and acc^.
+    off = (((uint64_t)dep * 4 + 255) / 256) * 256 / 8;
+    for (size_t i = 0; i < t.size(); ++i) {
+        t[i].chat_off = off;
+        off += (uint64_t)t[i].I * 2 * L * N;
+        t[i].ahat_off = off;
+        off += (uint64_t)t[i].O * 2 * L * N;
+    }
+    b->n_in = in0;
+    b->n_mac = mac0;
+    b->n_out = out0;
+    b->n_dep = dep;
+    b->ws_bytes = off * 8;
+    if (b->d_items) (void)hipFree(b->d_items);
+    b->d_items = nullptr;
+    int rc = check_hip(hipSetDevice(c.device), "hipSetDevice");
+    if (!rc) rc = check_hip(hipMalloc((void **)&b->d_items, t.size() * sizeof(BatchItemDev)),
+                            "hipMalloc batch table");
+    if (!rc) rc = check_hip(hipMemcpy(b->d_items, t.data(), t.size() * sizeof(BatchItemDev),
+                                      hipMemcpyHostToDevice), "copy batch table");
+    return rc;
+}
+
+template <int LOGN, int G>
+int run_batch(const pimm_batch *b, void *ws, hipStream_t s)
+{
+    const Ctx &c = *b->ctx;
+    const int n = (int)b->items.size();
+    double *wsd = (double *)ws;
+    if (b->schedule == kPhased) {
+        {
+            ProfScope prof("ntt_fwd", s);
+            hipLaunchKernelGGL(k_batch_in<LOGN>, dim3(b->n_in), dim3(kNttThreads), 0, s, b->d_items,
+                               n, wsd, c.dp);
+        }
+        {
+            ProfScope prof("mac", s);
+            hipLaunchKernelGGL(k_batch_mac<G>, dim3(b->n_mac), dim3(256), 0, s, b->d_items, n, wsd,
+                               b->xcd_map, c.dp);
+        }
+        {
+            ProfScope prof("ntt_inv", s);
+            hipLaunchKernelGGL(k_batch_out<LOGN>, dim3(b->n_out), dim3(kNttThreads), 0, s,
+                               b->d_items, n, wsd, c.dp);
+        }
+        return check_hip(hipGetLastError(), "batch launch");
+    }
+    uint32_t *ctr = (uint32_t *)ws;
+    hipLaunchKernelGGL(k_batch_reset, dim3((b->n_dep + 255) / 256), dim3(256), 0, s, ctr, b->n_dep);
+    uint32_t grid = b->grid;
+    if (!grid) {
+        int per_cu = 0;
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_fused<LOGN, G>,
+                                                           kNttThreads, 0);
+        int cus = 0;
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device);
+        grid = (uint32_t)std::max(1, per_cu) * (uint32_t)std::max(1, cus);
+    }
+    const uint32_t total = b->n_in + b->n_mac + b->n_out;
+    if (grid > total) grid = total;
+    {
+        ProfScope prof("fused", s);
+        hipLaunchKernelGGL((k_batch_fused<LOGN, G>), dim3(grid), dim3(kNttThreads), 0, s, b->d_items,
+                           n, wsd, ctr, b->n_in, b->n_mac, b->n_out, b->spin_limit, c.dp);
+    }
+    return check_hip(hipGetLastError(), "batch fused launch");
+}
+
+template <int LOGN>
+int run_batch_g(const pimm_batch *b, void *ws, hipStream_t s)
+{
+    switch (b->G) {
+    case 4: return run_batch<LOGN, 4>(b, ws, s);
+    case 16: return run_batch<LOGN, 16>(b, ws, s);
+    default: return run_batch<LOGN, 8>(b, ws, s);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int pimm_batch_create(const pimm_batch_item *items, uint32_t count, pimm_batch **out)
+{
+    if (!items || !count || !out) return set_error(PIMM_E_ARG, "pimm_batch_create: empty batch");
+    Ctx *ctx = items[0].plan ? items[0].plan->ctx : nullptr;
+    for (uint32_t i = 0; i < count; ++i) {
+        const pimm_batch_item &it = items[i];
+        if (!it.plan || !it.weights || !it.ct || !it.acc)
+            return set_error(PIMM_E_ARG, "pimm_batch_create: item %u has a NULL field", i);
+        if (it.plan->ctx != ctx)
+            return set_error(PIMM_E_ARG, "pimm_batch_create: items on different contexts");
+        if (!weights_fit(it.weights, it.plan))
+            return set_error(PIMM_E_ARG, "pimm_batch_create: item %u weights do not fit its plan", i);
+    }
+    pimm_batch *b = new pimm_batch();
+    b->ctx = ctx;
+    b->items.assign(items, items + count);
+    int rc = build_tables(b);
+    if (rc) {
+        pimm_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return PIMM_OK;
+}
+
+int pimm_batch_destroy(pimm_batch *b)
+{
+    if (!b) return PIMM_OK;
+    if (b->d_items) (void)hipFree(b->d_items);
+    delete b;
+    return PIMM_OK;
+}
+
+int pimm_batch_set_schedule(pimm_batch *b, int schedule, int mac_rows, int xcd_map, uint32_t grid)
+{
+    if (!b) return set_error(PIMM_E_ARG, "pimm_batch_set_schedule: NULL batch");
+    if (schedule != kPhased && schedule != kPersistent)
+        return set_error(PIMM_E_ARG, "schedule %d is not 0 (phased) or 1 (persistent)", schedule);
+    if (mac_rows != 4 && mac_rows != 8 && mac_rows != 16)
+        return set_error(PIMM_E_ARG, "mac_rows %d is not 4, 8 or 16", mac_rows);
+    b->schedule = schedule;
+    b->xcd_map = xcd_map ? 1 : 0;
+    b->grid = grid;
+    if (mac_rows != b->G) {
+        b->G = mac_rows;
+        return build_tables(b);
+    }
+    return PIMM_OK;
+}
+
+int pimm_batch_query(const pimm_batch *b, uint64_t *workspace_bytes, uint64_t *useful_macs)
+{
+    if (!b) return set_error(PIMM_E_ARG, "pimm_batch_query: NULL batch");
+    if (workspace_bytes) *workspace_bytes = b->ws_bytes;
+    if (useful_macs) *useful_macs = b->useful_macs;
+    return PIMM_OK;
+}
+
+int pimm_batch_matmul(const pimm_batch *b, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!b) return set_error(PIMM_E_ARG, "pimm_batch_matmul: NULL batch");
+    if (!ws || ws_bytes < b->ws_bytes)
+        return set_error(PIMM_E_WORKSPACE, "pimm_batch_matmul: workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    return b->ctx->dp.logN == 12 ? run_batch_g<12>(b, ws, s) : run_batch_g<13>(b, ws, s);
+}
+
+int pimm_batch_status(const pimm_batch *b, const void *ws, void *stream)
+{
+    if (!b || !ws) return set_error(PIMM_E_ARG, "pimm_batch_status: NULL argument");
+    if (b->schedule != kPersistent) return PIMM_OK;
+    uint32_t flag = 0;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = check_hip(hipMemcpyAsync(&flag, (const uint32_t *)ws + kCtrError, 4,
+                                      hipMemcpyDeviceToHost, s), "copy batch status");
+    if (!rc) rc = check_hip(hipStreamSynchronize(s), "batch status synchronize");
+    if (rc) return rc;
+    return flag ? set_error(PIMM_E_DEVICE, "persistent batch: a dependency wait hit its bound")
+                : PIMM_OK;
+}
+
+}  // extern "C"

@@ -218,8 +218,9 @@ struct SecretKey {
 };
 
 struct Weights {
-    const Plan *plan;
-    double *d_w_hat = nullptr; // [Wb][L][N] NTT slots, balanced
+    Ctx *ctx = nullptr;
+    pimm_plan_info info;        // of the plan it was made for (r, m, mb, rb, M, R, Wb matter)
+    double *d_w_hat = nullptr;  // [Wb][L][N] NTT slots, balanced
     int64_t wmax = 0;
 };
 
@@ -228,6 +229,7 @@ int set_error(int code, const char *fmt, ...);
 int check_hip(hipError_t e, const char *what);
 Key make_key(const uint8_t seed[32]);
 bool noise_ok(const Ctx &c, const pimm_plan_info &f, uint64_t wmax);
+bool weights_fit(const Weights *w, const Plan *plan);
 
 // Brackets one kernel launch with HIP events when profiling is on.
 class ProfScope {

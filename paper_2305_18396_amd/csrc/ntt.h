@@ -108,16 +108,16 @@ struct NttPasses {
     static constexpr int LDS = N + (N >> 5);
 };
 
-// Forward negacyclic NTT of one polynomial per workgroup.
+// Forward negacyclic NTT of polynomial `poly` by the calling workgroup
+// (kNttThreads threads), with `lds` holding NttPasses<LOGN>::LDS doubles.
 template <int LOGN, class Load, class Store>
-__global__ __launch_bounds__(kNttThreads) void k_ntt_fwd(Load ld, Store st, DevParams dp)
+__device__ __forceinline__ void ntt_fwd_block(const Load &ld, const Store &st, const DevParams &dp,
+                                              int poly, double *lds)
 {
     using NP = NttPasses<LOGN>;
     using PA = typename NP::A;
     using PB = typename NP::B;
     using PC = typename NP::C;
-    __shared__ double lds[NP::LDS];
-    const int poly = blockIdx.x;
     const int l = poly % dp.L;
     const double p = dp.p[l], pinv = dp.pinv[l];
     const double *tw = dp.tw_fwd + ((size_t)l << LOGN);
@@ -157,16 +157,15 @@ __global__ __launch_bounds__(kNttThreads) void k_ntt_fwd(Load ld, Store st, DevP
     }
 }
 
-// Inverse negacyclic NTT (including the factor N^-1) of one polynomial per workgroup.
+// Inverse negacyclic NTT (including the factor N^-1) of polynomial `poly`.
 template <int LOGN, class Load, class Store>
-__global__ __launch_bounds__(kNttThreads) void k_ntt_inv(Load ld, Store st, DevParams dp)
+__device__ __forceinline__ void ntt_inv_block(const Load &ld, const Store &st, const DevParams &dp,
+                                              int poly, double *lds)
 {
     using NP = NttPasses<LOGN>;
     using PA = typename NP::A;
     using PB = typename NP::B;
     using PC = typename NP::C;
-    __shared__ double lds[NP::LDS];
-    const int poly = blockIdx.x;
     const int l = poly % dp.L;
     const double p = dp.p[l], pinv = dp.pinv[l];
     const double *tw = dp.tw_inv + ((size_t)l << LOGN);
@@ -206,6 +205,20 @@ __global__ __launch_bounds__(kNttThreads) void k_ntt_inv(Load ld, Store st, DevP
         for (int c = 0; c < PA::E; ++c)
             st(poly, l, PA::elem(S, c), mulmod(x[c], ninv, p, pinv), p, pinv);
     }
+}
+
+template <int LOGN, class Load, class Store>
+__global__ __launch_bounds__(kNttThreads) void k_ntt_fwd(Load ld, Store st, DevParams dp)
+{
+    __shared__ double lds[NttPasses<LOGN>::LDS];
+    ntt_fwd_block<LOGN>(ld, st, dp, (int)blockIdx.x, lds);
+}
+
+template <int LOGN, class Load, class Store>
+__global__ __launch_bounds__(kNttThreads) void k_ntt_inv(Load ld, Store st, DevParams dp)
+{
+    __shared__ double lds[NttPasses<LOGN>::LDS];
+    ntt_inv_block<LOGN>(ld, st, dp, (int)blockIdx.x, lds);
 }
 
 // ---- loaders ----------------------------------------------------------------

@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include "common.h"
+#include "mac.h"
 #include "ntt.h"
 
 namespace pimm {
@@ -56,64 +57,17 @@ __global__ void k_absmax(const int64_t *W, size_t n, unsigned long long *out)
 
 // ---- the slot-wise products (step 3) -----------------------------------------
 
-// acc^[(ib*K + kb)][comp][l][z] = sum_jb W^[(ib*R + jb)][l][z] * c^[(jb*K + kb)][comp][l][z].
 // Grid: x = (N / 256) slot chunks times L primes, y = ceil(M / G) row tiles,
-// z = K column blocks.  Each thread owns one slot z and G output rows; it
-// streams G weight words per inner block and reuses the two input words.
-// Partial sums stay below 2^53 by a reduction every 8 inner blocks.
+// z = K column blocks.
 template <int G>
 __global__ __launch_bounds__(256) void k_mac(const double *__restrict__ Wh,
                                              const double *__restrict__ Ch, double *__restrict__ Ah,
                                              int M, int R, int K, DevParams dp)
 {
-    const int N = dp.N, L = dp.L;
-    const int chunks = N >> 8;
+    const int chunks = dp.N >> 8;
     const int l = blockIdx.x / chunks;
     const int z = ((blockIdx.x % chunks) << 8) + threadIdx.x;
-    const int ib0 = blockIdx.y * G;
-    const int kb = blockIdx.z;
-    const double p = dp.p[l], pinv = dp.pinv[l];
-    const int rows = M - ib0 < G ? M - ib0 : G;
-
-    double a0[G], a1[G];
-#pragma unroll
-    for (int g = 0; g < G; ++g) a0[g] = a1[g] = 0.0;
-
-    const size_t wstep = (size_t)L * N;                  // next jb in W^
-    const size_t cstep = (size_t)K * 2 * L * N;          // next jb in c^
-    const double *wp = Wh + ((size_t)ib0 * R * L + l) * N + z;
-    const double *cp = Ch + (((size_t)kb * 2) * L + l) * N + z;
-    const size_t wrow = (size_t)R * L * N;               // next ib in W^
-
-    for (int jb = 0; jb < R; ++jb) {
-        const double c0 = cp[0];
-        const double c1 = cp[(size_t)L * N];
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            if (g < rows) {
-                const double w = wp[g * wrow];
-                a0[g] += mulmod(w, c0, p, pinv);
-                a1[g] += mulmod(w, c1, p, pinv);
-            }
-        }
-        if ((jb & 7) == 7) {
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                a0[g] = reduce(a0[g], p, pinv);
-                a1[g] = reduce(a1[g], p, pinv);
-            }
-        }
-        wp += wstep;
-        cp += cstep;
-    }
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-        if (g < rows) {
-            const size_t y = (size_t)(ib0 + g) * K + kb;
-            Ah[((y * 2 + 0) * L + l) * N + z] = reduce(a0[g], p, pinv);
-            Ah[((y * 2 + 1) * L + l) * N + z] = reduce(a1[g], p, pinv);
-        }
-    }
+    mac_tile<G>(Wh, Ch, Ah, M, R, K, dp, l, z, (int)blockIdx.y * G, (int)blockIdx.z);
 }
 
 int launch_mac(const Ctx &c, const pimm_plan_info &f, const double *Wh, const double *Ch, double *Ah,
@@ -188,6 +142,16 @@ __global__ void k_mask_extract(Key key, uint32_t op, const uint64_t *acc, uint64
 
 using namespace pimm;
 
+namespace pimm {
+// A weight cache holds pi_A blocks in NTT form; it serves every plan with the
+// same context, matrix shape (r, m) and block split (mb, rb), whatever n and nb.
+bool weights_fit(const Weights *w, const Plan *plan)
+{
+    const pimm_plan_info &a = w->info, &b = plan->info;
+    return w->ctx == plan->ctx && a.r == b.r && a.m == b.m && a.mb == b.mb && a.rb == b.rb;
+}
+}  // namespace pimm
+
 extern "C" {
 
 int pimm_weights_create(const pimm_plan *plan, const int64_t *W, pimm_weights **out, void *stream)
@@ -217,7 +181,8 @@ int pimm_weights_create(const pimm_plan *plan, const int64_t *W, pimm_weights **
                          "these parameters and this plan",
                          h_max);
     pimm_weights *w = new pimm_weights();
-    w->plan = plan;
+    w->ctx = plan->ctx;
+    w->info = plan->info;
     w->wmax = (int64_t)h_max;
     rc = check_hip(hipMalloc((void **)&w->d_w_hat, f.weights_bytes), "hipMalloc weights");
     if (!rc)
@@ -245,8 +210,8 @@ int pimm_matmul(const pimm_plan *plan, const pimm_weights *w, const uint64_t *ct
                 void *ws, size_t ws_bytes, void *stream)
 {
     if (!plan || !w || !ct || !acc) return set_error(PIMM_E_ARG, "pimm_matmul: NULL argument");
-    if (w->plan->ctx != plan->ctx || memcmp(&w->plan->info, &plan->info, sizeof plan->info))
-        return set_error(PIMM_E_ARG, "pimm_matmul: weights were made for another plan");
+    if (!weights_fit(w, plan))
+        return set_error(PIMM_E_ARG, "pimm_matmul: weights were made for another shape or block split");
     const Ctx &c = *plan->ctx;
     const pimm_plan_info &f = plan->info;
     const size_t N = c.params.N, L = c.params.L;

@@ -35,6 +35,8 @@ EXPORTS = [
     "pimm_plan_create", "pimm_plan_destroy", "pimm_plan_query",
     "pimm_keygen", "pimm_sk_destroy", "pimm_encode_input", "pimm_encrypt", "pimm_decrypt",
     "pimm_weights_create", "pimm_weights_destroy", "pimm_matmul", "pimm_mask_share",
+    "pimm_batch_create", "pimm_batch_destroy", "pimm_batch_query", "pimm_batch_set_schedule",
+    "pimm_batch_matmul", "pimm_batch_status",
     "pimm_poly_mul", "pimm_poly_mul_workspace", "pimm_sample_poly",
     "pimm_profile_enable", "pimm_profile_read", "pimm_sync", "pimm_last_error",
 ]
@@ -96,6 +98,12 @@ def lib():
         "pimm_weights_destroy": [vp],
         "pimm_matmul": [vp, vp, vp, vp, vp, ctypes.c_size_t, vp],
         "pimm_mask_share": [vp, vp, vp, u32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp],
+        "pimm_batch_create": [vp, u32, vp],
+        "pimm_batch_destroy": [vp],
+        "pimm_batch_query": [vp, vp, vp],
+        "pimm_batch_set_schedule": [vp, i32, i32, i32, u32],
+        "pimm_batch_matmul": [vp, vp, ctypes.c_size_t, vp],
+        "pimm_batch_status": [vp, vp, vp],
         "pimm_poly_mul": [vp, vp, vp, vp, u32, vp, ctypes.c_size_t, vp],
         "pimm_poly_mul_workspace": [vp, u32],
         "pimm_sample_poly": [vp, i32, vp, u32, u32, u32, u32, vp, vp],
@@ -377,6 +385,66 @@ def decrypt(plan: Plan, sk: SecretKey, c1: torch.Tensor, c0s: torch.Tensor, shar
     _check(lib().pimm_decrypt(plan.h, sk.h, _ptr(c1), _ptr(c0s), _ptr(share), _ptr(ws),
                               ws.numel() * 8, _stream(stream)))
     return share
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("weights", ctypes.c_void_p), ("ct", ctypes.c_void_p),
+                ("acc", ctypes.c_void_p)]
+
+
+PHASED, PERSISTENT = 0, 1
+
+
+class Batch:
+    """pimm_batch: many products of any shapes in one pass (three launches or one
+    persistent launch).  items: list of (Plan, Weights, ct tensor, acc tensor)."""
+
+    def __init__(self, items):
+        self.items = list(items)  # keeps the tensors and handles alive
+        arr = (BatchItem * len(items))()
+        for k, (plan, w, ct, acc) in enumerate(items):
+            arr[k] = BatchItem(plan.h.value, w.h.value, ct.data_ptr(), acc.data_ptr())
+        self.h = ctypes.c_void_p()
+        _check(lib().pimm_batch_create(arr, len(items), ctypes.byref(self.h)))
+        self.ctx = items[0][0].ctx
+        self._ws = None
+        self.schedule = (PHASED, 8, 1, 0)
+
+    def query(self):
+        ws, macs = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().pimm_batch_query(self.h, ctypes.byref(ws), ctypes.byref(macs)))
+        return ws.value, macs.value
+
+    def set_schedule(self, schedule=PHASED, mac_rows=8, xcd_map=True, grid=0):
+        _check(lib().pimm_batch_set_schedule(self.h, schedule, mac_rows, 1 if xcd_map else 0, grid))
+        self.schedule = (schedule, mac_rows, xcd_map, grid)
+        need = self.query()[0]
+        if self._ws is not None and self._ws.numel() * 8 < need:
+            self._ws = None
+
+    def workspace(self):
+        if self._ws is None:
+            self._ws = _words(self.query()[0], self.ctx.device)
+        return self._ws
+
+    def run(self, ws=None, stream=None):
+        ws = self.workspace() if ws is None else ws
+        _check(lib().pimm_batch_matmul(self.h, _ptr(ws), ws.numel() * 8, _stream(stream)))
+
+    def status(self, ws=None, stream=None):
+        ws = self.workspace() if ws is None else ws
+        _check(lib().pimm_batch_status(self.h, _ptr(ws), _stream(stream)))
+
+    def close(self):
+        if self.h:
+            lib().pimm_batch_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def poly_mul(ctx: Context, a: torch.Tensor, b: torch.Tensor, stream=None):
