@@ -64,6 +64,7 @@ typedef struct pimm_plan pimm_plan;
 typedef struct pimm_sk pimm_sk;
 typedef struct pimm_weights pimm_weights;
 typedef struct pimm_batch pimm_batch;
+typedef struct pimm_server pimm_server;
 
 /* RNS-BFV parameters (section 2.2: N a power of two, plaintext modulus t = 2^l,
  * ciphertext modulus q a product of L word-size primes).
@@ -233,6 +234,59 @@ int pimm_batch_matmul(const pimm_batch *batch, void *ws, size_t ws_bytes, void *
 /* After a persistent run: synchronise `stream` and report PIMM_E_DEVICE if a
  * dependency wait hit its bound (the outputs are then invalid). */
 int pimm_batch_status(const pimm_batch *batch, const void *ws, void *stream);
+
+/* ---- serving: continuous batching of private-inference requests -------------------- */
+
+/* A stack of `layers` x `ops` products per request; op o of every layer is
+ * d_in[o] x d_out[o].  weights[layer * ops + o] must fit the plan with block area
+ * d_fix (same r, m, mb, rb), which makes one cache serve every sequence length.
+ * hbm_budget: device bytes the server allocates once and hands to requests
+ * (key, ciphertexts, accumulators, reply, scratch); max_active: most requests in
+ * flight; schedule / mac_rows: the batched product's schedule (as
+ * pimm_batch_set_schedule; mac_rows 0 means 8). */
+typedef struct {
+    uint32_t layers, ops;
+    const uint32_t *d_in, *d_out;
+    const pimm_weights *const *weights;
+    uint32_t d_fix;
+    uint64_t hbm_budget;
+    uint32_t max_active;
+    int32_t schedule;
+    uint32_t mac_rows;
+} pimm_serve_config;
+
+/* A request: unique id, sequence length, arrival time in seconds from the start of
+ * the run, and the two parties' 32-byte seeds.  Product k of the stack draws its
+ * client share X[seq][d_in] from stream (tag 10, op_id = k, object = low 32 bits of
+ * id) and uses op_id = k for encryption, re-randomisation and mask. */
+typedef struct {
+    uint64_t id;
+    uint32_t seq, reserved;
+    double arrival_s;
+    uint8_t client_seed[32], server_seed[32];
+} pimm_request;
+
+/* Per request: times (seconds from the start of the run) of arrival, admission and
+ * completion (the last product's client share is ready); two order-independent
+ * checksums over every product's shares: of the (client, server) pairs, and of
+ * their sum mod 2^l (which is X W); useful multiply-accumulates; products done. */
+typedef struct {
+    uint64_t id;
+    double arrival_s, admit_s, done_s;
+    uint64_t pair_checksum, sum_checksum, useful_macs;
+    uint32_t steps, reserved;
+} pimm_request_result;
+
+int pimm_serve_create(pimm_ctx *ctx, const pimm_serve_config *cfg, pimm_server **out);
+int pimm_serve_destroy(pimm_server *server);
+/* Device bytes one request of length seq holds while it is in flight. */
+int pimm_serve_footprint(const pimm_server *server, uint32_t seq, uint64_t *bytes);
+/* Replay `count` requests in real time on `stream`: admit each at or after its
+ * arrival when the budget has room (arrival order), run every admitted request's
+ * next product at each tick, all of a tick's products in one batched launch, and
+ * return when every request is done.  results[i] belongs to reqs[i]. */
+int pimm_serve_run(pimm_server *server, const pimm_request *reqs, uint32_t count,
+                   pimm_request_result *results, void *stream);
 
 /* ---- primitives exposed for checking ----------------------------------------- */
 

@@ -14,7 +14,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpimm.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-HIP_SOURCES = ["context.hip", "client.hip", "server.hip", "batch.hip", "profile.hip"]
+HIP_SOURCES = ["context.hip", "client.hip", "server.hip", "batch.hip", "serve.hip",
+               "profile.hip"]
 HOST_SOURCES = ["cdt.cpp"]
 
 HIPCC_FLAGS = [

@@ -27,30 +27,12 @@
 #include <algorithm>
 #include <vector>
 
+#include "batch.h"
 #include "common.h"
 #include "mac.h"
 #include "ntt.h"
 
 namespace pimm {
-
-struct BatchItemDev {
-    const uint64_t *ct;  // [I][2][L][N]
-    uint64_t *acc;       // [O][2][L][N]
-    const double *wh;    // [Wb][L][N]
-    uint64_t chat_off;   // doubles into the workspace: c^ [I][2][L][N]
-    uint64_t ahat_off;   // acc^ [O][2][L][N]
-    uint32_t M, R, K, I, O;
-    uint32_t mtiles;            // ceil(M / G)
-    uint32_t in0, mac0, out0;   // first unit of each kind
-    uint32_t dep_in0, dep_mac0; // first dependency counter of each kind
-};
-
-// Counter words at the start of the workspace (uint32).
-constexpr int kCtrQueue = 0;
-constexpr int kCtrError = 1;
-constexpr int kCtrFirstDep = 2;
-
-enum Schedule : int { kPhased = 0, kPersistent = 1 };
 
 __device__ __forceinline__ int find_item(const BatchItemDev *items, int n, uint32_t u, int which)
 {
@@ -235,32 +217,18 @@ __global__ __launch_bounds__(kNttThreads) void k_batch_fused(const BatchItemDev 
 
 using namespace pimm;
 
-struct pimm_batch {
-    Ctx *ctx = nullptr;
-    std::vector<pimm_batch_item> items;
-    int G = 8;
-    int schedule = kPhased;
-    int xcd_map = 1;
-    uint32_t grid = 0;          // persistent grid size (0: from occupancy)
-    uint32_t spin_limit = 1u << 22;
-    BatchItemDev *d_items = nullptr;
-    uint32_t n_in = 0, n_mac = 0, n_out = 0, n_dep = 0;
-    uint64_t ws_bytes = 0;
-    uint64_t useful_macs = 0;
-};
-
 namespace {
 
-int build_tables(pimm_batch *b)
+int build_tables(pimm_batch *b, bool async, hipStream_t s)
 {
     const Ctx &c = *b->ctx;
     const uint64_t N = c.params.N, L = c.params.L;
     const uint32_t chunks = (uint32_t)(N >> 8);
-    std::vector<BatchItemDev> t(b->items.size());
-    uint64_t off = 0;
+    const size_t n = b->items.size();
+    std::vector<BatchItemDev> t(n);
     uint32_t in0 = 0, mac0 = 0, out0 = 0, dep = kCtrFirstDep;
     b->useful_macs = 0;
-    for (size_t i = 0; i < b->items.size(); ++i) {
+    for (size_t i = 0; i < n; ++i) {
         const pimm_batch_item &it = b->items[i];
         const pimm_plan_info &f = it.plan->info;
         BatchItemDev &d = t[i];
@@ -286,8 +254,14 @@ int build_tables(pimm_batch *b)
         b->useful_macs += (uint64_t)f.n * f.r * f.m;
     }
     // Counters first (rounded to 256 bytes), then each item's c^ and acc^.
-    off = (((uint64_t)dep * 4 + 255) / 256) * 256 / 8;
-    for (size_t i = 0; i < t.size(); ++i) {
+    uint64_t off = (((uint64_t)dep * 4 + 255) / 256) * 256 / 8;
+    const bool fixed = b->fixed_chat.size() == n && b->fixed_ahat.size() == n;
+    for (size_t i = 0; i < n; ++i) {
+        if (fixed) {
+            t[i].chat_off = b->fixed_chat[i];
+            t[i].ahat_off = b->fixed_ahat[i];
+            continue;
+        }
         t[i].chat_off = off;
         off += (uint64_t)t[i].I * 2 * L * N;
         t[i].ahat_off = off;
@@ -297,15 +271,30 @@ int build_tables(pimm_batch *b)
     b->n_mac = mac0;
     b->n_out = out0;
     b->n_dep = dep;
-    b->ws_bytes = off * 8;
-    if (b->d_items) (void)hipFree(b->d_items);
-    b->d_items = nullptr;
-    int rc = check_hip(hipSetDevice(c.device), "hipSetDevice");
-    if (!rc) rc = check_hip(hipMalloc((void **)&b->d_items, t.size() * sizeof(BatchItemDev)),
-                            "hipMalloc batch table");
-    if (!rc) rc = check_hip(hipMemcpy(b->d_items, t.data(), t.size() * sizeof(BatchItemDev),
-                                      hipMemcpyHostToDevice), "copy batch table");
-    return rc;
+    b->ws_bytes = fixed ? (((uint64_t)dep * 4 + 255) / 256) * 256 : off * 8;
+    int rc = PIMM_OK;
+    if (n > b->cap) {
+        if (b->d_items) (void)hipFree(b->d_items);
+        if (b->h_items) (void)hipHostFree(b->h_items);
+        b->d_items = nullptr;
+        b->h_items = nullptr;
+        b->cap = 0;
+        rc = check_hip(hipSetDevice(c.device), "hipSetDevice");
+        if (!rc) rc = check_hip(hipMalloc((void **)&b->d_items, n * sizeof(BatchItemDev)),
+                                "hipMalloc batch table");
+        if (!rc && async)
+            rc = check_hip(hipHostMalloc((void **)&b->h_items, n * sizeof(BatchItemDev), 0),
+                           "hipHostMalloc batch table");
+        if (!rc) b->cap = n;
+        if (rc) return rc;
+    }
+    if (async) {
+        memcpy(b->h_items, t.data(), n * sizeof(BatchItemDev));
+        return check_hip(hipMemcpyAsync(b->d_items, b->h_items, n * sizeof(BatchItemDev),
+                                        hipMemcpyHostToDevice, s), "upload batch table");
+    }
+    return check_hip(hipMemcpy(b->d_items, t.data(), n * sizeof(BatchItemDev), hipMemcpyHostToDevice),
+                     "copy batch table");
 }
 
 template <int LOGN, int G>
@@ -365,6 +354,14 @@ int run_batch_g(const pimm_batch *b, void *ws, hipStream_t s)
 
 }  // namespace
 
+namespace pimm {
+int batch_rebuild(pimm_batch *b, bool async, hipStream_t s) { return build_tables(b, async, s); }
+int batch_run(const pimm_batch *b, void *ws, hipStream_t s)
+{
+    return b->ctx->dp.logN == 12 ? run_batch_g<12>(b, ws, s) : run_batch_g<13>(b, ws, s);
+}
+}  // namespace pimm
+
 extern "C" {
 
 int pimm_batch_create(const pimm_batch_item *items, uint32_t count, pimm_batch **out)
@@ -383,7 +380,7 @@ int pimm_batch_create(const pimm_batch_item *items, uint32_t count, pimm_batch *
     pimm_batch *b = new pimm_batch();
     b->ctx = ctx;
     b->items.assign(items, items + count);
-    int rc = build_tables(b);
+    int rc = build_tables(b, false, nullptr);
     if (rc) {
         pimm_batch_destroy(b);
         return rc;
@@ -396,6 +393,7 @@ int pimm_batch_destroy(pimm_batch *b)
 {
     if (!b) return PIMM_OK;
     if (b->d_items) (void)hipFree(b->d_items);
+    if (b->h_items) (void)hipHostFree(b->h_items);
     delete b;
     return PIMM_OK;
 }
@@ -412,7 +410,7 @@ int pimm_batch_set_schedule(pimm_batch *b, int schedule, int mac_rows, int xcd_m
     b->grid = grid;
     if (mac_rows != b->G) {
         b->G = mac_rows;
-        return build_tables(b);
+        return build_tables(b, false, nullptr);
     }
     return PIMM_OK;
 }
@@ -430,8 +428,7 @@ int pimm_batch_matmul(const pimm_batch *b, void *ws, size_t ws_bytes, void *stre
     if (!b) return set_error(PIMM_E_ARG, "pimm_batch_matmul: NULL batch");
     if (!ws || ws_bytes < b->ws_bytes)
         return set_error(PIMM_E_WORKSPACE, "pimm_batch_matmul: workspace too small");
-    hipStream_t s = (hipStream_t)stream;
-    return b->ctx->dp.logN == 12 ? run_batch_g<12>(b, ws, s) : run_batch_g<13>(b, ws, s);
+    return batch_run(b, ws, (hipStream_t)stream);
 }
 
 int pimm_batch_status(const pimm_batch *b, const void *ws, void *stream)

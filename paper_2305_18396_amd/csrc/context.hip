@@ -271,8 +271,8 @@ static void fill_info(const Ctx &c, pimm_plan_info &f)
     f.workspace_bytes = ws;
 }
 
-static int plan_rule(const Ctx &c, uint32_t n, uint32_t r, uint32_t m, uint32_t mb, uint32_t rb,
-                     uint32_t nb, uint32_t d_fix, pimm_plan_info &f)
+int plan_rule(const Ctx &c, uint32_t n, uint32_t r, uint32_t m, uint32_t mb, uint32_t rb,
+              uint32_t nb, uint32_t d_fix, pimm_plan_info &f)
 {
     const uint64_t N = c.params.N;
     memset(&f, 0, sizeof f);
@@ -440,6 +440,25 @@ struct StorePk0 {
     }
 };
 
+// Key generation into caller buffers: s (ternary, stream SK), s^ = NTT(s), and
+// when pk is given and re-randomisation is on, pk = ([-a' s + e']_q, a').
+// tmp: L*N doubles and e: N int64 of scratch.
+int keygen_into(const Ctx &c, const Key &key, int64_t *s, double *s_hat, uint64_t *pk, double *tmp,
+                int64_t *e, hipStream_t st)
+{
+    const int N = (int)c.params.N, L = (int)c.params.L, lg = c.dp.logN;
+    int rc = launch_sample(c, 1, key, kTagSK, 0, 0, 1, 0, 1, s, 0, 0, st);
+    if (!rc) rc = launch_fwd(c, LoadI64Shared{s, lg, L}, StoreSlots{s_hat, lg}, L, st);
+    if (rc || !pk || !c.params.rerandomize) return rc;
+    uint64_t *pk1 = pk + (size_t)L * N;
+    rc = launch_sample(c, 0, key, kTagPkA, 0, 0, 1, 0, L, pk1, 0, (size_t)N, st);
+    if (!rc) rc = launch_sample(c, 2, key, kTagPkE, 0, 0, 1, 0, 1, e, 0, 0, st);
+    if (!rc) rc = launch_fwd(c, LoadU64{pk1, lg}, StoreSlots{tmp, lg}, L, st);
+    if (!rc)
+        rc = launch_inv(c, LoadSlotsMul{tmp, s_hat, lg, L}, StorePk0{e, pk, lg}, L, st);
+    return rc;
+}
+
 }  // namespace pimm
 
 using namespace pimm;
@@ -578,27 +597,14 @@ int pimm_keygen(pimm_ctx *ctx, const uint8_t seed[32], pimm_sk **sk_out, uint64_
     if (rc) return rc;
     pimm_sk *sk = new pimm_sk();
     sk->ctx = ctx;
-    Key key = make_key(seed);
     double *tmp = nullptr;
     int64_t *e = nullptr;
     rc = check_hip(hipMalloc((void **)&sk->d_s, (size_t)N * 8), "hipMalloc sk");
     if (!rc) rc = check_hip(hipMalloc((void **)&sk->d_s_hat, (size_t)L * N * 8), "hipMalloc sk");
-    if (!rc) rc = launch_sample(*ctx, 1, key, kTagSK, 0, 0, 1, 0, 1, sk->d_s, 0, 0, s);
-    if (!rc)
-        rc = launch_fwd(*ctx, LoadI64Shared{sk->d_s, ctx->dp.logN, L},
-                        StoreSlots{sk->d_s_hat, ctx->dp.logN}, L, s);
-    if (!rc && pk_out && ctx->params.rerandomize) {
-        uint64_t *pk1 = pk_out + (size_t)L * N;
-        rc = check_hip(hipMalloc((void **)&tmp, (size_t)L * N * 8), "hipMalloc keygen");
-        if (!rc) rc = check_hip(hipMalloc((void **)&e, (size_t)N * 8), "hipMalloc keygen");
-        if (!rc) rc = launch_sample(*ctx, 0, key, kTagPkA, 0, 0, 1, 0, L, pk1, 0, (size_t)N, s);
-        if (!rc) rc = launch_sample(*ctx, 2, key, kTagPkE, 0, 0, 1, 0, 1, e, 0, 0, s);
-        if (!rc) rc = launch_fwd(*ctx, LoadU64{pk1, ctx->dp.logN}, StoreSlots{tmp, ctx->dp.logN}, L, s);
-        if (!rc)
-            rc = launch_inv(*ctx, LoadSlotsMul{tmp, sk->d_s_hat, ctx->dp.logN, L},
-                            StorePk0{e, pk_out, ctx->dp.logN}, L, s);
-        if (!rc) rc = check_hip(hipStreamSynchronize(s), "keygen synchronize");
-    }
+    if (!rc) rc = check_hip(hipMalloc((void **)&tmp, (size_t)L * N * 8), "hipMalloc keygen");
+    if (!rc) rc = check_hip(hipMalloc((void **)&e, (size_t)N * 8), "hipMalloc keygen");
+    if (!rc) rc = keygen_into(*ctx, make_key(seed), sk->d_s, sk->d_s_hat, pk_out, tmp, e, s);
+    if (!rc) rc = check_hip(hipStreamSynchronize(s), "keygen synchronize");
     if (tmp) (void)hipFree(tmp);
     if (e) (void)hipFree(e);
     if (rc) {

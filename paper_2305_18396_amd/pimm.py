@@ -37,6 +37,7 @@ EXPORTS = [
     "pimm_weights_create", "pimm_weights_destroy", "pimm_matmul", "pimm_mask_share",
     "pimm_batch_create", "pimm_batch_destroy", "pimm_batch_query", "pimm_batch_set_schedule",
     "pimm_batch_matmul", "pimm_batch_status",
+    "pimm_serve_create", "pimm_serve_destroy", "pimm_serve_footprint", "pimm_serve_run",
     "pimm_poly_mul", "pimm_poly_mul_workspace", "pimm_sample_poly",
     "pimm_profile_enable", "pimm_profile_read", "pimm_sync", "pimm_last_error",
 ]
@@ -104,6 +105,10 @@ def lib():
         "pimm_batch_set_schedule": [vp, i32, i32, i32, u32],
         "pimm_batch_matmul": [vp, vp, ctypes.c_size_t, vp],
         "pimm_batch_status": [vp, vp, vp],
+        "pimm_serve_create": [vp, vp, vp],
+        "pimm_serve_destroy": [vp],
+        "pimm_serve_footprint": [vp, u32, vp],
+        "pimm_serve_run": [vp, vp, u32, vp, vp],
         "pimm_poly_mul": [vp, vp, vp, vp, u32, vp, ctypes.c_size_t, vp],
         "pimm_poly_mul_workspace": [vp, u32],
         "pimm_sample_poly": [vp, i32, vp, u32, u32, u32, u32, vp, vp],
@@ -438,6 +443,73 @@ class Batch:
     def close(self):
         if self.h:
             lib().pimm_batch_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("layers", ctypes.c_uint32), ("ops", ctypes.c_uint32),
+                ("d_in", ctypes.POINTER(ctypes.c_uint32)), ("d_out", ctypes.POINTER(ctypes.c_uint32)),
+                ("weights", ctypes.POINTER(ctypes.c_void_p)), ("d_fix", ctypes.c_uint32),
+                ("hbm_budget", ctypes.c_uint64), ("max_active", ctypes.c_uint32),
+                ("schedule", ctypes.c_int32), ("mac_rows", ctypes.c_uint32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("seq", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("arrival_s", ctypes.c_double), ("client_seed", ctypes.c_uint8 * 32),
+                ("server_seed", ctypes.c_uint8 * 32)]
+
+
+class RequestResult(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("arrival_s", ctypes.c_double),
+                ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double),
+                ("pair_checksum", ctypes.c_uint64), ("sum_checksum", ctypes.c_uint64),
+                ("useful_macs", ctypes.c_uint64), ("steps", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class Server:
+    """pimm_server: replays request traces with continuous batching.
+    shapes: [(d_in, d_out)] per op; weights: [layers * ops] Weights made with block area d_fix."""
+
+    def __init__(self, ctx: Context, layers: int, shapes, weights, d_fix: int, hbm_budget: int,
+                 max_active: int, schedule: int = PHASED, mac_rows: int = 8):
+        self.ctx, self.weights = ctx, list(weights)
+        ops = len(shapes)
+        self._d_in = (ctypes.c_uint32 * ops)(*[r for r, _ in shapes])
+        self._d_out = (ctypes.c_uint32 * ops)(*[m for _, m in shapes])
+        self._w = (ctypes.c_void_p * len(self.weights))(*[w.h.value for w in self.weights])
+        cfg = ServeConfig(layers, ops, self._d_in, self._d_out, self._w, d_fix, int(hbm_budget),
+                          max_active, schedule, mac_rows)
+        self.h = ctypes.c_void_p()
+        _check(lib().pimm_serve_create(ctx.h, ctypes.byref(cfg), ctypes.byref(self.h)))
+
+    def footprint(self, seq: int) -> int:
+        b = ctypes.c_uint64()
+        _check(lib().pimm_serve_footprint(self.h, seq, ctypes.byref(b)))
+        return b.value
+
+    def run(self, requests, stream=None):
+        """requests: [(id, seq, arrival_s, client_seed, server_seed)] -> list of result dicts."""
+        arr = (Request * len(requests))()
+        for k, (rid, seq, t, cs, ss) in enumerate(requests):
+            arr[k].id, arr[k].seq, arr[k].arrival_s = rid, seq, t
+            arr[k].client_seed[:] = list(cs)
+            arr[k].server_seed[:] = list(ss)
+        res = (RequestResult * len(requests))()
+        _check(lib().pimm_serve_run(self.h, arr, len(requests), res, _stream(stream)))
+        return [{k: getattr(r, k) for k, _ in RequestResult._fields_ if k != "reserved"}
+                for r in res]
+
+    def close(self):
+        if self.h:
+            lib().pimm_serve_destroy(self.h)
             self.h = ctypes.c_void_p()
 
     def __del__(self):
