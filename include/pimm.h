@@ -143,6 +143,15 @@ int pimm_plan_create(pimm_ctx *ctx, uint32_t n, uint32_t r, uint32_t m, uint32_t
                      uint32_t nb, uint32_t d_fix, pimm_plan **out);
 int pimm_plan_destroy(pimm_plan *plan);
 int pimm_plan_query(const pimm_plan *plan, pimm_plan_info *info);
+/* Schedule of pimm_matmul's slot-wise products: mac_rows (4, 8, 16) output rows per
+ * thread, splits (1, 2, 4) of the inner dimension over workgroups (partial
+ * accumulators are summed by the inverse NTT).  Any schedule gives the same bytes. */
+int pimm_plan_set_tuning(pimm_plan *plan, int mac_rows, int splits);
+int pimm_plan_get_tuning(const pimm_plan *plan, int *mac_rows, int *splits);
+/* Time every (mac_rows, splits) on these buffers with HIP events on `stream`
+ * (`reps` timed runs each) and keep the fastest on the plan; best_ms may be NULL. */
+int pimm_plan_autotune(pimm_plan *plan, const pimm_weights *w, const uint64_t *ct, uint64_t *acc,
+                       void *ws, size_t ws_bytes, int reps, void *stream, double *best_ms);
 
 /* ---- client ---------------------------------------------------------------- */
 
@@ -231,6 +240,10 @@ int pimm_batch_set_schedule(pimm_batch *batch, int schedule, int mac_rows, int x
 /* Run every product of the batch on `stream` (plain kernel launches only, so the
  * call can be captured into a hipGraph and replayed; one run at a time per workspace). */
 int pimm_batch_matmul(const pimm_batch *batch, void *ws, size_t ws_bytes, void *stream);
+/* Time the batch under each schedule candidate (phased / persistent, rows per thread,
+ * XCD placement) with HIP events on `stream` and keep the fastest. */
+int pimm_batch_autotune(pimm_batch *batch, void *ws, size_t ws_bytes, int reps, void *stream,
+                        double *best_ms);
 /* After a persistent run: synchronise `stream` and report PIMM_E_DEVICE if a
  * dependency wait hit its bound (the outputs are then invalid). */
 int pimm_batch_status(const pimm_batch *batch, const void *ws, void *stream);

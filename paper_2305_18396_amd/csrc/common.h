@@ -206,9 +206,14 @@ struct Ctx {
     uint64_t psi[kMaxL];
 };
 
+// Largest split of the inner dimension pimm_matmul may use (workspace is sized for it).
+constexpr int kMaxSplits = 4;
+
 struct Plan {
-    Ctx *ctx;
+    Ctx *ctx = nullptr;
     pimm_plan_info info;
+    int mac_rows = 8;  // output rows per product thread (4, 8, 16)
+    int splits = 1;    // splits of the inner dimension (1, 2, 4)
 };
 
 struct SecretKey {

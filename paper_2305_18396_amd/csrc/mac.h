@@ -13,11 +13,15 @@
 
 namespace pimm {
 
+// Inner blocks jb0 .. jb1-1 only (a split of the inner dimension writes its own
+// partial accumulator; the inverse NTT's loader adds the partials).
 template <int G>
 __device__ __forceinline__ void mac_tile(const double *__restrict__ Wh, const double *__restrict__ Ch,
                                          double *__restrict__ Ah, int M, int R, int K,
-                                         const DevParams &dp, int l, int z, int ib0, int kb)
+                                         const DevParams &dp, int l, int z, int ib0, int kb,
+                                         int jb0 = 0, int jb1 = -1)
 {
+    if (jb1 < 0) jb1 = R;
     const int N = dp.N, L = dp.L;
     const double p = dp.p[l], pinv = dp.pinv[l];
     const int rows = M - ib0 < G ? M - ib0 : G;
@@ -29,10 +33,10 @@ __device__ __forceinline__ void mac_tile(const double *__restrict__ Wh, const do
     const size_t wstep = (size_t)L * N;          // next jb in W^
     const size_t cstep = (size_t)K * 2 * L * N;  // next jb in c^
     const size_t wrow = (size_t)R * L * N;       // next ib in W^
-    const double *wp = Wh + ((size_t)ib0 * R * L + l) * N + z;
-    const double *cp = Ch + (((size_t)kb * 2) * L + l) * N + z;
+    const double *wp = Wh + (((size_t)ib0 * R + jb0) * L + l) * N + z;
+    const double *cp = Ch + ((((size_t)jb0 * K + kb) * 2) * L + l) * N + z;
 
-    for (int jb = 0; jb < R; ++jb) {
+    for (int jb = jb0; jb < jb1; ++jb) {
         const double c0 = cp[0];
         const double c1 = cp[(size_t)L * N];
 #pragma unroll
@@ -43,7 +47,7 @@ __device__ __forceinline__ void mac_tile(const double *__restrict__ Wh, const do
                 a1[g] += mulmod(w, c1, p, pinv);
             }
         }
-        if ((jb & 7) == 7) {
+        if (((jb - jb0) & 7) == 7) {
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 a0[g] = reduce(a0[g], p, pinv);

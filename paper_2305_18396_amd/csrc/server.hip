@@ -58,29 +58,59 @@ __global__ void k_absmax(const int64_t *W, size_t n, unsigned long long *out)
 // ---- the slot-wise products (step 3) -----------------------------------------
 
 // Grid: x = (N / 256) slot chunks times L primes, y = ceil(M / G) row tiles,
-// z = K column blocks.
+// z = K column blocks times S splits of the inner dimension.  Split s covers
+// inner blocks [s R / S, (s+1) R / S) and writes partial accumulators at
+// Ah + s * O * 2 * L * N.
 template <int G>
 __global__ __launch_bounds__(256) void k_mac(const double *__restrict__ Wh,
                                              const double *__restrict__ Ch, double *__restrict__ Ah,
-                                             int M, int R, int K, DevParams dp)
+                                             int M, int R, int K, int S, DevParams dp)
 {
     const int chunks = dp.N >> 8;
     const int l = blockIdx.x / chunks;
     const int z = ((blockIdx.x % chunks) << 8) + threadIdx.x;
-    mac_tile<G>(Wh, Ch, Ah, M, R, K, dp, l, z, (int)blockIdx.y * G, (int)blockIdx.z);
+    const int kb = (int)blockIdx.z % K, sp = (int)blockIdx.z / K;
+    const int jb0 = (int)((int64_t)R * sp / S), jb1 = (int)((int64_t)R * (sp + 1) / S);
+    const size_t part = (size_t)M * K * 2 * dp.L * dp.N;
+    mac_tile<G>(Wh, Ch, Ah + sp * part, M, R, K, dp, l, z, (int)blockIdx.y * G, kb, jb0, jb1);
 }
 
-int launch_mac(const Ctx &c, const pimm_plan_info &f, const double *Wh, const double *Ch, double *Ah,
-               hipStream_t s)
+int launch_mac(const Ctx &c, const pimm_plan_info &f, int G, int S, const double *Wh,
+               const double *Ch, double *Ah, hipStream_t s)
 {
-    constexpr int G = 8;
-    const dim3 grid((unsigned)((c.params.N >> 8) * c.params.L), (unsigned)((f.M + G - 1) / G),
-                    (unsigned)f.K);
+    const unsigned gx = (unsigned)((c.params.N >> 8) * c.params.L);
+    const unsigned gz = (unsigned)(f.K * S);
     ProfScope prof("mac", s);
-    hipLaunchKernelGGL(k_mac<G>, grid, dim3(256), 0, s, Wh, Ch, Ah, (int)f.M, (int)f.R, (int)f.K,
-                       c.dp);
+    switch (G) {
+    case 4:
+        hipLaunchKernelGGL(k_mac<4>, dim3(gx, (f.M + 3) / 4, gz), dim3(256), 0, s, Wh, Ch, Ah,
+                           (int)f.M, (int)f.R, (int)f.K, S, c.dp);
+        break;
+    case 16:
+        hipLaunchKernelGGL(k_mac<16>, dim3(gx, (f.M + 15) / 16, gz), dim3(256), 0, s, Wh, Ch, Ah,
+                           (int)f.M, (int)f.R, (int)f.K, S, c.dp);
+        break;
+    default:
+        hipLaunchKernelGGL(k_mac<8>, dim3(gx, (f.M + 7) / 8, gz), dim3(256), 0, s, Wh, Ch, Ah,
+                           (int)f.M, (int)f.R, (int)f.K, S, c.dp);
+        break;
+    }
     return check_hip(hipGetLastError(), "mac launch");
 }
+
+// Sum of S partial accumulators [S][O*2*L][N] of one polynomial.
+struct LoadSlotsSum {
+    const double *a;
+    size_t part;  // doubles between partials
+    int logn, S;
+    __device__ double operator()(int poly, int, int z, double p, double pinv) const
+    {
+        const double *q = a + ((size_t)poly << logn) + z;
+        double v = q[0];
+        for (int k = 1; k < S; ++k) v += q[k * part];
+        return reduce(v, p, pinv);
+    }
+};
 
 // ---- re-randomisation, mask and extraction --------------------------------------
 
@@ -215,15 +245,22 @@ int pimm_matmul(const pimm_plan *plan, const pimm_weights *w, const uint64_t *ct
     const Ctx &c = *plan->ctx;
     const pimm_plan_info &f = plan->info;
     const size_t N = c.params.N, L = c.params.L;
-    const size_t need = ((size_t)f.I + f.O) * 2 * L * N * 8;
+    const size_t need = ((size_t)f.I + (size_t)plan->splits * f.O) * 2 * L * N * 8;
     if (!ws || ws_bytes < need) return set_error(PIMM_E_WORKSPACE, "pimm_matmul: workspace too small");
     hipStream_t s = (hipStream_t)stream;
     const int lg = c.dp.logN;
     double *ch = (double *)ws;
     double *ah = ch + (size_t)f.I * 2 * L * N;
+    const int G = plan->mac_rows, S = plan->splits;
     int rc = launch_fwd(c, LoadU64{ct, lg}, StoreSlots{ch, lg}, (int)(f.I * 2 * L), s);
-    if (!rc) rc = launch_mac(c, f, w->d_w_hat, ch, ah, s);
-    if (!rc) rc = launch_inv(c, LoadSlots{ah, lg}, StoreU64{acc, lg}, (int)(f.O * 2 * L), s);
+    if (!rc) rc = launch_mac(c, f, G, S, w->d_w_hat, ch, ah, s);
+    if (!rc) {
+        if (S == 1)
+            rc = launch_inv(c, LoadSlots{ah, lg}, StoreU64{acc, lg}, (int)(f.O * 2 * L), s);
+        else
+            rc = launch_inv(c, LoadSlotsSum{ah, (size_t)f.O * 2 * L * N, lg, S}, StoreU64{acc, lg},
+                            (int)(f.O * 2 * L), s);
+    }
     return rc;
 }
 

@@ -32,7 +32,8 @@ TAG_RR_U, TAG_RR_E1, TAG_RR_E2, TAG_MASK = 6, 7, 8, 9
 EXPORTS = [
     "pimm_ctx_create", "pimm_ctx_destroy", "pimm_ctx_primes", "pimm_ctx_cdt",
     "pimm_params_primes", "pimm_cdt", "pimm_plan_rule", "pimm_noise_ok",
-    "pimm_plan_create", "pimm_plan_destroy", "pimm_plan_query",
+    "pimm_plan_create", "pimm_plan_destroy", "pimm_plan_query", "pimm_plan_set_tuning",
+    "pimm_plan_get_tuning", "pimm_plan_autotune", "pimm_batch_autotune",
     "pimm_keygen", "pimm_sk_destroy", "pimm_encode_input", "pimm_encrypt", "pimm_decrypt",
     "pimm_weights_create", "pimm_weights_destroy", "pimm_matmul", "pimm_mask_share",
     "pimm_batch_create", "pimm_batch_destroy", "pimm_batch_query", "pimm_batch_set_schedule",
@@ -90,6 +91,10 @@ def lib():
         "pimm_plan_create": [vp, u32, u32, u32, u32, u32, u32, u32, vp],
         "pimm_plan_destroy": [vp],
         "pimm_plan_query": [vp, vp],
+        "pimm_plan_set_tuning": [vp, i32, i32],
+        "pimm_plan_get_tuning": [vp, vp, vp],
+        "pimm_plan_autotune": [vp, vp, vp, vp, vp, ctypes.c_size_t, i32, vp, vp],
+        "pimm_batch_autotune": [vp, vp, ctypes.c_size_t, i32, vp, vp],
         "pimm_keygen": [vp, vp, vp, vp, vp],
         "pimm_sk_destroy": [vp],
         "pimm_encode_input": [vp, vp, vp, vp],
@@ -264,6 +269,22 @@ class Plan:
             return getattr(info, k)
         raise AttributeError(k)
 
+    def set_tuning(self, mac_rows: int = 8, splits: int = 1):
+        _check(lib().pimm_plan_set_tuning(self.h, mac_rows, splits))
+
+    def tuning(self):
+        g, s = ctypes.c_int(), ctypes.c_int()
+        _check(lib().pimm_plan_get_tuning(self.h, ctypes.byref(g), ctypes.byref(s)))
+        return g.value, s.value
+
+    def autotune(self, w, ct, acc, reps: int = 3, stream=None) -> float:
+        """Time every product schedule on these buffers; keep the fastest.  -> best ms."""
+        ws = self.workspace()
+        best = ctypes.c_double()
+        _check(lib().pimm_plan_autotune(self.h, w.h, _ptr(ct), _ptr(acc), _ptr(ws), ws.numel() * 8,
+                                        reps, _stream(stream), ctypes.byref(best)))
+        return best.value
+
     def workspace(self) -> torch.Tensor:
         """A workspace tensor of the plan's size, allocated once by torch."""
         if self._ws is None:
@@ -435,6 +456,16 @@ class Batch:
     def run(self, ws=None, stream=None):
         ws = self.workspace() if ws is None else ws
         _check(lib().pimm_batch_matmul(self.h, _ptr(ws), ws.numel() * 8, _stream(stream)))
+
+    def autotune(self, reps: int = 3, stream=None) -> float:
+        """Time each schedule candidate and keep the fastest.  -> best ms."""
+        ws_need = max(self.query()[0], 1)
+        ws = _words(ws_need * 2, self.ctx.device)
+        best = ctypes.c_double()
+        _check(lib().pimm_batch_autotune(self.h, _ptr(ws), ws.numel() * 8, reps, _stream(stream),
+                                         ctypes.byref(best)))
+        self._ws = None
+        return best.value
 
     def status(self, ws=None, stream=None):
         ws = self.workspace() if ws is None else ws
