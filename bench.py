@@ -91,6 +91,9 @@ def main():
     ap.add_argument("--seq", type=int, default=128)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="after the timed steps, copy a buffer of this many MiB device to device "
+                         "(a known-size reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -164,6 +167,14 @@ def main():
         kernels[kname] = {"launches": cnt, "ms_total": round(ms, 3),
                           "ms_per_step": round(ms / args.steps, 4)}
     log(f"timed {args.steps} steps in {elapsed:.4f} s")
+
+    if args.calib_copy_mb:
+        src = torch.ones(args.calib_copy_mb << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # Per-step latency of the layer (each step synchronised), for p50/p99.
     lat = []

@@ -144,8 +144,9 @@ int pimm_plan_create(pimm_ctx *ctx, uint32_t n, uint32_t r, uint32_t m, uint32_t
 int pimm_plan_destroy(pimm_plan *plan);
 int pimm_plan_query(const pimm_plan *plan, pimm_plan_info *info);
 /* Schedule of pimm_matmul's slot-wise products: mac_rows (4, 8, 16) output rows per
- * thread, splits (1, 2, 4) of the inner dimension over workgroups (partial
- * accumulators are summed by the inverse NTT).  Any schedule gives the same bytes. */
+ * thread; the (tile, inner block) iterations are divided evenly over a grid of
+ * `splits` (1, 2, 4) times the workgroups the device holds at once.  Any schedule
+ * gives the same bytes. */
 int pimm_plan_set_tuning(pimm_plan *plan, int mac_rows, int splits);
 int pimm_plan_get_tuning(const pimm_plan *plan, int *mac_rows, int *splits);
 /* Time every (mac_rows, splits) on these buffers with HIP events on `stream`

@@ -20,6 +20,9 @@ HOST_SOURCES = ["cdt.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",
+    # Native FP64 atomic add for the product's split tiles (hipMalloc memory is
+    # coarse-grained, where the hardware instruction is valid).
+    "-munsafe-fp-atomics",
     # Packed FP32 instructions are kept out of every kernel.
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",

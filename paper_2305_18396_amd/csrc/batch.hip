@@ -62,7 +62,8 @@ template <int LOGN>
 __device__ __forceinline__ void run_in(const BatchItemDev &it, int poly, double *ws,
                                        const DevParams &dp, double *lds)
 {
-    ntt_fwd_block<LOGN>(LoadU64{it.ct, LOGN}, StoreSlots{ws + it.chat_off, LOGN}, dp, poly, lds);
+    ntt_fwd_block<LOGN>(LoadU64{it.ct, LOGN}, StoreCtTiled{ws + it.chat_off, LOGN, dp.L, it.K, it.R},
+                        dp, poly, lds);
 }
 
 template <int LOGN>
@@ -92,8 +93,9 @@ template <int G>
 __device__ __forceinline__ void run_mac(const BatchItemDev &it, const MacCoord &c, double *ws,
                                         const DevParams &dp)
 {
-    mac_tile<G>(it.wh, ws + it.chat_off, ws + it.ahat_off, (int)it.M, (int)it.R, (int)it.K, dp, c.l,
-                (c.zc << 8) + (int)threadIdx.x, c.ibt * G, c.kb);
+    const MacShape sh{(int)it.M, (int)it.R, (int)it.K, dp.N >> 8};
+    mac_range<G>(it.wh, ws + it.chat_off, ws + it.ahat_off, sh, dp, c.l, c.zc, c.kb, c.ibt * G, 0,
+                 (int)it.R, 0);
 }
 
 // ---- phased schedule ---------------------------------------------------------------

@@ -206,14 +206,11 @@ struct Ctx {
     uint64_t psi[kMaxL];
 };
 
-// Largest split of the inner dimension pimm_matmul may use (workspace is sized for it).
-constexpr int kMaxSplits = 4;
-
 struct Plan {
     Ctx *ctx = nullptr;
     pimm_plan_info info;
     int mac_rows = 8;  // output rows per product thread (4, 8, 16)
-    int splits = 1;    // splits of the inner dimension (1, 2, 4)
+    int splits = 1;    // product grid = splits x the workgroups the device holds at once
 };
 
 struct SecretKey {
@@ -225,7 +222,7 @@ struct SecretKey {
 struct Weights {
     Ctx *ctx = nullptr;
     pimm_plan_info info;        // of the plan it was made for (r, m, mb, rb, M, R, Wb matter)
-    double *d_w_hat = nullptr;  // [Wb][L][N] NTT slots, balanced
+    double *d_w_hat = nullptr;  // [L][N/256][M][R][256] NTT slots, balanced
     int64_t wmax = 0;
 };
 

@@ -261,7 +261,7 @@ static void fill_info(const Ctx &c, pimm_plan_info &f)
     f.weights_bytes = (uint64_t)f.Wb * L * N * 8;
     // Scratch of each call (see the call's implementation for the layout).
     const uint64_t enc = (uint64_t)f.I * N * 8 * (L + 1);
-    const uint64_t mm = ((uint64_t)f.I + (uint64_t)kMaxSplits * f.O) * 2 * L * N * 8;
+    const uint64_t mm = ((uint64_t)f.I + f.O) * 2 * L * N * 8;
     const uint64_t msk = 2 * L * N * 8 + (uint64_t)f.O * L * N * 8 + (uint64_t)f.O * 3 * N * 8;
     const uint64_t dec = (uint64_t)f.O * L * N * 8 + (uint64_t)f.O * L * f.mb * f.nb * 8;
     uint64_t ws = enc;
@@ -558,10 +558,6 @@ int pimm_plan_create(pimm_ctx *ctx, uint32_t n, uint32_t r, uint32_t m, uint32_t
     pimm_plan *p = new pimm_plan();
     p->ctx = ctx;
     p->info = f;
-    // Default split of the inner dimension: enough workgroups for ~8 per compute
-    // unit (256 units), keeping at least 16 inner blocks per split.
-    const uint64_t wgs = (uint64_t)(ctx->params.N >> 8) * ctx->params.L * ((f.M + 7) / 8) * f.K;
-    while (p->splits < kMaxSplits && wgs * p->splits < 2048 && f.R >= 32u * p->splits) p->splits *= 2;
     *out = p;
     return PIMM_OK;
 }

@@ -1,44 +1,93 @@
 // mac.h -- the slot-wise modular products of Algorithm 1 step 3.
 //
 // For NTT slot z and prime l the products of every inner block are summed:
-//     acc^[(ib*K + kb)][comp][l][z] = sum_jb W^[(ib*R + jb)][l][z] * c^[(jb*K + kb)][comp][l][z]
-// for both ciphertext components.  One thread owns one slot and G consecutive
-// output rows ib0 .. ib0+G-1; per inner block it streams G weight words and
-// reuses the two input words of that slot.  Partial sums of balanced products
-// (each below 0.6 p in magnitude) stay below 2^53 with a reduction every 8
-// inner blocks.
+//     acc^[(ib*K + kb)][comp][l][z] = sum_jb W^[ib, jb][l][z] * c^[jb, kb][comp][l][z]
+// for both ciphertext components.
+//
+// Slots are grouped in chunks of 256 (one per thread of a workgroup) and the
+// NTT-form operands are stored chunk-contiguous, so that a thread's stream over
+// the inner blocks is sequential in memory:
+//     W^   [L][chunks][M][R][256]        (weight cache)
+//     c^   [L][chunks][K][R][2][256]     (transformed inputs)
+//     acc^ [O][2][L][N], O = M*K         (accumulators, read by the inverse NTT)
+// A tile is (prime l, chunk zc, column block kb, rows ib0 .. ib0+G-1); a
+// thread owns one slot of the tile and G output rows, streams G weight words
+// and reuses the two input words per inner block.  Partial sums of balanced
+// products (each below 0.6 p in magnitude) stay below 2^53 with a reduction
+// every 8 inner blocks.
 #pragma once
 
 #include "common.h"
 
 namespace pimm {
 
-// Inner blocks jb0 .. jb1-1 only (a split of the inner dimension writes its own
-// partial accumulator; the inverse NTT's loader adds the partials).
-template <int G>
-__device__ __forceinline__ void mac_tile(const double *__restrict__ Wh, const double *__restrict__ Ch,
-                                         double *__restrict__ Ah, int M, int R, int K,
-                                         const DevParams &dp, int l, int z, int ib0, int kb,
-                                         int jb0 = 0, int jb1 = -1)
+struct MacShape {
+    int M, R, K, chunks;
+};
+
+__device__ __forceinline__ size_t w_tile_base(const MacShape &s, int l, int zc)
 {
-    if (jb1 < 0) jb1 = R;
-    const int N = dp.N, L = dp.L;
+    return ((size_t)l * s.chunks + zc) * (size_t)s.M * s.R * 256;
+}
+__device__ __forceinline__ size_t c_tile_base(const MacShape &s, int l, int zc, int kb)
+{
+    return (((size_t)l * s.chunks + zc) * s.K + kb) * (size_t)s.R * 512;
+}
+
+// Inner blocks [jb0, jb1) of one tile.  mode 0: store the reduced sums; mode 1:
+// add them atomically (exact: every addend and every partial total is an
+// integer below 2^53, so the order of the additions does not matter).
+template <int G>
+__device__ __forceinline__ void mac_range(const double *__restrict__ Wt, const double *__restrict__ Ct,
+                                          double *__restrict__ Ah, const MacShape &s,
+                                          const DevParams &dp, int l, int zc, int kb, int ib0, int jb0,
+                                          int jb1, int mode)
+{
+    const int L = dp.L, N = dp.N;
     const double p = dp.p[l], pinv = dp.pinv[l];
-    const int rows = M - ib0 < G ? M - ib0 : G;
+    const int rows = s.M - ib0 < G ? s.M - ib0 : G;
+    const int zz = threadIdx.x;
+    const double *wp = Wt + w_tile_base(s, l, zc) + ((size_t)ib0 * s.R + jb0) * 256 + zz;
+    const double *cp = Ct + c_tile_base(s, l, zc, kb) + (size_t)jb0 * 512 + zz;
+    const size_t wrow = (size_t)s.R * 256;
 
     double a0[G], a1[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) a0[g] = a1[g] = 0.0;
 
-    const size_t wstep = (size_t)L * N;          // next jb in W^
-    const size_t cstep = (size_t)K * 2 * L * N;  // next jb in c^
-    const size_t wrow = (size_t)R * L * N;       // next ib in W^
-    const double *wp = Wh + (((size_t)ib0 * R + jb0) * L + l) * N + z;
-    const double *cp = Ch + ((((size_t)jb0 * K + kb) * 2) * L + l) * N + z;
-
-    for (int jb = jb0; jb < jb1; ++jb) {
-        const double c0 = cp[0];
-        const double c1 = cp[(size_t)L * N];
+    int jb = jb0;
+    // Two inner blocks per iteration: all loads first, then the products.
+    for (; jb + 1 < jb1; jb += 2) {
+        const double c00 = cp[0], c01 = cp[256], c10 = cp[512], c11 = cp[768];
+        double w0[G], w1[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (g < rows) {
+                w0[g] = wp[g * wrow];
+                w1[g] = wp[g * wrow + 256];
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (g < rows) {
+                a0[g] += mulmod(w0[g], c00, p, pinv);
+                a1[g] += mulmod(w0[g], c01, p, pinv);
+                a0[g] += mulmod(w1[g], c10, p, pinv);
+                a1[g] += mulmod(w1[g], c11, p, pinv);
+            }
+        }
+        if (((jb - jb0) & 7) == 6) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                a0[g] = reduce(a0[g], p, pinv);
+                a1[g] = reduce(a1[g], p, pinv);
+            }
+        }
+        wp += 512;
+        cp += 1024;
+    }
+    if (jb < jb1) {
+        const double c0 = cp[0], c1 = cp[256];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             if (g < rows) {
@@ -47,24 +96,67 @@ __device__ __forceinline__ void mac_tile(const double *__restrict__ Wh, const do
                 a1[g] += mulmod(w, c1, p, pinv);
             }
         }
-        if (((jb - jb0) & 7) == 7) {
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                a0[g] = reduce(a0[g], p, pinv);
-                a1[g] = reduce(a1[g], p, pinv);
-            }
-        }
-        wp += wstep;
-        cp += cstep;
     }
+    const int z = (zc << 8) + zz;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         if (g < rows) {
-            const size_t y = (size_t)(ib0 + g) * K + kb;
-            Ah[((y * 2 + 0) * L + l) * N + z] = reduce(a0[g], p, pinv);
-            Ah[((y * 2 + 1) * L + l) * N + z] = reduce(a1[g], p, pinv);
+            const size_t y = (size_t)(ib0 + g) * s.K + kb;
+            double *d0 = Ah + ((y * 2 + 0) * L + l) * N + z;
+            double *d1 = Ah + ((y * 2 + 1) * L + l) * N + z;
+            const double v0 = reduce(a0[g], p, pinv), v1 = reduce(a1[g], p, pinv);
+            if (mode == 0) {
+                *d0 = v0;
+                *d1 = v1;
+            } else {
+                atomicAdd(d0, v0);
+                atomicAdd(d1, v1);
+            }
         }
     }
 }
+
+// ---- stores into the chunk-contiguous layouts (NTT output slot z) --------------
+
+// Weight block w = ib*R + jb, prime l: poly = w*L + l.
+struct StoreWeightTiled {
+    double *out;
+    int logn, L;
+    uint32_t M, R;
+    __device__ void operator()(int poly, int l, int z, double v, double, double) const
+    {
+        const uint32_t w = (uint32_t)(poly / L);
+        const uint32_t ib = w / R, jb = w % R;
+        const size_t chunks = (size_t)1 << (logn - 8);
+        const size_t zc = (size_t)(z >> 8), zz = (size_t)(z & 255);
+        out[((((size_t)l * chunks + zc) * M + ib) * R + jb) * 256 + zz] = v;
+    }
+};
+
+// Input ciphertext x = jb*K + kb, component c, prime l: poly = (x*2 + c)*L + l.
+struct StoreCtTiled {
+    double *out;
+    int logn, L;
+    uint32_t K, R;
+    __device__ void operator()(int poly, int l, int z, double v, double, double) const
+    {
+        const uint32_t x = (uint32_t)(poly / (2 * L));
+        const uint32_t c = (uint32_t)((poly / L) % 2);
+        const uint32_t jb = x / K, kb = x % K;
+        const size_t chunks = (size_t)1 << (logn - 8);
+        const size_t zc = (size_t)(z >> 8), zz = (size_t)(z & 255);
+        out[(((((size_t)l * chunks + zc) * K + kb) * R + jb) * 2 + c) * 256 + zz] = v;
+    }
+};
+
+// Accumulator slots that may hold unreduced sums of a few partials.
+struct LoadSlotsReduce {
+    const double *a;
+    int logn;
+    __device__ double operator()(int poly, int, int z, double p, double pinv) const
+    {
+        return reduce(a[((size_t)poly << logn) + z], p, pinv);
+    }
+};
 
 }  // namespace pimm

@@ -57,60 +57,77 @@ __global__ void k_absmax(const int64_t *W, size_t n, unsigned long long *out)
 
 // ---- the slot-wise products (step 3) -----------------------------------------
 
-// Grid: x = (N / 256) slot chunks times L primes, y = ceil(M / G) row tiles,
-// z = K column blocks times S splits of the inner dimension.  Split s covers
-// inner blocks [s R / S, (s+1) R / S) and writes partial accumulators at
-// Ah + s * O * 2 * L * N.
+// Stream-K schedule: the flattened space of (tile, inner block) iterations,
+// tile t = ((l * chunks + zc) * K + kb) * mtiles + ibt (row tiles fastest, so a
+// workgroup's consecutive tiles share their input slice), is cut into equal
+// contiguous ranges, one per workgroup of a grid sized to what the device
+// holds at once.  A workgroup that covers a whole tile stores its sums; pieces
+// of split tiles are added atomically into the zeroed accumulators.  At most
+// 12 pieces meet in one accumulator, so the total stays below 8p < 2^53.
 template <int G>
-__global__ __launch_bounds__(256) void k_mac(const double *__restrict__ Wh,
-                                             const double *__restrict__ Ch, double *__restrict__ Ah,
-                                             int M, int R, int K, int S, DevParams dp)
+__global__ __launch_bounds__(256) void k_mac_sk(const double *__restrict__ Wt,
+                                                const double *__restrict__ Ct,
+                                                double *__restrict__ Ah, MacShape sh, int mtiles,
+                                                uint64_t total, uint64_t per, DevParams dp)
 {
-    const int chunks = dp.N >> 8;
-    const int l = blockIdx.x / chunks;
-    const int z = ((blockIdx.x % chunks) << 8) + threadIdx.x;
-    const int kb = (int)blockIdx.z % K, sp = (int)blockIdx.z / K;
-    const int jb0 = (int)((int64_t)R * sp / S), jb1 = (int)((int64_t)R * (sp + 1) / S);
-    const size_t part = (size_t)M * K * 2 * dp.L * dp.N;
-    mac_tile<G>(Wh, Ch, Ah + sp * part, M, R, K, dp, l, z, (int)blockIdx.y * G, kb, jb0, jb1);
+    uint64_t u = (uint64_t)blockIdx.x * per;
+    const uint64_t end = u + per < total ? u + per : total;
+    const uint64_t R = (uint64_t)sh.R;
+    while (u < end) {
+        const uint64_t t = u / R;
+        const int jb0 = (int)(u % R);
+        const int jb1 = (int)(R - (uint64_t)jb0 < end - u ? R : (uint64_t)jb0 + (end - u));
+        const int ibt = (int)(t % mtiles);
+        uint64_t r = t / mtiles;
+        const int kb = (int)(r % sh.K);
+        r /= sh.K;
+        const int zc = (int)(r % sh.chunks);
+        const int l = (int)(r / sh.chunks);
+        const int mode = (jb0 == 0 && jb1 == sh.R) ? 0 : 1;
+        mac_range<G>(Wt, Ct, Ah, sh, dp, l, zc, kb, ibt * G, jb0, jb1, mode);
+        u += (uint64_t)(jb1 - jb0);
+    }
 }
 
-int launch_mac(const Ctx &c, const pimm_plan_info &f, int G, int S, const double *Wh,
-               const double *Ch, double *Ah, hipStream_t s)
+__global__ void k_fill_zero(double *p, size_t n)
 {
-    const unsigned gx = (unsigned)((c.params.N >> 8) * c.params.L);
-    const unsigned gz = (unsigned)(f.K * S);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+template <int G>
+int launch_mac_g(const Ctx &c, const pimm_plan_info &f, int waves, const double *Wt, const double *Ct,
+                 double *Ah, hipStream_t s)
+{
+    const MacShape sh{(int)f.M, (int)f.R, (int)f.K, (int)(c.params.N >> 8)};
+    const int mtiles = (int)((f.M + G - 1) / G);
+    const uint64_t total = (uint64_t)c.params.L * sh.chunks * f.K * mtiles * f.R;
+    int per_cu = 0, cus = 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mac_sk<G>, 256, 0);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device);
+    uint64_t grid = (uint64_t)(per_cu > 0 ? per_cu : 1) * (uint64_t)(cus > 0 ? cus : 1) * waves;
+    uint64_t per = (total + grid - 1) / grid;
+    const uint64_t min_per = (f.R + 10) / 11;  // at most 12 pieces per tile
+    if (per < min_per) per = min_per;
+    grid = (total + per - 1) / per;
+    const size_t acc_n = (size_t)f.O * 2 * c.params.L * c.params.N;
+    hipLaunchKernelGGL(k_fill_zero, dim3(1024), dim3(256), 0, s, Ah, acc_n);
     ProfScope prof("mac", s);
-    switch (G) {
-    case 4:
-        hipLaunchKernelGGL(k_mac<4>, dim3(gx, (f.M + 3) / 4, gz), dim3(256), 0, s, Wh, Ch, Ah,
-                           (int)f.M, (int)f.R, (int)f.K, S, c.dp);
-        break;
-    case 16:
-        hipLaunchKernelGGL(k_mac<16>, dim3(gx, (f.M + 15) / 16, gz), dim3(256), 0, s, Wh, Ch, Ah,
-                           (int)f.M, (int)f.R, (int)f.K, S, c.dp);
-        break;
-    default:
-        hipLaunchKernelGGL(k_mac<8>, dim3(gx, (f.M + 7) / 8, gz), dim3(256), 0, s, Wh, Ch, Ah,
-                           (int)f.M, (int)f.R, (int)f.K, S, c.dp);
-        break;
-    }
+    hipLaunchKernelGGL(k_mac_sk<G>, dim3((unsigned)grid), dim3(256), 0, s, Wt, Ct, Ah, sh, mtiles,
+                       total, per, c.dp);
     return check_hip(hipGetLastError(), "mac launch");
 }
 
-// Sum of S partial accumulators [S][O*2*L][N] of one polynomial.
-struct LoadSlotsSum {
-    const double *a;
-    size_t part;  // doubles between partials
-    int logn, S;
-    __device__ double operator()(int poly, int, int z, double p, double pinv) const
-    {
-        const double *q = a + ((size_t)poly << logn) + z;
-        double v = q[0];
-        for (int k = 1; k < S; ++k) v += q[k * part];
-        return reduce(v, p, pinv);
+int launch_mac(const Ctx &c, const pimm_plan_info &f, int G, int waves, const double *Wt,
+               const double *Ct, double *Ah, hipStream_t s)
+{
+    switch (G) {
+    case 4: return launch_mac_g<4>(c, f, waves, Wt, Ct, Ah, s);
+    case 16: return launch_mac_g<16>(c, f, waves, Wt, Ct, Ah, s);
+    default: return launch_mac_g<8>(c, f, waves, Wt, Ct, Ah, s);
     }
-};
+}
 
 // ---- re-randomisation, mask and extraction --------------------------------------
 
@@ -217,7 +234,8 @@ int pimm_weights_create(const pimm_plan *plan, const int64_t *W, pimm_weights **
     rc = check_hip(hipMalloc((void **)&w->d_w_hat, f.weights_bytes), "hipMalloc weights");
     if (!rc)
         rc = launch_fwd(c, LoadWeights{W, f.r, f.m, f.mb, f.rb, f.R, (int)c.params.L},
-                        StoreSlots{w->d_w_hat, c.dp.logN}, (int)(f.Wb * c.params.L), s);
+                        StoreWeightTiled{w->d_w_hat, c.dp.logN, (int)c.params.L, f.M, f.R},
+                        (int)(f.Wb * c.params.L), s);
     if (!rc) rc = check_hip(hipStreamSynchronize(s), "weights synchronize");
     if (rc) {
         pimm_weights_destroy(w);
@@ -245,22 +263,16 @@ int pimm_matmul(const pimm_plan *plan, const pimm_weights *w, const uint64_t *ct
     const Ctx &c = *plan->ctx;
     const pimm_plan_info &f = plan->info;
     const size_t N = c.params.N, L = c.params.L;
-    const size_t need = ((size_t)f.I + (size_t)plan->splits * f.O) * 2 * L * N * 8;
+    const size_t need = ((size_t)f.I + f.O) * 2 * L * N * 8;
     if (!ws || ws_bytes < need) return set_error(PIMM_E_WORKSPACE, "pimm_matmul: workspace too small");
     hipStream_t s = (hipStream_t)stream;
     const int lg = c.dp.logN;
     double *ch = (double *)ws;
     double *ah = ch + (size_t)f.I * 2 * L * N;
-    const int G = plan->mac_rows, S = plan->splits;
-    int rc = launch_fwd(c, LoadU64{ct, lg}, StoreSlots{ch, lg}, (int)(f.I * 2 * L), s);
-    if (!rc) rc = launch_mac(c, f, G, S, w->d_w_hat, ch, ah, s);
-    if (!rc) {
-        if (S == 1)
-            rc = launch_inv(c, LoadSlots{ah, lg}, StoreU64{acc, lg}, (int)(f.O * 2 * L), s);
-        else
-            rc = launch_inv(c, LoadSlotsSum{ah, (size_t)f.O * 2 * L * N, lg, S}, StoreU64{acc, lg},
-                            (int)(f.O * 2 * L), s);
-    }
+    int rc = launch_fwd(c, LoadU64{ct, lg}, StoreCtTiled{ch, lg, (int)L, f.K, f.R},
+                        (int)(f.I * 2 * L), s);
+    if (!rc) rc = launch_mac(c, f, plan->mac_rows, plan->splits, w->d_w_hat, ch, ah, s);
+    if (!rc) rc = launch_inv(c, LoadSlotsReduce{ah, lg}, StoreU64{acc, lg}, (int)(f.O * 2 * L), s);
     return rc;
 }
 

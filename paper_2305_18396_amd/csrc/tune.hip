@@ -67,7 +67,6 @@ int pimm_plan_autotune(pimm_plan *plan, const pimm_weights *w, const uint64_t *c
     int bg = plan->mac_rows, bs = plan->splits;
     for (int g : rows)
         for (int sp : splits) {
-            if (sp > 1 && (int)plan->info.R < 8 * sp) continue;
             plan->mac_rows = g;
             plan->splits = sp;
             double ms = 0;
