@@ -211,6 +211,17 @@ int pimm_mask_share(const pimm_plan *plan, const uint64_t *pk, const uint8_t see
                     uint32_t op_id, uint64_t *acc, uint64_t *c1, uint64_t *c0s,
                     uint64_t *server_share, void *ws, size_t ws_bytes, void *stream);
 
+/* pimm_matmul followed by pimm_mask_share in one pass: the same c1, c0s and
+ * server_share bytes, without the [O][2][L][N] accumulator buffer.  The
+ * re-randomisation term is added in the NTT domain before the inverse
+ * transform, and the transform's last stage writes c1, the masked decoded c0
+ * coefficients and the server's share directly (Algorithm 1 step 3 and the
+ * sparse reply of section 3.1.3). */
+int pimm_matmul_share(const pimm_plan *plan, const pimm_weights *w, const uint64_t *pk,
+                      const uint8_t seed[32], uint32_t op_id, const uint64_t *ct, uint64_t *c1,
+                      uint64_t *c0s, uint64_t *server_share, void *ws, size_t ws_bytes,
+                      void *stream);
+
 /* ---- batching: many products in one pass ----------------------------------------- */
 
 /* One product of a batch: a plan, a weight cache that fits it (same r, m, mb, rb),

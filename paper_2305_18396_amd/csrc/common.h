@@ -232,6 +232,7 @@ int check_hip(hipError_t e, const char *what);
 Key make_key(const uint8_t seed[32]);
 bool noise_ok(const Ctx &c, const pimm_plan_info &f, uint64_t wmax);
 bool weights_fit(const Weights *w, const Plan *plan);
+uint64_t fused_workspace_bytes(const Ctx &c, const pimm_plan_info &f);
 int plan_rule(const Ctx &c, uint32_t n, uint32_t r, uint32_t m, uint32_t mb, uint32_t rb, uint32_t nb,
               uint32_t d_fix, pimm_plan_info &f);
 

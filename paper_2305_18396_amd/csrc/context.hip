@@ -242,6 +242,13 @@ static uint64_t next_pow2(uint64_t x)
     return p;
 }
 
+uint64_t fused_workspace_bytes(const Ctx &c, const pimm_plan_info &f)
+{
+    const uint64_t N = c.params.N, L = c.params.L;
+    return (((uint64_t)f.I + f.O) * 2 * L * N + 2 * L * N + (uint64_t)f.O * L * N +
+            (uint64_t)f.O * 3 * N) * 8;
+}
+
 static void fill_info(const Ctx &c, pimm_plan_info &f)
 {
     const uint64_t N = c.params.N, L = c.params.L;
@@ -265,6 +272,8 @@ static void fill_info(const Ctx &c, pimm_plan_info &f)
     const uint64_t msk = 2 * L * N * 8 + (uint64_t)f.O * L * N * 8 + (uint64_t)f.O * 3 * N * 8;
     const uint64_t dec = (uint64_t)f.O * L * N * 8 + (uint64_t)f.O * L * f.mb * f.nb * 8;
     uint64_t ws = enc;
+    const uint64_t fused = fused_workspace_bytes(c, f);
+    if (fused > ws) ws = fused;
     if (mm > ws) ws = mm;
     if (msk > ws) ws = msk;
     if (dec > ws) ws = dec;

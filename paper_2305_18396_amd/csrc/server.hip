@@ -185,6 +185,62 @@ __global__ void k_mask_extract(Key key, uint32_t op, const uint64_t *acc, uint64
     if (row < f.n && col < f.m) share[(size_t)row * f.m + col] = sm;
 }
 
+// ---- fused server step: product, re-randomisation, mask and reply ----------------
+
+// acc^ (reduced) plus, with re-randomisation, u^ pk^ (NTT domain) for polynomials [O][2][L].
+struct LoadAccRerand {
+    const double *ah;   // [O][2][L][N]
+    const double *uh;   // [O][L][N]
+    const double *pkh;  // [2][L][N]
+    int logn, L, rr;
+    __device__ double operator()(int poly, int l, int z, double p, double pinv) const
+    {
+        double v = reduce(ah[((size_t)poly << logn) + z], p, pinv);
+        if (rr) {
+            const size_t o = (size_t)(poly / (2 * L)), comp = (size_t)((poly / L) % 2);
+            v += mulmod(uh[((o * L + l) << logn) + z], pkh[((comp * L + l) << logn) + z], p, pinv);
+        }
+        return v;
+    }
+};
+
+// Coefficient j of component comp, prime l of output ciphertext y: add the
+// re-randomisation error, then write c1 (comp 1, every j) or, at a decoded
+// position (comp 0), c0 - Delta_l s_y[j] and the server's share s_y[j].
+struct StoreShare {
+    uint64_t *c1, *c0s, *share;
+    const int64_t *e;  // [O][2][N]
+    Key key;
+    uint32_t op;
+    uint32_t mb, rb, nb, K, n, m;
+    uint64_t delta[kMaxL];
+    int logn, L, rr, ell;
+    __device__ void operator()(int poly, int l, int j, double v, double p, double pinv) const
+    {
+        const uint64_t q = (uint64_t)p;
+        const uint32_t y = (uint32_t)(poly / (2 * L)), comp = (uint32_t)((poly / L) % 2);
+        uint64_t x = to_canonical(v, p, pinv);
+        if (rr) x = add_mod(x, lift_signed(e[(((size_t)y * 2 + comp) << logn) + j], q), q);
+        if (comp == 1) {
+            c1[(((size_t)y * L + l) << logn) + j] = x;
+            return;
+        }
+        const uint32_t uj = (uint32_t)j;
+        if (uj % rb != rb - 1) return;
+        const uint32_t i = (uj / rb) % mb, k = uj / (mb * rb);
+        if (k >= nb) return;
+        uint32_t w[16];
+        chacha_block(key, uj / 8, nonce0(kTagMask, 0), op, y, w);
+        const uint64_t sm = mask_of(word64(w, (int)(uj % 8)), ell);
+        c0s[((size_t)y * L + l) * mb * nb + k * mb + i] = sub_mod(x, mul_mod(delta[l], sm, p, pinv), q);
+        if (l == 0) {
+            const uint32_t ib = y / K, kb = y % K;
+            const uint32_t row = kb * nb + k, col = ib * mb + i;
+            if (row < n && col < m) share[(size_t)row * m + col] = sm;
+        }
+    }
+};
+
 }  // namespace pimm
 
 using namespace pimm;
@@ -322,6 +378,51 @@ int pimm_mask_share(const pimm_plan *plan, const uint64_t *pk, const uint8_t see
         rc = check_hip(hipMemcpy2DAsync(c1, L * N * 8, acc + L * N, 2 * L * N * 8, L * N * 8, f.O,
                                         hipMemcpyDeviceToDevice, s),
                        "copy c1");
+    return rc;
+}
+
+// Workspace: c^ [I][2][L][N], acc^ [O][2][L][N], pk^ [2][L][N], u^ [O][L][N] doubles,
+// then u [O][N] and e [O][2][N] int64.
+int pimm_matmul_share(const pimm_plan *plan, const pimm_weights *w, const uint64_t *pk,
+                      const uint8_t seed[32], uint32_t op_id, const uint64_t *ct, uint64_t *c1,
+                      uint64_t *c0s, uint64_t *server_share, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!plan || !w || !seed || !ct || !c1 || !c0s || !server_share)
+        return set_error(PIMM_E_ARG, "pimm_matmul_share: NULL argument");
+    if (!weights_fit(w, plan))
+        return set_error(PIMM_E_ARG, "pimm_matmul_share: weights were made for another shape or block split");
+    const Ctx &c = *plan->ctx;
+    const pimm_plan_info &f = plan->info;
+    const size_t N = c.params.N, L = c.params.L;
+    const int rr = c.params.rerandomize ? 1 : 0;
+    if (rr && !pk) return set_error(PIMM_E_ARG, "pimm_matmul_share: re-randomisation needs pk");
+    const size_t need = fused_workspace_bytes(c, f);
+    if (!ws || ws_bytes < need)
+        return set_error(PIMM_E_WORKSPACE, "pimm_matmul_share: workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    const int lg = c.dp.logN;
+    double *ch = (double *)ws;
+    double *ah = ch + (size_t)f.I * 2 * L * N;
+    double *pkh = ah + (size_t)f.O * 2 * L * N;
+    double *uh = pkh + 2 * L * N;
+    int64_t *u = (int64_t *)(uh + (size_t)f.O * L * N);
+    int64_t *e = u + (size_t)f.O * N;
+    const Key key = make_key(seed);
+    int rc = launch_fwd(c, LoadU64{ct, lg}, StoreCtTiled{ch, lg, (int)L, f.K, f.R}, (int)(f.I * 2 * L), s);
+    if (!rc) rc = launch_mac(c, f, plan->mac_rows, plan->splits, w->d_w_hat, ch, ah, s);
+    if (!rc && rr) {
+        rc = launch_fwd(c, LoadU64{pk, lg}, StoreSlots{pkh, lg}, (int)(2 * L), s);
+        if (!rc) rc = launch_sample(c, 1, key, kTagRrU, op_id, 0, (int)f.O, 0, 1, u, N, 0, s);
+        if (!rc) rc = launch_sample(c, 2, key, kTagRrE1, op_id, 0, (int)f.O, 0, 1, e, 2 * N, 0, s);
+        if (!rc) rc = launch_sample(c, 2, key, kTagRrE2, op_id, 0, (int)f.O, 0, 1, e + N, 2 * N, 0, s);
+        if (!rc) rc = launch_fwd(c, LoadI64Shared{u, lg, (int)L}, StoreSlots{uh, lg}, (int)(f.O * L), s);
+    }
+    if (!rc) {
+        StoreShare st{c1, c0s, server_share, e, key, op_id, f.mb, f.rb, f.nb, f.K, f.n, f.m,
+                      {0, 0, 0, 0}, lg, (int)L, rr, c.dp.ell};
+        for (size_t l = 0; l < L; ++l) st.delta[l] = c.dp.delta[l];
+        rc = launch_inv(c, LoadAccRerand{ah, uh, pkh, lg, (int)L, rr}, st, (int)(f.O * 2 * L), s);
+    }
     return rc;
 }
 

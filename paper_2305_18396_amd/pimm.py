@@ -36,6 +36,7 @@ EXPORTS = [
     "pimm_plan_get_tuning", "pimm_plan_autotune", "pimm_batch_autotune",
     "pimm_keygen", "pimm_sk_destroy", "pimm_encode_input", "pimm_encrypt", "pimm_decrypt",
     "pimm_weights_create", "pimm_weights_destroy", "pimm_matmul", "pimm_mask_share",
+    "pimm_matmul_share",
     "pimm_batch_create", "pimm_batch_destroy", "pimm_batch_query", "pimm_batch_set_schedule",
     "pimm_batch_matmul", "pimm_batch_status",
     "pimm_serve_create", "pimm_serve_destroy", "pimm_serve_footprint", "pimm_serve_run",
@@ -104,6 +105,7 @@ def lib():
         "pimm_weights_destroy": [vp],
         "pimm_matmul": [vp, vp, vp, vp, vp, ctypes.c_size_t, vp],
         "pimm_mask_share": [vp, vp, vp, u32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp],
+        "pimm_matmul_share": [vp, vp, vp, vp, u32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp],
         "pimm_batch_create": [vp, u32, vp],
         "pimm_batch_destroy": [vp],
         "pimm_batch_query": [vp, vp, vp],
@@ -399,6 +401,24 @@ def mask_share(plan: Plan, pk: torch.Tensor | None, seed: bytes, op_id: int, acc
     _check(lib().pimm_mask_share(plan.h, _ptr(pk), _seed(seed), op_id, _ptr(acc), _ptr(c1),
                                  _ptr(c0s), _ptr(share), _ptr(ws), ws.numel() * 8,
                                  _stream(stream)))
+    return c1, c0s, share
+
+
+def matmul_share(plan: Plan, w: Weights, pk, seed: bytes, op_id: int, ct: torch.Tensor, c1=None,
+                 c0s=None, share=None, ws=None, stream=None):
+    """pimm_matmul + pimm_mask_share in one pass.  -> (c1, c0s, server_share)."""
+    f, c = plan.info, plan.ctx
+    dev = c.device
+    if c1 is None:
+        c1 = torch.empty((f.O, c.L, c.N), dtype=torch.int64, device=dev)
+    if c0s is None:
+        c0s = torch.empty((f.O, c.L, f.mb * f.nb), dtype=torch.int64, device=dev)
+    if share is None:
+        share = torch.empty((f.n, f.m), dtype=torch.int64, device=dev)
+    ws = plan.workspace() if ws is None else ws
+    _check(lib().pimm_matmul_share(plan.h, w.h, _ptr(pk), _seed(seed), op_id, _ptr(ct), _ptr(c1),
+                                   _ptr(c0s), _ptr(share), _ptr(ws), ws.numel() * 8,
+                                   _stream(stream)))
     return c1, c0s, share
 
 

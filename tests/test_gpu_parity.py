@@ -291,3 +291,46 @@ def test_full_size_bert_large_op(orc):
     pyp = orc.Params(8192, 3, 41, 14)
     wl = workloads.bert_large_layer(512)[3]
     check_layer_op(orc, ctx, pyp, wl, dict(d_fix=1024), 200)
+
+
+@pytest.mark.parametrize("name", ["single", "single_norr", "ragged_explicit", "n8192_l3", "fix256"])
+def test_fused_server_step_equals_two_calls(orc, name):
+    """pimm_matmul_share gives the bytes of pimm_matmul followed by pimm_mask_share."""
+    c = CASES[name]
+    n, r, m = c["shape"]
+    rng = np.random.default_rng(zlib.crc32(name.encode()) + 1)
+    X = workloads.share(rng, n, r, c["ell"])
+    W = workloads.weights(rng, r, m, c["f"])
+    ctx = context(c["N"], c["L"], c["ell"], c["f"], c["rr"])
+    plan = pimm.Plan(ctx, n, r, m, **c["plan"])
+    log(f"fused {name}")
+    cs, ss = workloads.seed("client", 60), workloads.seed("server", 60)
+    sk, pk = pimm.keygen(ctx, cs)
+    ct = pimm.encrypt(plan, sk, cs, 5, pimm.encode_input(plan, pimm.to_device_u64(X)))
+    w = pimm.Weights(plan, pimm.to_device_u64(W))
+    c1, c0s, y1 = pimm.mask_share(plan, pk, ss, 5, pimm.matmul(plan, w, ct))
+    d1, d0s, z1 = pimm.matmul_share(plan, w, pk, ss, 5, ct)
+    for a, b in [(c1, d1), (c0s, d0s), (y1, z1)]:
+        assert torch.equal(a, b)
+    Y = (u64(pimm.decrypt(plan, sk, d1, d0s)) + u64(z1)) & np.uint64((1 << c["ell"]) - 1)
+    assert np.array_equal(Y, xw_mod(X, W, c["ell"]))
+
+
+def test_fused_full_size_layer():
+    """The benchmark's step (fused server call) at the BERT-base shapes: shares add up to X W,
+    and the bytes equal the two-call path."""
+    ctx = context(4096, 2, 37, 12, True)
+    cs, ss = workloads.seed("client", 61), workloads.seed("server", 61)
+    sk, pk = pimm.keygen(ctx, cs)
+    for i, wl in enumerate(workloads.bert_base_layer(128)):
+        n, r, m = wl.shape
+        plan = pimm.Plan(ctx, n, r, m)
+        log(f"fused full-size {wl.name}")
+        ct = pimm.encrypt(plan, sk, cs, i, pimm.encode_input(plan, pimm.to_device_u64(wl.X)))
+        w = pimm.Weights(plan, pimm.to_device_u64(wl.W))
+        d1, d0s, z1 = pimm.matmul_share(plan, w, pk, ss, i, ct)
+        y0 = pimm.decrypt(plan, sk, d1, d0s)
+        Y = (u64(y0) + u64(z1)) & np.uint64((1 << 37) - 1)
+        assert np.array_equal(Y, xw_mod(wl.X, wl.W, 37))
+        c1, c0s, y1 = pimm.mask_share(plan, pk, ss, i, pimm.matmul(plan, w, ct))
+        assert torch.equal(c1, d1) and torch.equal(c0s, d0s) and torch.equal(y1, z1)
