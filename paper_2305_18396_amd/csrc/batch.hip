@@ -49,15 +49,6 @@ __device__ __forceinline__ int find_item(const BatchItemDev *items, int n, uint3
     return lo;
 }
 
-// Position of workgroup b among the workgroups dispatched to its XCD, so that
-// consecutive tiles (which share input slices) land on one XCD's L2.
-__device__ __forceinline__ uint32_t xcd_local(uint32_t b, uint32_t nblocks)
-{
-    const uint32_t xcd = b % 8, k = b / 8;
-    const uint32_t per = nblocks / 8, rem = nblocks % 8;
-    return xcd * per + (xcd < rem ? xcd : rem) + k;
-}
-
 template <int LOGN>
 __device__ __forceinline__ void run_in(const BatchItemDev &it, int poly, double *ws,
                                        const DevParams &dp, double *lds)

@@ -193,6 +193,17 @@ __device__ __forceinline__ uint64_t word64(const uint32_t b[16], int i)
     return (uint64_t)b[2 * i] | ((uint64_t)b[2 * i + 1] << 32);
 }
 
+// Workgroups of a launch are dispatched round-robin over the 8 XCDs (each with
+// its own L2).  xcd_local maps workgroup b to a logical index such that the
+// workgroups one XCD receives get one contiguous range of logical indices, so
+// neighbouring work items (which share input slices) share an L2.
+__device__ __forceinline__ uint32_t xcd_local(uint32_t b, uint32_t nblocks)
+{
+    const uint32_t xcd = b % 8, k = b / 8;
+    const uint32_t per = nblocks / 8, rem = nblocks % 8;
+    return xcd * per + (xcd < rem ? xcd : rem) + k;
+}
+
 // ---------------------------------------------------------------------------
 // Host-side objects
 // ---------------------------------------------------------------------------

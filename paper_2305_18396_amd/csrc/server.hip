@@ -61,7 +61,7 @@ __global__ void k_absmax(const int64_t *W, size_t n, unsigned long long *out)
 // tile t = ((l * chunks + zc) * K + kb) * mtiles + ibt (row tiles fastest, so a
 // workgroup's consecutive tiles share their input slice), is cut into equal
 // contiguous ranges, one per workgroup of a grid sized to what the device
-// holds at once.  A workgroup that covers a whole tile stores its sums; pieces
+// holds at once (ranges placed XCD by XCD).  A workgroup that covers a whole tile stores its sums; pieces
 // of split tiles are added atomically into the zeroed accumulators.  At most
 // 12 pieces meet in one accumulator, so the total stays below 8p < 2^53.
 template <int G>
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void k_mac_sk(const double *__restrict__ Wt,
                                                 double *__restrict__ Ah, MacShape sh, int mtiles,
                                                 uint64_t total, uint64_t per, DevParams dp)
 {
-    uint64_t u = (uint64_t)blockIdx.x * per;
+    uint64_t u = (uint64_t)xcd_local(blockIdx.x, gridDim.x) * per;
     const uint64_t end = u + per < total ? u + per : total;
     const uint64_t R = (uint64_t)sh.R;
     while (u < end) {
