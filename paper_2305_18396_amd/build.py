@@ -14,7 +14,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpimm.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-HIP_SOURCES = ["context.hip", "client.hip", "server.hip", "batch.hip", "serve.hip",
+HIP_SOURCES = ["context.hip", "client.hip", "server.hip", "mac.hip", "batch.hip", "serve.hip",
                "tune.hip", "profile.hip"]
 HOST_SOURCES = ["cdt.cpp"]
 

@@ -261,12 +261,9 @@ class ProfScope {
 };
 
 // Launch helpers implemented in the kernel translation units.
-int launch_ntt_fwd_u64(const Ctx &c, const uint64_t *in, double *out, int npoly, hipStream_t s);
-int launch_ntt_fwd_i64_shared(const Ctx &c, const int64_t *in, double *out, int nsrc,
-                              hipStream_t s);
-int launch_intt_mul_u64(const Ctx &c, const double *a, const double *b, int b_mod, uint64_t *out,
-                        int npoly, hipStream_t s);
-int launch_intt_u64(const Ctx &c, const double *in, uint64_t *out, int npoly, hipStream_t s);
+// Slot-wise products of one plan into zeroed-then-accumulated acc^ (mac.hip).
+int launch_mac(const Ctx &c, const pimm_plan_info &f, int G, int waves, const double *Wt,
+               const double *Ct, double *Ah, hipStream_t s);
 
 }  // namespace pimm
 

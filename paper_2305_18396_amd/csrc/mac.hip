@@ -1,0 +1,79 @@
+// mac.hip -- launch of the slot-wise products (Algorithm 1 step 3) for one product.
+#include "common.h"
+#include "mac.h"
+
+namespace pimm {
+
+// Stream-K schedule: the flattened space of (tile, inner block) iterations,
+// tile t = ((l * chunks + zc) * K + kb) * mtiles + ibt (row tiles fastest, so a
+// workgroup's consecutive tiles share their input slice), is cut into equal
+// contiguous ranges, one per workgroup of a grid sized to what the device
+// holds at once (ranges placed XCD by XCD).  A workgroup that covers a whole tile stores its sums; pieces
+// of split tiles are added atomically into the zeroed accumulators.  At most
+// 12 pieces meet in one accumulator, so the total stays below 8p < 2^53.
+template <int G>
+__global__ __launch_bounds__(256) void k_mac_sk(const double *__restrict__ Wt,
+                                                const double *__restrict__ Ct,
+                                                double *__restrict__ Ah, MacShape sh, int mtiles,
+                                                uint64_t total, uint64_t per, DevParams dp)
+{
+    uint64_t u = (uint64_t)xcd_local(blockIdx.x, gridDim.x) * per;
+    const uint64_t end = u + per < total ? u + per : total;
+    const uint64_t R = (uint64_t)sh.R;
+    while (u < end) {
+        const uint64_t t = u / R;
+        const int jb0 = (int)(u % R);
+        const int jb1 = (int)(R - (uint64_t)jb0 < end - u ? R : (uint64_t)jb0 + (end - u));
+        const int ibt = (int)(t % mtiles);
+        uint64_t r = t / mtiles;
+        const int kb = (int)(r % sh.K);
+        r /= sh.K;
+        const int zc = (int)(r % sh.chunks);
+        const int l = (int)(r / sh.chunks);
+        const int mode = (jb0 == 0 && jb1 == sh.R) ? 0 : 1;
+        mac_range<G>(Wt, Ct, Ah, sh, dp, l, zc, kb, ibt * G, jb0, jb1, mode);
+        u += (uint64_t)(jb1 - jb0);
+    }
+}
+
+__global__ void k_fill_zero(double *p, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+template <int G>
+int launch_mac_g(const Ctx &c, const pimm_plan_info &f, int waves, const double *Wt, const double *Ct,
+                 double *Ah, hipStream_t s)
+{
+    const MacShape sh{(int)f.M, (int)f.R, (int)f.K, (int)(c.params.N >> 8)};
+    const int mtiles = (int)((f.M + G - 1) / G);
+    const uint64_t total = (uint64_t)c.params.L * sh.chunks * f.K * mtiles * f.R;
+    int per_cu = 0, cus = 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mac_sk<G>, 256, 0);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device);
+    uint64_t grid = (uint64_t)(per_cu > 0 ? per_cu : 1) * (uint64_t)(cus > 0 ? cus : 1) * waves;
+    uint64_t per = (total + grid - 1) / grid;
+    const uint64_t min_per = (f.R + 10) / 11;  // at most 12 pieces per tile
+    if (per < min_per) per = min_per;
+    grid = (total + per - 1) / per;
+    const size_t acc_n = (size_t)f.O * 2 * c.params.L * c.params.N;
+    hipLaunchKernelGGL(k_fill_zero, dim3(1024), dim3(256), 0, s, Ah, acc_n);
+    ProfScope prof("mac", s);
+    hipLaunchKernelGGL(k_mac_sk<G>, dim3((unsigned)grid), dim3(256), 0, s, Wt, Ct, Ah, sh, mtiles,
+                       total, per, c.dp);
+    return check_hip(hipGetLastError(), "mac launch");
+}
+
+int launch_mac(const Ctx &c, const pimm_plan_info &f, int G, int waves, const double *Wt,
+               const double *Ct, double *Ah, hipStream_t s)
+{
+    switch (G) {
+    case 4: return launch_mac_g<4>(c, f, waves, Wt, Ct, Ah, s);
+    case 16: return launch_mac_g<16>(c, f, waves, Wt, Ct, Ah, s);
+    default: return launch_mac_g<8>(c, f, waves, Wt, Ct, Ah, s);
+    }
+}
+
+}  // namespace pimm

@@ -57,78 +57,6 @@ __global__ void k_absmax(const int64_t *W, size_t n, unsigned long long *out)
 
 // ---- the slot-wise products (step 3) -----------------------------------------
 
-// Stream-K schedule: the flattened space of (tile, inner block) iterations,
-// tile t = ((l * chunks + zc) * K + kb) * mtiles + ibt (row tiles fastest, so a
-// workgroup's consecutive tiles share their input slice), is cut into equal
-// contiguous ranges, one per workgroup of a grid sized to what the device
-// holds at once (ranges placed XCD by XCD).  A workgroup that covers a whole tile stores its sums; pieces
-// of split tiles are added atomically into the zeroed accumulators.  At most
-// 12 pieces meet in one accumulator, so the total stays below 8p < 2^53.
-template <int G>
-__global__ __launch_bounds__(256) void k_mac_sk(const double *__restrict__ Wt,
-                                                const double *__restrict__ Ct,
-                                                double *__restrict__ Ah, MacShape sh, int mtiles,
-                                                uint64_t total, uint64_t per, DevParams dp)
-{
-    uint64_t u = (uint64_t)xcd_local(blockIdx.x, gridDim.x) * per;
-    const uint64_t end = u + per < total ? u + per : total;
-    const uint64_t R = (uint64_t)sh.R;
-    while (u < end) {
-        const uint64_t t = u / R;
-        const int jb0 = (int)(u % R);
-        const int jb1 = (int)(R - (uint64_t)jb0 < end - u ? R : (uint64_t)jb0 + (end - u));
-        const int ibt = (int)(t % mtiles);
-        uint64_t r = t / mtiles;
-        const int kb = (int)(r % sh.K);
-        r /= sh.K;
-        const int zc = (int)(r % sh.chunks);
-        const int l = (int)(r / sh.chunks);
-        const int mode = (jb0 == 0 && jb1 == sh.R) ? 0 : 1;
-        mac_range<G>(Wt, Ct, Ah, sh, dp, l, zc, kb, ibt * G, jb0, jb1, mode);
-        u += (uint64_t)(jb1 - jb0);
-    }
-}
-
-__global__ void k_fill_zero(double *p, size_t n)
-{
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x)
-        p[i] = 0.0;
-}
-
-template <int G>
-int launch_mac_g(const Ctx &c, const pimm_plan_info &f, int waves, const double *Wt, const double *Ct,
-                 double *Ah, hipStream_t s)
-{
-    const MacShape sh{(int)f.M, (int)f.R, (int)f.K, (int)(c.params.N >> 8)};
-    const int mtiles = (int)((f.M + G - 1) / G);
-    const uint64_t total = (uint64_t)c.params.L * sh.chunks * f.K * mtiles * f.R;
-    int per_cu = 0, cus = 0;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mac_sk<G>, 256, 0);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device);
-    uint64_t grid = (uint64_t)(per_cu > 0 ? per_cu : 1) * (uint64_t)(cus > 0 ? cus : 1) * waves;
-    uint64_t per = (total + grid - 1) / grid;
-    const uint64_t min_per = (f.R + 10) / 11;  // at most 12 pieces per tile
-    if (per < min_per) per = min_per;
-    grid = (total + per - 1) / per;
-    const size_t acc_n = (size_t)f.O * 2 * c.params.L * c.params.N;
-    hipLaunchKernelGGL(k_fill_zero, dim3(1024), dim3(256), 0, s, Ah, acc_n);
-    ProfScope prof("mac", s);
-    hipLaunchKernelGGL(k_mac_sk<G>, dim3((unsigned)grid), dim3(256), 0, s, Wt, Ct, Ah, sh, mtiles,
-                       total, per, c.dp);
-    return check_hip(hipGetLastError(), "mac launch");
-}
-
-int launch_mac(const Ctx &c, const pimm_plan_info &f, int G, int waves, const double *Wt,
-               const double *Ct, double *Ah, hipStream_t s)
-{
-    switch (G) {
-    case 4: return launch_mac_g<4>(c, f, waves, Wt, Ct, Ah, s);
-    case 16: return launch_mac_g<16>(c, f, waves, Wt, Ct, Ah, s);
-    default: return launch_mac_g<8>(c, f, waves, Wt, Ct, Ah, s);
-    }
-}
-
 // ---- re-randomisation, mask and extraction --------------------------------------
 
 // Pointwise u^[o][l] * pk^[comp][l] for polynomials [O][2][L].
@@ -204,42 +132,76 @@ struct LoadAccRerand {
     }
 };
 
+// n / d for n * d < 2^32 by one multiply-high: M = ceil(2^32 / d) (d = 1 is kept apart,
+// its M would not fit in 32 bits).
+struct FastDiv {
+    uint32_t d, M;
+    static FastDiv make(uint32_t d)
+    {
+        return FastDiv{d, d == 1 ? 0u : (uint32_t)(((1ull << 32) + d - 1) / d)};
+    }
+    __device__ __forceinline__ uint32_t div(uint32_t n) const { return d == 1 ? n : __umulhi(n, M); }
+    __device__ __forceinline__ uint32_t mod(uint32_t n) const { return n - div(n) * d; }
+};
+
 // Coefficient j of component comp, prime l of output ciphertext y: add the
 // re-randomisation error, then write c1 (comp 1, every j) or, at a decoded
-// position (comp 0), c0 - Delta_l s_y[j] and the server's share s_y[j].
-struct StoreShare {
-    uint64_t *c1, *c0s, *share;
+// position (comp 0), the unmasked c0 into its reply slot.
+struct StoreReply {
+    uint64_t *c1, *c0s;
     const int64_t *e;  // [O][2][N]
-    Key key;
-    uint32_t op;
-    uint32_t mb, rb, nb, K, n, m;
-    uint64_t delta[kMaxL];
-    int logn, L, rr, ell;
+    FastDiv rb, mbrb, mb;
+    uint32_t nb;
+    int logn, L, rr;
     __device__ void operator()(int poly, int l, int j, double v, double p, double pinv) const
     {
         const uint64_t q = (uint64_t)p;
         const uint32_t y = (uint32_t)(poly / (2 * L)), comp = (uint32_t)((poly / L) % 2);
+        const uint32_t uj = (uint32_t)j;
+        if (comp == 0) {
+            if (rb.mod(uj) != rb.d - 1) return;
+            if (mbrb.div(uj) >= nb) return;
+        }
         uint64_t x = to_canonical(v, p, pinv);
         if (rr) x = add_mod(x, lift_signed(e[(((size_t)y * 2 + comp) << logn) + j], q), q);
         if (comp == 1) {
             c1[(((size_t)y * L + l) << logn) + j] = x;
             return;
         }
-        const uint32_t uj = (uint32_t)j;
-        if (uj % rb != rb - 1) return;
-        const uint32_t i = (uj / rb) % mb, k = uj / (mb * rb);
-        if (k >= nb) return;
-        uint32_t w[16];
-        chacha_block(key, uj / 8, nonce0(kTagMask, 0), op, y, w);
-        const uint64_t sm = mask_of(word64(w, (int)(uj % 8)), ell);
-        c0s[((size_t)y * L + l) * mb * nb + k * mb + i] = sub_mod(x, mul_mod(delta[l], sm, p, pinv), q);
-        if (l == 0) {
-            const uint32_t ib = y / K, kb = y % K;
-            const uint32_t row = kb * nb + k, col = ib * mb + i;
-            if (row < n && col < m) share[(size_t)row * m + col] = sm;
-        }
+        const uint32_t k = mbrb.div(uj), i = mb.mod(rb.div(uj));
+        c0s[((size_t)y * L + l) * mb.d * nb + k * mb.d + i] = x;
     }
 };
+
+// The mask of output ciphertext y over Z_t: one thread per ChaCha20 block b of
+// stream (MASK, 0, op, y), i.e. coefficient positions 8b .. 8b+7; at each decoded
+// position pos = k*mb*rb + i*rb + rb-1: c0s[y][l][k*mb + i] -= Delta_l s (all
+// primes) and the server's share is s.
+__global__ void k_mask_reply(Key key, uint32_t op, uint64_t *c0s, uint64_t *share, uint32_t blocks,
+                             pimm_plan_info f, DevParams dp)
+{
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (size_t)f.O * blocks) return;
+    const uint32_t y = (uint32_t)(gid / blocks), b = (uint32_t)(gid % blocks);
+    uint32_t w[16];
+    chacha_block(key, b, nonce0(kTagMask, 0), op, y, w);
+    const uint32_t per = f.mb * f.nb;
+    const uint32_t ib = y / f.K, kb = y % f.K;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const uint32_t pos = b * 8 + t;
+        if (pos % f.rb != f.rb - 1) continue;
+        const uint32_t k = pos / (f.mb * f.rb), i = (pos / f.rb) % f.mb;
+        if (k >= f.nb) continue;
+        const uint64_t sm = mask_of(word64(w, t), dp.ell);
+        for (int l = 0; l < dp.L; ++l) {
+            uint64_t *dst = c0s + ((size_t)y * dp.L + l) * per + k * f.mb + i;
+            *dst = sub_mod(*dst, mul_mod(dp.delta[l], sm, dp.p[l], dp.pinv[l]), dp.q[l]);
+        }
+        const uint32_t row = kb * f.nb + k, col = ib * f.mb + i;
+        if (row < f.n && col < f.m) share[(size_t)row * f.m + col] = sm;
+    }
+}
 
 }  // namespace pimm
 
@@ -418,10 +380,17 @@ int pimm_matmul_share(const pimm_plan *plan, const pimm_weights *w, const uint64
         if (!rc) rc = launch_fwd(c, LoadI64Shared{u, lg, (int)L}, StoreSlots{uh, lg}, (int)(f.O * L), s);
     }
     if (!rc) {
-        StoreShare st{c1, c0s, server_share, e, key, op_id, f.mb, f.rb, f.nb, f.K, f.n, f.m,
-                      {0, 0, 0, 0}, lg, (int)L, rr, c.dp.ell};
-        for (size_t l = 0; l < L; ++l) st.delta[l] = c.dp.delta[l];
+        StoreReply st{c1, c0s, e, FastDiv::make(f.rb), FastDiv::make(f.mb * f.rb), FastDiv::make(f.mb),
+                      f.nb, lg, (int)L, rr};
         rc = launch_inv(c, LoadAccRerand{ah, uh, pkh, lg, (int)L, rr}, st, (int)(f.O * 2 * L), s);
+    }
+    if (!rc) {
+        const uint32_t blocks = (f.mb * f.rb * f.nb + 7) / 8;
+        const size_t total = (size_t)f.O * blocks;
+        ProfScope prof("mask_extract", s);
+        hipLaunchKernelGGL(k_mask_reply, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, key,
+                           op_id, c0s, server_share, blocks, f, c.dp);
+        rc = check_hip(hipGetLastError(), "mask_reply launch");
     }
     return rc;
 }

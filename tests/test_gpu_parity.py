@@ -293,7 +293,8 @@ def test_full_size_bert_large_op(orc):
     check_layer_op(orc, ctx, pyp, wl, dict(d_fix=1024), 200)
 
 
-@pytest.mark.parametrize("name", ["single", "single_norr", "ragged_explicit", "n8192_l3", "fix256"])
+@pytest.mark.parametrize("name", ["single", "single_norr", "ragged_explicit", "n8192_l3", "fix256",
+                                  "scalar", "n4096_l1"])
 def test_fused_server_step_equals_two_calls(orc, name):
     """pimm_matmul_share gives the bytes of pimm_matmul followed by pimm_mask_share."""
     c = CASES[name]
