@@ -248,9 +248,9 @@ def main():
     ap.add_argument("--d-fix", type=int, default=32)
     ap.add_argument("--layers", type=int, default=12)
     ap.add_argument("--serve-budget-gb", type=float, default=48.0)
-    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-max-active", type=int, default=32)
-    ap.add_argument("--serve-rate0", type=float, default=2.0)
+    ap.add_argument("--serve-rate0", type=float, default=4.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
