@@ -59,7 +59,7 @@ def measured_traffic(schedules):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
     h = hashlib.sha256(b"".join(open(f, "rb").read() for f in MAC_SOURCES)).hexdigest()
-    want = ";".join(f"{g},{w}" for g, w in schedules)
+    want = ";".join(",".join(str(v) for v in sch) for sch in schedules)
     if fields.get("mac_sources_sha256") != h or fields.get("product_schedules") != want:
         return None
     try:
@@ -145,6 +145,18 @@ def bench_batch(args):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / reps
 
+    # The plain form runs each product with its own autotuned schedule (one tuning per
+    # distinct plan shape).
+    tuned = {}
+    for plan, w, ct, acc in rows:
+        key = (plan.r, plan.m, plan.n)
+        if key not in tuned:
+            plan.autotune(w, ct, acc, reps=1)
+            tuned[key] = plan.tuning()
+        plan.set_tuning(*tuned[key])
+    torch.cuda.synchronize()
+    log(f"plain form: {len(tuned)} plan shapes autotuned")
+
     def plain():
         for plan, w, ct, acc in rows:
             pimm.matmul(plan, w, ct, acc)
@@ -165,7 +177,7 @@ def bench_batch(args):
         batch.run(ws=ws, stream=s)
     graph_t = timed(g.replay, args.steps)
     batch.status(ws=ws)
-    sched = dict(zip(("schedule", "mac_rows", "xcd_map", "grid"), batch.schedule))
+    sched = dict(zip(("schedule", "mac_rows", "mac_cols", "xcd_map", "grid"), batch.get_schedule()))
     return {"workload": f"{len(rows)} products, seq uniform in [16, 512], BERT-base shapes, "
                         f"N=4096, 2 primes, block area {args.d_fix}",
             "useful_macs": useful, "plain_ms": t_plain * 1e3, "batched_ms": t_batch * 1e3,
@@ -230,6 +242,42 @@ def bench_serve(args):
             "sweep": sweep, "one_at_a_time": one}
 
 
+def bench_peak(args):
+    """Sustained device rates next to the published peaks: the HBM read and copy
+    bandwidth of plain streaming kernels (and of torch's own sum and copy), the FP64
+    fma rate, and the modular-product rates of the FP64 form the library uses and of
+    the 64-bit integer Barrett and Shoup forms."""
+    import torch
+
+    from paper_2305_18396_amd import pimm
+
+    out = {"spec_hbm_GBps": HBM_PEAK_GBS, "spec_fp64_TFLOPs": 78.6}
+    gib = 1 << 30
+    out["read_GBps"] = pimm.probe(pimm.PROBE_READ, 8 * gib, args.steps) / 1e9
+    out["copy_GBps"] = pimm.probe(pimm.PROBE_COPY, 4 * gib, args.steps) / 1e9
+    out["fma64_TFLOPs"] = pimm.probe(pimm.PROBE_FMA64, 4096, args.steps) / 1e12
+    out["modmul_f64_G_per_s"] = pimm.probe(pimm.PROBE_MODMUL_F64, 4096, args.steps) / 1e9
+    out["modmul_barrett_u64_G_per_s"] = pimm.probe(pimm.PROBE_MODMUL_BARRETT, 1024, args.steps) / 1e9
+    out["modmul_shoup_u64_G_per_s"] = pimm.probe(pimm.PROBE_MODMUL_SHOUP, 1024, args.steps) / 1e9
+    x = torch.ones((8 * gib) // 8, dtype=torch.float64, device="cuda")
+    x.sum()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        x.sum()
+    torch.cuda.synchronize()
+    out["torch_sum_GBps"] = 8 * gib / ((time.perf_counter() - t0) / args.steps) / 1e9
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    out["torch_copy_GBps"] = 2 * 8 * gib / ((time.perf_counter() - t0) / args.steps) / 1e9
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -241,7 +289,11 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the timed steps, copy a buffer of this many MiB device to device "
                          "(a known-size reference for hardware byte counters)")
-    ap.add_argument("--workload", choices=["layer", "batch", "serve"], default="layer")
+    ap.add_argument("--workload", choices=["layer", "batch", "serve", "peak"], default="layer")
+    ap.add_argument("--layer-d", type=int, default=0,
+                    help="layer workload: fixed block area m_b*r_b (0: the fewest-wire plan)")
+    ap.add_argument("--schedules", default="",
+                    help="product schedules 'rows,cols,waves;...' per product (skips the autotuner)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default product schedule instead of autotuning it per product")
     ap.add_argument("--batch-count", type=int, default=64)
@@ -265,6 +317,9 @@ def main():
     if args.workload == "batch":
         print(json.dumps({"metric": METRIC, "batch": bench_batch(args)}), flush=True)
         return
+    if args.workload == "peak":
+        print(json.dumps({"metric": METRIC, "peak": bench_peak(args)}), flush=True)
+        return
     if args.workload == "serve":
         print(json.dumps({"metric": METRIC, "serve": bench_serve(args)}), flush=True)
         return
@@ -276,11 +331,10 @@ def main():
     cseed, sseed = workloads.seed("client", 1), workloads.seed("server", 1)
     sk, pk = pimm.keygen(ctx, cseed)
     state = []
-    useful = 0
-    mac_bytes = 0
+    useful = mac_bytes = slot_macs = butterflies = wire = cache = 0
     for i, wl in enumerate(ops):
         n, r, m = wl.shape
-        plan = pimm.Plan(ctx, n, r, m)
+        plan = pimm.Plan(ctx, n, r, m, d_fix=args.layer_d)
         w = pimm.Weights(plan, pimm.to_device_u64(wl.W))
         fi = plan.info
         st = dict(
@@ -294,16 +348,23 @@ def main():
             y1=torch.empty((n, m), dtype=torch.int64, device=dev),
             ws=plan.workspace(), op=i)
         state.append(st)
-        if not args.no_autotune:
+        if args.schedules:
+            plan.set_tuning(*(int(v) for v in args.schedules.split(";")[i].split(",")))
+        elif not args.no_autotune:
             # The product's schedule is picked by the library's autotuner on these buffers.
             ct0 = pimm.encrypt(plan, sk, cseed, 10_000 + i, pimm.encode_input(plan, st["X"]))
             acc0 = torch.empty((fi.O, 2, L, N), dtype=torch.int64, device=dev)
             best = plan.autotune(w, ct0, acc0, reps=2)
             st["tuning"] = plan.tuning()
-            log(f"  autotuned product schedule (rows, grid waves) = {st['tuning']}: {best:.3f} ms")
+            log(f"  autotuned product schedule (rows, column blocks, grid waves) = {st['tuning']}: "
+                f"{best:.3f} ms")
             del ct0, acc0
         useful += n * r * m
         mac_bytes += (fi.Wb + 2 * fi.I + 2 * fi.O) * L * N * 8
+        slot_macs += 2 * L * N * fi.P
+        butterflies += L * (N // 2) * (N.bit_length() - 1) * (2 * fi.I + 2 * fi.O)
+        wire += fi.ct_bytes + fi.c1_bytes + fi.c0s_bytes
+        cache += fi.weights_bytes
         log(f"{wl.name}: plan ({fi.mb},{fi.rb},{fi.nb}) I={fi.I} O={fi.O} Wb={fi.Wb} "
             f"weights {fi.weights_bytes / 1e9:.2f} GB")
     torch.cuda.synchronize()
@@ -378,13 +439,18 @@ def main():
         "config": {
             "workload": f"BERT-base-shaped linear layer, seq {args.seq}: QKV 768x2304, "
                         "attn-out 768x768, FFN 768x3072 and 3072x768; RNS-BFV N=4096, "
-                        "2x50-bit primes, t=2^37, 12 fractional bits; fewest-wire plan; "
-                        "weight cache built at load",
+                        "2x50-bit primes, t=2^37, 12 fractional bits; "
+                        + ("fewest-wire plan" if not args.layer_d else
+                           f"fixed block area {args.layer_d}") + "; weight cache built at load",
             "global_batch": 1, "seq_len": args.seq, "parallelism": "single GPU",
             "plans": [[s["plan"].mb, s["plan"].rb, s["plan"].nb] for s in state],
             "product_schedules": [list(s["plan"].tuning()) for s in state],
             "useful_macs_per_step": useful,
         },
+        "slot_mac_per_s": slot_macs * args.steps / elapsed,
+        "server_ntt_butterflies_per_s": butterflies * args.steps / elapsed,
+        "wire_bytes_per_step": wire,
+        "weight_cache_bytes": cache,
         "layer_latency_ms": {"p50": float(np.percentile(lat, 50)),
                              "p99": float(np.percentile(lat, 99)), "samples": len(lat)},
         "kernels": kernels,

@@ -143,13 +143,15 @@ int pimm_plan_create(pimm_ctx *ctx, uint32_t n, uint32_t r, uint32_t m, uint32_t
                      uint32_t nb, uint32_t d_fix, pimm_plan **out);
 int pimm_plan_destroy(pimm_plan *plan);
 int pimm_plan_query(const pimm_plan *plan, pimm_plan_info *info);
-/* Schedule of pimm_matmul's slot-wise products: mac_rows (4, 8, 16) output rows per
- * thread; the (tile, inner block) iterations are divided evenly over a grid of
- * `splits` (1, 2, 4) times the workgroups the device holds at once.  Any schedule
- * gives the same bytes. */
-int pimm_plan_set_tuning(pimm_plan *plan, int mac_rows, int splits);
-int pimm_plan_get_tuning(const pimm_plan *plan, int *mac_rows, int *splits);
-/* Time every (mac_rows, splits) on these buffers with HIP events on `stream`
+/* Schedule of pimm_matmul's slot-wise products: each thread owns mac_rows output
+ * rows by mac_cols output column blocks (rows x cols one of 4x1, 8x1, 16x1, 4x2,
+ * 8x2, 2x4, 4x4), so that a weight word it loads serves mac_cols column blocks;
+ * the (tile, inner block) iterations are divided evenly over a grid of `waves`
+ * (1, 2, 4) times the workgroups the device holds at once.  Any schedule gives
+ * the same bytes. */
+int pimm_plan_set_tuning(pimm_plan *plan, int mac_rows, int mac_cols, int waves);
+int pimm_plan_get_tuning(const pimm_plan *plan, int *mac_rows, int *mac_cols, int *waves);
+/* Time every (mac_rows, mac_cols, waves) on these buffers with HIP events on `stream`
  * (`reps` timed runs each) and keep the fastest on the plan; best_ms may be NULL. */
 int pimm_plan_autotune(pimm_plan *plan, const pimm_weights *w, const uint64_t *ct, uint64_t *acc,
                        void *ws, size_t ws_bytes, int reps, void *stream, double *best_ms);
@@ -244,15 +246,19 @@ int pimm_batch_destroy(pimm_batch *batch);
 int pimm_batch_query(const pimm_batch *batch, uint64_t *workspace_bytes, uint64_t *useful_macs);
 /* Schedule: schedule 0 = three launches (all forward NTTs, all slot-wise products,
  * all inverse NTTs); 1 = one persistent launch whose workgroups take units from an
- * atomic queue in dependency order, with bounded waits.  mac_rows (4, 8 or 16) is
- * the number of output rows a product thread owns; xcd_map != 0 places consecutive
- * product tiles on one XCD; grid = persistent workgroups (0: fill the device). */
-int pimm_batch_set_schedule(pimm_batch *batch, int schedule, int mac_rows, int xcd_map,
-                            uint32_t grid);
+ * atomic queue in dependency order, with bounded waits.  mac_rows x mac_cols is the
+ * product tile a thread owns (as pimm_plan_set_tuning); xcd_map != 0 places
+ * consecutive product tiles on one XCD; grid = persistent workgroups (0: fill the
+ * device). */
+int pimm_batch_set_schedule(pimm_batch *batch, int schedule, int mac_rows, int mac_cols,
+                            int xcd_map, uint32_t grid);
+/* The schedule in force (after pimm_batch_set_schedule or pimm_batch_autotune). */
+int pimm_batch_get_schedule(const pimm_batch *batch, int *schedule, int *mac_rows, int *mac_cols,
+                            int *xcd_map, uint32_t *grid);
 /* Run every product of the batch on `stream` (plain kernel launches only, so the
  * call can be captured into a hipGraph and replayed; one run at a time per workspace). */
 int pimm_batch_matmul(const pimm_batch *batch, void *ws, size_t ws_bytes, void *stream);
-/* Time the batch under each schedule candidate (phased / persistent, rows per thread,
+/* Time the batch under each schedule candidate (phased / persistent, product tile,
  * XCD placement) with HIP events on `stream` and keep the fastest. */
 int pimm_batch_autotune(pimm_batch *batch, void *ws, size_t ws_bytes, int reps, void *stream,
                         double *best_ms);
@@ -267,8 +273,8 @@ int pimm_batch_status(const pimm_batch *batch, const void *ws, void *stream);
  * d_fix (same r, m, mb, rb), which makes one cache serve every sequence length.
  * hbm_budget: device bytes the server allocates once and hands to requests
  * (key, ciphertexts, accumulators, reply, scratch); max_active: most requests in
- * flight; schedule / mac_rows: the batched product's schedule (as
- * pimm_batch_set_schedule; mac_rows 0 means 8). */
+ * flight; schedule / mac_rows / mac_cols: the batched product's schedule (as
+ * pimm_batch_set_schedule; mac_rows 0 means 8, mac_cols 0 means 1). */
 typedef struct {
     uint32_t layers, ops;
     const uint32_t *d_in, *d_out;
@@ -277,7 +283,7 @@ typedef struct {
     uint64_t hbm_budget;
     uint32_t max_active;
     int32_t schedule;
-    uint32_t mac_rows;
+    uint32_t mac_rows, mac_cols;
 } pimm_serve_config;
 
 /* A request: unique id, sequence length, arrival time in seconds from the start of

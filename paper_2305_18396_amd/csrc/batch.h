@@ -14,7 +14,7 @@ struct BatchItemDev {
     uint64_t chat_off;   // doubles into the workspace: c^ [I][2][L][N]
     uint64_t ahat_off;   // acc^ [O][2][L][N]
     uint32_t M, R, K, I, O;
-    uint32_t mtiles;            // ceil(M / G)
+    uint32_t mtiles, ktiles;    // ceil(M / G), ceil(K / KB)
     uint32_t in0, mac0, out0;   // first unit of each kind
     uint32_t dep_in0, dep_mac0; // first dependency counter of each kind
 };
@@ -31,7 +31,8 @@ enum Schedule : int { kPhased = 0, kPersistent = 1 };
 struct pimm_batch {
     pimm::Ctx *ctx = nullptr;
     std::vector<pimm_batch_item> items;
-    int G = 8;
+    int G = 8;   // product rows per thread
+    int KB = 1;  // product column blocks per thread
     int schedule = pimm::kPhased;
     int xcd_map = 1;
     uint32_t grid = 0;          // persistent grid size (0: from occupancy)

@@ -4,16 +4,16 @@
 // items of any shapes and sequence lengths on one context.  Its work is the
 // union of three kinds of units:
 //   in   forward NTT of one input polynomial      (sum over items of I*2*L)
-//   mac  one slot-chunk x row-tile x column-block  (sum of (N/256)*L*ceil(M/G)*K)
+//   mac  one slot-chunk x row tile x column tile   (sum of (N/256)*L*ceil(M/G)*ceil(K/KB))
 //   out  inverse NTT of one accumulator polynomial (sum of O*2*L)
 // Two schedules run them:
 //   PHASED      three launches (all in, all mac, all out), each over a flat
 //               list of units of every item;
 //   PERSISTENT  one launch of a resident grid that takes units from an atomic
 //               counter in dependency order (in, then mac, then out).  A mac
-//               unit waits until the 2R input NTTs of its column block and
-//               prime are done; an out unit waits until the N/256 slot chunks
-//               of its row tile are done.  Every unit it waits for was taken
+//               unit waits until the 2R input NTTs of each column block of its
+//               column tile and prime are done; an out unit waits until the
+//               N/256 slot chunks of its (row tile, column tile) are done.  Every unit it waits for was taken
 //               earlier by a running workgroup that itself only waits on
 //               earlier units, so the waits always end; each wait is also
 //               bounded (a spin limit sets an error flag and every later wait
@@ -64,29 +64,29 @@ __device__ __forceinline__ void run_out(const BatchItemDev &it, int poly, double
     ntt_inv_block<LOGN>(LoadSlots{ws + it.ahat_off, LOGN}, StoreU64{it.acc, LOGN}, dp, poly, lds);
 }
 
-// mac unit t of an item -> (l, slot chunk, row tile, column block); row tiles vary fastest.
+// mac unit t of an item -> (l, slot chunk, row tile, column tile); row tiles vary fastest.
 struct MacCoord {
-    int l, zc, ibt, kb;
+    int l, zc, ibt, kbt;
 };
 __device__ __forceinline__ MacCoord mac_coord(const BatchItemDev &it, uint32_t t, int chunks)
 {
     MacCoord c;
     c.ibt = (int)(t % it.mtiles);
     t /= it.mtiles;
-    c.kb = (int)(t % it.K);
-    t /= it.K;
+    c.kbt = (int)(t % it.ktiles);
+    t /= it.ktiles;
     c.zc = (int)(t % chunks);
     c.l = (int)(t / chunks);
     return c;
 }
 
-template <int G>
+template <int G, int KB>
 __device__ __forceinline__ void run_mac(const BatchItemDev &it, const MacCoord &c, double *ws,
                                         const DevParams &dp)
 {
     const MacShape sh{(int)it.M, (int)it.R, (int)it.K, dp.N >> 8};
-    mac_range<G>(it.wh, ws + it.chat_off, ws + it.ahat_off, sh, dp, c.l, c.zc, c.kb, c.ibt * G, 0,
-                 (int)it.R, 0);
+    mac_range<G, KB>(it.wh, ws + it.chat_off, ws + it.ahat_off, sh, dp, c.l, c.zc, c.kbt * KB,
+                     c.ibt * G, 0, (int)it.R, 0);
 }
 
 // ---- phased schedule ---------------------------------------------------------------
@@ -101,13 +101,13 @@ __global__ __launch_bounds__(kNttThreads) void k_batch_in(const BatchItemDev *it
     run_in<LOGN>(it, (int)(u - it.in0), ws, dp, lds);
 }
 
-template <int G>
+template <int G, int KB>
 __global__ __launch_bounds__(256) void k_batch_mac(const BatchItemDev *items, int n, double *ws,
                                                    int xcd_map, DevParams dp)
 {
     const uint32_t u = xcd_map ? xcd_local(blockIdx.x, gridDim.x) : blockIdx.x;
     const BatchItemDev &it = items[find_item(items, n, u, 1)];
-    run_mac<G>(it, mac_coord(it, u - it.mac0, dp.N >> 8), ws, dp);
+    run_mac<G, KB>(it, mac_coord(it, u - it.mac0, dp.N >> 8), ws, dp);
 }
 
 template <int LOGN>
@@ -146,7 +146,7 @@ __device__ __forceinline__ bool wait_for(uint32_t *ctr, uint32_t idx, uint32_t t
     return true;
 }
 
-template <int LOGN, int G>
+template <int LOGN, int G, int KB>
 __global__ __launch_bounds__(kNttThreads) void k_batch_fused(const BatchItemDev *items, int n,
                                                              double *ws, uint32_t *ctr,
                                                              uint32_t n_in, uint32_t n_mac,
@@ -172,25 +172,29 @@ __global__ __launch_bounds__(kNttThreads) void k_batch_fused(const BatchItemDev 
             const int poly = (int)(u - it.in0);
             run_in<LOGN>(it, poly, ws, dp, lds);
             const int x = poly / (2 * L), l = poly % L;
-            sig = it.dep_in0 + (uint32_t)((x % (int)it.K) * L + l);
+            sig = it.dep_in0 + (uint32_t)(((x % (int)it.K) / KB) * L + l);
         } else if (u < n_in + n_mac) {
             const uint32_t v = u - n_in;
             const BatchItemDev &it = items[find_item(items, n, v, 1)];
             const MacCoord c = mac_coord(it, v - it.mac0, chunks);
+            // Every input NTT of the column tile's blocks for this prime.
+            const int left = (int)it.K - c.kbt * KB;
+            const uint32_t cols = (uint32_t)(left < KB ? left : KB);
             if (threadIdx.x == 0)
-                s_ok = wait_for(ctr, it.dep_in0 + (uint32_t)(c.kb * L + c.l), 2 * it.R, spin_limit);
+                s_ok = wait_for(ctr, it.dep_in0 + (uint32_t)(c.kbt * L + c.l), 2 * it.R * cols,
+                                spin_limit);
             __syncthreads();
             __threadfence();
-            if (s_ok) run_mac<G>(it, c, ws, dp);
-            sig = it.dep_mac0 + (uint32_t)(((c.ibt * (int)it.K) + c.kb) * L + c.l);
+            if (s_ok) run_mac<G, KB>(it, c, ws, dp);
+            sig = it.dep_mac0 + (uint32_t)(((c.ibt * (int)it.ktiles) + c.kbt) * L + c.l);
         } else {
             const uint32_t v = u - n_in - n_mac;
             const BatchItemDev &it = items[find_item(items, n, v, 2)];
             const int poly = (int)(v - it.out0);
             const int y = poly / (2 * L), l = poly % L;
-            const int ibt = (y / (int)it.K) / G, kb = y % (int)it.K;
+            const int ibt = (y / (int)it.K) / G, kbt = (y % (int)it.K) / KB;
             if (threadIdx.x == 0)
-                s_ok = wait_for(ctr, it.dep_mac0 + (uint32_t)((ibt * (int)it.K + kb) * L + l),
+                s_ok = wait_for(ctr, it.dep_mac0 + (uint32_t)((ibt * (int)it.ktiles + kbt) * L + l),
                                 (uint32_t)chunks, spin_limit);
             __syncthreads();
             __threadfence();
@@ -234,15 +238,16 @@ int build_tables(pimm_batch *b, bool async, hipStream_t s)
         d.I = f.I;
         d.O = f.O;
         d.mtiles = (f.M + b->G - 1) / b->G;
+        d.ktiles = (f.K + b->KB - 1) / b->KB;
         d.in0 = in0;
         d.mac0 = mac0;
         d.out0 = out0;
         d.dep_in0 = dep;
-        dep += f.K * (uint32_t)L;
+        dep += d.ktiles * (uint32_t)L;
         d.dep_mac0 = dep;
-        dep += d.mtiles * f.K * (uint32_t)L;
+        dep += d.mtiles * d.ktiles * (uint32_t)L;
         in0 += f.I * 2 * (uint32_t)L;
-        mac0 += chunks * (uint32_t)L * d.mtiles * f.K;
+        mac0 += chunks * (uint32_t)L * d.mtiles * d.ktiles;
         out0 += f.O * 2 * (uint32_t)L;
         b->useful_macs += (uint64_t)f.n * f.r * f.m;
     }
@@ -290,7 +295,7 @@ int build_tables(pimm_batch *b, bool async, hipStream_t s)
                      "copy batch table");
 }
 
-template <int LOGN, int G>
+template <int LOGN, int G, int KB>
 int run_batch(const pimm_batch *b, void *ws, hipStream_t s)
 {
     const Ctx &c = *b->ctx;
@@ -304,8 +309,8 @@ int run_batch(const pimm_batch *b, void *ws, hipStream_t s)
         }
         {
             ProfScope prof("mac", s);
-            hipLaunchKernelGGL(k_batch_mac<G>, dim3(b->n_mac), dim3(256), 0, s, b->d_items, n, wsd,
-                               b->xcd_map, c.dp);
+            hipLaunchKernelGGL((k_batch_mac<G, KB>), dim3(b->n_mac), dim3(256), 0, s, b->d_items, n,
+                               wsd, b->xcd_map, c.dp);
         }
         {
             ProfScope prof("ntt_inv", s);
@@ -319,7 +324,7 @@ int run_batch(const pimm_batch *b, void *ws, hipStream_t s)
     uint32_t grid = b->grid;
     if (!grid) {
         int per_cu = 0;
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_fused<LOGN, G>,
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_fused<LOGN, G, KB>,
                                                            kNttThreads, 0);
         int cus = 0;
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device);
@@ -329,7 +334,7 @@ int run_batch(const pimm_batch *b, void *ws, hipStream_t s)
     if (grid > total) grid = total;
     {
         ProfScope prof("fused", s);
-        hipLaunchKernelGGL((k_batch_fused<LOGN, G>), dim3(grid), dim3(kNttThreads), 0, s, b->d_items,
+        hipLaunchKernelGGL((k_batch_fused<LOGN, G, KB>), dim3(grid), dim3(kNttThreads), 0, s, b->d_items,
                            n, wsd, ctr, b->n_in, b->n_mac, b->n_out, b->spin_limit, c.dp);
     }
     return check_hip(hipGetLastError(), "batch fused launch");
@@ -338,11 +343,11 @@ int run_batch(const pimm_batch *b, void *ws, hipStream_t s)
 template <int LOGN>
 int run_batch_g(const pimm_batch *b, void *ws, hipStream_t s)
 {
-    switch (b->G) {
-    case 4: return run_batch<LOGN, 4>(b, ws, s);
-    case 16: return run_batch<LOGN, 16>(b, ws, s);
-    default: return run_batch<LOGN, 8>(b, ws, s);
-    }
+#define PIMM_RUN_BATCH(g, kb) \
+    if (b->G == g && b->KB == kb) return run_batch<LOGN, g, kb>(b, ws, s);
+    PIMM_MAC_SHAPES(PIMM_RUN_BATCH)
+#undef PIMM_RUN_BATCH
+    return set_error(PIMM_E_ARG, "product tile %dx%d is not built", b->G, b->KB);
 }
 
 }  // namespace
@@ -391,20 +396,36 @@ int pimm_batch_destroy(pimm_batch *b)
     return PIMM_OK;
 }
 
-int pimm_batch_set_schedule(pimm_batch *b, int schedule, int mac_rows, int xcd_map, uint32_t grid)
+int pimm_batch_set_schedule(pimm_batch *b, int schedule, int mac_rows, int mac_cols, int xcd_map,
+                            uint32_t grid)
 {
     if (!b) return set_error(PIMM_E_ARG, "pimm_batch_set_schedule: NULL batch");
     if (schedule != kPhased && schedule != kPersistent)
         return set_error(PIMM_E_ARG, "schedule %d is not 0 (phased) or 1 (persistent)", schedule);
-    if (mac_rows != 4 && mac_rows != 8 && mac_rows != 16)
-        return set_error(PIMM_E_ARG, "mac_rows %d is not 4, 8 or 16", mac_rows);
+    if (!mac_shape_ok(mac_rows, mac_cols))
+        return set_error(PIMM_E_ARG, "product tile %d rows x %d column blocks is not built",
+                         mac_rows, mac_cols);
     b->schedule = schedule;
     b->xcd_map = xcd_map ? 1 : 0;
     b->grid = grid;
-    if (mac_rows != b->G) {
+    if (mac_rows != b->G || mac_cols != b->KB) {
         b->G = mac_rows;
+        b->KB = mac_cols;
         return build_tables(b, false, nullptr);
     }
+    return PIMM_OK;
+}
+
+int pimm_batch_get_schedule(const pimm_batch *b, int *schedule, int *mac_rows, int *mac_cols,
+                            int *xcd_map, uint32_t *grid)
+{
+    if (!b || !schedule || !mac_rows || !mac_cols || !xcd_map || !grid)
+        return set_error(PIMM_E_ARG, "pimm_batch_get_schedule: NULL argument");
+    *schedule = b->schedule;
+    *mac_rows = b->G;
+    *mac_cols = b->KB;
+    *xcd_map = b->xcd_map;
+    *grid = b->grid;
     return PIMM_OK;
 }
 

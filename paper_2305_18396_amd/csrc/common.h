@@ -220,8 +220,9 @@ struct Ctx {
 struct Plan {
     Ctx *ctx = nullptr;
     pimm_plan_info info;
-    int mac_rows = 8;  // output rows per product thread (4, 8, 16)
-    int splits = 1;    // product grid = splits x the workgroups the device holds at once
+    int mac_rows = 8;  // output rows per product thread
+    int mac_cols = 1;  // output column blocks per product thread
+    int waves = 1;     // product grid = waves x the workgroups the device holds at once
 };
 
 struct SecretKey {
@@ -262,7 +263,7 @@ class ProfScope {
 
 // Launch helpers implemented in the kernel translation units.
 // Slot-wise products of one plan into zeroed-then-accumulated acc^ (mac.hip).
-int launch_mac(const Ctx &c, const pimm_plan_info &f, int G, int waves, const double *Wt,
+int launch_mac(const Ctx &c, const pimm_plan_info &f, int G, int KB, int waves, const double *Wt,
                const double *Ct, double *Ah, hipStream_t s);
 
 }  // namespace pimm

@@ -34,86 +34,131 @@ __device__ __forceinline__ size_t c_tile_base(const MacShape &s, int l, int zc, 
     return (((size_t)l * s.chunks + zc) * s.K + kb) * (size_t)s.R * 512;
 }
 
-// Inner blocks [jb0, jb1) of one tile.  mode 0: store the reduced sums; mode 1:
-// add them atomically (exact: every addend and every partial total is an
-// integer below 2^53, so the order of the additions does not matter).
-template <int G>
+// Inner blocks [jb0, jb1) of one tile of G rows (ib0 ..) and KB column blocks
+// (kb0 ..): every weight word loaded is used for KB column blocks and every
+// input word for G rows.  mode 0: store the reduced sums; mode 1: add them
+// atomically (exact: every addend and every partial total is an integer below
+// 2^53, so the order of the additions does not matter).
+template <int G, int KB>
 __device__ __forceinline__ void mac_range(const double *__restrict__ Wt, const double *__restrict__ Ct,
                                           double *__restrict__ Ah, const MacShape &s,
-                                          const DevParams &dp, int l, int zc, int kb, int ib0, int jb0,
-                                          int jb1, int mode)
+                                          const DevParams &dp, int l, int zc, int kb0, int ib0,
+                                          int jb0, int jb1, int mode)
 {
     const int L = dp.L, N = dp.N;
     const double p = dp.p[l], pinv = dp.pinv[l];
     const int rows = s.M - ib0 < G ? s.M - ib0 : G;
+    const int cols = s.K - kb0 < KB ? s.K - kb0 : KB;
     const int zz = threadIdx.x;
     const double *wp = Wt + w_tile_base(s, l, zc) + ((size_t)ib0 * s.R + jb0) * 256 + zz;
-    const double *cp = Ct + c_tile_base(s, l, zc, kb) + (size_t)jb0 * 512 + zz;
-    const size_t wrow = (size_t)s.R * 256;
+    const double *cp = Ct + c_tile_base(s, l, zc, kb0) + (size_t)jb0 * 512 + zz;
+    const size_t wrow = (size_t)s.R * 256, ccol = (size_t)s.R * 512;
 
-    double a0[G], a1[G];
+    double a0[G][KB], a1[G][KB];
 #pragma unroll
-    for (int g = 0; g < G; ++g) a0[g] = a1[g] = 0.0;
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int k = 0; k < KB; ++k) a0[g][k] = a1[g][k] = 0.0;
 
     int jb = jb0;
     // Two inner blocks per iteration: all loads first, then the products.
     for (; jb + 1 < jb1; jb += 2) {
-        const double c00 = cp[0], c01 = cp[256], c10 = cp[512], c11 = cp[768];
+        double c00[KB], c01[KB], c10[KB], c11[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            if (k < cols) {
+                const double *ck = cp + k * ccol;
+                c00[k] = ck[0];
+                c01[k] = ck[256];
+                c10[k] = ck[512];
+                c11[k] = ck[768];
+            } else {
+                c00[k] = c01[k] = c10[k] = c11[k] = 0.0;
+            }
+        }
         double w0[G], w1[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             if (g < rows) {
-                w0[g] = wp[g * wrow];
-                w1[g] = wp[g * wrow + 256];
+                // Weight words are used once per launch: stream them past the caches.
+                w0[g] = __builtin_nontemporal_load(wp + g * wrow);
+                w1[g] = __builtin_nontemporal_load(wp + g * wrow + 256);
+            } else {
+                w0[g] = w1[g] = 0.0;
             }
         }
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            if (g < rows) {
-                a0[g] += mulmod(w0[g], c00, p, pinv);
-                a1[g] += mulmod(w0[g], c01, p, pinv);
-                a0[g] += mulmod(w1[g], c10, p, pinv);
-                a1[g] += mulmod(w1[g], c11, p, pinv);
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                a0[g][k] += mulmod(w0[g], c00[k], p, pinv);
+                a1[g][k] += mulmod(w0[g], c01[k], p, pinv);
+                a0[g][k] += mulmod(w1[g], c10[k], p, pinv);
+                a1[g][k] += mulmod(w1[g], c11[k], p, pinv);
             }
         }
         if (((jb - jb0) & 7) == 6) {
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                a0[g] = reduce(a0[g], p, pinv);
-                a1[g] = reduce(a1[g], p, pinv);
-            }
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int k = 0; k < KB; ++k) {
+                    a0[g][k] = reduce(a0[g][k], p, pinv);
+                    a1[g][k] = reduce(a1[g][k], p, pinv);
+                }
         }
         wp += 512;
         cp += 1024;
     }
     if (jb < jb1) {
-        const double c0 = cp[0], c1 = cp[256];
+        double c0[KB], c1[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            if (k < cols) {
+                c0[k] = cp[k * ccol];
+                c1[k] = cp[k * ccol + 256];
+            } else {
+                c0[k] = c1[k] = 0.0;
+            }
+        }
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            if (g < rows) {
-                const double w = wp[g * wrow];
-                a0[g] += mulmod(w, c0, p, pinv);
-                a1[g] += mulmod(w, c1, p, pinv);
+            const double w = g < rows ? __builtin_nontemporal_load(wp + g * wrow) : 0.0;
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                a0[g][k] += mulmod(w, c0[k], p, pinv);
+                a1[g][k] += mulmod(w, c1[k], p, pinv);
             }
         }
     }
     const int z = (zc << 8) + zz;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        if (g < rows) {
-            const size_t y = (size_t)(ib0 + g) * s.K + kb;
-            double *d0 = Ah + ((y * 2 + 0) * L + l) * N + z;
-            double *d1 = Ah + ((y * 2 + 1) * L + l) * N + z;
-            const double v0 = reduce(a0[g], p, pinv), v1 = reduce(a1[g], p, pinv);
-            if (mode == 0) {
-                *d0 = v0;
-                *d1 = v1;
-            } else {
-                atomicAdd(d0, v0);
-                atomicAdd(d1, v1);
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            if (g < rows && k < cols) {
+                const size_t y = (size_t)(ib0 + g) * s.K + kb0 + k;
+                double *d0 = Ah + ((y * 2 + 0) * L + l) * N + z;
+                double *d1 = Ah + ((y * 2 + 1) * L + l) * N + z;
+                const double v0 = reduce(a0[g][k], p, pinv), v1 = reduce(a1[g][k], p, pinv);
+                if (mode == 0) {
+                    *d0 = v0;
+                    *d1 = v1;
+                } else {
+                    atomicAdd(d0, v0);
+                    atomicAdd(d1, v1);
+                }
             }
         }
     }
+}
+
+// Product tile shapes (G rows, KB column blocks per thread) the library instantiates.
+#define PIMM_MAC_SHAPES(X) X(4, 1) X(8, 1) X(16, 1) X(4, 2) X(8, 2) X(2, 4) X(4, 4)
+
+__host__ __device__ constexpr bool mac_shape_ok(int G, int KB)
+{
+    return (KB == 1 && (G == 4 || G == 8 || G == 16)) || (KB == 2 && (G == 4 || G == 8)) ||
+           (KB == 4 && (G == 2 || G == 4));
 }
 
 // ---- stores into the chunk-contiguous layouts (NTT output slot z) --------------

@@ -5,17 +5,19 @@
 namespace pimm {
 
 // Stream-K schedule: the flattened space of (tile, inner block) iterations,
-// tile t = ((l * chunks + zc) * K + kb) * mtiles + ibt (row tiles fastest, so a
-// workgroup's consecutive tiles share their input slice), is cut into equal
-// contiguous ranges, one per workgroup of a grid sized to what the device
-// holds at once (ranges placed XCD by XCD).  A workgroup that covers a whole tile stores its sums; pieces
-// of split tiles are added atomically into the zeroed accumulators.  At most
-// 12 pieces meet in one accumulator, so the total stays below 8p < 2^53.
-template <int G>
+// tile t = ((l * chunks + zc) * ktiles + kbt) * mtiles + ibt (row tiles fastest,
+// so a workgroup's consecutive tiles share their input slice), is cut into
+// equal contiguous ranges, one per workgroup of a grid sized to what the device
+// holds at once (ranges placed XCD by XCD).  A workgroup that covers a whole
+// tile stores its sums; pieces of split tiles are added atomically into the
+// zeroed accumulators.  At most 12 pieces meet in one accumulator, so the total
+// stays below 8p < 2^53.
+template <int G, int KB>
 __global__ __launch_bounds__(256) void k_mac_sk(const double *__restrict__ Wt,
                                                 const double *__restrict__ Ct,
                                                 double *__restrict__ Ah, MacShape sh, int mtiles,
-                                                uint64_t total, uint64_t per, DevParams dp)
+                                                int ktiles, uint64_t total, uint64_t per,
+                                                DevParams dp)
 {
     uint64_t u = (uint64_t)xcd_local(blockIdx.x, gridDim.x) * per;
     const uint64_t end = u + per < total ? u + per : total;
@@ -26,12 +28,12 @@ __global__ __launch_bounds__(256) void k_mac_sk(const double *__restrict__ Wt,
         const int jb1 = (int)(R - (uint64_t)jb0 < end - u ? R : (uint64_t)jb0 + (end - u));
         const int ibt = (int)(t % mtiles);
         uint64_t r = t / mtiles;
-        const int kb = (int)(r % sh.K);
-        r /= sh.K;
+        const int kbt = (int)(r % ktiles);
+        r /= ktiles;
         const int zc = (int)(r % sh.chunks);
         const int l = (int)(r / sh.chunks);
         const int mode = (jb0 == 0 && jb1 == sh.R) ? 0 : 1;
-        mac_range<G>(Wt, Ct, Ah, sh, dp, l, zc, kb, ibt * G, jb0, jb1, mode);
+        mac_range<G, KB>(Wt, Ct, Ah, sh, dp, l, zc, kbt * KB, ibt * G, jb0, jb1, mode);
         u += (uint64_t)(jb1 - jb0);
     }
 }
@@ -43,15 +45,15 @@ __global__ void k_fill_zero(double *p, size_t n)
         p[i] = 0.0;
 }
 
-template <int G>
-int launch_mac_g(const Ctx &c, const pimm_plan_info &f, int waves, const double *Wt, const double *Ct,
-                 double *Ah, hipStream_t s)
+template <int G, int KB>
+int launch_mac_gk(const Ctx &c, const pimm_plan_info &f, int waves, const double *Wt,
+                  const double *Ct, double *Ah, hipStream_t s)
 {
     const MacShape sh{(int)f.M, (int)f.R, (int)f.K, (int)(c.params.N >> 8)};
-    const int mtiles = (int)((f.M + G - 1) / G);
-    const uint64_t total = (uint64_t)c.params.L * sh.chunks * f.K * mtiles * f.R;
+    const int mtiles = (int)((f.M + G - 1) / G), ktiles = (int)((f.K + KB - 1) / KB);
+    const uint64_t total = (uint64_t)c.params.L * sh.chunks * ktiles * mtiles * f.R;
     int per_cu = 0, cus = 0;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mac_sk<G>, 256, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mac_sk<G, KB>, 256, 0);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device);
     uint64_t grid = (uint64_t)(per_cu > 0 ? per_cu : 1) * (uint64_t)(cus > 0 ? cus : 1) * waves;
     uint64_t per = (total + grid - 1) / grid;
@@ -61,19 +63,19 @@ int launch_mac_g(const Ctx &c, const pimm_plan_info &f, int waves, const double 
     const size_t acc_n = (size_t)f.O * 2 * c.params.L * c.params.N;
     hipLaunchKernelGGL(k_fill_zero, dim3(1024), dim3(256), 0, s, Ah, acc_n);
     ProfScope prof("mac", s);
-    hipLaunchKernelGGL(k_mac_sk<G>, dim3((unsigned)grid), dim3(256), 0, s, Wt, Ct, Ah, sh, mtiles,
-                       total, per, c.dp);
+    hipLaunchKernelGGL((k_mac_sk<G, KB>), dim3((unsigned)grid), dim3(256), 0, s, Wt, Ct, Ah, sh,
+                       mtiles, ktiles, total, per, c.dp);
     return check_hip(hipGetLastError(), "mac launch");
 }
 
-int launch_mac(const Ctx &c, const pimm_plan_info &f, int G, int waves, const double *Wt,
+int launch_mac(const Ctx &c, const pimm_plan_info &f, int G, int KB, int waves, const double *Wt,
                const double *Ct, double *Ah, hipStream_t s)
 {
-    switch (G) {
-    case 4: return launch_mac_g<4>(c, f, waves, Wt, Ct, Ah, s);
-    case 16: return launch_mac_g<16>(c, f, waves, Wt, Ct, Ah, s);
-    default: return launch_mac_g<8>(c, f, waves, Wt, Ct, Ah, s);
-    }
+#define PIMM_LAUNCH_MAC(g, kb) \
+    if (G == g && KB == kb) return launch_mac_gk<g, kb>(c, f, waves, Wt, Ct, Ah, s);
+    PIMM_MAC_SHAPES(PIMM_LAUNCH_MAC)
+#undef PIMM_LAUNCH_MAC
+    return set_error(PIMM_E_ARG, "product tile %dx%d is not built", G, KB);
 }
 
 }  // namespace pimm

@@ -34,6 +34,7 @@
 
 #include "batch.h"
 #include "common.h"
+#include "mac.h"
 
 namespace pimm {
 
@@ -242,6 +243,12 @@ int pimm_serve_create(pimm_ctx *ctx, const pimm_serve_config *cfg, pimm_server *
     sv->batch.ctx = ctx;
     sv->batch.schedule = cfg->schedule;
     sv->batch.G = cfg->mac_rows ? (int)cfg->mac_rows : 8;
+    sv->batch.KB = cfg->mac_cols ? (int)cfg->mac_cols : 1;
+    if (!mac_shape_ok(sv->batch.G, sv->batch.KB)) {
+        delete sv;
+        return set_error(PIMM_E_ARG, "pimm_serve_create: product tile %d rows x %d column blocks "
+                                     "is not built", (int)cfg->mac_rows, (int)cfg->mac_cols);
+    }
     // Dependency counters of the persistent schedule sit at the start of the arena.
     sv->counters_bytes = a256(4ull * (2 + (uint64_t)cfg->max_active * 4096));
     sv->arena_bytes = cfg->hbm_budget;

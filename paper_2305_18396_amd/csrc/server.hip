@@ -289,7 +289,7 @@ int pimm_matmul(const pimm_plan *plan, const pimm_weights *w, const uint64_t *ct
     double *ah = ch + (size_t)f.I * 2 * L * N;
     int rc = launch_fwd(c, LoadU64{ct, lg}, StoreCtTiled{ch, lg, (int)L, f.K, f.R},
                         (int)(f.I * 2 * L), s);
-    if (!rc) rc = launch_mac(c, f, plan->mac_rows, plan->splits, w->d_w_hat, ch, ah, s);
+    if (!rc) rc = launch_mac(c, f, plan->mac_rows, plan->mac_cols, plan->waves, w->d_w_hat, ch, ah, s);
     if (!rc) rc = launch_inv(c, LoadSlotsReduce{ah, lg}, StoreU64{acc, lg}, (int)(f.O * 2 * L), s);
     return rc;
 }
@@ -371,7 +371,7 @@ int pimm_matmul_share(const pimm_plan *plan, const pimm_weights *w, const uint64
     int64_t *e = u + (size_t)f.O * N;
     const Key key = make_key(seed);
     int rc = launch_fwd(c, LoadU64{ct, lg}, StoreCtTiled{ch, lg, (int)L, f.K, f.R}, (int)(f.I * 2 * L), s);
-    if (!rc) rc = launch_mac(c, f, plan->mac_rows, plan->splits, w->d_w_hat, ch, ah, s);
+    if (!rc) rc = launch_mac(c, f, plan->mac_rows, plan->mac_cols, plan->waves, w->d_w_hat, ch, ah, s);
     if (!rc && rr) {
         rc = launch_fwd(c, LoadU64{pk, lg}, StoreSlots{pkh, lg}, (int)(2 * L), s);
         if (!rc) rc = launch_sample(c, 1, key, kTagRrU, op_id, 0, (int)f.O, 0, 1, u, N, 0, s);

@@ -9,6 +9,7 @@
 
 #include "batch.h"
 #include "common.h"
+#include "mac.h"
 
 using namespace pimm;
 
@@ -37,23 +38,27 @@ int time_ms(hipStream_t s, int reps, F &&run, double *ms)
 
 extern "C" {
 
-int pimm_plan_set_tuning(pimm_plan *plan, int mac_rows, int splits)
+int pimm_plan_set_tuning(pimm_plan *plan, int mac_rows, int mac_cols, int waves)
 {
     if (!plan) return set_error(PIMM_E_ARG, "pimm_plan_set_tuning: NULL plan");
-    if (mac_rows != 4 && mac_rows != 8 && mac_rows != 16)
-        return set_error(PIMM_E_ARG, "mac_rows %d is not 4, 8 or 16", mac_rows);
-    if (splits != 1 && splits != 2 && splits != 4)
-        return set_error(PIMM_E_ARG, "splits %d is not 1, 2 or 4", splits);
+    if (!mac_shape_ok(mac_rows, mac_cols))
+        return set_error(PIMM_E_ARG, "product tile %d rows x %d column blocks is not built",
+                         mac_rows, mac_cols);
+    if (waves != 1 && waves != 2 && waves != 4)
+        return set_error(PIMM_E_ARG, "waves %d is not 1, 2 or 4", waves);
     plan->mac_rows = mac_rows;
-    plan->splits = splits;
+    plan->mac_cols = mac_cols;
+    plan->waves = waves;
     return PIMM_OK;
 }
 
-int pimm_plan_get_tuning(const pimm_plan *plan, int *mac_rows, int *splits)
+int pimm_plan_get_tuning(const pimm_plan *plan, int *mac_rows, int *mac_cols, int *waves)
 {
-    if (!plan || !mac_rows || !splits) return set_error(PIMM_E_ARG, "pimm_plan_get_tuning: NULL argument");
+    if (!plan || !mac_rows || !mac_cols || !waves)
+        return set_error(PIMM_E_ARG, "pimm_plan_get_tuning: NULL argument");
     *mac_rows = plan->mac_rows;
-    *splits = plan->splits;
+    *mac_cols = plan->mac_cols;
+    *waves = plan->waves;
     return PIMM_OK;
 }
 
@@ -62,29 +67,41 @@ int pimm_plan_autotune(pimm_plan *plan, const pimm_weights *w, const uint64_t *c
 {
     if (!plan || !w || !ct || !acc) return set_error(PIMM_E_ARG, "pimm_plan_autotune: NULL argument");
     hipStream_t s = (hipStream_t)stream;
-    const int rows[3] = {4, 8, 16}, splits[3] = {1, 2, 4};
+    struct Shape {
+        int g, kb;
+    };
+    const Shape shapes[] = {{4, 1}, {8, 1}, {16, 1}, {4, 2}, {8, 2}, {2, 4}, {4, 4}};
+    const int waves[3] = {1, 2, 4};
+    const int K = (int)plan->info.K;
     double best = DBL_MAX;
-    int bg = plan->mac_rows, bs = plan->splits;
-    for (int g : rows)
-        for (int sp : splits) {
-            plan->mac_rows = g;
-            plan->splits = sp;
+    int bg = plan->mac_rows, bk = plan->mac_cols, bw = plan->waves;
+    for (const Shape &sh : shapes) {
+        // Column blocking only pays when there are columns to share a weight word.
+        if (sh.kb > 1 && sh.kb > 2 * K - 1) continue;
+        for (int wv : waves) {
+            plan->mac_rows = sh.g;
+            plan->mac_cols = sh.kb;
+            plan->waves = wv;
             double ms = 0;
             int rc = time_ms(s, reps,
                              [&]() { return pimm_matmul(plan, w, ct, acc, ws, ws_bytes, stream); }, &ms);
             if (rc) {
                 plan->mac_rows = bg;
-                plan->splits = bs;
+                plan->mac_cols = bk;
+                plan->waves = bw;
                 return rc;
             }
             if (ms < best) {
                 best = ms;
-                bg = g;
-                bs = sp;
+                bg = sh.g;
+                bk = sh.kb;
+                bw = wv;
             }
         }
+    }
     plan->mac_rows = bg;
-    plan->splits = bs;
+    plan->mac_cols = bk;
+    plan->waves = bw;
     if (best_ms) *best_ms = best;
     return PIMM_OK;
 }
@@ -95,14 +112,16 @@ int pimm_batch_autotune(pimm_batch *b, void *ws, size_t ws_bytes, int reps, void
     if (!b) return set_error(PIMM_E_ARG, "pimm_batch_autotune: NULL batch");
     hipStream_t s = (hipStream_t)stream;
     struct Cand {
-        int sched, g, xcd;
+        int sched, g, kb, xcd;
     };
-    const Cand cands[] = {{kPhased, 8, 1}, {kPhased, 8, 0}, {kPhased, 4, 1}, {kPhased, 16, 1},
-                          {kPersistent, 8, 1}, {kPersistent, 16, 1}};
+    const Cand cands[] = {{kPhased, 8, 1, 1},     {kPhased, 8, 1, 0},     {kPhased, 4, 1, 1},
+                          {kPhased, 16, 1, 1},    {kPhased, 4, 2, 1},     {kPhased, 8, 2, 1},
+                          {kPhased, 2, 4, 1},     {kPhased, 4, 4, 1},     {kPersistent, 8, 1, 1},
+                          {kPersistent, 16, 1, 1}, {kPersistent, 4, 2, 1}, {kPersistent, 4, 4, 1}};
     double best = DBL_MAX;
-    Cand bc = {b->schedule, b->G, b->xcd_map};
+    Cand bc = {b->schedule, b->G, b->KB, b->xcd_map};
     for (const Cand &c : cands) {
-        int rc = pimm_batch_set_schedule(b, c.sched, c.g, c.xcd, 0);
+        int rc = pimm_batch_set_schedule(b, c.sched, c.g, c.kb, c.xcd, 0);
         if (rc) return rc;
         if (b->ws_bytes > ws_bytes) continue;
         double ms = 0;
@@ -115,7 +134,7 @@ int pimm_batch_autotune(pimm_batch *b, void *ws, size_t ws_bytes, int reps, void
         }
     }
     if (best_ms) *best_ms = best;
-    return pimm_batch_set_schedule(b, bc.sched, bc.g, bc.xcd, 0);
+    return pimm_batch_set_schedule(b, bc.sched, bc.g, bc.kb, bc.xcd, 0);
 }
 
 }  // extern "C"

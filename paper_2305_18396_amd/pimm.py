@@ -28,7 +28,7 @@ ERRORS = {-1: "PIMM_E_ARG", -2: "PIMM_E_SHAPE", -3: "PIMM_E_PARAMS", -4: "PIMM_E
 TAG_SK, TAG_PK_A, TAG_PK_E, TAG_ENC_A, TAG_ENC_E = 1, 2, 3, 4, 5
 TAG_RR_U, TAG_RR_E1, TAG_RR_E2, TAG_MASK = 6, 7, 8, 9
 
-# Every function include/pimm.h declares.
+# Every function include/pimm.h and include/pimm_probe.h declare.
 EXPORTS = [
     "pimm_ctx_create", "pimm_ctx_destroy", "pimm_ctx_primes", "pimm_ctx_cdt",
     "pimm_params_primes", "pimm_cdt", "pimm_plan_rule", "pimm_noise_ok",
@@ -38,11 +38,17 @@ EXPORTS = [
     "pimm_weights_create", "pimm_weights_destroy", "pimm_matmul", "pimm_mask_share",
     "pimm_matmul_share",
     "pimm_batch_create", "pimm_batch_destroy", "pimm_batch_query", "pimm_batch_set_schedule",
+    "pimm_batch_get_schedule",
     "pimm_batch_matmul", "pimm_batch_status",
     "pimm_serve_create", "pimm_serve_destroy", "pimm_serve_footprint", "pimm_serve_run",
     "pimm_poly_mul", "pimm_poly_mul_workspace", "pimm_sample_poly",
     "pimm_profile_enable", "pimm_profile_read", "pimm_sync", "pimm_last_error",
+    "pimm_probe",
 ]
+
+# Device-rate probes (include/pimm_probe.h).
+PROBE_READ, PROBE_COPY, PROBE_FMA64 = 0, 1, 2
+PROBE_MODMUL_F64, PROBE_MODMUL_BARRETT, PROBE_MODMUL_SHOUP = 3, 4, 5
 
 
 class PimmError(RuntimeError):
@@ -92,7 +98,7 @@ def lib():
         "pimm_plan_create": [vp, u32, u32, u32, u32, u32, u32, u32, vp],
         "pimm_plan_destroy": [vp],
         "pimm_plan_query": [vp, vp],
-        "pimm_plan_set_tuning": [vp, i32, i32],
+        "pimm_plan_set_tuning": [vp, i32, i32, i32],
         "pimm_plan_get_tuning": [vp, vp, vp],
         "pimm_plan_autotune": [vp, vp, vp, vp, vp, ctypes.c_size_t, i32, vp, vp],
         "pimm_batch_autotune": [vp, vp, ctypes.c_size_t, i32, vp, vp],
@@ -109,7 +115,8 @@ def lib():
         "pimm_batch_create": [vp, u32, vp],
         "pimm_batch_destroy": [vp],
         "pimm_batch_query": [vp, vp, vp],
-        "pimm_batch_set_schedule": [vp, i32, i32, i32, u32],
+        "pimm_batch_set_schedule": [vp, i32, i32, i32, i32, u32],
+        "pimm_batch_get_schedule": [vp, vp, vp, vp, vp, vp],
         "pimm_batch_matmul": [vp, vp, ctypes.c_size_t, vp],
         "pimm_batch_status": [vp, vp, vp],
         "pimm_serve_create": [vp, vp, vp],
@@ -118,6 +125,7 @@ def lib():
         "pimm_serve_run": [vp, vp, u32, vp, vp],
         "pimm_poly_mul": [vp, vp, vp, vp, u32, vp, ctypes.c_size_t, vp],
         "pimm_poly_mul_workspace": [vp, u32],
+        "pimm_probe": [i32, i32, u64, i32, vp],
         "pimm_sample_poly": [vp, i32, vp, u32, u32, u32, u32, vp, vp],
         "pimm_profile_enable": [i32],
         "pimm_profile_read": [ctypes.c_char_p, vp, vp],
@@ -271,13 +279,14 @@ class Plan:
             return getattr(info, k)
         raise AttributeError(k)
 
-    def set_tuning(self, mac_rows: int = 8, splits: int = 1):
-        _check(lib().pimm_plan_set_tuning(self.h, mac_rows, splits))
+    def set_tuning(self, mac_rows: int = 8, mac_cols: int = 1, waves: int = 1):
+        _check(lib().pimm_plan_set_tuning(self.h, mac_rows, mac_cols, waves))
 
     def tuning(self):
-        g, s = ctypes.c_int(), ctypes.c_int()
-        _check(lib().pimm_plan_get_tuning(self.h, ctypes.byref(g), ctypes.byref(s)))
-        return g.value, s.value
+        """-> (mac_rows, mac_cols, waves) of the product schedule."""
+        g, k, w = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().pimm_plan_get_tuning(self.h, ctypes.byref(g), ctypes.byref(k), ctypes.byref(w)))
+        return g.value, k.value, w.value
 
     def autotune(self, w, ct, acc, reps: int = 3, stream=None) -> float:
         """Time every product schedule on these buffers; keep the fastest.  -> best ms."""
@@ -454,19 +463,24 @@ class Batch:
         _check(lib().pimm_batch_create(arr, len(items), ctypes.byref(self.h)))
         self.ctx = items[0][0].ctx
         self._ws = None
-        self.schedule = (PHASED, 8, 1, 0)
 
     def query(self):
         ws, macs = ctypes.c_uint64(), ctypes.c_uint64()
         _check(lib().pimm_batch_query(self.h, ctypes.byref(ws), ctypes.byref(macs)))
         return ws.value, macs.value
 
-    def set_schedule(self, schedule=PHASED, mac_rows=8, xcd_map=True, grid=0):
-        _check(lib().pimm_batch_set_schedule(self.h, schedule, mac_rows, 1 if xcd_map else 0, grid))
-        self.schedule = (schedule, mac_rows, xcd_map, grid)
+    def set_schedule(self, schedule=PHASED, mac_rows=8, mac_cols=1, xcd_map=True, grid=0):
+        _check(lib().pimm_batch_set_schedule(self.h, schedule, mac_rows, mac_cols,
+                                             1 if xcd_map else 0, grid))
         need = self.query()[0]
         if self._ws is not None and self._ws.numel() * 8 < need:
             self._ws = None
+
+    def get_schedule(self):
+        """-> (schedule, mac_rows, mac_cols, xcd_map, grid) in force."""
+        v = [ctypes.c_int() for _ in range(4)] + [ctypes.c_uint32()]
+        _check(lib().pimm_batch_get_schedule(self.h, *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v[:3]) + (bool(v[3].value), v[4].value)
 
     def workspace(self):
         if self._ws is None:
@@ -508,7 +522,8 @@ class ServeConfig(ctypes.Structure):
                 ("d_in", ctypes.POINTER(ctypes.c_uint32)), ("d_out", ctypes.POINTER(ctypes.c_uint32)),
                 ("weights", ctypes.POINTER(ctypes.c_void_p)), ("d_fix", ctypes.c_uint32),
                 ("hbm_budget", ctypes.c_uint64), ("max_active", ctypes.c_uint32),
-                ("schedule", ctypes.c_int32), ("mac_rows", ctypes.c_uint32)]
+                ("schedule", ctypes.c_int32), ("mac_rows", ctypes.c_uint32),
+                ("mac_cols", ctypes.c_uint32)]
 
 
 class Request(ctypes.Structure):
@@ -530,14 +545,14 @@ class Server:
     shapes: [(d_in, d_out)] per op; weights: [layers * ops] Weights made with block area d_fix."""
 
     def __init__(self, ctx: Context, layers: int, shapes, weights, d_fix: int, hbm_budget: int,
-                 max_active: int, schedule: int = PHASED, mac_rows: int = 8):
+                 max_active: int, schedule: int = PHASED, mac_rows: int = 8, mac_cols: int = 1):
         self.ctx, self.weights = ctx, list(weights)
         ops = len(shapes)
         self._d_in = (ctypes.c_uint32 * ops)(*[r for r, _ in shapes])
         self._d_out = (ctypes.c_uint32 * ops)(*[m for _, m in shapes])
         self._w = (ctypes.c_void_p * len(self.weights))(*[w.h.value for w in self.weights])
         cfg = ServeConfig(layers, ops, self._d_in, self._d_out, self._w, d_fix, int(hbm_budget),
-                          max_active, schedule, mac_rows)
+                          max_active, schedule, mac_rows, mac_cols)
         self.h = ctypes.c_void_p()
         _check(lib().pimm_serve_create(ctx.h, ctypes.byref(cfg), ctypes.byref(self.h)))
 
@@ -601,6 +616,13 @@ def profile_read(kernel: str):
 
 def sync(stream=None):
     _check(lib().pimm_sync(_stream(stream)))
+
+
+def probe(kind: int, size: int, reps: int = 5, device: int = 0) -> float:
+    """Sustained device rate of one probe kind (PROBE_*): bytes/s, flop/s or products/s."""
+    rate = ctypes.c_double()
+    _check(lib().pimm_probe(device, kind, size, reps, ctypes.byref(rate)))
+    return rate.value
 
 
 class Party:

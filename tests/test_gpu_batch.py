@@ -50,15 +50,18 @@ def batch_setup():
     return ctx, batch, rows, sk, pk, cseed
 
 
-@pytest.mark.parametrize("schedule,rows_per_thread,xcd", [
-    (pimm.PHASED, 8, True), (pimm.PHASED, 4, False), (pimm.PHASED, 16, True),
-    (pimm.PERSISTENT, 8, True), (pimm.PERSISTENT, 16, False)])
-def test_batch_equals_solo(batch_setup, schedule, rows_per_thread, xcd):
+@pytest.mark.parametrize("schedule,rows_per_thread,cols,xcd", [
+    (pimm.PHASED, 8, 1, True), (pimm.PHASED, 4, 1, False), (pimm.PHASED, 16, 1, True),
+    (pimm.PHASED, 4, 2, True), (pimm.PHASED, 8, 2, True), (pimm.PHASED, 2, 4, True),
+    (pimm.PHASED, 4, 4, False),
+    (pimm.PERSISTENT, 8, 1, True), (pimm.PERSISTENT, 16, 1, False), (pimm.PERSISTENT, 4, 2, True),
+    (pimm.PERSISTENT, 4, 4, True), (pimm.PERSISTENT, 2, 4, False)])
+def test_batch_equals_solo(batch_setup, schedule, rows_per_thread, cols, xcd):
     ctx, batch, rows, *_ = batch_setup
-    log(f"schedule {schedule} G {rows_per_thread} xcd {xcd}")
+    log(f"schedule {schedule} tile {rows_per_thread}x{cols} xcd {xcd}")
     for r in rows:
         r[3].zero_()
-    batch.set_schedule(schedule, rows_per_thread, xcd, 0)
+    batch.set_schedule(schedule, rows_per_thread, cols, xcd, 0)
     batch.run()
     batch.status()
     torch.cuda.synchronize()
@@ -71,7 +74,7 @@ def test_batch_persistent_small_grid(batch_setup):
     ctx, batch, rows, *_ = batch_setup
     for r in rows:
         r[3].zero_()
-    batch.set_schedule(pimm.PERSISTENT, 8, True, 7)
+    batch.set_schedule(pimm.PERSISTENT, 4, 2, True, 7)
     batch.run()
     batch.status()
     for k, r in enumerate(rows):
@@ -80,7 +83,7 @@ def test_batch_persistent_small_grid(batch_setup):
 
 def test_batch_item_against_oracle(batch_setup, orc):
     ctx, batch, rows, sk, pk, cseed = batch_setup
-    batch.set_schedule(pimm.PHASED, 8, True, 0)
+    batch.set_schedule(pimm.PHASED, 4, 4, True, 0)
     for r in rows:
         r[3].zero_()
     batch.run()
@@ -102,7 +105,7 @@ def test_batch_graph_replay(batch_setup, schedule):
     """Capture the batch into a hipGraph; replay it three times with eager work and
     synchronisations in between; every replay equals the eager result."""
     ctx, batch, rows, *_ = batch_setup
-    batch.set_schedule(schedule, 8, True, 0)
+    batch.set_schedule(schedule, 4, 2, True, 0)
     ws = batch.workspace()
     s = torch.cuda.Stream()
     torch.cuda.synchronize()

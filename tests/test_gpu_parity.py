@@ -293,6 +293,61 @@ def test_full_size_bert_large_op(orc):
     check_layer_op(orc, ctx, pyp, wl, dict(d_fix=1024), 200)
 
 
+TUNINGS = [(g, kb, wv) for g, kb in [(4, 1), (8, 1), (16, 1), (4, 2), (8, 2), (2, 4), (4, 4)]
+           for wv in (1, 2, 4)]
+
+
+@pytest.mark.parametrize("name,shape,plan_kw", [
+    ("ragged_k3", (19, 70, 45), dict(mb=3, rb=5, nb=7)),
+    ("fix256_k3", (40, 300, 200), dict(d_fix=256)),
+    ("fix512_k13", (100, 64, 48), dict(d_fix=512)),
+    ("comm_k1", (16, 64, 64), {})])
+def test_product_schedules_bitexact(orc, name, shape, plan_kw):
+    """Every product schedule (rows x column blocks per thread, grid size) gives the
+    oracle's accumulators, also with ragged row and column tiles."""
+    n, r, m = shape
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    X = workloads.share(rng, n, r, 37)
+    W = workloads.weights(rng, r, m, 12)
+    ctx = context(4096, 2, 37, 12, True)
+    plan = pimm.Plan(ctx, n, r, m, **plan_kw)
+    pyp = orc.Params(4096, 2, 37, 12)
+    oplan = orc.Plan(n, r, m, plan.mb, plan.rb, plan.nb, 4096)
+    cs = workloads.seed("client", 70)
+    log(f"schedules {name}: plan=({plan.mb},{plan.rb},{plan.nb}) M={plan.M} R={plan.R} K={plan.K}")
+    sk, _ = pimm.keygen(ctx, cs)
+    ct = pimm.encrypt(plan, sk, cs, 3, pimm.encode_input(plan, pimm.to_device_u64(X)))
+    w = pimm.Weights(plan, pimm.to_device_u64(W))
+    s_ref, _ = orc.keygen(pyp, cs)
+    ct_ref = orc.encrypt(pyp, s_ref, cs, 3, orc.encode_input(oplan, X))
+    assert np.array_equal(u64(ct), ct_ref)
+    want = orc.matmul(pyp, oplan, orc.encode_weights(oplan, W), ct_ref, list(range(plan.O)))
+    for g, kb, wv in TUNINGS:
+        plan.set_tuning(g, kb, wv)
+        acc = pimm.matmul(plan, w, ct)
+        assert np.array_equal(u64(acc), want), (g, kb, wv)
+
+
+def test_product_schedules_full_size_bert_large():
+    """At the BERT-large FFN2 product (K = 64 column blocks) the column-blocked
+    schedules give the bytes of the one-column schedule (which the full-size oracle
+    check covers)."""
+    ctx = context(8192, 3, 41, 14, True)
+    wl = workloads.bert_large_layer(512)[3]
+    n, r, m = wl.shape
+    plan = pimm.Plan(ctx, n, r, m, d_fix=1024)
+    cs = workloads.seed("client", 71)
+    sk, _ = pimm.keygen(ctx, cs)
+    ct = pimm.encrypt(plan, sk, cs, 1, pimm.encode_input(plan, pimm.to_device_u64(wl.X)))
+    w = pimm.Weights(plan, pimm.to_device_u64(wl.W))
+    plan.set_tuning(8, 1, 1)
+    ref = pimm.matmul(plan, w, ct)
+    for g, kb, wv in [(4, 4, 1), (2, 4, 2), (8, 2, 4)]:
+        log(f"full-size schedule {g}x{kb} waves {wv}")
+        plan.set_tuning(g, kb, wv)
+        assert torch.equal(pimm.matmul(plan, w, ct), ref), (g, kb, wv)
+
+
 @pytest.mark.parametrize("name", ["single", "single_norr", "ragged_explicit", "n8192_l3", "fix256",
                                   "scalar", "n4096_l1"])
 def test_fused_server_step_equals_two_calls(orc, name):

@@ -14,8 +14,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def header_functions():
-    text = open(os.path.join(ROOT, "include", "pimm.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+[\s\*]+(pimm_\w+)\(", text, re.M)))
+    names = set()
+    for h in ("pimm.h", "pimm_probe.h"):
+        text = open(os.path.join(ROOT, "include", h)).read()
+        names |= set(re.findall(r"^\s*(?:const\s+)?\w+[\s\*]+(pimm_\w+)\(", text, re.M))
+    return sorted(names)
 
 
 def test_exports_every_declared_function():
