@@ -26,6 +26,7 @@ chunks until about --cpu-seconds have passed, encryption of all inputs counted
 pro rata.
 """
 import argparse
+import collections
 import json
 import os
 import sys
@@ -161,11 +162,25 @@ def bench_batch(args):
         for plan, w, ct, acc in rows:
             pimm.matmul(plan, w, ct, acc)
 
+    def phases(fn, reps):
+        """Kernel-class milliseconds per pass, from the library's HIP events."""
+        kinds = ("ntt_fwd", "mac", "ntt_inv", "fused")
+        for k in kinds:
+            pimm.profile_read(k)
+        pimm.profile_enable(True)
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        pimm.profile_enable(False)
+        return {k: round(pimm.profile_read(k)[1] / reps, 3) for k in kinds}
+
     t_plain = timed(plain, args.steps)
+    plain_phases = phases(plain, 2)
     ref = [acc.clone() for *_, acc in rows]
     batch = pimm.Batch(rows)
     best_ms = batch.autotune(reps=2)
     t_batch = timed(batch.run, args.steps)
+    batch_phases = phases(batch.run, 2)
     batch.status()
     same = all(torch.equal(acc, r) for (*_, acc), r in zip(rows, ref))
     graph_t = None
@@ -184,7 +199,10 @@ def bench_batch(args):
             "graph_ms": graph_t * 1e3, "autotune_best_ms": best_ms,
             "plain_int_mac_per_s": useful / t_plain, "batched_int_mac_per_s": useful / t_batch,
             "graph_int_mac_per_s": useful / graph_t, "speedup": t_plain / t_batch,
-            "schedule": sched, "bitexact_vs_plain": bool(same)}
+            "schedule": sched, "bitexact_vs_plain": bool(same),
+            "plain_schedule_counts": {",".join(map(str, t)): c for t, c in
+                                      collections.Counter(tuned.values()).most_common()},
+            "plain_kernel_ms": plain_phases, "batched_kernel_ms": batch_phases}
 
 
 def bench_serve(args):
@@ -254,6 +272,7 @@ def bench_peak(args):
     out = {"spec_hbm_GBps": HBM_PEAK_GBS, "spec_fp64_TFLOPs": 78.6}
     gib = 1 << 30
     out["read_GBps"] = pimm.probe(pimm.PROBE_READ, 8 * gib, args.steps) / 1e9
+    out["read8_GBps"] = pimm.probe(pimm.PROBE_READ8, 8 * gib, args.steps) / 1e9
     out["copy_GBps"] = pimm.probe(pimm.PROBE_COPY, 4 * gib, args.steps) / 1e9
     out["fma64_TFLOPs"] = pimm.probe(pimm.PROBE_FMA64, 4096, args.steps) / 1e12
     out["modmul_f64_G_per_s"] = pimm.probe(pimm.PROBE_MODMUL_F64, 4096, args.steps) / 1e9
@@ -400,6 +419,17 @@ def main():
                           "ms_per_step": round(ms / args.steps, 4)}
     log(f"timed {args.steps} steps in {elapsed:.4f} s")
 
+    # The server's part alone (rows A4-A9: forward NTT through the masked reply) on inputs
+    # encrypted beforehand.
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        for st in state:
+            pimm.matmul_share(st["plan"], st["w"], pk, sseed, (20_000 + k) * 8 + st["op"], st["ct"],
+                              st["c1"], st["c0s"], st["y1"], st["ws"])
+    torch.cuda.synchronize()
+    server_s = (time.perf_counter() - t0) / args.steps
+
     if args.calib_copy_mb:
         src = torch.ones(args.calib_copy_mb << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -447,6 +477,8 @@ def main():
             "product_schedules": [list(s["plan"].tuning()) for s in state],
             "useful_macs_per_step": useful,
         },
+        "server_path_ms": server_s * 1e3,
+        "server_path_int_mac_per_s": useful / server_s,
         "slot_mac_per_s": slot_macs * args.steps / elapsed,
         "server_ntt_butterflies_per_s": butterflies * args.steps / elapsed,
         "wire_bytes_per_step": wire,

@@ -37,9 +37,11 @@ enum pimm_probe_kind {
     PIMM_PROBE_MODMUL_BARRETT = 4,
     /* uint64 Shoup products by a fixed multiplier, `size` per lane; rate in products/s. */
     PIMM_PROBE_MODMUL_SHOUP = 5,
+    /* Streaming read of `size` bytes with 8-byte loads (the product's load width); bytes/s. */
+    PIMM_PROBE_READ8 = 6,
 };
 
-/* Run probe `kind` on `device`.  For the two memory probes `size` is the
+/* Run probe `kind` on `device`.  For the three memory probes `size` is the
  * buffer size in bytes (a multiple of 16, at least 16 MiB); the rate is the
  * best over a few grid sizes.  For the arithmetic probes `size` is the chain
  * length per lane (at least 1024).  `reps` >= 1. */

@@ -152,13 +152,39 @@ __device__ __forceinline__ void mac_range(const double *__restrict__ Wt, const d
     }
 }
 
+// A tile whose last column tile is ragged (fewer than KB column blocks left) is
+// run as narrower tiles, so that no product is spent on absent columns: a column
+// tile of c < KB blocks becomes tiles of KB/2, KB/4, ... blocks.
+template <int G, int KB>
+__device__ __forceinline__ void mac_tile(const double *__restrict__ Wt, const double *__restrict__ Ct,
+                                         double *__restrict__ Ah, const MacShape &s,
+                                         const DevParams &dp, int l, int zc, int kb0, int ib0,
+                                         int jb0, int jb1, int mode)
+{
+    const int cols = s.K - kb0;
+    if (KB == 1 || cols >= KB) {
+        mac_range<G, KB>(Wt, Ct, Ah, s, dp, l, zc, kb0, ib0, jb0, jb1, mode);
+        return;
+    }
+    if constexpr (KB >= 2) {
+        constexpr int H = KB / 2;
+        if (cols >= H) {
+            mac_range<G, H>(Wt, Ct, Ah, s, dp, l, zc, kb0, ib0, jb0, jb1, mode);
+            if (cols > H) mac_tile<G, H>(Wt, Ct, Ah, s, dp, l, zc, kb0 + H, ib0, jb0, jb1, mode);
+        } else {
+            mac_tile<G, H>(Wt, Ct, Ah, s, dp, l, zc, kb0, ib0, jb0, jb1, mode);
+        }
+    }
+}
+
 // Product tile shapes (G rows, KB column blocks per thread) the library instantiates.
-#define PIMM_MAC_SHAPES(X) X(4, 1) X(8, 1) X(16, 1) X(4, 2) X(8, 2) X(2, 4) X(4, 4)
+#define PIMM_MAC_SHAPES(X) \
+    X(4, 1) X(8, 1) X(16, 1) X(4, 2) X(8, 2) X(16, 2) X(2, 4) X(4, 4) X(8, 4)
 
 __host__ __device__ constexpr bool mac_shape_ok(int G, int KB)
 {
-    return (KB == 1 && (G == 4 || G == 8 || G == 16)) || (KB == 2 && (G == 4 || G == 8)) ||
-           (KB == 4 && (G == 2 || G == 4));
+    return (KB == 1 && (G == 4 || G == 8 || G == 16)) ||
+           (KB == 2 && (G == 4 || G == 8 || G == 16)) || (KB == 4 && (G == 2 || G == 4 || G == 8));
 }
 
 // ---- stores into the chunk-contiguous layouts (NTT output slot z) --------------

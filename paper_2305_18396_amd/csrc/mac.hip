@@ -33,7 +33,7 @@ __global__ __launch_bounds__(256) void k_mac_sk(const double *__restrict__ Wt,
         const int zc = (int)(r % sh.chunks);
         const int l = (int)(r / sh.chunks);
         const int mode = (jb0 == 0 && jb1 == sh.R) ? 0 : 1;
-        mac_range<G, KB>(Wt, Ct, Ah, sh, dp, l, zc, kbt * KB, ibt * G, jb0, jb1, mode);
+        mac_tile<G, KB>(Wt, Ct, Ah, sh, dp, l, zc, kbt * KB, ibt * G, jb0, jb1, mode);
         u += (uint64_t)(jb1 - jb0);
     }
 }

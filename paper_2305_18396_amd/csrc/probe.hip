@@ -31,6 +31,23 @@ __global__ __launch_bounds__(kThreads) void k_read(const double2 *__restrict__ a
     out[(size_t)blockIdx.x * kThreads + threadIdx.x] = s0 + s1;
 }
 
+__global__ __launch_bounds__(kThreads) void k_read8(const double *__restrict__ a, size_t n,
+                                                    double *__restrict__ out)
+{
+    const size_t stride = (size_t)gridDim.x * kThreads;
+    size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x;
+    double s0 = 0.0, s1 = 0.0;
+    for (; i + 7 * stride < n; i += 8 * stride) {
+        double x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = a[i + k * stride];
+        s0 += (x[0] + x[1]) + (x[2] + x[3]);
+        s1 += (x[4] + x[5]) + (x[6] + x[7]);
+    }
+    for (; i < n; i += stride) s0 += a[i];
+    out[(size_t)blockIdx.x * kThreads + threadIdx.x] = s0 + s1;
+}
+
 __global__ __launch_bounds__(kThreads) void k_copy(const double2 *__restrict__ a,
                                                    double2 *__restrict__ b, size_t n2)
 {
@@ -163,9 +180,8 @@ int timed(Run &r, int reps, F launch, double *sec)
 
 extern "C" int pimm_probe(int device, int kind, uint64_t size, int reps, double *rate)
 {
-    if (!rate || reps < 1 || kind < PIMM_PROBE_READ || kind > PIMM_PROBE_MODMUL_SHOUP)
-        return PIMM_E_ARG;
-    const bool mem = kind <= PIMM_PROBE_COPY;
+    if (!rate || reps < 1 || kind < PIMM_PROBE_READ || kind > PIMM_PROBE_READ8) return PIMM_E_ARG;
+    const bool mem = kind <= PIMM_PROBE_COPY || kind == PIMM_PROBE_READ8;
     if (mem ? (size < (16u << 20) || size % 16 != 0) : (size < 1024 || size > (1u << 30)))
         return PIMM_E_ARG;
     if (hipSetDevice(device) != hipSuccess) return PIMM_E_DEVICE;
@@ -195,13 +211,18 @@ extern "C" int pimm_probe(int device, int kind, uint64_t size, int reps, double 
                     hipLaunchKernelGGL(k_read, dim3(grid), dim3(kThreads), 0, r.s,
                                        (const double2 *)r.a, n2, (double *)r.o);
                 }, &sec);
+            else if (kind == PIMM_PROBE_READ8)
+                rc = timed(r, reps, [&] {
+                    hipLaunchKernelGGL(k_read8, dim3(grid), dim3(kThreads), 0, r.s,
+                                       (const double *)r.a, size / 8, (double *)r.o);
+                }, &sec);
             else
                 rc = timed(r, reps, [&] {
                     hipLaunchKernelGGL(k_copy, dim3(grid), dim3(kThreads), 0, r.s,
                                        (const double2 *)r.a, (double2 *)r.b, n2);
                 }, &sec);
             if (rc != PIMM_OK) return rc;
-            const double bytes = kind == PIMM_PROBE_READ ? (double)size : 2.0 * (double)size;
+            const double bytes = kind == PIMM_PROBE_COPY ? 2.0 * (double)size : (double)size;
             if (bytes / sec > best) best = bytes / sec;
         }
         *rate = best;

@@ -49,6 +49,7 @@ EXPORTS = [
 # Device-rate probes (include/pimm_probe.h).
 PROBE_READ, PROBE_COPY, PROBE_FMA64 = 0, 1, 2
 PROBE_MODMUL_F64, PROBE_MODMUL_BARRETT, PROBE_MODMUL_SHOUP = 3, 4, 5
+PROBE_READ8 = 6
 
 
 class PimmError(RuntimeError):

@@ -53,9 +53,9 @@ def batch_setup():
 @pytest.mark.parametrize("schedule,rows_per_thread,cols,xcd", [
     (pimm.PHASED, 8, 1, True), (pimm.PHASED, 4, 1, False), (pimm.PHASED, 16, 1, True),
     (pimm.PHASED, 4, 2, True), (pimm.PHASED, 8, 2, True), (pimm.PHASED, 2, 4, True),
-    (pimm.PHASED, 4, 4, False),
+    (pimm.PHASED, 4, 4, False), (pimm.PHASED, 8, 4, True), (pimm.PHASED, 16, 2, True),
     (pimm.PERSISTENT, 8, 1, True), (pimm.PERSISTENT, 16, 1, False), (pimm.PERSISTENT, 4, 2, True),
-    (pimm.PERSISTENT, 4, 4, True), (pimm.PERSISTENT, 2, 4, False)])
+    (pimm.PERSISTENT, 4, 4, True), (pimm.PERSISTENT, 2, 4, False), (pimm.PERSISTENT, 8, 4, True)])
 def test_batch_equals_solo(batch_setup, schedule, rows_per_thread, cols, xcd):
     ctx, batch, rows, *_ = batch_setup
     log(f"schedule {schedule} tile {rows_per_thread}x{cols} xcd {xcd}")

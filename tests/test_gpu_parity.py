@@ -293,7 +293,8 @@ def test_full_size_bert_large_op(orc):
     check_layer_op(orc, ctx, pyp, wl, dict(d_fix=1024), 200)
 
 
-TUNINGS = [(g, kb, wv) for g, kb in [(4, 1), (8, 1), (16, 1), (4, 2), (8, 2), (2, 4), (4, 4)]
+TUNINGS = [(g, kb, wv) for g, kb in [(4, 1), (8, 1), (16, 1), (4, 2), (8, 2), (16, 2), (2, 4),
+                                    (4, 4), (8, 4)]
            for wv in (1, 2, 4)]
 
 
@@ -342,7 +343,7 @@ def test_product_schedules_full_size_bert_large():
     w = pimm.Weights(plan, pimm.to_device_u64(wl.W))
     plan.set_tuning(8, 1, 1)
     ref = pimm.matmul(plan, w, ct)
-    for g, kb, wv in [(4, 4, 1), (2, 4, 2), (8, 2, 4)]:
+    for g, kb, wv in [(4, 4, 1), (2, 4, 2), (8, 2, 4), (8, 4, 1), (16, 2, 2)]:
         log(f"full-size schedule {g}x{kb} waves {wv}")
         plan.set_tuning(g, kb, wv)
         assert torch.equal(pimm.matmul(plan, w, ct), ref), (g, kb, wv)
