@@ -340,8 +340,13 @@ int pimm_sample_poly(pimm_ctx *ctx, int kind, const uint8_t seed[32], uint32_t t
 
 /* on != 0: from now on bracket every kernel launch of the library with two HIP
  * events recorded on the launch's stream, filed under the kernel class
- * ("ntt_fwd", "ntt_inv", "mac", "sample", "encode", "decode", "mask_extract"). */
+ * ("ntt_fwd", "ntt_inv", "mac", "sample", "encode", "decode", "mask_extract",
+ * "fused").  Each recorded event delays the next dependent launch by a few
+ * microseconds, so a timed region should record only the classes it reports. */
 int pimm_profile_enable(int on);
+/* Restrict recording to a comma-separated list of kernel classes (NULL or "":
+ * every class). */
+int pimm_profile_select(const char *classes);
 /* Wait for the events recorded for `kernel`, report how many launches they cover
  * and their summed duration in milliseconds, and forget them. */
 int pimm_profile_read(const char *kernel, uint64_t *count, double *total_ms);

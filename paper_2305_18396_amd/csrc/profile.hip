@@ -1,10 +1,11 @@
 // profile.hip -- optional per-kernel timing with HIP events.
 //
-// When enabled, every kernel launch the library makes is bracketed by two
-// events recorded on the launch's own stream, filed under the kernel's class
-// name ("ntt_fwd", "ntt_inv", "mac", "sample", "encode", "decode",
-// "mask_extract").  pimm_profile_read waits for the recorded events, returns
-// the number of launches and their summed duration, and forgets them.
+// When enabled, every kernel launch the library makes (or those of the
+// selected classes) is bracketed by two events recorded on the launch's own
+// stream, filed under the kernel's class name ("ntt_fwd", "ntt_inv", "mac",
+// "sample", "encode", "decode", "mask_extract", "fused").  pimm_profile_read
+// waits for the recorded events, returns the number of launches and their
+// summed duration, and forgets them.
 #include <map>
 #include <mutex>
 #include <string>
@@ -18,6 +19,7 @@ namespace pimm {
 namespace {
 struct ProfState {
     bool on = false;
+    std::string select;  // ",a,b," or empty for every class
     std::mutex mu;
     std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> ev;
 };
@@ -31,6 +33,12 @@ ProfState &prof()
 ProfScope::ProfScope(const char *name, hipStream_t s) : name_(name), s_(s)
 {
     if (!prof().on) return;
+    {
+        std::lock_guard<std::mutex> g(prof().mu);
+        if (!prof().select.empty() &&
+            prof().select.find("," + std::string(name) + ",") == std::string::npos)
+            return;
+    }
     if (hipEventCreate(&a_) != hipSuccess || hipEventCreate(&b_) != hipSuccess) return;
     if (hipEventRecord(a_, s_) == hipSuccess) active_ = true;
 }
@@ -52,6 +60,19 @@ extern "C" {
 int pimm_profile_enable(int on)
 {
     prof().on = on != 0;
+    return PIMM_OK;
+}
+
+int pimm_profile_select(const char *classes)
+{
+    std::lock_guard<std::mutex> g(prof().mu);
+    prof().select.clear();
+    if (classes && *classes) {
+        prof().select = ",";
+        for (const char *c = classes; *c; ++c)
+            if (*c != ' ') prof().select += *c;
+        prof().select += ",";
+    }
     return PIMM_OK;
 }
 

@@ -42,7 +42,8 @@ EXPORTS = [
     "pimm_batch_matmul", "pimm_batch_status",
     "pimm_serve_create", "pimm_serve_destroy", "pimm_serve_footprint", "pimm_serve_run",
     "pimm_poly_mul", "pimm_poly_mul_workspace", "pimm_sample_poly",
-    "pimm_profile_enable", "pimm_profile_read", "pimm_sync", "pimm_last_error",
+    "pimm_profile_enable", "pimm_profile_select", "pimm_profile_read", "pimm_sync",
+    "pimm_last_error",
     "pimm_probe",
 ]
 
@@ -129,6 +130,7 @@ def lib():
         "pimm_probe": [i32, i32, u64, i32, vp],
         "pimm_sample_poly": [vp, i32, vp, u32, u32, u32, u32, vp, vp],
         "pimm_profile_enable": [i32],
+        "pimm_profile_select": [ctypes.c_char_p],
         "pimm_profile_read": [ctypes.c_char_p, vp, vp],
         "pimm_sync": [vp],
         "pimm_last_error": [],
@@ -606,6 +608,11 @@ def sample_poly(ctx: Context, kind: int, seed: bytes, tag: int, prime: int, op_i
 
 def profile_enable(on: bool = True):
     _check(lib().pimm_profile_enable(1 if on else 0))
+
+
+def profile_select(classes=None):
+    """Record only these kernel classes (an iterable of names; None: every class)."""
+    _check(lib().pimm_profile_select(",".join(classes).encode() if classes else None))
 
 
 def profile_read(kernel: str):
