@@ -57,25 +57,31 @@ struct StoreEncC0 {
         const uint64_t q = (uint64_t)p;
         const uint64_t as = to_canonical(v, p, pinv);
         const uint64_t m = mul_mod(delta[l], pt[(x << logn) + j], p, pinv);
-        const uint64_t c0 = sub_mod(add_mod(m, lift_signed(e[(x << logn) + j], q), q), as, q);
+        const uint64_t c0 = sub_mod(add_mod(m, lift_small(e[(x << logn) + j], q), q), as, q);
         ct[(((x * 2) * L + l) << logn) + j] = c0;
     }
 };
 
 // ---- decrypt (Algorithm 1 step 4, section 3.1.3) ---------------------------------
 
-// (c1 s) at the decoded positions pos = k*mb*rb + i*rb + rb-1 -> cs[o][l][k*mb + i].
-struct StoreDecoded {
+// (c1 s) of polynomial `poly` (output ciphertext poly / L, prime poly % L) from
+// its coefficient form in LDS, at the decoded positions
+// pos = k*mb*rb + i*rb + rb-1 -> cs[poly][k*mb + i].
+struct DecodedOut {
     uint64_t *cs;
-    int logn;
-    uint32_t mb, rb, nb;
-    __device__ void operator()(int poly, int, int j, double v, double p, double pinv) const
+    FastDiv mb;
+    uint32_t rb, nb;
+    __device__ void operator()(int poly, const double *lds, const DevParams &dp) const
     {
-        const uint32_t uj = (uint32_t)j;
-        if (uj % rb != rb - 1) return;
-        const uint32_t i = (uj / rb) % mb, k = uj / (mb * rb);
-        if (k >= nb) return;
-        cs[(size_t)poly * mb * nb + k * mb + i] = to_canonical(v, p, pinv);
+        const int l = poly % dp.L;
+        const double p = dp.p[l], pinv = dp.pinv[l];
+        const uint32_t per = mb.d * nb;
+        uint64_t *dst = cs + (size_t)poly * per;
+        for (uint32_t idx = threadIdx.x; idx < per; idx += kNttThreads) {
+            const uint32_t k = mb.div(idx), i = idx - k * mb.d;
+            const uint32_t j = (k * mb.d + i) * rb + rb - 1;
+            dst[idx] = to_canonical(lds[lds_idx((int)j)], p, pinv);
+        }
     }
 };
 
@@ -130,8 +136,9 @@ __device__ uint64_t crt_round(const uint64_t *res, const DevParams &dp)
         const double p = dp.p[l], pinv = dp.pinv[l];
         const uint64_t q = dp.q[l];
         uint64_t t = res[l];
+        // v[i] < q_i < 2^50 < 2 q_l: the FP64 product takes it unreduced.
         for (int i = 0; i < l; ++i)
-            t = sub_mod(t, mul_mod(v[i] % q, (uint64_t)dp.garner_c[l][i], p, pinv), q);
+            t = sub_mod(t, mul_mod(v[i], (uint64_t)dp.garner_c[l][i], p, pinv), q);
         v[l] = mul_mod(t, (uint64_t)dp.garner_inv[l], p, pinv);
     }
     uint64_t X[W] = {0, 0, 0, 0, 0};
@@ -265,8 +272,8 @@ int pimm_decrypt(const pimm_plan *plan, const pimm_sk *sk, const uint64_t *c1, c
     uint64_t *cs = (uint64_t *)(ch + (size_t)f.O * L * N);
     int rc = launch_fwd(c, LoadU64{c1, lg}, StoreSlots{ch, lg}, (int)(f.O * L), s);
     if (!rc)
-        rc = launch_inv(c, LoadSlotsMul{ch, sk->d_s_hat, lg, (int)L},
-                        StoreDecoded{cs, lg, f.mb, f.rb, f.nb}, (int)(f.O * L), s);
+        rc = launch_inv_lds(c, LoadSlotsMul{ch, sk->d_s_hat, lg, (int)L},
+                            DecodedOut{cs, FastDiv::make(f.mb), f.rb, f.nb}, (int)(f.O * L), s);
     if (!rc) {
         const size_t total = (size_t)f.O * per;
         const int threads = 256;

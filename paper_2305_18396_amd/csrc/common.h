@@ -102,16 +102,29 @@ __device__ __forceinline__ uint64_t sub_mod(uint64_t a, uint64_t b, uint64_t q)
 {
     return a >= b ? a - b : a + q - b;
 }
-// Signed small integer -> canonical residue.
-__device__ __forceinline__ uint64_t lift_signed(int64_t x, uint64_t q)
+// Signed integer of magnitude below q -> canonical residue (the callers pass
+// noise and ternary values, |x| <= 19).
+__device__ __forceinline__ uint64_t lift_small(int64_t x, uint64_t q)
 {
-    return x >= 0 ? (uint64_t)x % q : q - ((uint64_t)(-x) % q);
+    return x >= 0 ? (uint64_t)x : q - (uint64_t)(-x);
 }
 // Canonical product through the FP64 path.
 __device__ __forceinline__ uint64_t mul_mod(uint64_t a, uint64_t b, double p, double pinv)
 {
     return to_canonical(mulmod((double)a, (double)b, p, pinv), p, pinv);
 }
+
+// n / d for n * d < 2^32 by one multiply-high: M = ceil(2^32 / d) (d = 1 is kept apart,
+// its M would not fit in 32 bits).
+struct FastDiv {
+    uint32_t d, M;
+    static FastDiv make(uint32_t d)
+    {
+        return FastDiv{d, d == 1 ? 0u : (uint32_t)(((1ull << 32) + d - 1) / d)};
+    }
+    __device__ __forceinline__ uint32_t div(uint32_t n) const { return d == 1 ? n : __umulhi(n, M); }
+    __device__ __forceinline__ uint32_t mod(uint32_t n) const { return n - div(n) * d; }
+};
 
 // ---------------------------------------------------------------------------
 // ChaCha20 block function (RFC 8439 section 2.3) and the samplers

@@ -445,7 +445,7 @@ struct StorePk0 {
     {
         const uint64_t q = (uint64_t)p;
         const uint64_t as = to_canonical(v, p, pinv);
-        pk0[((size_t)poly << logn) + j] = sub_mod(lift_signed(e[j], q), as, q);
+        pk0[((size_t)poly << logn) + j] = sub_mod(lift_small(e[j], q), as, q);
     }
 };
 

@@ -221,6 +221,28 @@ __global__ __launch_bounds__(kNttThreads) void k_ntt_inv(Load ld, Store st, DevP
     ntt_inv_block<LOGN>(ld, st, dp, (int)blockIdx.x, lds);
 }
 
+// Inverse transform whose result stays in the workgroup's LDS (natural order,
+// lds_idx layout), followed by an epilogue that reads it with the whole
+// workgroup: epi(poly, lds, dp).  The last pass's storer writes exactly the
+// elements its thread has just read, so no barrier is needed before it.
+struct StoreLds {
+    double *lds;
+    __device__ void operator()(int, int, int j, double v, double, double) const
+    {
+        lds[lds_idx(j)] = v;
+    }
+};
+
+template <int LOGN, class Load, class Epi>
+__global__ __launch_bounds__(kNttThreads) void k_ntt_inv_lds(Load ld, Epi epi, DevParams dp)
+{
+    __shared__ double lds[NttPasses<LOGN>::LDS];
+    const int poly = (int)blockIdx.x;
+    ntt_inv_block<LOGN>(ld, StoreLds{lds}, dp, poly, lds);
+    __syncthreads();
+    epi(poly, lds, dp);
+}
+
 // ---- loaders ----------------------------------------------------------------
 
 // Canonical uint64 residues, [npoly][N].
@@ -310,6 +332,20 @@ int launch_inv(const Ctx &c, Load ld, Store st, int npoly, hipStream_t s)
     else
         hipLaunchKernelGGL((k_ntt_inv<13, Load, Store>), dim3(npoly), dim3(kNttThreads), 0, s, ld,
                            st, c.dp);
+    return check_hip(hipGetLastError(), "ntt_inv launch");
+}
+
+template <class Load, class Epi>
+int launch_inv_lds(const Ctx &c, Load ld, Epi epi, int npoly, hipStream_t s)
+{
+    if (npoly <= 0) return PIMM_OK;
+    ProfScope prof("ntt_inv", s);
+    if (c.dp.logN == 12)
+        hipLaunchKernelGGL((k_ntt_inv_lds<12, Load, Epi>), dim3(npoly), dim3(kNttThreads), 0, s, ld,
+                           epi, c.dp);
+    else
+        hipLaunchKernelGGL((k_ntt_inv_lds<13, Load, Epi>), dim3(npoly), dim3(kNttThreads), 0, s, ld,
+                           epi, c.dp);
     return check_hip(hipGetLastError(), "ntt_inv launch");
 }
 

@@ -82,7 +82,7 @@ struct StoreAddErr {
         const uint64_t q = (uint64_t)p;
         const size_t at = ((size_t)poly << logn) + j;
         const uint64_t up = to_canonical(v, p, pinv);
-        const uint64_t ee = lift_signed(e[((size_t)(poly / L) << logn) + j], q);
+        const uint64_t ee = lift_small(e[((size_t)(poly / L) << logn) + j], q);
         acc[at] = add_mod(add_mod(acc[at], up, q), ee, q);
     }
 };
@@ -132,44 +132,42 @@ struct LoadAccRerand {
     }
 };
 
-// n / d for n * d < 2^32 by one multiply-high: M = ceil(2^32 / d) (d = 1 is kept apart,
-// its M would not fit in 32 bits).
-struct FastDiv {
-    uint32_t d, M;
-    static FastDiv make(uint32_t d)
-    {
-        return FastDiv{d, d == 1 ? 0u : (uint32_t)(((1ull << 32) + d - 1) / d)};
-    }
-    __device__ __forceinline__ uint32_t div(uint32_t n) const { return d == 1 ? n : __umulhi(n, M); }
-    __device__ __forceinline__ uint32_t mod(uint32_t n) const { return n - div(n) * d; }
-};
-
-// Coefficient j of component comp, prime l of output ciphertext y: add the
-// re-randomisation error, then write c1 (comp 1, every j) or, at a decoded
-// position (comp 0), the unmasked c0 into its reply slot.
-struct StoreReply {
+// The reply of output ciphertext y from its coefficient form in LDS: add the
+// re-randomisation error, then write c1 (component 1, every coefficient) or
+// the unmasked c0 at the m_b n_b decoded positions k*mb*rb + i*rb + rb - 1
+// (component 0).
+struct ReplyOut {
     uint64_t *c1, *c0s;
     const int64_t *e;  // [O][2][N]
-    FastDiv rb, mbrb, mb;
-    uint32_t nb;
+    FastDiv mb;
+    uint32_t rb, nb;
     int logn, L, rr;
-    __device__ void operator()(int poly, int l, int j, double v, double p, double pinv) const
+    __device__ void operator()(int poly, const double *lds, const DevParams &dp) const
     {
-        const uint64_t q = (uint64_t)p;
+        const int l = poly % L;
         const uint32_t y = (uint32_t)(poly / (2 * L)), comp = (uint32_t)((poly / L) % 2);
-        const uint32_t uj = (uint32_t)j;
-        if (comp == 0) {
-            if (rb.mod(uj) != rb.d - 1) return;
-            if (mbrb.div(uj) >= nb) return;
-        }
-        uint64_t x = to_canonical(v, p, pinv);
-        if (rr) x = add_mod(x, lift_signed(e[(((size_t)y * 2 + comp) << logn) + j], q), q);
+        const double p = dp.p[l], pinv = dp.pinv[l];
+        const uint64_t q = dp.q[l];
+        const int64_t *ey = e + (((size_t)y * 2 + comp) << logn);
+        const int n = 1 << logn;
         if (comp == 1) {
-            c1[(((size_t)y * L + l) << logn) + j] = x;
+            uint64_t *dst = c1 + (((size_t)y * L + l) << logn);
+            for (int j = threadIdx.x; j < n; j += kNttThreads) {
+                uint64_t x = to_canonical(lds[lds_idx(j)], p, pinv);
+                if (rr) x = add_mod(x, lift_small(ey[j], q), q);
+                dst[j] = x;
+            }
             return;
         }
-        const uint32_t k = mbrb.div(uj), i = mb.mod(rb.div(uj));
-        c0s[((size_t)y * L + l) * mb.d * nb + k * mb.d + i] = x;
+        const uint32_t per = mb.d * nb;
+        uint64_t *dst = c0s + ((size_t)y * L + l) * per;
+        for (uint32_t idx = threadIdx.x; idx < per; idx += kNttThreads) {
+            const uint32_t k = mb.div(idx), i = idx - k * mb.d;
+            const uint32_t j = (k * mb.d + i) * rb + rb - 1;
+            uint64_t x = to_canonical(lds[lds_idx((int)j)], p, pinv);
+            if (rr) x = add_mod(x, lift_small(ey[j], q), q);
+            dst[idx] = x;
+        }
     }
 };
 
@@ -379,11 +377,10 @@ int pimm_matmul_share(const pimm_plan *plan, const pimm_weights *w, const uint64
         if (!rc) rc = launch_sample(c, 2, key, kTagRrE2, op_id, 0, (int)f.O, 0, 1, e + N, 2 * N, 0, s);
         if (!rc) rc = launch_fwd(c, LoadI64Shared{u, lg, (int)L}, StoreSlots{uh, lg}, (int)(f.O * L), s);
     }
-    if (!rc) {
-        StoreReply st{c1, c0s, e, FastDiv::make(f.rb), FastDiv::make(f.mb * f.rb), FastDiv::make(f.mb),
-                      f.nb, lg, (int)L, rr};
-        rc = launch_inv(c, LoadAccRerand{ah, uh, pkh, lg, (int)L, rr}, st, (int)(f.O * 2 * L), s);
-    }
+    if (!rc)
+        rc = launch_inv_lds(c, LoadAccRerand{ah, uh, pkh, lg, (int)L, rr},
+                            ReplyOut{c1, c0s, e, FastDiv::make(f.mb), f.rb, f.nb, lg, (int)L, rr},
+                            (int)(f.O * 2 * L), s);
     if (!rc) {
         const uint32_t blocks = (f.mb * f.rb * f.nb + 7) / 8;
         const size_t total = (size_t)f.O * blocks;
