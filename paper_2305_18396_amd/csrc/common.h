@@ -18,8 +18,6 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <mutex>
-
 #include "pimm.h"
 
 namespace pimm {
@@ -230,13 +228,6 @@ struct Ctx {
     double *d_tw = nullptr;   // [2][L][N] device: forward then inverse twiddles
     uint64_t q[kMaxL];
     uint64_t psi[kMaxL];
-    // A second stream of the context's device for work that can run beside the
-    // caller's stream (the re-randomisation chain of the fused server step), with
-    // the fork / join events and a lock that keeps one fork-join sequence at a
-    // time on it.
-    hipStream_t side = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
-    std::mutex *side_mu = nullptr;
 };
 
 struct Plan {

@@ -483,36 +483,25 @@ int pimm_sync(void *stream)
     return check_hip(hipStreamSynchronize((hipStream_t)stream), "stream synchronize");
 }
 
-int pimm_ctx_destroy(pimm_ctx *ctx)
-{
-    if (!ctx) return PIMM_OK;
-    if (ctx->side) (void)hipStreamSynchronize(ctx->side);
-    if (ctx->d_tw) (void)hipFree(ctx->d_tw);
-    if (ctx->fork) (void)hipEventDestroy(ctx->fork);
-    if (ctx->join) (void)hipEventDestroy(ctx->join);
-    if (ctx->side) (void)hipStreamDestroy(ctx->side);
-    delete ctx->side_mu;
-    delete ctx;
-    return PIMM_OK;
-}
-
 int pimm_ctx_create(const pimm_params *params, int device, pimm_ctx **out)
 {
     if (!params || !out) return set_error(PIMM_E_ARG, "pimm_ctx_create: NULL argument");
     pimm_ctx *c = new pimm_ctx();
     int rc = build_context(*params, device, c, true);
-    if (!rc)
-        rc = check_hip(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking), "side stream");
-    if (!rc)
-        rc = check_hip(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming), "fork event");
-    if (!rc)
-        rc = check_hip(hipEventCreateWithFlags(&c->join, hipEventDisableTiming), "join event");
     if (rc) {
-        pimm_ctx_destroy(c);
+        if (c->d_tw) (void)hipFree(c->d_tw);
+        delete c;
         return rc;
     }
-    c->side_mu = new std::mutex();
     *out = c;
+    return PIMM_OK;
+}
+
+int pimm_ctx_destroy(pimm_ctx *ctx)
+{
+    if (!ctx) return PIMM_OK;
+    if (ctx->d_tw) (void)hipFree(ctx->d_tw);
+    delete ctx;
     return PIMM_OK;
 }
 

@@ -12,8 +12,6 @@
 // accumulators.
 #include <string.h>
 
-#include <mutex>
-
 #include "common.h"
 #include "mac.h"
 #include "ntt.h"
@@ -370,37 +368,14 @@ int pimm_matmul_share(const pimm_plan *plan, const pimm_weights *w, const uint64
     int64_t *u = (int64_t *)(uh + (size_t)f.O * L * N);
     int64_t *e = u + (size_t)f.O * N;
     const Key key = make_key(seed);
-    // The re-randomisation chain (pk^, u, e1, e2, u^) does not depend on the inputs:
-    // it runs on the context's side stream, forked from and joined back into the
-    // caller's stream, beside the forward transforms and the product.
-    std::unique_lock<std::mutex> side_lock;
-    int rc = PIMM_OK;
-    if (rr) {
-        side_lock = std::unique_lock<std::mutex>(*c.side_mu);
-        hipStream_t t = c.side;
-        rc = check_hip(hipEventRecord(c.fork, s), "fork record");
-        if (!rc) rc = check_hip(hipStreamWaitEvent(t, c.fork, 0), "fork wait");
-        if (!rc) {
-            rc = launch_fwd(c, LoadU64{pk, lg}, StoreSlots{pkh, lg}, (int)(2 * L), t);
-            if (!rc) rc = launch_sample(c, 1, key, kTagRrU, op_id, 0, (int)f.O, 0, 1, u, N, 0, t);
-            if (!rc) rc = launch_sample(c, 2, key, kTagRrE1, op_id, 0, (int)f.O, 0, 1, e, 2 * N, 0, t);
-            if (!rc)
-                rc = launch_sample(c, 2, key, kTagRrE2, op_id, 0, (int)f.O, 0, 1, e + N, 2 * N, 0, t);
-            if (!rc)
-                rc = launch_fwd(c, LoadI64Shared{u, lg, (int)L}, StoreSlots{uh, lg}, (int)(f.O * L), t);
-            // Recorded whatever happened above, so that the join below covers every
-            // side launch this call made.
-            const int jr = check_hip(hipEventRecord(c.join, t), "join record");
-            if (!rc) rc = jr;
-        }
-    }
-    if (!rc) rc = launch_fwd(c, LoadU64{ct, lg}, StoreCtTiled{ch, lg, (int)L, f.K, f.R}, (int)(f.I * 2 * L), s);
+    int rc = launch_fwd(c, LoadU64{ct, lg}, StoreCtTiled{ch, lg, (int)L, f.K, f.R}, (int)(f.I * 2 * L), s);
     if (!rc) rc = launch_mac(c, f, plan->mac_rows, plan->mac_cols, plan->waves, w->d_w_hat, ch, ah, s);
-    if (rr) {
-        // Join even after an error above, so the side stream never runs ahead of
-        // a later call's use of this workspace.
-        const int jr = check_hip(hipStreamWaitEvent(s, c.join, 0), "join wait");
-        if (!rc) rc = jr;
+    if (!rc && rr) {
+        rc = launch_fwd(c, LoadU64{pk, lg}, StoreSlots{pkh, lg}, (int)(2 * L), s);
+        if (!rc) rc = launch_sample(c, 1, key, kTagRrU, op_id, 0, (int)f.O, 0, 1, u, N, 0, s);
+        if (!rc) rc = launch_sample(c, 2, key, kTagRrE1, op_id, 0, (int)f.O, 0, 1, e, 2 * N, 0, s);
+        if (!rc) rc = launch_sample(c, 2, key, kTagRrE2, op_id, 0, (int)f.O, 0, 1, e + N, 2 * N, 0, s);
+        if (!rc) rc = launch_fwd(c, LoadI64Shared{u, lg, (int)L}, StoreSlots{uh, lg}, (int)(f.O * L), s);
     }
     if (!rc)
         rc = launch_inv_lds(c, LoadAccRerand{ah, uh, pkh, lg, (int)L, rr},

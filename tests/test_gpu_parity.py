@@ -366,8 +366,8 @@ def test_fused_server_step_equals_two_calls(orc, name):
     ct = pimm.encrypt(plan, sk, cs, 5, pimm.encode_input(plan, pimm.to_device_u64(X)))
     w = pimm.Weights(plan, pimm.to_device_u64(W))
     c1, c0s, y1 = pimm.mask_share(plan, pk, ss, 5, pimm.matmul(plan, w, ct))
-    # Poison the shared workspace: the fused call must fill every scratch word it
-    # reads (its re-randomisation chain runs on a second stream) before reading it.
+    # Poison the shared workspace: the fused call must write every scratch word
+    # before it reads it.
     plan.workspace().fill_(-1)
     d1, d0s, z1 = pimm.matmul_share(plan, w, pk, ss, 5, ct)
     for a, b in [(c1, d1), (c0s, d0s), (y1, z1)]:
