@@ -4,9 +4,6 @@
 
 namespace pimm {
 
-int launch_sample(const Ctx &c, int kind, const Key &key, uint32_t tag, uint32_t op, uint32_t obj0,
-                  int nobj, int prime0, int nprime, void *out, size_t obj_stride,
-                  size_t prime_stride, hipStream_t s);
 
 // ---- encode (Algorithm 1 step 1, pi_B) -------------------------------------------
 
@@ -239,10 +236,12 @@ int pimm_encrypt(const pimm_plan *plan, const pimm_sk *sk, const uint8_t seed[32
     double *ah = (double *)ws;
     int64_t *e = (int64_t *)(ah + (size_t)f.I * L * N);
     const Key key = make_key(seed);
-    // c1 = a: uniform per prime, written straight into the ciphertexts.
-    int rc = launch_sample(c, 0, key, kTagEncA, op_id, 0, (int)f.I, 0, (int)L, ct + L * N, 2 * L * N,
-                           N, s);
-    if (!rc) rc = launch_sample(c, 2, key, kTagEncE, op_id, 0, (int)f.I, 0, 1, e, N, 0, s);
+    // c1 = a (uniform per prime, written straight into the ciphertexts) and e, in one launch.
+    SampleJobs js{};
+    js.n = 2;
+    js.job[0] = SampleJob{0, kTagEncA, 0, (int)f.I, 0, (int)L, ct + L * N, 2 * L * N, N, 0};
+    js.job[1] = SampleJob{2, kTagEncE, 0, (int)f.I, 0, 1, e, N, 0, 0};
+    int rc = launch_samples(c, key, op_id, js, s);
     if (!rc)
         rc = launch_fwd(c, LoadCtComp{ct, lg, (int)L, 1}, StoreSlots{ah, lg}, (int)(f.I * L), s);
     if (!rc) {

@@ -274,10 +274,32 @@ class ProfScope {
     bool active_ = false;
 };
 
+// One sampling job (see k_sample): `nobj` objects x `nprime` primes of draws
+// from stream (tag, prime, op, obj0 + o), written at out + o * obj_stride +
+// prime_index * prime_stride.
+constexpr int kMaxSampleJobs = 3;
+struct SampleJob {
+    int kind;
+    uint32_t tag, obj0;
+    int nobj, prime0, nprime;
+    void *out;
+    size_t obj_stride, prime_stride;
+    uint32_t blocks;  // workgroups of this job (set by launch_samples)
+};
+struct SampleJobs {
+    SampleJob job[kMaxSampleJobs];
+    int n;
+};
+int launch_samples(const Ctx &c, const Key &key, uint32_t op, SampleJobs js, hipStream_t s);
+int launch_sample(const Ctx &c, int kind, const Key &key, uint32_t tag, uint32_t op, uint32_t obj0,
+                  int nobj, int prime0, int nprime, void *out, size_t obj_stride,
+                  size_t prime_stride, hipStream_t s);
+
 // Launch helpers implemented in the kernel translation units.
 // Slot-wise products of one plan into zeroed-then-accumulated acc^ (mac.hip).
+// The product of one plan (acc^ zeroed first unless `zeroed` says the caller did).
 int launch_mac(const Ctx &c, const pimm_plan_info &f, int G, int KB, int waves, const double *Wt,
-               const double *Ct, double *Ah, hipStream_t s);
+               const double *Ct, double *Ah, bool zeroed, hipStream_t s);
 
 }  // namespace pimm
 

@@ -370,70 +370,86 @@ bool noise_ok(const Ctx &c, const pimm_plan_info &f, uint64_t wmax)
 // KIND 0 writes four uniform residues mod q_prime (uint64), 1 eight ternary
 // values (int64), 2 eight Gaussian values (int64), 3 eight Z_{2^l} values (uint64).
 template <int KIND>
-__global__ void k_sample(Key key, uint32_t tag, uint32_t op, uint32_t obj0, int nobj, int prime0,
-                         int nprime, void *out, size_t obj_stride, size_t prime_stride, DevParams dp)
+__device__ __forceinline__ void sample_block(const Key &key, uint32_t op, const SampleJob &jb,
+                                             long gid, const DevParams &dp)
 {
     const int per = KIND == 0 ? 4 : 8;
     const int nblk = dp.N / per;
-    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (long)nblk * nprime * nobj) return;
+    if (gid >= (long)nblk * jb.nprime * jb.nobj) return;
     const int b = (int)(gid % nblk);
-    const int li = (int)((gid / nblk) % nprime);
-    const int l = prime0 + li;
-    const int o = (int)(gid / ((long)nblk * nprime));
+    const int li = (int)((gid / nblk) % jb.nprime);
+    const int l = jb.prime0 + li;
+    const int o = (int)(gid / ((long)nblk * jb.nprime));
     uint32_t w[16];
-    chacha_block(key, (uint32_t)b, nonce0(tag, KIND == 0 ? (uint32_t)l : 0u), op, obj0 + (uint32_t)o,
-                 w);
-    const size_t base = (size_t)o * obj_stride + (size_t)li * prime_stride + (size_t)b * per;
+    chacha_block(key, (uint32_t)b, nonce0(jb.tag, KIND == 0 ? (uint32_t)l : 0u), op,
+                 jb.obj0 + (uint32_t)o, w);
+    const size_t base = (size_t)o * jb.obj_stride + (size_t)li * jb.prime_stride + (size_t)b * per;
     if (KIND == 0) {
-        uint64_t *dst = (uint64_t *)out + base;
+        uint64_t *dst = (uint64_t *)jb.out + base;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
             dst[i] = mod_u128(word64(w, 2 * i), word64(w, 2 * i + 1), dp.q[l], dp.p[l], dp.pinv[l]);
     } else if (KIND == 1) {
-        int64_t *dst = (int64_t *)out + base;
+        int64_t *dst = (int64_t *)jb.out + base;
 #pragma unroll
         for (int i = 0; i < 8; ++i) dst[i] = ternary_of(word64(w, i));
     } else if (KIND == 2) {
-        int64_t *dst = (int64_t *)out + base;
+        int64_t *dst = (int64_t *)jb.out + base;
 #pragma unroll
         for (int i = 0; i < 8; ++i) dst[i] = gauss_of(word64(w, i), dp.cdt);
     } else {
-        uint64_t *dst = (uint64_t *)out + base;
+        uint64_t *dst = (uint64_t *)jb.out + base;
 #pragma unroll
         for (int i = 0; i < 8; ++i) dst[i] = mask_of(word64(w, i), dp.ell);
     }
+}
+
+// Up to kMaxSampleJobs independent sampling jobs of one party and operation in
+// one launch: workgroups [first_k, first_k + blocks_k) serve job k.
+__global__ __launch_bounds__(256) void k_sample(Key key, uint32_t op, SampleJobs js, DevParams dp)
+{
+    uint32_t b = blockIdx.x;
+    int k = 0;
+    while (k + 1 < js.n && b >= js.job[k].blocks) {
+        b -= js.job[k].blocks;
+        ++k;
+    }
+    const SampleJob &jb = js.job[k];
+    const long gid = (long)b * blockDim.x + threadIdx.x;
+    switch (jb.kind) {
+    case 0: sample_block<0>(key, op, jb, gid, dp); break;
+    case 1: sample_block<1>(key, op, jb, gid, dp); break;
+    case 2: sample_block<2>(key, op, jb, gid, dp); break;
+    default: sample_block<3>(key, op, jb, gid, dp); break;
+    }
+}
+
+int launch_samples(const Ctx &c, const Key &key, uint32_t op, SampleJobs js, hipStream_t s)
+{
+    if (js.n < 1 || js.n > kMaxSampleJobs) return set_error(PIMM_E_ARG, "launch_samples: %d jobs", js.n);
+    const int threads = 256;
+    unsigned grid = 0;
+    for (int k = 0; k < js.n; ++k) {
+        SampleJob &jb = js.job[k];
+        const int per = jb.kind == 0 ? 4 : 8;
+        const long total = jb.nobj > 0 ? (long)(c.dp.N / per) * jb.nprime * jb.nobj : 0;
+        jb.blocks = (uint32_t)((total + threads - 1) / threads);
+        grid += jb.blocks;
+    }
+    if (!grid) return PIMM_OK;
+    ProfScope prof("sample", s);
+    hipLaunchKernelGGL(k_sample, dim3(grid), dim3(threads), 0, s, key, op, js, c.dp);
+    return check_hip(hipGetLastError(), "sample launch");
 }
 
 int launch_sample(const Ctx &c, int kind, const Key &key, uint32_t tag, uint32_t op, uint32_t obj0,
                   int nobj, int prime0, int nprime, void *out, size_t obj_stride,
                   size_t prime_stride, hipStream_t s)
 {
-    if (nobj <= 0) return PIMM_OK;
-    const int per = kind == 0 ? 4 : 8;
-    const long total = (long)(c.dp.N / per) * nprime * nobj;
-    const int threads = 256;
-    const dim3 grid((unsigned)((total + threads - 1) / threads));
-    ProfScope prof("sample", s);
-    switch (kind) {
-    case 0:
-        hipLaunchKernelGGL(k_sample<0>, grid, dim3(threads), 0, s, key, tag, op, obj0, nobj, prime0,
-                           nprime, out, obj_stride, prime_stride, c.dp);
-        break;
-    case 1:
-        hipLaunchKernelGGL(k_sample<1>, grid, dim3(threads), 0, s, key, tag, op, obj0, nobj, prime0,
-                           nprime, out, obj_stride, prime_stride, c.dp);
-        break;
-    case 2:
-        hipLaunchKernelGGL(k_sample<2>, grid, dim3(threads), 0, s, key, tag, op, obj0, nobj, prime0,
-                           nprime, out, obj_stride, prime_stride, c.dp);
-        break;
-    default:
-        hipLaunchKernelGGL(k_sample<3>, grid, dim3(threads), 0, s, key, tag, op, obj0, nobj, prime0,
-                           nprime, out, obj_stride, prime_stride, c.dp);
-        break;
-    }
-    return check_hip(hipGetLastError(), "sample launch");
+    SampleJobs js{};
+    js.n = 1;
+    js.job[0] = SampleJob{kind, tag, obj0, nobj, prime0, nprime, out, obj_stride, prime_stride, 0};
+    return launch_samples(c, key, op, js, s);
 }
 
 // pk0[l][j] = [e'_j - (a' s)_j]_{q_l}: storer of the inverse NTT of a'^ s^.

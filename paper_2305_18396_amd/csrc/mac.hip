@@ -47,7 +47,7 @@ __global__ void k_fill_zero(double *p, size_t n)
 
 template <int G, int KB>
 int launch_mac_gk(const Ctx &c, const pimm_plan_info &f, int waves, const double *Wt,
-                  const double *Ct, double *Ah, hipStream_t s)
+                  const double *Ct, double *Ah, bool zeroed, hipStream_t s)
 {
     const MacShape sh{(int)f.M, (int)f.R, (int)f.K, (int)(c.params.N >> 8)};
     const int mtiles = (int)((f.M + G - 1) / G), ktiles = (int)((f.K + KB - 1) / KB);
@@ -60,8 +60,10 @@ int launch_mac_gk(const Ctx &c, const pimm_plan_info &f, int waves, const double
     const uint64_t min_per = (f.R + 10) / 11;  // at most 12 pieces per tile
     if (per < min_per) per = min_per;
     grid = (total + per - 1) / per;
-    const size_t acc_n = (size_t)f.O * 2 * c.params.L * c.params.N;
-    hipLaunchKernelGGL(k_fill_zero, dim3(1024), dim3(256), 0, s, Ah, acc_n);
+    if (!zeroed) {
+        const size_t acc_n = (size_t)f.O * 2 * c.params.L * c.params.N;
+        hipLaunchKernelGGL(k_fill_zero, dim3(1024), dim3(256), 0, s, Ah, acc_n);
+    }
     ProfScope prof("mac", s);
     hipLaunchKernelGGL((k_mac_sk<G, KB>), dim3((unsigned)grid), dim3(256), 0, s, Wt, Ct, Ah, sh,
                        mtiles, ktiles, total, per, c.dp);
@@ -69,10 +71,10 @@ int launch_mac_gk(const Ctx &c, const pimm_plan_info &f, int waves, const double
 }
 
 int launch_mac(const Ctx &c, const pimm_plan_info &f, int G, int KB, int waves, const double *Wt,
-               const double *Ct, double *Ah, hipStream_t s)
+               const double *Ct, double *Ah, bool zeroed, hipStream_t s)
 {
 #define PIMM_LAUNCH_MAC(g, kb) \
-    if (G == g && KB == kb) return launch_mac_gk<g, kb>(c, f, waves, Wt, Ct, Ah, s);
+    if (G == g && KB == kb) return launch_mac_gk<g, kb>(c, f, waves, Wt, Ct, Ah, zeroed, s);
     PIMM_MAC_SHAPES(PIMM_LAUNCH_MAC)
 #undef PIMM_LAUNCH_MAC
     return set_error(PIMM_E_ARG, "product tile %dx%d is not built", G, KB);

@@ -214,6 +214,21 @@ __global__ __launch_bounds__(kNttThreads) void k_ntt_fwd(Load ld, Store st, DevP
     ntt_fwd_block<LOGN>(ld, st, dp, (int)blockIdx.x, lds);
 }
 
+// Forward transform that also clears its share of another buffer (the
+// product's accumulators), saving a launch: workgroup b zeroes
+// zero[b * per, (b + 1) * per), per = ceil(zero_n / gridDim.x).
+template <int LOGN, class Load, class Store>
+__global__ __launch_bounds__(kNttThreads) void k_ntt_fwd_zero(Load ld, Store st, double *zero,
+                                                              size_t zero_n, DevParams dp)
+{
+    __shared__ double lds[NttPasses<LOGN>::LDS];
+    ntt_fwd_block<LOGN>(ld, st, dp, (int)blockIdx.x, lds);
+    const size_t per = (zero_n + gridDim.x - 1) / gridDim.x;
+    const size_t b = (size_t)blockIdx.x * per;
+    const size_t e = b + per < zero_n ? b + per : zero_n;
+    for (size_t i = b + threadIdx.x; i < e; i += kNttThreads) zero[i] = 0.0;
+}
+
 template <int LOGN, class Load, class Store>
 __global__ __launch_bounds__(kNttThreads) void k_ntt_inv(Load ld, Store st, DevParams dp)
 {
@@ -318,6 +333,21 @@ int launch_fwd(const Ctx &c, Load ld, Store st, int npoly, hipStream_t s)
     else
         hipLaunchKernelGGL((k_ntt_fwd<13, Load, Store>), dim3(npoly), dim3(kNttThreads), 0, s, ld,
                            st, c.dp);
+    return check_hip(hipGetLastError(), "ntt_fwd launch");
+}
+
+template <class Load, class Store>
+int launch_fwd_zero(const Ctx &c, Load ld, Store st, int npoly, double *zero, size_t zero_n,
+                    hipStream_t s)
+{
+    if (npoly <= 0) return PIMM_OK;
+    ProfScope prof("ntt_fwd", s);
+    if (c.dp.logN == 12)
+        hipLaunchKernelGGL((k_ntt_fwd_zero<12, Load, Store>), dim3(npoly), dim3(kNttThreads), 0, s,
+                           ld, st, zero, zero_n, c.dp);
+    else
+        hipLaunchKernelGGL((k_ntt_fwd_zero<13, Load, Store>), dim3(npoly), dim3(kNttThreads), 0, s,
+                           ld, st, zero, zero_n, c.dp);
     return check_hip(hipGetLastError(), "ntt_fwd launch");
 }
 

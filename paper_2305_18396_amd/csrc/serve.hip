@@ -38,9 +38,6 @@
 
 namespace pimm {
 
-int launch_sample(const Ctx &c, int kind, const Key &key, uint32_t tag, uint32_t op, uint32_t obj0,
-                  int nobj, int prime0, int nprime, void *out, size_t obj_stride,
-                  size_t prime_stride, hipStream_t s);
 int keygen_into(const Ctx &c, const Key &key, int64_t *s, double *s_hat, uint64_t *pk, double *tmp,
                 int64_t *e, hipStream_t st);
 

@@ -18,9 +18,6 @@
 
 namespace pimm {
 
-int launch_sample(const Ctx &c, int kind, const Key &key, uint32_t tag, uint32_t op, uint32_t obj0,
-                  int nobj, int prime0, int nprime, void *out, size_t obj_stride,
-                  size_t prime_stride, hipStream_t s);
 
 // ---- weights (Algorithm 1 step 1, pi_A) ---------------------------------------------
 
@@ -59,6 +56,19 @@ __global__ void k_absmax(const int64_t *W, size_t n, unsigned long long *out)
 
 // ---- re-randomisation, mask and extraction --------------------------------------
 
+// The re-randomisation draws of every output ciphertext y in one launch: u_y
+// (ternary, stream RR_U) into u [O][N], e1_y and e2_y (Gaussian, RR_E1 / RR_E2)
+// into e [O][2][N].
+static SampleJobs rerand_jobs(uint32_t O, size_t N, int64_t *u, int64_t *e)
+{
+    SampleJobs js{};
+    js.n = 3;
+    js.job[0] = SampleJob{1, kTagRrU, 0, (int)O, 0, 1, u, N, 0, 0};
+    js.job[1] = SampleJob{2, kTagRrE1, 0, (int)O, 0, 1, e, 2 * N, 0, 0};
+    js.job[2] = SampleJob{2, kTagRrE2, 0, (int)O, 0, 1, e + N, 2 * N, 0, 0};
+    return js;
+}
+
 // Pointwise u^[o][l] * pk^[comp][l] for polynomials [O][2][L].
 struct LoadRerand {
     const double *uh;   // [O][L][N]
@@ -69,6 +79,21 @@ struct LoadRerand {
         const size_t o = (size_t)(poly / (2 * L));
         const size_t comp = (size_t)((poly / L) % 2);
         return mulmod(uh[((o * L + l) << logn) + z], pkh[((comp * L + l) << logn) + z], p, pinv);
+    }
+};
+
+// Inputs of the re-randomisation transforms as one polynomial list: the 2L
+// polynomials of pk (canonical residues, [2][L][N]) then, for each output
+// ciphertext, u shared by the L primes (int64 [O][N]).  Polynomial index poly
+// keeps prime poly % L in both parts (2L is a multiple of L).
+struct LoadPkU {
+    const uint64_t *pk;
+    const int64_t *u;
+    int logn, L;
+    __device__ double operator()(int poly, int, int j, double, double) const
+    {
+        if (poly < 2 * L) return (double)pk[((size_t)poly << logn) + j];
+        return (double)u[((size_t)((poly - 2 * L) / L) << logn) + j];
     }
 };
 
@@ -285,9 +310,10 @@ int pimm_matmul(const pimm_plan *plan, const pimm_weights *w, const uint64_t *ct
     const int lg = c.dp.logN;
     double *ch = (double *)ws;
     double *ah = ch + (size_t)f.I * 2 * L * N;
-    int rc = launch_fwd(c, LoadU64{ct, lg}, StoreCtTiled{ch, lg, (int)L, f.K, f.R},
-                        (int)(f.I * 2 * L), s);
-    if (!rc) rc = launch_mac(c, f, plan->mac_rows, plan->mac_cols, plan->waves, w->d_w_hat, ch, ah, s);
+    int rc = launch_fwd_zero(c, LoadU64{ct, lg}, StoreCtTiled{ch, lg, (int)L, f.K, f.R},
+                             (int)(f.I * 2 * L), ah, (size_t)f.O * 2 * L * N, s);
+    if (!rc)
+        rc = launch_mac(c, f, plan->mac_rows, plan->mac_cols, plan->waves, w->d_w_hat, ch, ah, true, s);
     if (!rc) rc = launch_inv(c, LoadSlotsReduce{ah, lg}, StoreU64{acc, lg}, (int)(f.O * 2 * L), s);
     return rc;
 }
@@ -316,12 +342,10 @@ int pimm_mask_share(const pimm_plan *plan, const uint64_t *pk, const uint8_t see
         double *uh = pkh + 2 * L * N;
         int64_t *u = (int64_t *)(uh + (size_t)f.O * L * N);
         int64_t *e = u + (size_t)f.O * N;
-        rc = launch_fwd(c, LoadU64{pk, lg}, StoreSlots{pkh, lg}, (int)(2 * L), s);
-        if (!rc) rc = launch_sample(c, 1, key, kTagRrU, op_id, 0, (int)f.O, 0, 1, u, N, 0, s);
-        if (!rc) rc = launch_sample(c, 2, key, kTagRrE1, op_id, 0, (int)f.O, 0, 1, e, 2 * N, 0, s);
-        if (!rc) rc = launch_sample(c, 2, key, kTagRrE2, op_id, 0, (int)f.O, 0, 1, e + N, 2 * N, 0, s);
+        rc = launch_samples(c, key, op_id, rerand_jobs(f.O, N, u, e), s);
+        // pk^ and u^ in one launch: they are adjacent in the workspace.
         if (!rc)
-            rc = launch_fwd(c, LoadI64Shared{u, lg, (int)L}, StoreSlots{uh, lg}, (int)(f.O * L), s);
+            rc = launch_fwd(c, LoadPkU{pk, u, lg, (int)L}, StoreSlots{pkh, lg}, (int)((2 + f.O) * L), s);
         if (!rc)
             rc = launch_inv(c, LoadRerand{uh, pkh, lg, (int)L}, StoreAddErr{acc, e, lg, (int)L},
                             (int)(f.O * 2 * L), s);
@@ -368,14 +392,15 @@ int pimm_matmul_share(const pimm_plan *plan, const pimm_weights *w, const uint64
     int64_t *u = (int64_t *)(uh + (size_t)f.O * L * N);
     int64_t *e = u + (size_t)f.O * N;
     const Key key = make_key(seed);
-    int rc = launch_fwd(c, LoadU64{ct, lg}, StoreCtTiled{ch, lg, (int)L, f.K, f.R}, (int)(f.I * 2 * L), s);
-    if (!rc) rc = launch_mac(c, f, plan->mac_rows, plan->mac_cols, plan->waves, w->d_w_hat, ch, ah, s);
+    int rc = launch_fwd_zero(c, LoadU64{ct, lg}, StoreCtTiled{ch, lg, (int)L, f.K, f.R},
+                             (int)(f.I * 2 * L), ah, (size_t)f.O * 2 * L * N, s);
+    if (!rc)
+        rc = launch_mac(c, f, plan->mac_rows, plan->mac_cols, plan->waves, w->d_w_hat, ch, ah, true, s);
     if (!rc && rr) {
-        rc = launch_fwd(c, LoadU64{pk, lg}, StoreSlots{pkh, lg}, (int)(2 * L), s);
-        if (!rc) rc = launch_sample(c, 1, key, kTagRrU, op_id, 0, (int)f.O, 0, 1, u, N, 0, s);
-        if (!rc) rc = launch_sample(c, 2, key, kTagRrE1, op_id, 0, (int)f.O, 0, 1, e, 2 * N, 0, s);
-        if (!rc) rc = launch_sample(c, 2, key, kTagRrE2, op_id, 0, (int)f.O, 0, 1, e + N, 2 * N, 0, s);
-        if (!rc) rc = launch_fwd(c, LoadI64Shared{u, lg, (int)L}, StoreSlots{uh, lg}, (int)(f.O * L), s);
+        rc = launch_samples(c, key, op_id, rerand_jobs(f.O, N, u, e), s);
+        // pk^ and u^ in one launch: they are adjacent in the workspace.
+        if (!rc)
+            rc = launch_fwd(c, LoadPkU{pk, u, lg, (int)L}, StoreSlots{pkh, lg}, (int)((2 + f.O) * L), s);
     }
     if (!rc)
         rc = launch_inv_lds(c, LoadAccRerand{ah, uh, pkh, lg, (int)L, rr},
