@@ -260,6 +260,97 @@ def bench_serve(args):
             "sweep": sweep, "one_at_a_time": one}
 
 
+def bench_stack(args):
+    """BERT-large / GPT-2-medium-shaped stack: `--stack-layers` encoder layers (24 by default) of
+    four products each at seq 512 (QKV 1024x3072, attn-out 1024x1024, FFN 1024x4096 and
+    4096x1024), N = 8192, three 50-bit primes, t = 2^41, 14 fractional bits, block area 1024.
+    Every layer has its own weights and weight cache (all resident at once); a step is the whole
+    stack, each product through encode, encrypt, fused server step and decrypt."""
+    import numpy as np
+    import torch
+
+    from paper_2305_18396_amd import pimm, workloads
+
+    N, L, ell, f, D = 8192, 3, 41, 14, 1024
+    ctx = pimm.Context(N, L, ell, f, rerandomize=True, device=0)
+    dev = torch.device("cuda", 0)
+    cseed, sseed = workloads.seed("client", 11), workloads.seed("server", 11)
+    sk, pk = pimm.keygen(ctx, cseed)
+    shapes = workloads.BERT_LARGE_SHAPES
+    seq = 512
+    plans, bufs = [], []
+    for name, r, m in shapes:
+        plan = pimm.Plan(ctx, seq, r, m, d_fix=D)
+        fi = plan.info
+        plans.append(plan)
+        bufs.append(dict(
+            pt=torch.empty((fi.I, N), dtype=torch.int64, device=dev),
+            ct=torch.empty((fi.I, 2, L, N), dtype=torch.int64, device=dev),
+            c1=torch.empty((fi.O, L, N), dtype=torch.int64, device=dev),
+            c0s=torch.empty((fi.O, L, fi.mb * fi.nb), dtype=torch.int64, device=dev),
+            y0=torch.empty((seq, m), dtype=torch.int64, device=dev),
+            y1=torch.empty((seq, m), dtype=torch.int64, device=dev)))
+    layers = []
+    cache = 0
+    for k in range(args.stack_layers):
+        ops = workloads.bert_large_layer(seq, layer_index=k)
+        row = []
+        for i, wl in enumerate(ops):
+            w = pimm.Weights(plans[i], pimm.to_device_u64(wl.W))
+            row.append((w, pimm.to_device_u64(wl.X)))
+            cache += plans[i].info.weights_bytes
+        layers.append(row)
+    torch.cuda.synchronize()
+    log(f"stack: {args.stack_layers} layers, weight caches {cache / 1e9:.1f} GB")
+    useful = args.stack_layers * sum(seq * r * m for _, r, m in shapes)
+    slot = args.stack_layers * sum(2 * L * N * p.info.P for p in plans)
+    # One schedule per product shape, tuned on layer 0's buffers.
+    for i, plan in enumerate(plans):
+        b = bufs[i]
+        pimm.encrypt(plan, sk, cseed, 90_000 + i, pimm.encode_input(plan, layers[0][i][1], b["pt"]),
+                     b["ct"])
+        acc = torch.empty((plan.O, 2, L, N), dtype=torch.int64, device=dev)
+        best = plan.autotune(layers[0][i][0], b["ct"], acc, reps=1)
+        log(f"  {shapes[i][0]}: plan ({plan.mb},{plan.rb},{plan.nb}) K={plan.K} "
+            f"schedule {plan.tuning()} {best:.2f} ms")
+        del acc
+
+    def step(t):
+        for k, row in enumerate(layers):
+            for i, (w, X) in enumerate(row):
+                plan, b = plans[i], bufs[i]
+                op = (t * args.stack_layers + k) * 4 + i
+                pimm.encode_input(plan, X, b["pt"])
+                pimm.encrypt(plan, sk, cseed, op, b["pt"], b["ct"])
+                pimm.matmul_share(plan, w, pk, sseed, op, b["ct"], b["c1"], b["c0s"], b["y1"])
+                pimm.decrypt(plan, sk, b["c1"], b["c0s"], b["y0"])
+
+    for t in range(args.warmup):
+        step(t)
+    torch.cuda.synchronize()
+    pimm.profile_select(["mac"])
+    pimm.profile_enable(True)
+    t0 = time.perf_counter()
+    for t in range(args.steps):
+        step(args.warmup + t)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    pimm.profile_enable(False)
+    pimm.profile_select(None)
+    cnt, mac_ms = pimm.profile_read("mac")
+    mac_s = mac_ms / 1e3 / args.steps
+    return {"workload": f"BERT-large-shaped stack, {args.stack_layers} layers x 4 products at seq "
+                        f"{seq}; N={N}, {L}x50-bit primes, t=2^{ell}, {f} fractional bits, block "
+                        f"area {D}, weight caches resident",
+            "plans": [[p.mb, p.rb, p.nb] for p in plans],
+            "schedules": [list(p.tuning()) for p in plans],
+            "weight_cache_bytes": cache, "useful_macs_per_step": useful,
+            "s_per_step": el, "ms_per_layer": el * 1e3 / args.stack_layers,
+            "int_mac_per_s": useful / el, "slot_mac_per_s": slot / el,
+            "product_s_per_step": mac_s,
+            "product_slot_mac_per_s": slot / mac_s if mac_s else None}
+
+
 def bench_peak(args):
     """Sustained device rates next to the published peaks: the HBM read and copy
     bandwidth of plain streaming kernels (and of torch's own sum and copy), the FP64
@@ -308,7 +399,9 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the timed steps, copy a buffer of this many MiB device to device "
                          "(a known-size reference for hardware byte counters)")
-    ap.add_argument("--workload", choices=["layer", "batch", "serve", "peak"], default="layer")
+    ap.add_argument("--workload", choices=["layer", "batch", "serve", "peak", "stack"],
+                    default="layer")
+    ap.add_argument("--stack-layers", type=int, default=24)
     ap.add_argument("--layer-d", type=int, default=0,
                     help="layer workload: fixed block area m_b*r_b (0: the fewest-wire plan)")
     ap.add_argument("--schedules", default="",
@@ -335,6 +428,9 @@ def main():
 
     if args.workload == "batch":
         print(json.dumps({"metric": METRIC, "batch": bench_batch(args)}), flush=True)
+        return
+    if args.workload == "stack":
+        print(json.dumps({"metric": METRIC, "stack": bench_stack(args)}), flush=True)
         return
     if args.workload == "peak":
         print(json.dumps({"metric": METRIC, "peak": bench_peak(args)}), flush=True)
