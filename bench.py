@@ -122,7 +122,7 @@ def bench_batch(args):
     ctx = pimm.Context(4096, 2, 37, 12, rerandomize=True, device=0)
     wts, items = workloads.batched_uneven(count=args.batch_count)
     caches, rows = {}, []
-    useful = 0
+    useful = wire = slot = 0
     for k, it in enumerate(items):
         r, m, W = wts[it.shape_index]
         plan = pimm.Plan(ctx, it.seq, r, m, d_fix=args.d_fix)
@@ -134,6 +134,8 @@ def bench_batch(args):
         acc = torch.empty((plan.O, 2, 2, 4096), dtype=torch.int64, device="cuda")
         rows.append((plan, caches[(r, m)], ct, acc))
         useful += it.seq * r * m
+        wire += plan.info.ct_bytes + plan.info.c1_bytes + plan.info.c0s_bytes
+        slot += 2 * 2 * 4096 * plan.info.P
     torch.cuda.synchronize()
     log(f"batch: {len(rows)} items, {useful / 1e9:.2f} G useful MACs, d_fix {args.d_fix}")
 
@@ -195,7 +197,8 @@ def bench_batch(args):
     sched = dict(zip(("schedule", "mac_rows", "mac_cols", "xcd_map", "grid"), batch.get_schedule()))
     return {"workload": f"{len(rows)} products, seq uniform in [16, 512], BERT-base shapes, "
                         f"N=4096, 2 primes, block area {args.d_fix}",
-            "useful_macs": useful, "plain_ms": t_plain * 1e3, "batched_ms": t_batch * 1e3,
+            "useful_macs": useful, "slot_macs": slot, "wire_bytes": wire,
+            "plain_ms": t_plain * 1e3, "batched_ms": t_batch * 1e3,
             "graph_ms": graph_t * 1e3, "autotune_best_ms": best_ms,
             "plain_int_mac_per_s": useful / t_plain, "batched_int_mac_per_s": useful / t_batch,
             "graph_int_mac_per_s": useful / graph_t, "speedup": t_plain / t_batch,

@@ -85,8 +85,8 @@ __device__ __forceinline__ void run_mac(const BatchItemDev &it, const MacCoord &
                                         const DevParams &dp)
 {
     const MacShape sh{(int)it.M, (int)it.R, (int)it.K, dp.N >> 8};
-    mac_tile<G, KB>(it.wh, ws + it.chat_off, ws + it.ahat_off, sh, dp, c.l, c.zc, c.kbt * KB,
-                    c.ibt * G, 0, (int)it.R, 0);
+    mac_tile<G, KB>(it.wh, ws + it.chat_off, ws + it.ahat_off, sh, dp, c.l, c.zc, (int)threadIdx.x,
+                    c.kbt * KB, c.ibt * G, 0, (int)it.R, 0);
 }
 
 // ---- phased schedule ---------------------------------------------------------------

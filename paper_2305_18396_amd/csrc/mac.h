@@ -42,14 +42,13 @@ __device__ __forceinline__ size_t c_tile_base(const MacShape &s, int l, int zc, 
 template <int G, int KB>
 __device__ __forceinline__ void mac_range(const double *__restrict__ Wt, const double *__restrict__ Ct,
                                           double *__restrict__ Ah, const MacShape &s,
-                                          const DevParams &dp, int l, int zc, int kb0, int ib0,
-                                          int jb0, int jb1, int mode)
+                                          const DevParams &dp, int l, int zc, int zz, int kb0,
+                                          int ib0, int jb0, int jb1, int mode)
 {
     const int L = dp.L, N = dp.N;
     const double p = dp.p[l], pinv = dp.pinv[l];
     const int rows = s.M - ib0 < G ? s.M - ib0 : G;
     const int cols = s.K - kb0 < KB ? s.K - kb0 : KB;
-    const int zz = threadIdx.x;
     const double *wp = Wt + w_tile_base(s, l, zc) + ((size_t)ib0 * s.R + jb0) * 256 + zz;
     const double *cp = Ct + c_tile_base(s, l, zc, kb0) + (size_t)jb0 * 512 + zz;
     const size_t wrow = (size_t)s.R * 256, ccol = (size_t)s.R * 512;
@@ -158,24 +157,32 @@ __device__ __forceinline__ void mac_range(const double *__restrict__ Wt, const d
 template <int G, int KB>
 __device__ __forceinline__ void mac_tile(const double *__restrict__ Wt, const double *__restrict__ Ct,
                                          double *__restrict__ Ah, const MacShape &s,
-                                         const DevParams &dp, int l, int zc, int kb0, int ib0,
-                                         int jb0, int jb1, int mode)
+                                         const DevParams &dp, int l, int zc, int zz, int kb0,
+                                         int ib0, int jb0, int jb1, int mode)
 {
     const int cols = s.K - kb0;
     if (KB == 1 || cols >= KB) {
-        mac_range<G, KB>(Wt, Ct, Ah, s, dp, l, zc, kb0, ib0, jb0, jb1, mode);
+        mac_range<G, KB>(Wt, Ct, Ah, s, dp, l, zc, zz, kb0, ib0, jb0, jb1, mode);
         return;
     }
     if constexpr (KB >= 2) {
         constexpr int H = KB / 2;
         if (cols >= H) {
-            mac_range<G, H>(Wt, Ct, Ah, s, dp, l, zc, kb0, ib0, jb0, jb1, mode);
-            if (cols > H) mac_tile<G, H>(Wt, Ct, Ah, s, dp, l, zc, kb0 + H, ib0, jb0, jb1, mode);
+            mac_range<G, H>(Wt, Ct, Ah, s, dp, l, zc, zz, kb0, ib0, jb0, jb1, mode);
+            if (cols > H)
+                mac_tile<G, H>(Wt, Ct, Ah, s, dp, l, zc, zz, kb0 + H, ib0, jb0, jb1, mode);
         } else {
-            mac_tile<G, H>(Wt, Ct, Ah, s, dp, l, zc, kb0, ib0, jb0, jb1, mode);
+            mac_tile<G, H>(Wt, Ct, Ah, s, dp, l, zc, zz, kb0, ib0, jb0, jb1, mode);
         }
     }
 }
+
+// Row tiles per workgroup of the stream-K product.  With RT > 1 a workgroup
+// covers 256 / RT slots of a chunk for RT consecutive row tiles (one per group
+// of 256 / RT lanes), so the input words of its column tile are fetched once
+// into the CU's L1 and read by all RT row tiles; at RT = 1 it covers the whole
+// chunk for one row tile.
+__host__ __device__ constexpr int mac_rt(int G, int KB) { return KB > 1 ? 4 : 1; }
 
 // Product tile shapes (G rows, KB column blocks per thread) the library instantiates.
 #define PIMM_MAC_SHAPES(X) \

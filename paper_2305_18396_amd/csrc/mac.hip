@@ -4,14 +4,16 @@
 
 namespace pimm {
 
-// Stream-K schedule: the flattened space of (tile, inner block) iterations,
-// tile t = ((l * chunks + zc) * ktiles + kbt) * mtiles + ibt (row tiles fastest,
-// so a workgroup's consecutive tiles share their input slice), is cut into
-// equal contiguous ranges, one per workgroup of a grid sized to what the device
-// holds at once (ranges placed XCD by XCD).  A workgroup that covers a whole
-// tile stores its sums; pieces of split tiles are added atomically into the
-// zeroed accumulators.  At most 12 pieces meet in one accumulator, so the total
-// stays below 8p < 2^53.
+// Stream-K schedule: the flattened space of (tile, inner block) iterations is
+// cut into equal contiguous ranges, one per workgroup of a grid sized to what
+// the device holds at once (ranges placed XCD by XCD).  A tile is
+// (prime l, chunk zc, slot group sub, column tile kbt, row-tile group ig) with
+//     t = (((l * chunks + zc) * RT + sub) * ktiles + kbt) * mgroups + ig,
+// row-tile groups fastest, so a workgroup's consecutive tiles share their input
+// slice.  Lane group w of the workgroup takes row tile ig * RT + w.  A
+// workgroup that covers a whole tile stores its sums; pieces of split tiles
+// are added atomically into the zeroed accumulators.  At most 12 pieces meet
+// in one accumulator, so the total stays below 8p < 2^53.
 template <int G, int KB>
 __global__ __launch_bounds__(256) void k_mac_sk(const double *__restrict__ Wt,
                                                 const double *__restrict__ Ct,
@@ -19,6 +21,9 @@ __global__ __launch_bounds__(256) void k_mac_sk(const double *__restrict__ Wt,
                                                 int ktiles, uint64_t total, uint64_t per,
                                                 DevParams dp)
 {
+    constexpr int RT = mac_rt(G, KB), SPW = 256 / RT;
+    const int mgroups = (mtiles + RT - 1) / RT;
+    const int lane = (int)threadIdx.x % SPW, w = (int)threadIdx.x / SPW;
     uint64_t u = (uint64_t)xcd_local(blockIdx.x, gridDim.x) * per;
     const uint64_t end = u + per < total ? u + per : total;
     const uint64_t R = (uint64_t)sh.R;
@@ -26,14 +31,19 @@ __global__ __launch_bounds__(256) void k_mac_sk(const double *__restrict__ Wt,
         const uint64_t t = u / R;
         const int jb0 = (int)(u % R);
         const int jb1 = (int)(R - (uint64_t)jb0 < end - u ? R : (uint64_t)jb0 + (end - u));
-        const int ibt = (int)(t % mtiles);
-        uint64_t r = t / mtiles;
+        const int ig = (int)(t % mgroups);
+        uint64_t r = t / mgroups;
         const int kbt = (int)(r % ktiles);
         r /= ktiles;
+        const int sub = (int)(r % RT);
+        r /= RT;
         const int zc = (int)(r % sh.chunks);
         const int l = (int)(r / sh.chunks);
         const int mode = (jb0 == 0 && jb1 == sh.R) ? 0 : 1;
-        mac_tile<G, KB>(Wt, Ct, Ah, sh, dp, l, zc, kbt * KB, ibt * G, jb0, jb1, mode);
+        const int ibt = ig * RT + w;
+        if (ibt < mtiles)
+            mac_tile<G, KB>(Wt, Ct, Ah, sh, dp, l, zc, sub * SPW + lane, kbt * KB, ibt * G, jb0, jb1,
+                            mode);
         u += (uint64_t)(jb1 - jb0);
     }
 }
@@ -50,8 +60,10 @@ int launch_mac_gk(const Ctx &c, const pimm_plan_info &f, int waves, const double
                   const double *Ct, double *Ah, bool zeroed, hipStream_t s)
 {
     const MacShape sh{(int)f.M, (int)f.R, (int)f.K, (int)(c.params.N >> 8)};
+    constexpr int RT = mac_rt(G, KB);
     const int mtiles = (int)((f.M + G - 1) / G), ktiles = (int)((f.K + KB - 1) / KB);
-    const uint64_t total = (uint64_t)c.params.L * sh.chunks * ktiles * mtiles * f.R;
+    const uint64_t mgroups = (uint64_t)((mtiles + RT - 1) / RT);
+    const uint64_t total = (uint64_t)c.params.L * sh.chunks * RT * ktiles * mgroups * f.R;
     int per_cu = 0, cus = 0;
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mac_sk<G, KB>, 256, 0);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device);
