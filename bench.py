@@ -233,7 +233,8 @@ def bench_serve(args):
 
     def run(rate, count, max_active):
         srv = pimm.Server(ctx, args.layers, shapes, weights, args.d_fix, budget, max_active,
-                          schedule=pimm.PHASED)
+                          schedule=pimm.PHASED, mac_rows=args.serve_tile[0],
+                          mac_cols=args.serve_tile[1])
         trace = workloads.poisson_trace(rate, count)
         reqs = [(q.rid, q.seq, q.arrival_s, workloads.seed("client", 7000 + q.rid),
                  workloads.seed("server", 7000 + q.rid)) for q in trace]
@@ -258,7 +259,8 @@ def bench_serve(args):
             break
         rate *= 2
     one = run(sweep[0]["rate_per_s"], args.serve_requests, 1)
-    return {"workload": f"Poisson stream, prompt length log-uniform in [32, 512], {args.layers}-layer "
+    return {"product_tile": list(args.serve_tile),
+            "workload": f"Poisson stream, prompt length log-uniform in [32, 512], {args.layers}-layer "
                         f"BERT-base linear stack, N=4096, 2 primes, block area {args.d_fix}",
             "sweep": sweep, "one_at_a_time": one}
 
@@ -405,6 +407,8 @@ def main():
     ap.add_argument("--workload", choices=["layer", "batch", "serve", "peak", "stack"],
                     default="layer")
     ap.add_argument("--stack-layers", type=int, default=24)
+    ap.add_argument("--serve-tile", type=lambda v: tuple(int(x) for x in v.split(",")),
+                    default=(8, 4), help="serve: product tile 'rows,cols' of the batched launch")
     ap.add_argument("--layer-d", type=int, default=0,
                     help="layer workload: fixed block area m_b*r_b (0: the fewest-wire plan)")
     ap.add_argument("--schedules", default="",

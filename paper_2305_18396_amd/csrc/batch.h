@@ -15,6 +15,7 @@ struct BatchItemDev {
     uint64_t ahat_off;   // acc^ [O][2][L][N]
     uint32_t M, R, K, I, O;
     uint32_t mtiles, ktiles;    // ceil(M / G), ceil(K / KB)
+    uint32_t mgroups;           // ceil(mtiles / RT), RT = mac_rt(G, KB) row tiles per unit
     uint32_t in0, mac0, out0;   // first unit of each kind
     uint32_t dep_in0, dep_mac0; // first dependency counter of each kind
 };

@@ -4,7 +4,8 @@
 // items of any shapes and sequence lengths on one context.  Its work is the
 // union of three kinds of units:
 //   in   forward NTT of one input polynomial      (sum over items of I*2*L)
-//   mac  one slot-chunk x row tile x column tile   (sum of (N/256)*L*ceil(M/G)*ceil(K/KB))
+//   mac  one slot group x row-tile group x column tile
+//        (sum of (N/256)*L*RT*ceil(ceil(M/G)/RT)*ceil(K/KB), RT row tiles per group)
 //   out  inverse NTT of one accumulator polynomial (sum of O*2*L)
 // Two schedules run them:
 //   PHASED      three launches (all in, all mac, all out), each over a flat
@@ -13,7 +14,8 @@
 //               counter in dependency order (in, then mac, then out).  A mac
 //               unit waits until the 2R input NTTs of each column block of its
 //               column tile and prime are done; an out unit waits until the
-//               N/256 slot chunks of its (row tile, column tile) are done.  Every unit it waits for was taken
+//               mac units of its (row-tile group, column tile, prime) are
+//               done.  Every unit it waits for was taken
 //               earlier by a running workgroup that itself only waits on
 //               earlier units, so the waits always end; each wait is also
 //               bounded (a spin limit sets an error flag and every later wait
@@ -64,17 +66,21 @@ __device__ __forceinline__ void run_out(const BatchItemDev &it, int poly, double
     ntt_inv_block<LOGN>(LoadSlots{ws + it.ahat_off, LOGN}, StoreU64{it.acc, LOGN}, dp, poly, lds);
 }
 
-// mac unit t of an item -> (l, slot chunk, row tile, column tile); row tiles vary fastest.
+// mac unit t of an item -> (l, slot chunk, slot group, column tile, row-tile group), row-tile
+// groups fastest.  With RT = mac_rt(G, KB) row tiles per group, lane group w of the
+// workgroup (256 / RT lanes) takes row tile ig * RT + w over slots sub * 256 / RT ...
 struct MacCoord {
-    int l, zc, ibt, kbt;
+    int l, zc, sub, kbt, ig;
 };
-__device__ __forceinline__ MacCoord mac_coord(const BatchItemDev &it, uint32_t t, int chunks)
+__device__ __forceinline__ MacCoord mac_coord(const BatchItemDev &it, uint32_t t, int chunks, int RT)
 {
     MacCoord c;
-    c.ibt = (int)(t % it.mtiles);
-    t /= it.mtiles;
+    c.ig = (int)(t % it.mgroups);
+    t /= it.mgroups;
     c.kbt = (int)(t % it.ktiles);
     t /= it.ktiles;
+    c.sub = (int)(t % RT);
+    t /= RT;
     c.zc = (int)(t % chunks);
     c.l = (int)(t / chunks);
     return c;
@@ -84,9 +90,13 @@ template <int G, int KB>
 __device__ __forceinline__ void run_mac(const BatchItemDev &it, const MacCoord &c, double *ws,
                                         const DevParams &dp)
 {
+    constexpr int RT = mac_rt(G, KB), SPW = 256 / RT;
+    const int lane = (int)threadIdx.x % SPW, w = (int)threadIdx.x / SPW;
+    const int ibt = c.ig * RT + w;
+    if (ibt >= (int)it.mtiles) return;
     const MacShape sh{(int)it.M, (int)it.R, (int)it.K, dp.N >> 8};
-    mac_tile<G, KB>(it.wh, ws + it.chat_off, ws + it.ahat_off, sh, dp, c.l, c.zc, (int)threadIdx.x,
-                    c.kbt * KB, c.ibt * G, 0, (int)it.R, 0);
+    mac_tile<G, KB>(it.wh, ws + it.chat_off, ws + it.ahat_off, sh, dp, c.l, c.zc, c.sub * SPW + lane,
+                    c.kbt * KB, ibt * G, 0, (int)it.R, 0);
 }
 
 // ---- phased schedule ---------------------------------------------------------------
@@ -107,7 +117,7 @@ __global__ __launch_bounds__(256) void k_batch_mac(const BatchItemDev *items, in
 {
     const uint32_t u = xcd_map ? xcd_local(blockIdx.x, gridDim.x) : blockIdx.x;
     const BatchItemDev &it = items[find_item(items, n, u, 1)];
-    run_mac<G, KB>(it, mac_coord(it, u - it.mac0, dp.N >> 8), ws, dp);
+    run_mac<G, KB>(it, mac_coord(it, u - it.mac0, dp.N >> 8, mac_rt(G, KB)), ws, dp);
 }
 
 template <int LOGN>
@@ -176,7 +186,7 @@ __global__ __launch_bounds__(kNttThreads) void k_batch_fused(const BatchItemDev 
         } else if (u < n_in + n_mac) {
             const uint32_t v = u - n_in;
             const BatchItemDev &it = items[find_item(items, n, v, 1)];
-            const MacCoord c = mac_coord(it, v - it.mac0, chunks);
+            const MacCoord c = mac_coord(it, v - it.mac0, chunks, mac_rt(G, KB));
             // Every input NTT of the column tile's blocks for this prime.
             const int left = (int)it.K - c.kbt * KB;
             const uint32_t cols = (uint32_t)(left < KB ? left : KB);
@@ -186,16 +196,18 @@ __global__ __launch_bounds__(kNttThreads) void k_batch_fused(const BatchItemDev 
             __syncthreads();
             __threadfence();
             if (s_ok) run_mac<G, KB>(it, c, ws, dp);
-            sig = it.dep_mac0 + (uint32_t)(((c.ibt * (int)it.ktiles) + c.kbt) * L + c.l);
+            sig = it.dep_mac0 + (uint32_t)(((c.ig * (int)it.ktiles) + c.kbt) * L + c.l);
         } else {
             const uint32_t v = u - n_in - n_mac;
             const BatchItemDev &it = items[find_item(items, n, v, 2)];
             const int poly = (int)(v - it.out0);
             const int y = poly / (2 * L), l = poly % L;
-            const int ibt = (y / (int)it.K) / G, kbt = (y % (int)it.K) / KB;
+            // Every (slot chunk, slot group) unit of its row-tile group and column tile.
+            constexpr int RT = mac_rt(G, KB);
+            const int ig = (y / (int)it.K) / G / RT, kbt = (y % (int)it.K) / KB;
             if (threadIdx.x == 0)
-                s_ok = wait_for(ctr, it.dep_mac0 + (uint32_t)((ibt * (int)it.ktiles + kbt) * L + l),
-                                (uint32_t)chunks, spin_limit);
+                s_ok = wait_for(ctr, it.dep_mac0 + (uint32_t)((ig * (int)it.ktiles + kbt) * L + l),
+                                (uint32_t)(chunks * RT), spin_limit);
             __syncthreads();
             __threadfence();
             if (s_ok) run_out<LOGN>(it, poly, ws, dp, lds);
@@ -237,7 +249,9 @@ int build_tables(pimm_batch *b, bool async, hipStream_t s)
         d.K = f.K;
         d.I = f.I;
         d.O = f.O;
+        const uint32_t RT = (uint32_t)mac_rt(b->G, b->KB);
         d.mtiles = (f.M + b->G - 1) / b->G;
+        d.mgroups = (d.mtiles + RT - 1) / RT;
         d.ktiles = (f.K + b->KB - 1) / b->KB;
         d.in0 = in0;
         d.mac0 = mac0;
@@ -245,9 +259,9 @@ int build_tables(pimm_batch *b, bool async, hipStream_t s)
         d.dep_in0 = dep;
         dep += d.ktiles * (uint32_t)L;
         d.dep_mac0 = dep;
-        dep += d.mtiles * d.ktiles * (uint32_t)L;
+        dep += d.mgroups * d.ktiles * (uint32_t)L;
         in0 += f.I * 2 * (uint32_t)L;
-        mac0 += chunks * (uint32_t)L * d.mtiles * d.ktiles;
+        mac0 += chunks * (uint32_t)L * RT * d.mgroups * d.ktiles;
         out0 += f.O * 2 * (uint32_t)L;
         b->useful_macs += (uint64_t)f.n * f.r * f.m;
     }
