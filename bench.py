@@ -24,6 +24,12 @@ cpu_baseline: the oracle (plain C + Python big integers, OpenMP) on a bounded
 sample: the 768x768 product at sequence 128, output ciphertexts taken in
 chunks until about --cpu-seconds have passed, encryption of all inputs counted
 pro rata.
+
+Other workloads (each prints one JSON line of its own): --workload batch (64
+uneven products, one batched pass against one call per product), serve (a
+Poisson stream of requests through a 12-layer stack with continuous batching,
+p50/p99 per arrival rate), stack (the BERT-large-shaped 24-layer stack at
+N = 8192) and peak (the device's streaming and arithmetic ceilings).
 """
 import argparse
 import collections
@@ -601,7 +607,7 @@ def main():
                              "p99": float(np.percentile(lat, 99)), "samples": len(lat)},
         "kernels_untimed_breakdown": kernels,
         "roofline": {
-            "kernel": "mac (k_mac)", "bound": "hbm", "achieved": achieved,
+            "kernel": "k_mac_sk (the slot-wise product)", "bound": "hbm", "achieved": achieved,
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic([s["plan"].tuning() for s in state]),
             "alg_bytes_per_launch": bytes_per_launch,

@@ -53,7 +53,9 @@ namespace pimm {
 // Rebuild the item table; async uploads use pinned staging on `s` (the caller
 // must not have a run of this batch in flight).
 int batch_rebuild(pimm_batch *b, bool async, hipStream_t s);
-int batch_run(const pimm_batch *b, void *ws, hipStream_t s);
+// with_out = false stops after the products: each item's acc^ stays in its
+// workspace (summed over the inner blocks, in NTT form) and its acc is not written.
+int batch_run(const pimm_batch *b, void *ws, hipStream_t s, bool with_out = true);
 }  // namespace pimm
 
 

@@ -310,7 +310,7 @@ int build_tables(pimm_batch *b, bool async, hipStream_t s)
 }
 
 template <int LOGN, int G, int KB>
-int run_batch(const pimm_batch *b, void *ws, hipStream_t s)
+int run_batch(const pimm_batch *b, void *ws, bool with_out, hipStream_t s)
 {
     const Ctx &c = *b->ctx;
     const int n = (int)b->items.size();
@@ -326,7 +326,7 @@ int run_batch(const pimm_batch *b, void *ws, hipStream_t s)
             hipLaunchKernelGGL((k_batch_mac<G, KB>), dim3(b->n_mac), dim3(256), 0, s, b->d_items, n,
                                wsd, b->xcd_map, c.dp);
         }
-        {
+        if (with_out) {
             ProfScope prof("ntt_inv", s);
             hipLaunchKernelGGL(k_batch_out<LOGN>, dim3(b->n_out), dim3(kNttThreads), 0, s,
                                b->d_items, n, wsd, c.dp);
@@ -344,21 +344,22 @@ int run_batch(const pimm_batch *b, void *ws, hipStream_t s)
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device);
         grid = (uint32_t)std::max(1, per_cu) * (uint32_t)std::max(1, cus);
     }
-    const uint32_t total = b->n_in + b->n_mac + b->n_out;
+    const uint32_t n_out = with_out ? b->n_out : 0;
+    const uint32_t total = b->n_in + b->n_mac + n_out;
     if (grid > total) grid = total;
     {
         ProfScope prof("fused", s);
         hipLaunchKernelGGL((k_batch_fused<LOGN, G, KB>), dim3(grid), dim3(kNttThreads), 0, s, b->d_items,
-                           n, wsd, ctr, b->n_in, b->n_mac, b->n_out, b->spin_limit, c.dp);
+                           n, wsd, ctr, b->n_in, b->n_mac, n_out, b->spin_limit, c.dp);
     }
     return check_hip(hipGetLastError(), "batch fused launch");
 }
 
 template <int LOGN>
-int run_batch_g(const pimm_batch *b, void *ws, hipStream_t s)
+int run_batch_g(const pimm_batch *b, void *ws, bool with_out, hipStream_t s)
 {
 #define PIMM_RUN_BATCH(g, kb) \
-    if (b->G == g && b->KB == kb) return run_batch<LOGN, g, kb>(b, ws, s);
+    if (b->G == g && b->KB == kb) return run_batch<LOGN, g, kb>(b, ws, with_out, s);
     PIMM_MAC_SHAPES(PIMM_RUN_BATCH)
 #undef PIMM_RUN_BATCH
     return set_error(PIMM_E_ARG, "product tile %dx%d is not built", b->G, b->KB);
@@ -368,9 +369,10 @@ int run_batch_g(const pimm_batch *b, void *ws, hipStream_t s)
 
 namespace pimm {
 int batch_rebuild(pimm_batch *b, bool async, hipStream_t s) { return build_tables(b, async, s); }
-int batch_run(const pimm_batch *b, void *ws, hipStream_t s)
+int batch_run(const pimm_batch *b, void *ws, hipStream_t s, bool with_out)
 {
-    return b->ctx->dp.logN == 12 ? run_batch_g<12>(b, ws, s) : run_batch_g<13>(b, ws, s);
+    return b->ctx->dp.logN == 12 ? run_batch_g<12>(b, ws, with_out, s)
+                                 : run_batch_g<13>(b, ws, with_out, s);
 }
 }  // namespace pimm
 

@@ -297,6 +297,10 @@ int launch_sample(const Ctx &c, int kind, const Key &key, uint32_t tag, uint32_t
 
 // Launch helpers implemented in the kernel translation units.
 // Slot-wise products of one plan into zeroed-then-accumulated acc^ (mac.hip).
+// The fused server step after the product (server.hip), on a workspace laid out as
+// pimm_matmul_share's; pk may be NULL without re-randomisation.
+int fused_tail(const pimm_plan *plan, const uint64_t *pk, const Key &key, uint32_t op_id,
+               double *ws, uint64_t *c1, uint64_t *c0s, uint64_t *server_share, hipStream_t s);
 // The product of one plan (acc^ zeroed first unless `zeroed` says the caller did).
 int launch_mac(const Ctx &c, const pimm_plan_info &f, int G, int KB, int waves, const double *Wt,
                const double *Ct, double *Ah, bool zeroed, hipStream_t s);

@@ -10,11 +10,13 @@
 //
 // The server replays an arrival trace in real time.  At every tick it
 //   1. admits waiting requests in arrival order while the HBM budget has room
-//      for the request's buffers (key, ciphertexts, accumulators, reply and
-//      scratch, sized for its largest product) and fewer than max_active run;
+//      for the request's buffers (key, ciphertexts, reply, shares and scratch,
+//      sized for its largest product) and fewer than max_active run;
 //   2. for every admitted request runs its next product: client share, encode,
-//      encrypt; one batched slot-wise product over all requests (pimm_batch
-//      machinery); re-randomise + mask + reply; decrypt;
+//      encrypt; one batched pass of forward transforms and slot-wise products
+//      over all requests (pimm_batch machinery, stopping at acc^); then per
+//      request the fused server tail (re-randomisation, inverse transform with
+//      the reply epilogue, mask) and decryption;
 //   3. waits for the device, then retires requests whose last product is done.
 // A request's key material and buffers stay in device memory from admission to
 // completion.  Requests admitted while others are running join the next tick,
@@ -130,7 +132,7 @@ struct Active {
     uint64_t off = 0, bytes = 0;
     std::vector<pimm_plan> plans;  // one per op of a layer
     pimm_sk sk;                    // views into the arena (never destroyed through the ABI)
-    uint64_t *pk, *X, *pt, *ct, *acc, *c1, *c0s, *y0, *y1;
+    uint64_t *pk, *X, *pt, *ct, *c1, *c0s, *y0, *y1;
     double *ws;
     uint64_t ws_bytes;
     unsigned long long *cs;
@@ -159,19 +161,18 @@ uint64_t a256(uint64_t x) { return (x + 255) & ~255ull; }
 
 // Buffer layout of one request (sizes for its largest product).
 struct Layout {
-    uint64_t s, s_hat, pk, X, pt, ct, acc, c1, c0s, y0, y1, ws, cs, total;
+    uint64_t s, s_hat, pk, X, pt, ct, c1, c0s, y0, y1, ws, cs, total;
 };
 
 Layout layout_for(const pimm_server &sv, const std::vector<pimm_plan> &plans)
 {
     const uint64_t N = sv.ctx->params.N, L = sv.ctx->params.L;
-    uint64_t X = 0, pt = 0, ct = 0, acc = 0, c1 = 0, c0s = 0, y = 0, ws = 0;
+    uint64_t X = 0, pt = 0, ct = 0, c1 = 0, c0s = 0, y = 0, ws = 0;
     for (const pimm_plan &p : plans) {
         const pimm_plan_info &f = p.info;
         X = std::max<uint64_t>(X, (uint64_t)f.n * f.r * 8);
         pt = std::max(pt, f.pt_bytes);
         ct = std::max(ct, f.ct_bytes);
-        acc = std::max(acc, f.acc_bytes);
         c1 = std::max(c1, f.c1_bytes);
         c0s = std::max(c0s, f.c0s_bytes);
         y = std::max(y, f.share_bytes);
@@ -186,7 +187,6 @@ Layout layout_for(const pimm_server &sv, const std::vector<pimm_plan> &plans)
     l.X = take(X);
     l.pt = take(pt);
     l.ct = take(ct);
-    l.acc = take(acc);
     l.c1 = take(c1);
     l.c0s = take(c0s);
     l.y0 = take(y);
@@ -356,7 +356,6 @@ int pimm_serve_run(pimm_server *sv, const pimm_request *reqs, uint32_t count,
             a->X = (uint64_t *)(p + lay.X);
             a->pt = (uint64_t *)(p + lay.pt);
             a->ct = (uint64_t *)(p + lay.ct);
-            a->acc = (uint64_t *)(p + lay.acc);
             a->c1 = (uint64_t *)(p + lay.c1);
             a->c0s = (uint64_t *)(p + lay.c0s);
             a->y0 = (uint64_t *)(p + lay.y0);
@@ -405,7 +404,9 @@ int pimm_serve_run(pimm_server *sv, const pimm_request *reqs, uint32_t count,
             if (!rc) rc = pimm_encrypt(plan, &a->sk, a->req.client_seed, a->step, a->pt, a->ct, a->ws,
                                        a->ws_bytes, s);
             if (rc) return fail(rc);
-            items[i] = pimm_batch_item{plan, sv->weights[a->step], a->ct, a->acc};
+            // No accumulator in coefficient form: the batched pass stops after the
+            // products and each request's fused tail reads acc^ from its workspace.
+            items[i] = pimm_batch_item{plan, sv->weights[a->step], a->ct, nullptr};
             // The product's NTT forms live in the request's workspace (as pimm_matmul lays them).
             const uint64_t ws_off = (uint64_t)((uint8_t *)a->ws - sv->arena_base) / 8;
             sv->batch.fixed_chat[i] = ws_off;
@@ -415,14 +416,14 @@ int pimm_serve_run(pimm_server *sv, const pimm_request *reqs, uint32_t count,
         rc = batch_rebuild(&sv->batch, true, s);
         if (!rc && sv->batch.ws_bytes > sv->counters_bytes)
             rc = set_error(PIMM_E_ARG, "serve: too many dependency counters for the reserve");
-        if (!rc) rc = batch_run(&sv->batch, sv->arena_base, s);
+        if (!rc) rc = batch_run(&sv->batch, sv->arena_base, s, false);
         if (rc) return fail(rc);
         for (size_t i = 0; i < active.size(); ++i) {
             Active *a = active[i];
             const pimm_plan *plan = &a->plans[a->step % sv->cfg.ops];
             const pimm_plan_info &f = plan->info;
-            rc = pimm_mask_share(plan, a->pk, a->req.server_seed, a->step, a->acc, a->c1, a->c0s, a->y1,
-                                 a->ws, a->ws_bytes, s);
+            rc = fused_tail(plan, a->pk, make_key(a->req.server_seed), a->step, a->ws, a->c1, a->c0s,
+                            a->y1, s);
             if (!rc) rc = pimm_decrypt(plan, &a->sk, a->c1, a->c0s, a->y0, a->ws, a->ws_bytes, s);
             if (!rc) {
                 hipLaunchKernelGGL(k_checksum, dim3(64), dim3(256), 0, s, a->y0, a->y1, f.n * f.m,

@@ -18,7 +18,6 @@
 
 namespace pimm {
 
-
 // ---- weights (Algorithm 1 step 1, pi_A) ---------------------------------------------
 
 // Coefficient j of block w = ib*R + jb of pi_A(W^T), read straight from W [r][m]:
@@ -52,7 +51,7 @@ __global__ void k_absmax(const int64_t *W, size_t n, unsigned long long *out)
     atomicMax(out, best);
 }
 
-// ---- the slot-wise products (step 3) -----------------------------------------
+// (The slot-wise products of step 3 are in mac.h / mac.hip.)
 
 // ---- re-randomisation, mask and extraction --------------------------------------
 
@@ -226,6 +225,46 @@ __global__ void k_mask_reply(Key key, uint32_t op, uint64_t *c0s, uint64_t *shar
     }
 }
 
+// The fused step after the product, on the workspace laid out as
+// c^ [I][2][L][N], acc^ [O][2][L][N], pk^ [2][L][N], u^ [O][L][N] (doubles),
+// u [O][N], e [O][2][N] (int64), acc^ already summed over the inner blocks:
+// re-randomisation draws and transforms, the inverse transform with the reply
+// epilogue, then the mask at the decoded positions and the server's share.
+int fused_tail(const pimm_plan *plan, const uint64_t *pk, const Key &key, uint32_t op_id,
+               double *ws, uint64_t *c1, uint64_t *c0s, uint64_t *server_share, hipStream_t s)
+{
+    const Ctx &c = *plan->ctx;
+    const pimm_plan_info &f = plan->info;
+    const size_t N = c.params.N, L = c.params.L;
+    const int rr = c.params.rerandomize ? 1 : 0;
+    const int lg = c.dp.logN;
+    double *ah = ws + (size_t)f.I * 2 * L * N;
+    double *pkh = ah + (size_t)f.O * 2 * L * N;
+    double *uh = pkh + 2 * L * N;
+    int64_t *u = (int64_t *)(uh + (size_t)f.O * L * N);
+    int64_t *e = u + (size_t)f.O * N;
+    int rc = PIMM_OK;
+    if (rr) {
+        rc = launch_samples(c, key, op_id, rerand_jobs(f.O, N, u, e), s);
+        // pk^ and u^ in one launch: they are adjacent in the workspace.
+        if (!rc)
+            rc = launch_fwd(c, LoadPkU{pk, u, lg, (int)L}, StoreSlots{pkh, lg}, (int)((2 + f.O) * L), s);
+    }
+    if (!rc)
+        rc = launch_inv_lds(c, LoadAccRerand{ah, uh, pkh, lg, (int)L, rr},
+                            ReplyOut{c1, c0s, e, FastDiv::make(f.mb), f.rb, f.nb, lg, (int)L, rr},
+                            (int)(f.O * 2 * L), s);
+    if (!rc) {
+        const uint32_t blocks = (f.mb * f.rb * f.nb + 7) / 8;
+        const size_t total = (size_t)f.O * blocks;
+        ProfScope prof("mask_extract", s);
+        hipLaunchKernelGGL(k_mask_reply, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, key,
+                           op_id, c0s, server_share, blocks, f, c.dp);
+        rc = check_hip(hipGetLastError(), "mask_reply launch");
+    }
+    return rc;
+}
+
 }  // namespace pimm
 
 using namespace pimm;
@@ -387,33 +426,11 @@ int pimm_matmul_share(const pimm_plan *plan, const pimm_weights *w, const uint64
     const int lg = c.dp.logN;
     double *ch = (double *)ws;
     double *ah = ch + (size_t)f.I * 2 * L * N;
-    double *pkh = ah + (size_t)f.O * 2 * L * N;
-    double *uh = pkh + 2 * L * N;
-    int64_t *u = (int64_t *)(uh + (size_t)f.O * L * N);
-    int64_t *e = u + (size_t)f.O * N;
-    const Key key = make_key(seed);
     int rc = launch_fwd_zero(c, LoadU64{ct, lg}, StoreCtTiled{ch, lg, (int)L, f.K, f.R},
                              (int)(f.I * 2 * L), ah, (size_t)f.O * 2 * L * N, s);
     if (!rc)
         rc = launch_mac(c, f, plan->mac_rows, plan->mac_cols, plan->waves, w->d_w_hat, ch, ah, true, s);
-    if (!rc && rr) {
-        rc = launch_samples(c, key, op_id, rerand_jobs(f.O, N, u, e), s);
-        // pk^ and u^ in one launch: they are adjacent in the workspace.
-        if (!rc)
-            rc = launch_fwd(c, LoadPkU{pk, u, lg, (int)L}, StoreSlots{pkh, lg}, (int)((2 + f.O) * L), s);
-    }
-    if (!rc)
-        rc = launch_inv_lds(c, LoadAccRerand{ah, uh, pkh, lg, (int)L, rr},
-                            ReplyOut{c1, c0s, e, FastDiv::make(f.mb), f.rb, f.nb, lg, (int)L, rr},
-                            (int)(f.O * 2 * L), s);
-    if (!rc) {
-        const uint32_t blocks = (f.mb * f.rb * f.nb + 7) / 8;
-        const size_t total = (size_t)f.O * blocks;
-        ProfScope prof("mask_extract", s);
-        hipLaunchKernelGGL(k_mask_reply, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, key,
-                           op_id, c0s, server_share, blocks, f, c.dp);
-        rc = check_hip(hipGetLastError(), "mask_reply launch");
-    }
+    if (!rc) rc = fused_tail(plan, pk, make_key(seed), op_id, (double *)ws, c1, c0s, server_share, s);
     return rc;
 }
 
