@@ -55,7 +55,7 @@ template <int LOGN>
 __device__ __forceinline__ void run_in(const BatchItemDev &it, int poly, double *ws,
                                        const DevParams &dp, double *lds)
 {
-    ntt_fwd_block<LOGN>(LoadU64{it.ct, LOGN}, StoreCtTiled{ws + it.chat_off, LOGN, dp.L, it.K, it.R},
+    ntt_fwd_block<LOGN, kNttThreads>(LoadU64{it.ct, LOGN}, StoreCtTiled{ws + it.chat_off, LOGN, dp.L, it.K, it.R},
                         dp, poly, lds);
 }
 
@@ -63,7 +63,7 @@ template <int LOGN>
 __device__ __forceinline__ void run_out(const BatchItemDev &it, int poly, double *ws,
                                         const DevParams &dp, double *lds)
 {
-    ntt_inv_block<LOGN>(LoadSlots{ws + it.ahat_off, LOGN}, StoreU64{it.acc, LOGN}, dp, poly, lds);
+    ntt_inv_block<LOGN, kNttThreads>(LoadSlots{ws + it.ahat_off, LOGN}, StoreU64{it.acc, LOGN}, dp, poly, lds);
 }
 
 // mac unit t of an item -> (l, slot chunk, slot group, column tile, row-tile group), row-tile
@@ -105,7 +105,7 @@ template <int LOGN>
 __global__ __launch_bounds__(kNttThreads) void k_batch_in(const BatchItemDev *items, int n,
                                                           double *ws, DevParams dp)
 {
-    __shared__ double lds[NttPasses<LOGN>::LDS];
+    __shared__ double lds[NttPasses<LOGN, kNttThreads>::LDS];
     const uint32_t u = blockIdx.x;
     const BatchItemDev &it = items[find_item(items, n, u, 0)];
     run_in<LOGN>(it, (int)(u - it.in0), ws, dp, lds);
@@ -124,7 +124,7 @@ template <int LOGN>
 __global__ __launch_bounds__(kNttThreads) void k_batch_out(const BatchItemDev *items, int n,
                                                            double *ws, DevParams dp)
 {
-    __shared__ double lds[NttPasses<LOGN>::LDS];
+    __shared__ double lds[NttPasses<LOGN, kNttThreads>::LDS];
     const uint32_t u = blockIdx.x;
     const BatchItemDev &it = items[find_item(items, n, u, 2)];
     run_out<LOGN>(it, (int)(u - it.out0), ws, dp, lds);
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(kNttThreads) void k_batch_fused(const BatchItemDev 
                                                              uint32_t n_out, uint32_t spin_limit,
                                                              DevParams dp)
 {
-    __shared__ double lds[NttPasses<LOGN>::LDS];
+    __shared__ double lds[NttPasses<LOGN, kNttThreads>::LDS];
     __shared__ uint32_t s_unit;
     __shared__ int s_ok;
     const uint32_t total = n_in + n_mac + n_out;

@@ -74,7 +74,7 @@ struct DecodedOut {
         const double p = dp.p[l], pinv = dp.pinv[l];
         const uint32_t per = mb.d * nb;
         uint64_t *dst = cs + (size_t)poly * per;
-        for (uint32_t idx = threadIdx.x; idx < per; idx += kNttThreads) {
+        for (uint32_t idx = threadIdx.x; idx < per; idx += blockDim.x) {
             const uint32_t k = mb.div(idx), i = idx - k * mb.d;
             const uint32_t j = (k * mb.d + i) * rb + rb - 1;
             dst[idx] = to_canonical(lds[lds_idx((int)j)], p, pinv);

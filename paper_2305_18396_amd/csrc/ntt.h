@@ -25,31 +25,48 @@
 
 namespace pimm {
 
+// Workgroup size of the batch kernels (and of every N = 4096 transform).
 constexpr int kNttThreads = 256;
 
-template <int LOGN>
+// Pass sizes (stages per register pass) for a transform of 2^LOGN points done
+// by T threads.  Every pass gives each thread whole sets of 2^PS elements.  At
+// N = 8192 with 512 threads the 13 stages are 1 + 4 + 4 + 4, so that every
+// thread holds 16 elements and two workgroups (16 waves) fit in a CU's LDS;
+// with 256 threads they are 5 + 4 + 4.
+template <int LOGN, int T>
 struct NttSched;
 template <>
-struct NttSched<12> {
-    static constexpr int P0 = 4, P1 = 4, P2 = 4;
+struct NttSched<12, 256> {
+    static constexpr int P0 = 4, P1 = 4, P2 = 4, P3 = 0;
 };
 template <>
-struct NttSched<13> {
-    static constexpr int P0 = 5, P1 = 4, P2 = 4;
+struct NttSched<13, 256> {
+    static constexpr int P0 = 5, P1 = 4, P2 = 4, P3 = 0;
 };
+template <>
+struct NttSched<13, 512> {
+    static constexpr int P0 = 1, P1 = 4, P2 = 4, P3 = 4;
+};
+
+// Threads of a stand-alone transform kernel.
+template <int LOGN>
+constexpr int ntt_threads()
+{
+    return LOGN == 13 ? 512 : 256;
+}
 
 // LDS slot of element j, padded by one double every 32 to break bank aliasing
 // of the strided pass patterns.
 __device__ __forceinline__ int lds_idx(int j) { return j + (j >> 5); }
 
-template <int LOGN, int S0, int PS>
+template <int LOGN, int S0, int PS, int T>
 struct Pass {
     static constexpr int N = 1 << LOGN;
     static constexpr int E = 1 << PS;
     static constexpr int STRIDE = N >> (S0 + PS);
     static constexpr int NSETS = N >> PS;
-    static constexpr int PER_THREAD = NSETS / kNttThreads;
-    static_assert(PER_THREAD >= 1 && NSETS % kNttThreads == 0, "pass shape");
+    static constexpr int PER_THREAD = NSETS / T;
+    static_assert(PER_THREAD >= 1 && NSETS % T == 0, "pass shape");
 
     // Element index of member c of set S.
     __device__ static __forceinline__ int elem(int S, int c)
@@ -97,143 +114,144 @@ struct Pass {
     }
 };
 
-template <int LOGN>
+template <int LOGN, int T>
 struct NttPasses {
-    using S = NttSched<LOGN>;
-    using A = Pass<LOGN, 0, S::P0>;
-    using B = Pass<LOGN, S::P0, S::P1>;
-    using C = Pass<LOGN, S::P0 + S::P1, S::P2>;
-    static_assert(S::P0 + S::P1 + S::P2 == LOGN, "schedule covers every stage");
+    using S = NttSched<LOGN, T>;
+    using A = Pass<LOGN, 0, S::P0, T>;
+    using B = Pass<LOGN, S::P0, S::P1, T>;
+    using C = Pass<LOGN, S::P0 + S::P1, S::P2, T>;
+    // Fourth pass (only when P3 > 0; otherwise a placeholder that is never used).
+    using D = Pass<LOGN, S::P0 + S::P1 + S::P2, (S::P3 > 0 ? S::P3 : 1), T>;
+    static_assert(S::P0 + S::P1 + S::P2 + S::P3 == LOGN, "schedule covers every stage");
     static constexpr int N = 1 << LOGN;
     static constexpr int LDS = N + (N >> 5);
 };
 
-// Forward negacyclic NTT of polynomial `poly` by the calling workgroup
-// (kNttThreads threads), with `lds` holding NttPasses<LOGN>::LDS doubles.
-template <int LOGN, class Load, class Store>
+// Forward stages of pass P on every set the thread owns: read from LDS (or the
+// loader for the first pass), write to LDS (or the storer, in slot order, for
+// the last pass).
+template <class P, int T, bool FIRST, bool LAST, class Load, class Store>
+__device__ __forceinline__ void fwd_pass(const Load &ld, const Store &st, int poly, int l,
+                                         const double *tw, double p, double pinv, double *lds)
+{
+#pragma unroll
+    for (int k = 0; k < P::PER_THREAD; ++k) {
+        const int S = (int)threadIdx.x + k * T;
+        double x[P::E];
+#pragma unroll
+        for (int c = 0; c < P::E; ++c)
+            x[c] = FIRST ? ld(poly, l, P::elem(S, c), p, pinv) : lds[lds_idx(P::elem(S, c))];
+        P::fwd(x, S, tw, p, pinv);
+#pragma unroll
+        for (int c = 0; c < P::E; ++c) {
+            if (LAST)
+                st(poly, l, c * P::NSETS + S, reduce(x[c], p, pinv), p, pinv);
+            else
+                lds[lds_idx(P::elem(S, c))] = reduce(x[c], p, pinv);
+        }
+    }
+}
+
+// Inverse stages of pass P (the mirror of fwd_pass: the first inverse pass reads
+// the loader in slot order, the last one multiplies by N^-1 and calls the storer
+// in natural order).
+template <class P, int T, bool FIRST, bool LAST, class Load, class Store>
+__device__ __forceinline__ void inv_pass(const Load &ld, const Store &st, int poly, int l,
+                                         const double *tw, double p, double pinv, double ninv,
+                                         double *lds)
+{
+#pragma unroll
+    for (int k = 0; k < P::PER_THREAD; ++k) {
+        const int S = (int)threadIdx.x + k * T;
+        double x[P::E];
+#pragma unroll
+        for (int c = 0; c < P::E; ++c)
+            x[c] = FIRST ? ld(poly, l, c * P::NSETS + S, p, pinv) : lds[lds_idx(P::elem(S, c))];
+        P::inv(x, S, tw, p, pinv);
+#pragma unroll
+        for (int c = 0; c < P::E; ++c) {
+            if (LAST)
+                st(poly, l, P::elem(S, c), mulmod(x[c], ninv, p, pinv), p, pinv);
+            else
+                lds[lds_idx(P::elem(S, c))] = reduce(x[c], p, pinv);
+        }
+    }
+}
+
+// Forward negacyclic NTT of polynomial `poly` by the calling workgroup of T
+// threads, with `lds` holding NttPasses<LOGN, T>::LDS doubles.
+template <int LOGN, int T, class Load, class Store>
 __device__ __forceinline__ void ntt_fwd_block(const Load &ld, const Store &st, const DevParams &dp,
                                               int poly, double *lds)
 {
-    using NP = NttPasses<LOGN>;
-    using PA = typename NP::A;
-    using PB = typename NP::B;
-    using PC = typename NP::C;
+    using NP = NttPasses<LOGN, T>;
+    constexpr bool FOUR = NP::S::P3 > 0;
     const int l = poly % dp.L;
     const double p = dp.p[l], pinv = dp.pinv[l];
     const double *tw = dp.tw_fwd + ((size_t)l << LOGN);
-    const int tid = threadIdx.x;
-
-#pragma unroll
-    for (int k = 0; k < PA::PER_THREAD; ++k) {
-        const int S = tid + k * kNttThreads;
-        double x[PA::E];
-#pragma unroll
-        for (int c = 0; c < PA::E; ++c) x[c] = ld(poly, l, PA::elem(S, c), p, pinv);
-        PA::fwd(x, S, tw, p, pinv);
-#pragma unroll
-        for (int c = 0; c < PA::E; ++c) lds[lds_idx(PA::elem(S, c))] = reduce(x[c], p, pinv);
-    }
+    fwd_pass<typename NP::A, T, true, false>(ld, st, poly, l, tw, p, pinv, lds);
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < PB::PER_THREAD; ++k) {
-        const int S = tid + k * kNttThreads;
-        double x[PB::E];
-#pragma unroll
-        for (int c = 0; c < PB::E; ++c) x[c] = lds[lds_idx(PB::elem(S, c))];
-        PB::fwd(x, S, tw, p, pinv);
-#pragma unroll
-        for (int c = 0; c < PB::E; ++c) lds[lds_idx(PB::elem(S, c))] = reduce(x[c], p, pinv);
-    }
+    fwd_pass<typename NP::B, T, false, false>(ld, st, poly, l, tw, p, pinv, lds);
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < PC::PER_THREAD; ++k) {
-        const int S = tid + k * kNttThreads;
-        double x[PC::E];
-#pragma unroll
-        for (int c = 0; c < PC::E; ++c) x[c] = lds[lds_idx(PC::elem(S, c))];
-        PC::fwd(x, S, tw, p, pinv);
-#pragma unroll
-        for (int c = 0; c < PC::E; ++c) st(poly, l, c * PC::NSETS + S, reduce(x[c], p, pinv), p, pinv);
+    fwd_pass<typename NP::C, T, false, !FOUR>(ld, st, poly, l, tw, p, pinv, lds);
+    if constexpr (FOUR) {
+        __syncthreads();
+        fwd_pass<typename NP::D, T, false, true>(ld, st, poly, l, tw, p, pinv, lds);
     }
 }
 
 // Inverse negacyclic NTT (including the factor N^-1) of polynomial `poly`.
-template <int LOGN, class Load, class Store>
+template <int LOGN, int T, class Load, class Store>
 __device__ __forceinline__ void ntt_inv_block(const Load &ld, const Store &st, const DevParams &dp,
                                               int poly, double *lds)
 {
-    using NP = NttPasses<LOGN>;
-    using PA = typename NP::A;
-    using PB = typename NP::B;
-    using PC = typename NP::C;
+    using NP = NttPasses<LOGN, T>;
+    constexpr bool FOUR = NP::S::P3 > 0;
     const int l = poly % dp.L;
     const double p = dp.p[l], pinv = dp.pinv[l];
     const double *tw = dp.tw_inv + ((size_t)l << LOGN);
-    const int tid = threadIdx.x;
-
-#pragma unroll
-    for (int k = 0; k < PC::PER_THREAD; ++k) {
-        const int S = tid + k * kNttThreads;
-        double x[PC::E];
-#pragma unroll
-        for (int c = 0; c < PC::E; ++c) x[c] = ld(poly, l, c * PC::NSETS + S, p, pinv);
-        PC::inv(x, S, tw, p, pinv);
-#pragma unroll
-        for (int c = 0; c < PC::E; ++c) lds[lds_idx(PC::elem(S, c))] = reduce(x[c], p, pinv);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < PB::PER_THREAD; ++k) {
-        const int S = tid + k * kNttThreads;
-        double x[PB::E];
-#pragma unroll
-        for (int c = 0; c < PB::E; ++c) x[c] = lds[lds_idx(PB::elem(S, c))];
-        PB::inv(x, S, tw, p, pinv);
-#pragma unroll
-        for (int c = 0; c < PB::E; ++c) lds[lds_idx(PB::elem(S, c))] = reduce(x[c], p, pinv);
-    }
-    __syncthreads();
     const double ninv = dp.n_inv[l];
-#pragma unroll
-    for (int k = 0; k < PA::PER_THREAD; ++k) {
-        const int S = tid + k * kNttThreads;
-        double x[PA::E];
-#pragma unroll
-        for (int c = 0; c < PA::E; ++c) x[c] = lds[lds_idx(PA::elem(S, c))];
-        PA::inv(x, S, tw, p, pinv);
-#pragma unroll
-        for (int c = 0; c < PA::E; ++c)
-            st(poly, l, PA::elem(S, c), mulmod(x[c], ninv, p, pinv), p, pinv);
+    if constexpr (FOUR) {
+        inv_pass<typename NP::D, T, true, false>(ld, st, poly, l, tw, p, pinv, ninv, lds);
+        __syncthreads();
     }
+    inv_pass<typename NP::C, T, !FOUR, false>(ld, st, poly, l, tw, p, pinv, ninv, lds);
+    __syncthreads();
+    inv_pass<typename NP::B, T, false, false>(ld, st, poly, l, tw, p, pinv, ninv, lds);
+    __syncthreads();
+    inv_pass<typename NP::A, T, false, true>(ld, st, poly, l, tw, p, pinv, ninv, lds);
 }
 
 template <int LOGN, class Load, class Store>
-__global__ __launch_bounds__(kNttThreads) void k_ntt_fwd(Load ld, Store st, DevParams dp)
+__global__ __launch_bounds__(ntt_threads<LOGN>()) void k_ntt_fwd(Load ld, Store st, DevParams dp)
 {
-    __shared__ double lds[NttPasses<LOGN>::LDS];
-    ntt_fwd_block<LOGN>(ld, st, dp, (int)blockIdx.x, lds);
+    constexpr int T = ntt_threads<LOGN>();
+    __shared__ double lds[NttPasses<LOGN, T>::LDS];
+    ntt_fwd_block<LOGN, T>(ld, st, dp, (int)blockIdx.x, lds);
 }
 
 // Forward transform that also clears its share of another buffer (the
 // product's accumulators), saving a launch: workgroup b zeroes
 // zero[b * per, (b + 1) * per), per = ceil(zero_n / gridDim.x).
 template <int LOGN, class Load, class Store>
-__global__ __launch_bounds__(kNttThreads) void k_ntt_fwd_zero(Load ld, Store st, double *zero,
-                                                              size_t zero_n, DevParams dp)
+__global__ __launch_bounds__(ntt_threads<LOGN>()) void k_ntt_fwd_zero(Load ld, Store st, double *zero,
+                                                                       size_t zero_n, DevParams dp)
 {
-    __shared__ double lds[NttPasses<LOGN>::LDS];
-    ntt_fwd_block<LOGN>(ld, st, dp, (int)blockIdx.x, lds);
+    constexpr int T = ntt_threads<LOGN>();
+    __shared__ double lds[NttPasses<LOGN, T>::LDS];
+    ntt_fwd_block<LOGN, T>(ld, st, dp, (int)blockIdx.x, lds);
     const size_t per = (zero_n + gridDim.x - 1) / gridDim.x;
     const size_t b = (size_t)blockIdx.x * per;
     const size_t e = b + per < zero_n ? b + per : zero_n;
-    for (size_t i = b + threadIdx.x; i < e; i += kNttThreads) zero[i] = 0.0;
+    for (size_t i = b + threadIdx.x; i < e; i += T) zero[i] = 0.0;
 }
 
 template <int LOGN, class Load, class Store>
-__global__ __launch_bounds__(kNttThreads) void k_ntt_inv(Load ld, Store st, DevParams dp)
+__global__ __launch_bounds__(ntt_threads<LOGN>()) void k_ntt_inv(Load ld, Store st, DevParams dp)
 {
-    __shared__ double lds[NttPasses<LOGN>::LDS];
-    ntt_inv_block<LOGN>(ld, st, dp, (int)blockIdx.x, lds);
+    constexpr int T = ntt_threads<LOGN>();
+    __shared__ double lds[NttPasses<LOGN, T>::LDS];
+    ntt_inv_block<LOGN, T>(ld, st, dp, (int)blockIdx.x, lds);
 }
 
 // Inverse transform whose result stays in the workgroup's LDS (natural order,
@@ -249,11 +267,12 @@ struct StoreLds {
 };
 
 template <int LOGN, class Load, class Epi>
-__global__ __launch_bounds__(kNttThreads) void k_ntt_inv_lds(Load ld, Epi epi, DevParams dp)
+__global__ __launch_bounds__(ntt_threads<LOGN>()) void k_ntt_inv_lds(Load ld, Epi epi, DevParams dp)
 {
-    __shared__ double lds[NttPasses<LOGN>::LDS];
+    constexpr int T = ntt_threads<LOGN>();
+    __shared__ double lds[NttPasses<LOGN, T>::LDS];
     const int poly = (int)blockIdx.x;
-    ntt_inv_block<LOGN>(ld, StoreLds{lds}, dp, poly, lds);
+    ntt_inv_block<LOGN, T>(ld, StoreLds{lds}, dp, poly, lds);
     __syncthreads();
     epi(poly, lds, dp);
 }
@@ -328,10 +347,10 @@ int launch_fwd(const Ctx &c, Load ld, Store st, int npoly, hipStream_t s)
     if (npoly <= 0) return PIMM_OK;
     ProfScope prof("ntt_fwd", s);
     if (c.dp.logN == 12)
-        hipLaunchKernelGGL((k_ntt_fwd<12, Load, Store>), dim3(npoly), dim3(kNttThreads), 0, s, ld,
+        hipLaunchKernelGGL((k_ntt_fwd<12, Load, Store>), dim3(npoly), dim3(ntt_threads<12>()), 0, s, ld,
                            st, c.dp);
     else
-        hipLaunchKernelGGL((k_ntt_fwd<13, Load, Store>), dim3(npoly), dim3(kNttThreads), 0, s, ld,
+        hipLaunchKernelGGL((k_ntt_fwd<13, Load, Store>), dim3(npoly), dim3(ntt_threads<13>()), 0, s, ld,
                            st, c.dp);
     return check_hip(hipGetLastError(), "ntt_fwd launch");
 }
@@ -343,10 +362,10 @@ int launch_fwd_zero(const Ctx &c, Load ld, Store st, int npoly, double *zero, si
     if (npoly <= 0) return PIMM_OK;
     ProfScope prof("ntt_fwd", s);
     if (c.dp.logN == 12)
-        hipLaunchKernelGGL((k_ntt_fwd_zero<12, Load, Store>), dim3(npoly), dim3(kNttThreads), 0, s,
+        hipLaunchKernelGGL((k_ntt_fwd_zero<12, Load, Store>), dim3(npoly), dim3(ntt_threads<12>()), 0, s,
                            ld, st, zero, zero_n, c.dp);
     else
-        hipLaunchKernelGGL((k_ntt_fwd_zero<13, Load, Store>), dim3(npoly), dim3(kNttThreads), 0, s,
+        hipLaunchKernelGGL((k_ntt_fwd_zero<13, Load, Store>), dim3(npoly), dim3(ntt_threads<13>()), 0, s,
                            ld, st, zero, zero_n, c.dp);
     return check_hip(hipGetLastError(), "ntt_fwd launch");
 }
@@ -357,10 +376,10 @@ int launch_inv(const Ctx &c, Load ld, Store st, int npoly, hipStream_t s)
     if (npoly <= 0) return PIMM_OK;
     ProfScope prof("ntt_inv", s);
     if (c.dp.logN == 12)
-        hipLaunchKernelGGL((k_ntt_inv<12, Load, Store>), dim3(npoly), dim3(kNttThreads), 0, s, ld,
+        hipLaunchKernelGGL((k_ntt_inv<12, Load, Store>), dim3(npoly), dim3(ntt_threads<12>()), 0, s, ld,
                            st, c.dp);
     else
-        hipLaunchKernelGGL((k_ntt_inv<13, Load, Store>), dim3(npoly), dim3(kNttThreads), 0, s, ld,
+        hipLaunchKernelGGL((k_ntt_inv<13, Load, Store>), dim3(npoly), dim3(ntt_threads<13>()), 0, s, ld,
                            st, c.dp);
     return check_hip(hipGetLastError(), "ntt_inv launch");
 }
@@ -371,10 +390,10 @@ int launch_inv_lds(const Ctx &c, Load ld, Epi epi, int npoly, hipStream_t s)
     if (npoly <= 0) return PIMM_OK;
     ProfScope prof("ntt_inv", s);
     if (c.dp.logN == 12)
-        hipLaunchKernelGGL((k_ntt_inv_lds<12, Load, Epi>), dim3(npoly), dim3(kNttThreads), 0, s, ld,
+        hipLaunchKernelGGL((k_ntt_inv_lds<12, Load, Epi>), dim3(npoly), dim3(ntt_threads<12>()), 0, s, ld,
                            epi, c.dp);
     else
-        hipLaunchKernelGGL((k_ntt_inv_lds<13, Load, Epi>), dim3(npoly), dim3(kNttThreads), 0, s, ld,
+        hipLaunchKernelGGL((k_ntt_inv_lds<13, Load, Epi>), dim3(npoly), dim3(ntt_threads<13>()), 0, s, ld,
                            epi, c.dp);
     return check_hip(hipGetLastError(), "ntt_inv launch");
 }

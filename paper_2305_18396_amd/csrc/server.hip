@@ -176,7 +176,7 @@ struct ReplyOut {
         const int n = 1 << logn;
         if (comp == 1) {
             uint64_t *dst = c1 + (((size_t)y * L + l) << logn);
-            for (int j = threadIdx.x; j < n; j += kNttThreads) {
+            for (int j = threadIdx.x; j < n; j += (int)blockDim.x) {
                 uint64_t x = to_canonical(lds[lds_idx(j)], p, pinv);
                 if (rr) x = add_mod(x, lift_small(ey[j], q), q);
                 dst[j] = x;
@@ -185,7 +185,7 @@ struct ReplyOut {
         }
         const uint32_t per = mb.d * nb;
         uint64_t *dst = c0s + ((size_t)y * L + l) * per;
-        for (uint32_t idx = threadIdx.x; idx < per; idx += kNttThreads) {
+        for (uint32_t idx = threadIdx.x; idx < per; idx += blockDim.x) {
             const uint32_t k = mb.div(idx), i = idx - k * mb.d;
             const uint32_t j = (k * mb.d + i) * rb + rb - 1;
             uint64_t x = to_canonical(lds[lds_idx((int)j)], p, pinv);
