@@ -21,7 +21,7 @@ plus the accumulators it writes (O * 2 * L * N * 8), divided by its average
 launch duration from HIP events recorded on its stream during the timed steps.
 
 cpu_baseline: the oracle (plain C + Python big integers, OpenMP) on a bounded
-sample: the 768x768 product at sequence 128, output ciphertexts taken in
+sample: the QKV 768x2304 product at sequence 128, output ciphertexts taken in
 chunks until about --cpu-seconds have passed, encryption of all inputs counted
 pro rata.
 
@@ -81,7 +81,7 @@ def cpu_baseline(seconds: float):
     from oracle import oracle as orc
     from paper_2305_18396_amd import workloads
 
-    wl = workloads.bert_base_layer(128)[1]  # attn-out 768x768
+    wl = workloads.bert_base_layer(128)[0]  # QKV 768x2304
     n, r, m = wl.shape
     pyp = orc.Params(4096, 2, 37, 12)
     plan = orc.plan_comm(4096, n, r, m)
@@ -111,7 +111,7 @@ def cpu_baseline(seconds: float):
         done += len(outs)
     elapsed = t_out + t_enc * done / plan.O
     return {"value": macs / elapsed, "unit": "int-MAC/s", "cores": threads, "kind": "oracle",
-            "sample": f"768x768 product at seq 128 (N=4096, 2 primes): {done} of {plan.O} output "
+            "sample": f"QKV 768x2304 product at seq 128 (N=4096, 2 primes): {done} of {plan.O} output "
                       f"ciphertexts through product, re-randomisation, mask and decryption, "
                       f"encryption of all {plan.I} inputs counted pro rata; {elapsed:.1f} s"}
 
