@@ -49,10 +49,12 @@ def stack():
     return ctx, shapes, layers, D, Ws, weights, reqs
 
 
-@pytest.mark.parametrize("schedule", [pimm.PHASED, pimm.PERSISTENT])
-def test_mix_equals_solo_and_xw(stack, orc, schedule):
+@pytest.mark.parametrize("schedule,tile", [(pimm.PHASED, (8, 1)), (pimm.PERSISTENT, (8, 1)),
+                                           (pimm.PHASED, (8, 4)), (pimm.PERSISTENT, (4, 2))])
+def test_mix_equals_solo_and_xw(stack, orc, schedule, tile):
     ctx, shapes, layers, D, Ws, weights, reqs = stack
-    srv = pimm.Server(ctx, layers, shapes, weights, D, 4 << 30, 8, schedule=schedule)
+    srv = pimm.Server(ctx, layers, shapes, weights, D, 4 << 30, 8, schedule=schedule,
+                      mac_rows=tile[0], mac_cols=tile[1])
     mix = srv.run(reqs)
     for rq, res in zip(reqs, mix):
         assert res["steps"] == layers * len(shapes)

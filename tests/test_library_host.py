@@ -115,3 +115,15 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(pimm, "LIB_PATH", str(tmp_path / "absent.so"))
     with pytest.raises(ImportError, match="not built"):
         pimm.lib()
+
+
+def test_probe_rejects_bad_arguments():
+    """pimm_probe validates its arguments before touching a device."""
+    import ctypes
+    rate = ctypes.c_double()
+    lib = pimm.lib()
+    assert lib.pimm_probe(0, 99, 1 << 26, 1, ctypes.byref(rate)) == -1       # kind
+    assert lib.pimm_probe(0, pimm.PROBE_READ, 1000, 1, ctypes.byref(rate)) == -1  # too small
+    assert lib.pimm_probe(0, pimm.PROBE_FMA64, 10, 1, ctypes.byref(rate)) == -1   # chain too short
+    assert lib.pimm_probe(0, pimm.PROBE_READ, 1 << 26, 0, ctypes.byref(rate)) == -1  # reps
+    assert lib.pimm_probe(0, pimm.PROBE_READ, 1 << 26, 1, None) == -1
