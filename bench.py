@@ -255,6 +255,11 @@ def bench_serve(args):
                 "wall_s": wall, "max_active": max_active}
 
     sweep = []
+    if args.serve_rates:
+        # Explicit rates only (no saturation search, no one-at-a-time replay).
+        for rate in args.serve_rates:
+            sweep.append(run(rate, args.serve_requests, args.serve_max_active))
+        return {"product_tile": list(args.serve_tile), "sweep": sweep}
     rate = args.serve_rate0
     while True:
         r = run(rate, args.serve_requests, args.serve_max_active)
@@ -428,6 +433,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-max-active", type=int, default=32)
     ap.add_argument("--serve-rate0", type=float, default=4.0)
+    ap.add_argument("--serve-rates", type=lambda v: [float(x) for x in v.split(",")], default=None,
+                    help="serve: run only these arrival rates (comma-separated)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
