@@ -151,9 +151,11 @@ __device__ __forceinline__ void mac_range(const double *__restrict__ Wt, const d
     }
 }
 
-// A tile whose last column tile is ragged (fewer than KB column blocks left) is
-// run as narrower tiles, so that no product is spent on absent columns: a column
-// tile of c < KB blocks becomes tiles of KB/2, KB/4, ... blocks.
+// A tile whose last column tile is ragged (c < KB column blocks left) reads the
+// weight words once either way: with c > KB/2 it runs at full width with the
+// absent columns' input words taken as zero (the product is usually bound by
+// HBM, not by those extra modular products); with c <= KB/2 it runs as
+// narrower tiles (KB/2, KB/4, ...), each of which fits the columns left.
 template <int G, int KB>
 __device__ __forceinline__ void mac_tile(const double *__restrict__ Wt, const double *__restrict__ Ct,
                                          double *__restrict__ Ah, const MacShape &s,
@@ -161,20 +163,11 @@ __device__ __forceinline__ void mac_tile(const double *__restrict__ Wt, const do
                                          int ib0, int jb0, int jb1, int mode)
 {
     const int cols = s.K - kb0;
-    if (KB == 1 || cols >= KB) {
+    if (KB == 1 || 2 * cols > KB) {
         mac_range<G, KB>(Wt, Ct, Ah, s, dp, l, zc, zz, kb0, ib0, jb0, jb1, mode);
         return;
     }
-    if constexpr (KB >= 2) {
-        constexpr int H = KB / 2;
-        if (cols >= H) {
-            mac_range<G, H>(Wt, Ct, Ah, s, dp, l, zc, zz, kb0, ib0, jb0, jb1, mode);
-            if (cols > H)
-                mac_tile<G, H>(Wt, Ct, Ah, s, dp, l, zc, zz, kb0 + H, ib0, jb0, jb1, mode);
-        } else {
-            mac_tile<G, H>(Wt, Ct, Ah, s, dp, l, zc, zz, kb0, ib0, jb0, jb1, mode);
-        }
-    }
+    if constexpr (KB >= 2) mac_tile<G, KB / 2>(Wt, Ct, Ah, s, dp, l, zc, zz, kb0, ib0, jb0, jb1, mode);
 }
 
 // Row tiles per workgroup of the stream-K product.  With RT > 1 a workgroup
