@@ -20,6 +20,20 @@ struct BatchItemDev {
     uint32_t dep_in0, dep_mac0; // first dependency counter of each kind
 };
 
+// Items that share one weight cache line up their column blocks for the phased
+// product, so that a weight word is read once per column tile of the whole
+// group rather than once per item.  Column j of a group is block kb of item.
+struct BatchColDev {
+    uint32_t item, kb;
+};
+struct BatchGroupDev {
+    const double *wh;  // the shared weight cache
+    uint32_t M, R;
+    uint32_t mtiles, mgroups;  // ceil(M / G), ceil(mtiles / RT)
+    uint32_t ncols, ktiles;    // sum of the items' K, ceil(ncols / KB)
+    uint32_t col0, mac0;       // first column, first phased product unit
+};
+
 // Counter words at the start of the workspace (uint32).
 constexpr int kCtrQueue = 0;
 constexpr int kCtrError = 1;
@@ -38,15 +52,21 @@ struct pimm_batch {
     int xcd_map = 1;
     uint32_t grid = 0;          // persistent grid size (0: from occupancy)
     uint32_t spin_limit = 1u << 22;
+    // Device tables, one allocation: items, then weight groups, then group columns.
     pimm::BatchItemDev *d_items = nullptr;
+    pimm::BatchGroupDev *d_groups = nullptr;
+    pimm::BatchColDev *d_cols = nullptr;
+    uint32_t n_groups = 0;
     uint32_t n_in = 0, n_mac = 0, n_out = 0, n_dep = 0;
+    uint32_t n_mac_grouped = 0;  // product units of the phased schedule
     uint64_t ws_bytes = 0;
     uint64_t useful_macs = 0;
     // Owner-supplied workspace offsets (doubles) of each item's c^ and acc^
     // (empty: the batch lays them out itself after the counters).
     std::vector<uint64_t> fixed_chat, fixed_ahat;
-    size_t cap = 0;                          // capacity of d_items (items)
-    pimm::BatchItemDev *h_items = nullptr;   // pinned staging for asynchronous uploads
+    uint8_t *d_tab = nullptr;  // the table allocation
+    uint8_t *h_tab = nullptr;  // pinned staging for asynchronous uploads
+    size_t tab_cap = 0, h_cap = 0;
 };
 
 namespace pimm {
@@ -56,6 +76,7 @@ int batch_rebuild(pimm_batch *b, bool async, hipStream_t s);
 // with_out = false stops after the products: each item's acc^ stays in its
 // workspace (summed over the inner blocks, in NTT form) and its acc is not written.
 int batch_run(const pimm_batch *b, void *ws, hipStream_t s, bool with_out = true);
+void batch_free_tables(pimm_batch *b);
 }  // namespace pimm
 
 

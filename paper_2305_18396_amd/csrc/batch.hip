@@ -4,8 +4,13 @@
 // items of any shapes and sequence lengths on one context.  Its work is the
 // union of three kinds of units:
 //   in   forward NTT of one input polynomial      (sum over items of I*2*L)
-//   mac  one slot group x row-tile group x column tile
-//        (sum of (N/256)*L*RT*ceil(ceil(M/G)/RT)*ceil(K/KB), RT row tiles per group)
+//   mac  one slot group x row-tile group x column tile (RT row tiles per group);
+//        under the phased schedule the items that share a weight cache line up
+//        their column blocks, and a column tile may span items, so every weight
+//        word is read once per KB columns of the whole group
+//        (sum over weight caches of (N/256)*L*RT*ceil(ceil(M/G)/RT)*ceil(sum K/KB));
+//        the persistent schedule keeps one set per item (its dependency counters
+//        are per item)
 //   out  inverse NTT of one accumulator polynomial (sum of O*2*L)
 // Two schedules run them:
 //   PHASED      three launches (all in, all mac, all out), each over a flat
@@ -27,6 +32,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <vector>
 
 #include "batch.h"
@@ -95,8 +101,8 @@ __device__ __forceinline__ void run_mac(const BatchItemDev &it, const MacCoord &
     const int ibt = c.ig * RT + w;
     if (ibt >= (int)it.mtiles) return;
     const MacShape sh{(int)it.M, (int)it.R, (int)it.K, dp.N >> 8};
-    mac_tile<G, KB>(it.wh, ws + it.chat_off, ws + it.ahat_off, sh, dp, c.l, c.zc, c.sub * SPW + lane,
-                    c.kbt * KB, ibt * G, 0, (int)it.R, 0);
+    mac_tile<G, KB>(it.wh, ColsOne{ws + it.chat_off, ws + it.ahat_off, sh, dp.L, dp.N}, sh, dp, c.l,
+                    c.zc, c.sub * SPW + lane, c.kbt * KB, ibt * G, 0, (int)it.R, 0);
 }
 
 // ---- phased schedule ---------------------------------------------------------------
@@ -111,13 +117,66 @@ __global__ __launch_bounds__(kNttThreads) void k_batch_in(const BatchItemDev *it
     run_in<LOGN>(it, (int)(u - it.in0), ws, dp, lds);
 }
 
+// The columns of one weight group (see BatchGroupDev): column j is block kb of
+// item `item`, with that item's c^ and acc^ in the workspace.
+struct ColsGroup {
+    const BatchColDev *cols;  // the group's first column
+    const BatchItemDev *items;
+    double *ws;
+    int n, chunks, L, N;
+    __device__ __forceinline__ int ncols() const { return n; }
+    __device__ __forceinline__ const double *c(int j, int l, int zc, int zz) const
+    {
+        const BatchColDev cd = cols[j];
+        const BatchItemDev &it = items[cd.item];
+        return ws + it.chat_off + ((((size_t)l * chunks + zc) * it.K + cd.kb) * it.R) * 512 + zz;
+    }
+    __device__ __forceinline__ double *a(int j, int l, int z) const
+    {
+        const BatchColDev cd = cols[j];
+        return ws + items[cd.item].ahat_off + ((size_t)cd.kb * 2 * L + l) * N + z;
+    }
+    __device__ __forceinline__ size_t arow(int j) const
+    {
+        return (size_t)items[cols[j].item].K * 2 * L * N;
+    }
+};
+
+// Phased product: one unit per (prime, slot chunk, slot group, column tile, row-tile
+// group) of a weight group, whole inner dimension, row-tile groups fastest.
 template <int G, int KB>
-__global__ __launch_bounds__(256) void k_batch_mac(const BatchItemDev *items, int n, double *ws,
+__global__ __launch_bounds__(256) void k_batch_mac(const BatchGroupDev *groups, int ng,
+                                                   const BatchColDev *cols,
+                                                   const BatchItemDev *items, double *ws,
                                                    int xcd_map, DevParams dp)
 {
+    constexpr int RT = mac_rt(G, KB), SPW = 256 / RT;
     const uint32_t u = xcd_map ? xcd_local(blockIdx.x, gridDim.x) : blockIdx.x;
-    const BatchItemDev &it = items[find_item(items, n, u, 1)];
-    run_mac<G, KB>(it, mac_coord(it, u - it.mac0, dp.N >> 8, mac_rt(G, KB)), ws, dp);
+    int lo = 0, hi = ng - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (groups[mid].mac0 <= u)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const BatchGroupDev &g = groups[lo];
+    const int chunks = dp.N >> 8;
+    uint32_t t = u - g.mac0;
+    const int ig = (int)(t % g.mgroups);
+    t /= g.mgroups;
+    const int kbt = (int)(t % g.ktiles);
+    t /= g.ktiles;
+    const int sub = (int)(t % RT);
+    t /= RT;
+    const int zc = (int)(t % chunks);
+    const int l = (int)(t / chunks);
+    const int lane = (int)threadIdx.x % SPW, w = (int)threadIdx.x / SPW;
+    const int ibt = ig * RT + w;
+    if (ibt >= (int)g.mtiles) return;
+    const MacShape sh{(int)g.M, (int)g.R, 0, chunks};
+    mac_tile<G, KB>(g.wh, ColsGroup{cols + g.col0, items, ws, (int)g.ncols, chunks, dp.L, dp.N}, sh,
+                    dp, l, zc, sub * SPW + lane, kbt * KB, ibt * G, 0, (int)g.R, 0);
 }
 
 template <int LOGN>
@@ -284,29 +343,78 @@ int build_tables(pimm_batch *b, bool async, hipStream_t s)
     b->n_out = out0;
     b->n_dep = dep;
     b->ws_bytes = fixed ? (((uint64_t)dep * 4 + 255) / 256) * 256 : off * 8;
+
+    // Weight groups (first-appearance order) and their columns.
+    std::vector<BatchGroupDev> grp;
+    std::vector<BatchColDev> cols;
+    std::map<const double *, std::vector<uint32_t>> members;
+    std::vector<const double *> order;
+    for (size_t i = 0; i < n; ++i) {
+        auto it = members.find(t[i].wh);
+        if (it == members.end()) {
+            order.push_back(t[i].wh);
+            members[t[i].wh] = {(uint32_t)i};
+        } else {
+            it->second.push_back((uint32_t)i);
+        }
+    }
+    const uint32_t RT = (uint32_t)mac_rt(b->G, b->KB);
+    uint32_t gmac0 = 0;
+    for (const double *wh : order) {
+        const std::vector<uint32_t> &mem = members[wh];
+        BatchGroupDev g;
+        g.wh = wh;
+        g.M = t[mem[0]].M;
+        g.R = t[mem[0]].R;
+        g.mtiles = (g.M + b->G - 1) / b->G;
+        g.mgroups = (g.mtiles + RT - 1) / RT;
+        g.col0 = (uint32_t)cols.size();
+        for (uint32_t i : mem)
+            for (uint32_t kb = 0; kb < t[i].K; ++kb) cols.push_back(BatchColDev{i, kb});
+        g.ncols = (uint32_t)cols.size() - g.col0;
+        g.ktiles = (g.ncols + b->KB - 1) / b->KB;
+        g.mac0 = gmac0;
+        gmac0 += chunks * (uint32_t)L * RT * g.mgroups * g.ktiles;
+        grp.push_back(g);
+    }
+    b->n_groups = (uint32_t)grp.size();
+    b->n_mac_grouped = gmac0;
+
+    // One table allocation: items | groups | columns (each 256-byte aligned).
+    auto a256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t o_grp = a256(n * sizeof(BatchItemDev));
+    const size_t o_col = o_grp + a256(grp.size() * sizeof(BatchGroupDev));
+    const size_t bytes = o_col + a256(cols.size() * sizeof(BatchColDev));
     int rc = PIMM_OK;
-    if (n > b->cap) {
-        if (b->d_items) (void)hipFree(b->d_items);
-        if (b->h_items) (void)hipHostFree(b->h_items);
-        b->d_items = nullptr;
-        b->h_items = nullptr;
-        b->cap = 0;
+    if (bytes > b->tab_cap) {
+        if (b->d_tab) (void)hipFree(b->d_tab);
+        b->d_tab = nullptr;
+        b->tab_cap = 0;
         rc = check_hip(hipSetDevice(c.device), "hipSetDevice");
-        if (!rc) rc = check_hip(hipMalloc((void **)&b->d_items, n * sizeof(BatchItemDev)),
-                                "hipMalloc batch table");
-        if (!rc && async)
-            rc = check_hip(hipHostMalloc((void **)&b->h_items, n * sizeof(BatchItemDev), 0),
-                           "hipHostMalloc batch table");
-        if (!rc) b->cap = n;
+        if (!rc) rc = check_hip(hipMalloc((void **)&b->d_tab, bytes), "hipMalloc batch table");
         if (rc) return rc;
+        b->tab_cap = bytes;
     }
-    if (async) {
-        memcpy(b->h_items, t.data(), n * sizeof(BatchItemDev));
-        return check_hip(hipMemcpyAsync(b->d_items, b->h_items, n * sizeof(BatchItemDev),
-                                        hipMemcpyHostToDevice, s), "upload batch table");
+    if (async && bytes > b->h_cap) {
+        if (b->h_tab) (void)hipHostFree(b->h_tab);
+        b->h_tab = nullptr;
+        b->h_cap = 0;
+        rc = check_hip(hipHostMalloc((void **)&b->h_tab, bytes, 0), "hipHostMalloc batch table");
+        if (rc) return rc;
+        b->h_cap = bytes;
     }
-    return check_hip(hipMemcpy(b->d_items, t.data(), n * sizeof(BatchItemDev), hipMemcpyHostToDevice),
-                     "copy batch table");
+    b->d_items = (BatchItemDev *)b->d_tab;
+    b->d_groups = (BatchGroupDev *)(b->d_tab + o_grp);
+    b->d_cols = (BatchColDev *)(b->d_tab + o_col);
+    std::vector<uint8_t> host(async ? 0 : bytes);
+    uint8_t *h = async ? b->h_tab : host.data();
+    memcpy(h, t.data(), n * sizeof(BatchItemDev));
+    memcpy(h + o_grp, grp.data(), grp.size() * sizeof(BatchGroupDev));
+    memcpy(h + o_col, cols.data(), cols.size() * sizeof(BatchColDev));
+    if (async)
+        return check_hip(hipMemcpyAsync(b->d_tab, h, bytes, hipMemcpyHostToDevice, s),
+                         "upload batch table");
+    return check_hip(hipMemcpy(b->d_tab, h, bytes, hipMemcpyHostToDevice), "copy batch table");
 }
 
 template <int LOGN, int G, int KB>
@@ -323,8 +431,9 @@ int run_batch(const pimm_batch *b, void *ws, bool with_out, hipStream_t s)
         }
         {
             ProfScope prof("mac", s);
-            hipLaunchKernelGGL((k_batch_mac<G, KB>), dim3(b->n_mac), dim3(256), 0, s, b->d_items, n,
-                               wsd, b->xcd_map, c.dp);
+            hipLaunchKernelGGL((k_batch_mac<G, KB>), dim3(b->n_mac_grouped), dim3(256), 0, s,
+                               b->d_groups, (int)b->n_groups, b->d_cols, b->d_items, wsd, b->xcd_map,
+                               c.dp);
         }
         if (with_out) {
             ProfScope prof("ntt_inv", s);
@@ -369,6 +478,16 @@ int run_batch_g(const pimm_batch *b, void *ws, bool with_out, hipStream_t s)
 
 namespace pimm {
 int batch_rebuild(pimm_batch *b, bool async, hipStream_t s) { return build_tables(b, async, s); }
+void batch_free_tables(pimm_batch *b)
+{
+    if (b->d_tab) (void)hipFree(b->d_tab);
+    if (b->h_tab) (void)hipHostFree(b->h_tab);
+    b->d_tab = b->h_tab = nullptr;
+    b->d_items = nullptr;
+    b->d_groups = nullptr;
+    b->d_cols = nullptr;
+    b->tab_cap = b->h_cap = 0;
+}
 int batch_run(const pimm_batch *b, void *ws, hipStream_t s, bool with_out)
 {
     return b->ctx->dp.logN == 12 ? run_batch_g<12>(b, ws, with_out, s)
@@ -406,8 +525,7 @@ int pimm_batch_create(const pimm_batch_item *items, uint32_t count, pimm_batch *
 int pimm_batch_destroy(pimm_batch *b)
 {
     if (!b) return PIMM_OK;
-    if (b->d_items) (void)hipFree(b->d_items);
-    if (b->h_items) (void)hipHostFree(b->h_items);
+    batch_free_tables(b);
     delete b;
     return PIMM_OK;
 }

@@ -34,24 +34,49 @@ __device__ __forceinline__ size_t c_tile_base(const MacShape &s, int l, int zc, 
     return (((size_t)l * s.chunks + zc) * s.K + kb) * (size_t)s.R * 512;
 }
 
-// Inner blocks [jb0, jb1) of one tile of G rows (ib0 ..) and KB column blocks
-// (kb0 ..): every weight word loaded is used for KB column blocks and every
-// input word for G rows.  mode 0: store the reduced sums; mode 1: add them
+// Column blocks of the product as seen by one tile: column `col` has its input
+// words (transformed ciphertext, both components) and its accumulators.  For a
+// single product the columns are its K column blocks; a batch may also line up
+// the columns of several products that share one weight cache.
+struct ColsOne {
+    const double *Ct;  // c^ [L][chunks][K][R][2][256]
+    double *Ah;        // acc^ [O][2][L][N], O = M*K
+    MacShape s;
+    int L, N;
+    __device__ __forceinline__ int ncols() const { return s.K; }
+    // c^ of column col at inner block 0, component 0, slot zz of chunk zc.
+    __device__ __forceinline__ const double *c(int col, int l, int zc, int zz) const
+    {
+        return Ct + c_tile_base(s, l, zc, col) + zz;
+    }
+    // acc^ of column col, row 0, component 0, prime l, slot z; rows are arow() apart.
+    __device__ __forceinline__ double *a(int col, int l, int z) const
+    {
+        return Ah + ((size_t)col * 2 * L + l) * N + z;
+    }
+    __device__ __forceinline__ size_t arow(int) const { return (size_t)s.K * 2 * L * N; }
+};
+
+// Inner blocks [jb0, jb1) of one tile of G rows (ib0 ..) and KB columns (kb0 ..
+// of `cs`): every weight word loaded is used for KB columns and every input
+// word for G rows.  mode 0: store the reduced sums; mode 1: add them
 // atomically (exact: every addend and every partial total is an integer below
 // 2^53, so the order of the additions does not matter).
-template <int G, int KB>
-__device__ __forceinline__ void mac_range(const double *__restrict__ Wt, const double *__restrict__ Ct,
-                                          double *__restrict__ Ah, const MacShape &s,
-                                          const DevParams &dp, int l, int zc, int zz, int kb0,
-                                          int ib0, int jb0, int jb1, int mode)
+template <int G, int KB, class Cols>
+__device__ __forceinline__ void mac_range(const double *__restrict__ Wt, const Cols &cs,
+                                          const MacShape &s, const DevParams &dp, int l, int zc,
+                                          int zz, int kb0, int ib0, int jb0, int jb1, int mode)
 {
     const int L = dp.L, N = dp.N;
     const double p = dp.p[l], pinv = dp.pinv[l];
     const int rows = s.M - ib0 < G ? s.M - ib0 : G;
-    const int cols = s.K - kb0 < KB ? s.K - kb0 : KB;
+    const int cols = cs.ncols() - kb0 < KB ? cs.ncols() - kb0 : KB;
     const double *wp = Wt + w_tile_base(s, l, zc) + ((size_t)ib0 * s.R + jb0) * 256 + zz;
-    const double *cp = Ct + c_tile_base(s, l, zc, kb0) + (size_t)jb0 * 512 + zz;
-    const size_t wrow = (size_t)s.R * 256, ccol = (size_t)s.R * 512;
+    const size_t wrow = (size_t)s.R * 256;
+    const double *cpk[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+        cpk[k] = k < cols ? cs.c(kb0 + k, l, zc, zz) + (size_t)jb0 * 512 : nullptr;
 
     double a0[G][KB], a1[G][KB];
 #pragma unroll
@@ -66,11 +91,12 @@ __device__ __forceinline__ void mac_range(const double *__restrict__ Wt, const d
 #pragma unroll
         for (int k = 0; k < KB; ++k) {
             if (k < cols) {
-                const double *ck = cp + k * ccol;
+                const double *ck = cpk[k];
                 c00[k] = ck[0];
                 c01[k] = ck[256];
                 c10[k] = ck[512];
                 c11[k] = ck[768];
+                cpk[k] = ck + 1024;
             } else {
                 c00[k] = c01[k] = c10[k] = c11[k] = 0.0;
             }
@@ -106,15 +132,14 @@ __device__ __forceinline__ void mac_range(const double *__restrict__ Wt, const d
                 }
         }
         wp += 512;
-        cp += 1024;
     }
     if (jb < jb1) {
         double c0[KB], c1[KB];
 #pragma unroll
         for (int k = 0; k < KB; ++k) {
             if (k < cols) {
-                c0[k] = cp[k * ccol];
-                c1[k] = cp[k * ccol + 256];
+                c0[k] = cpk[k][0];
+                c1[k] = cpk[k][256];
             } else {
                 c0[k] = c1[k] = 0.0;
             }
@@ -130,44 +155,45 @@ __device__ __forceinline__ void mac_range(const double *__restrict__ Wt, const d
         }
     }
     const int z = (zc << 8) + zz;
+    const size_t comp = (size_t)L * N;
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
+    for (int k = 0; k < KB; ++k) {
+        if (k >= cols) continue;
+        double *ak = cs.a(kb0 + k, l, z);
+        const size_t ar = cs.arow(kb0 + k);
 #pragma unroll
-        for (int k = 0; k < KB; ++k) {
-            if (g < rows && k < cols) {
-                const size_t y = (size_t)(ib0 + g) * s.K + kb0 + k;
-                double *d0 = Ah + ((y * 2 + 0) * L + l) * N + z;
-                double *d1 = Ah + ((y * 2 + 1) * L + l) * N + z;
+        for (int g = 0; g < G; ++g) {
+            if (g < rows) {
+                double *d0 = ak + (size_t)(ib0 + g) * ar;
                 const double v0 = reduce(a0[g][k], p, pinv), v1 = reduce(a1[g][k], p, pinv);
                 if (mode == 0) {
-                    *d0 = v0;
-                    *d1 = v1;
+                    d0[0] = v0;
+                    d0[comp] = v1;
                 } else {
                     atomicAdd(d0, v0);
-                    atomicAdd(d1, v1);
+                    atomicAdd(d0 + comp, v1);
                 }
             }
         }
     }
 }
 
-// A tile whose last column tile is ragged (c < KB column blocks left) reads the
+// A tile whose last column tile is ragged (c < KB columns left) reads the
 // weight words once either way: with c > KB/2 it runs at full width with the
 // absent columns' input words taken as zero (the product is usually bound by
 // HBM, not by those extra modular products); with c <= KB/2 it runs as
 // narrower tiles (KB/2, KB/4, ...), each of which fits the columns left.
-template <int G, int KB>
-__device__ __forceinline__ void mac_tile(const double *__restrict__ Wt, const double *__restrict__ Ct,
-                                         double *__restrict__ Ah, const MacShape &s,
-                                         const DevParams &dp, int l, int zc, int zz, int kb0,
-                                         int ib0, int jb0, int jb1, int mode)
+template <int G, int KB, class Cols>
+__device__ __forceinline__ void mac_tile(const double *__restrict__ Wt, const Cols &cs,
+                                         const MacShape &s, const DevParams &dp, int l, int zc,
+                                         int zz, int kb0, int ib0, int jb0, int jb1, int mode)
 {
-    const int cols = s.K - kb0;
+    const int cols = cs.ncols() - kb0;
     if (KB == 1 || 2 * cols > KB) {
-        mac_range<G, KB>(Wt, Ct, Ah, s, dp, l, zc, zz, kb0, ib0, jb0, jb1, mode);
+        mac_range<G, KB>(Wt, cs, s, dp, l, zc, zz, kb0, ib0, jb0, jb1, mode);
         return;
     }
-    if constexpr (KB >= 2) mac_tile<G, KB / 2>(Wt, Ct, Ah, s, dp, l, zc, zz, kb0, ib0, jb0, jb1, mode);
+    if constexpr (KB >= 2) mac_tile<G, KB / 2>(Wt, cs, s, dp, l, zc, zz, kb0, ib0, jb0, jb1, mode);
 }
 
 // Row tiles per workgroup of the stream-K product.  With RT > 1 a workgroup

@@ -42,8 +42,8 @@ __global__ __launch_bounds__(256) void k_mac_sk(const double *__restrict__ Wt,
         const int mode = (jb0 == 0 && jb1 == sh.R) ? 0 : 1;
         const int ibt = ig * RT + w;
         if (ibt < mtiles)
-            mac_tile<G, KB>(Wt, Ct, Ah, sh, dp, l, zc, sub * SPW + lane, kbt * KB, ibt * G, jb0, jb1,
-                            mode);
+            mac_tile<G, KB>(Wt, ColsOne{Ct, Ah, sh, dp.L, dp.N}, sh, dp, l, zc, sub * SPW + lane,
+                            kbt * KB, ibt * G, jb0, jb1, mode);
         u += (uint64_t)(jb1 - jb0);
     }
 }

@@ -263,8 +263,7 @@ int pimm_serve_destroy(pimm_server *sv)
 {
     if (!sv) return PIMM_OK;
     if (sv->arena_base) (void)hipFree(sv->arena_base);
-    if (sv->batch.d_items) (void)hipFree(sv->batch.d_items);
-    if (sv->batch.h_items) (void)hipHostFree(sv->batch.h_items);
+    batch_free_tables(&sv->batch);
     delete sv;
     return PIMM_OK;
 }
