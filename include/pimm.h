@@ -145,7 +145,7 @@ int pimm_plan_destroy(pimm_plan *plan);
 int pimm_plan_query(const pimm_plan *plan, pimm_plan_info *info);
 /* Schedule of pimm_matmul's slot-wise products: each thread owns mac_rows output
  * rows by mac_cols output column blocks (rows x cols one of 4x1, 8x1, 16x1, 4x2,
- * 8x2, 16x2, 2x4, 4x4, 8x4), so that a weight word it loads serves mac_cols column
+ * 8x2, 16x2, 2x4, 4x4, 8x4, 2x8, 4x8), so that a weight word it loads serves mac_cols column
  * blocks (a ragged last column tile runs as narrower tiles);
  * the (tile, inner block) iterations are divided evenly over a grid of `waves`
  * (1, 2, 4) times the workgroups the device holds at once.  Any schedule gives

@@ -205,12 +205,13 @@ __host__ __device__ constexpr int mac_rt(int G, int KB) { return KB > 1 ? 4 : 1;
 
 // Product tile shapes (G rows, KB column blocks per thread) the library instantiates.
 #define PIMM_MAC_SHAPES(X) \
-    X(4, 1) X(8, 1) X(16, 1) X(4, 2) X(8, 2) X(16, 2) X(2, 4) X(4, 4) X(8, 4)
+    X(4, 1) X(8, 1) X(16, 1) X(4, 2) X(8, 2) X(16, 2) X(2, 4) X(4, 4) X(8, 4) X(2, 8) X(4, 8)
 
 __host__ __device__ constexpr bool mac_shape_ok(int G, int KB)
 {
     return (KB == 1 && (G == 4 || G == 8 || G == 16)) ||
-           (KB == 2 && (G == 4 || G == 8 || G == 16)) || (KB == 4 && (G == 2 || G == 4 || G == 8));
+           (KB == 2 && (G == 4 || G == 8 || G == 16)) ||
+           (KB == 4 && (G == 2 || G == 4 || G == 8)) || (KB == 8 && (G == 2 || G == 4));
 }
 
 // ---- stores into the chunk-contiguous layouts (NTT output slot z) --------------

@@ -70,7 +70,8 @@ int pimm_plan_autotune(pimm_plan *plan, const pimm_weights *w, const uint64_t *c
     struct Shape {
         int g, kb;
     };
-    const Shape shapes[] = {{4, 1}, {8, 1}, {16, 1}, {4, 2}, {8, 2}, {16, 2}, {2, 4}, {4, 4}, {8, 4}};
+    const Shape shapes[] = {{4, 1}, {8, 1}, {16, 1}, {4, 2}, {8, 2}, {16, 2},
+                            {2, 4}, {4, 4}, {8, 4}, {2, 8}, {4, 8}};
     const int waves[3] = {1, 2, 4};
     const int K = (int)plan->info.K;
     double best = DBL_MAX;
@@ -116,7 +117,8 @@ int pimm_batch_autotune(pimm_batch *b, void *ws, size_t ws_bytes, int reps, void
     };
     const Cand cands[] = {{kPhased, 8, 1, 1},      {kPhased, 8, 1, 0},      {kPhased, 16, 1, 1},
                           {kPhased, 8, 2, 1},      {kPhased, 16, 2, 1},     {kPhased, 4, 4, 1},
-                          {kPhased, 8, 4, 1},      {kPhased, 8, 4, 0},      {kPersistent, 8, 1, 1},
+                          {kPhased, 8, 4, 1},      {kPhased, 8, 4, 0},      {kPhased, 4, 8, 1},
+                          {kPhased, 2, 8, 1},      {kPersistent, 8, 1, 1},
                           {kPersistent, 16, 2, 1}, {kPersistent, 4, 4, 1}, {kPersistent, 8, 4, 1}};
     double best = DBL_MAX;
     Cand bc = {b->schedule, b->G, b->KB, b->xcd_map};

@@ -54,6 +54,7 @@ def batch_setup():
     (pimm.PHASED, 8, 1, True), (pimm.PHASED, 4, 1, False), (pimm.PHASED, 16, 1, True),
     (pimm.PHASED, 4, 2, True), (pimm.PHASED, 8, 2, True), (pimm.PHASED, 2, 4, True),
     (pimm.PHASED, 4, 4, False), (pimm.PHASED, 8, 4, True), (pimm.PHASED, 16, 2, True),
+    (pimm.PHASED, 4, 8, True), (pimm.PHASED, 2, 8, False),
     (pimm.PERSISTENT, 8, 1, True), (pimm.PERSISTENT, 16, 1, False), (pimm.PERSISTENT, 4, 2, True),
     (pimm.PERSISTENT, 4, 4, True), (pimm.PERSISTENT, 2, 4, False), (pimm.PERSISTENT, 8, 4, True)])
 def test_batch_equals_solo(batch_setup, schedule, rows_per_thread, cols, xcd):

@@ -294,7 +294,7 @@ def test_full_size_bert_large_op(orc):
 
 
 TUNINGS = [(g, kb, wv) for g, kb in [(4, 1), (8, 1), (16, 1), (4, 2), (8, 2), (16, 2), (2, 4),
-                                    (4, 4), (8, 4)]
+                                    (4, 4), (8, 4), (2, 8), (4, 8)]
            for wv in (1, 2, 4)]
 
 
