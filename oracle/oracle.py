@@ -513,3 +513,20 @@ def pi_matmul(params: Params, plan: Plan, X: np.ndarray, W: np.ndarray, client_s
     Y1 = place_shares(plan, sm, outs)
     return dict(s=s, pk=pk, pt=pt, ptA=ptA, ct=ct, acc=acc, acc_rr=acc_rr, c1=c1, c0s=c0s,
                 smask=sm, Y0=Y0, Y1=Y1, outs=outs)
+
+
+def fc_complete(params: Params, X1: np.ndarray, W: np.ndarray, bias, Y1: np.ndarray) -> np.ndarray:
+    """Server side of a fully connected layer y = x W + b on additive shares (section 3.1, the
+    linear layers).  The input x is shared as X0 (client) + X1 (server) mod 2^l; Pi_MatMul on
+    X0 leaves the server with Y1, where Y0 + Y1 = X0 W.  The server holds X1, W and b, so it
+    adds its local product and the bias:
+        Y1' = Y1 + X1 W + b  (mod 2^l),   Y0 + Y1' = X W + b.
+    b is at the scale of the product (2f fractional bits).  uint64 wrap-around arithmetic is
+    exact mod 2^l; X1 is read mod 2^l."""
+    mask = np.uint64(params.t - 1)
+    Xu = np.asarray(X1, dtype=np.uint64) & mask
+    Wu = np.asarray(W, dtype=np.int64).astype(np.uint64)
+    out = np.asarray(Y1, dtype=np.uint64) + Xu @ Wu
+    if bias is not None:
+        out = out + np.asarray(bias, dtype=np.int64).astype(np.uint64)[None, :]
+    return out & mask
