@@ -25,7 +25,8 @@ extern "C" {
 #endif
 
 enum pimm_probe_kind {
-    /* Streaming read of `size` bytes (16-byte loads); rate in bytes/s. */
+    /* Streaming read of `size` bytes (16-byte non-temporal loads, each wave over one
+     * contiguous span); rate in bytes/s. */
     PIMM_PROBE_READ = 0,
     /* Copy of `size` bytes into a second buffer; rate counts read + write bytes/s. */
     PIMM_PROBE_COPY = 1,
@@ -37,7 +38,7 @@ enum pimm_probe_kind {
     PIMM_PROBE_MODMUL_BARRETT = 4,
     /* uint64 Shoup products by a fixed multiplier, `size` per lane; rate in products/s. */
     PIMM_PROBE_MODMUL_SHOUP = 5,
-    /* Streaming read of `size` bytes with 8-byte loads (the product's load width); bytes/s. */
+    /* As PIMM_PROBE_READ with 8-byte loads (the product's load width); bytes/s. */
     PIMM_PROBE_READ8 = 6,
 };
 

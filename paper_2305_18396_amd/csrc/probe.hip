@@ -13,39 +13,56 @@ namespace {
 constexpr int kChains = 8;
 constexpr int kThreads = 256;
 
+// Streaming reads: every wave reads one contiguous span of the buffer, eight
+// loads in flight per lane, each wave instruction over 64 consecutive elements
+// (1 KiB with 16-byte loads, 512 bytes with 8-byte loads), non-temporal.  A
+// grid-stride loop, whose consecutive loads of a wave lie a grid apart, reads
+// about 10% slower on MI355X.
+template <class T>
+__device__ __forceinline__ double read_span(const T *__restrict__ a, size_t n)
+{
+    constexpr int U = 8;
+    const size_t waves = (size_t)gridDim.x * (kThreads / 64);
+    const size_t wave = (size_t)blockIdx.x * (kThreads / 64) + threadIdx.x / 64;
+    const size_t lane = threadIdx.x % 64;
+    const size_t per = (n + waves - 1) / waves;
+    const size_t begin = wave * per, end = begin + per < n ? begin + per : n;
+    double s0 = 0.0, s1 = 0.0;
+    size_t i = begin + lane;
+    for (; i + (U - 1) * 64 < end; i += U * 64) {
+        T x[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) x[k] = __builtin_nontemporal_load(a + i + k * 64);
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            if constexpr (sizeof(T) == 16) {
+                s0 += x[k][0];
+                s1 += x[k][1];
+            } else {
+                s0 += x[k];
+            }
+        }
+    }
+    for (; i < end; i += 64) {
+        if constexpr (sizeof(T) == 16)
+            s0 += a[i][0] + a[i][1];
+        else
+            s0 += a[i];
+    }
+    return s0 + s1;
+}
+
 __global__ __launch_bounds__(kThreads) void k_read(const double2 *__restrict__ a, size_t n2,
                                                    double *__restrict__ out)
 {
-    const size_t stride = (size_t)gridDim.x * kThreads;
-    size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x;
-    double s0 = 0.0, s1 = 0.0;
-    for (; i + 3 * stride < n2; i += 4 * stride) {
-        const double2 x0 = a[i], x1 = a[i + stride], x2 = a[i + 2 * stride], x3 = a[i + 3 * stride];
-        s0 += (x0.x + x1.x) + (x2.x + x3.x);
-        s1 += (x0.y + x1.y) + (x2.y + x3.y);
-    }
-    for (; i < n2; i += stride) {
-        s0 += a[i].x;
-        s1 += a[i].y;
-    }
-    out[(size_t)blockIdx.x * kThreads + threadIdx.x] = s0 + s1;
+    typedef double v2 __attribute__((ext_vector_type(2)));
+    out[(size_t)blockIdx.x * kThreads + threadIdx.x] = read_span((const v2 *)a, n2);
 }
 
 __global__ __launch_bounds__(kThreads) void k_read8(const double *__restrict__ a, size_t n,
                                                     double *__restrict__ out)
 {
-    const size_t stride = (size_t)gridDim.x * kThreads;
-    size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x;
-    double s0 = 0.0, s1 = 0.0;
-    for (; i + 7 * stride < n; i += 8 * stride) {
-        double x[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) x[k] = a[i + k * stride];
-        s0 += (x[0] + x[1]) + (x[2] + x[3]);
-        s1 += (x[4] + x[5]) + (x[6] + x[7]);
-    }
-    for (; i < n; i += stride) s0 += a[i];
-    out[(size_t)blockIdx.x * kThreads + threadIdx.x] = s0 + s1;
+    out[(size_t)blockIdx.x * kThreads + threadIdx.x] = read_span(a, n);
 }
 
 __global__ __launch_bounds__(kThreads) void k_copy(const double2 *__restrict__ a,
