@@ -558,6 +558,24 @@ def main():
     torch.cuda.synchronize()
     server_s = (time.perf_counter() - t0) / args.steps
 
+    # The server's completion of each fully connected layer (x1 W + b added to its share;
+    # not part of the timed step): x1 and b are synthetic, the shares are the step's.
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    for st in state:
+        fi = st["plan"].info
+        st["x1"] = torch.randint(0, 1 << ell, (fi.n, fi.r), generator=gen, device=dev)
+        st["b"] = torch.randint(-(1 << 30), 1 << 30, (fi.m,), generator=gen, device=dev)
+    for st in state:
+        pimm.fc_complete(st["plan"], st["w"], st["x1"], st["b"], st["y1"], st["ws"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        for st in state:
+            pimm.fc_complete(st["plan"], st["w"], st["x1"], st["b"], st["y1"], st["ws"])
+    torch.cuda.synchronize()
+    fc_s = (time.perf_counter() - t0) / args.steps
+
     if args.calib_copy_mb:
         src = torch.ones(args.calib_copy_mb << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -606,6 +624,8 @@ def main():
         },
         "server_path_ms": server_s * 1e3,
         "server_path_int_mac_per_s": useful / server_s,
+        "fc_completion_ms": fc_s * 1e3,
+        "fc_completion_int_mac_per_s": useful / fc_s,
         "slot_mac_per_s": slot_macs * args.steps / elapsed,
         "server_ntt_butterflies_per_s": butterflies * args.steps / elapsed,
         "wire_bytes_per_step": wire,

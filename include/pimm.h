@@ -225,6 +225,22 @@ int pimm_matmul_share(const pimm_plan *plan, const pimm_weights *w, const uint64
                       uint64_t *c0s, uint64_t *server_share, void *ws, size_t ws_bytes,
                       void *stream);
 
+/* Completion of a fully connected layer y = x W + b on additive shares (section
+ * 3.1, the linear layers).  The input is shared as x = x0 + x1 mod 2^l; the client
+ * runs Pi_MatMul on x0, after which the server holds share1 with
+ * share0 + share1 = x0 W.  The server holds x1, W and b and adds its local part:
+ *     share1[i][j] <- (share1[i][j] + sum_k x1[i][k] W[k][j] + bias[j]) mod 2^l,
+ * so that share0 + share1 = x W + b (mod 2^l).
+ * x1: device u64 [n][r] (read mod 2^l); W is the matrix `w` was made from (the
+ * weights object keeps a copy); bias: device i64 [m] at the scale of the product
+ * (2f fractional bits), or NULL; share1: device u64 [n][m], updated in place.
+ * Exact: the product runs on FP64 limb sums, so the call fails with PIMM_E_ARG
+ * when r * max|W| * (2^ceil(l/2) - 1) reaches 2^53.  ws: at least
+ * pimm_plan_info.workspace_bytes (uses n*m*16 bytes). */
+int pimm_fc_complete(const pimm_plan *plan, const pimm_weights *w, const uint64_t *x1,
+                     const int64_t *bias, uint64_t *share1, void *ws, size_t ws_bytes,
+                     void *stream);
+
 /* ---- batching: many products in one pass ----------------------------------------- */
 
 /* One product of a batch: a plan, a weight cache that fits it (same r, m, mb, rb),

@@ -248,6 +248,7 @@ struct Weights {
     Ctx *ctx = nullptr;
     pimm_plan_info info;        // of the plan it was made for (r, m, mb, rb, M, R, Wb matter)
     double *d_w_hat = nullptr;  // [L][N/256][M][R][256] NTT slots, balanced
+    double *d_w_plain = nullptr;  // [r][m] the weights as doubles (the FC completion's product)
     int64_t wmax = 0;
 };
 
@@ -257,6 +258,10 @@ int check_hip(hipError_t e, const char *what);
 Key make_key(const uint8_t seed[32]);
 bool noise_ok(const Ctx &c, const pimm_plan_info &f, uint64_t wmax);
 bool weights_fit(const Weights *w, const Plan *plan);
+// FC completion (fc.hip): the weights as doubles, and whether the limb sums of
+// X1 W stay exact for this shape, share width and weight bound.
+int weights_plain(const int64_t *W, double *Wd, size_t n, hipStream_t s);
+bool fc_exact(const pimm_plan_info &f, int ell, uint64_t wmax);
 uint64_t fused_workspace_bytes(const Ctx &c, const pimm_plan_info &f);
 int plan_rule(const Ctx &c, uint32_t n, uint32_t r, uint32_t m, uint32_t mb, uint32_t rb, uint32_t nb,
               uint32_t d_fix, pimm_plan_info &f);

@@ -277,6 +277,8 @@ static void fill_info(const Ctx &c, pimm_plan_info &f)
     if (mm > ws) ws = mm;
     if (msk > ws) ws = msk;
     if (dec > ws) ws = dec;
+    const uint64_t fc = (uint64_t)f.n * f.m * 2 * 8;  // the FC completion's two limb sums
+    if (fc > ws) ws = fc;
     f.workspace_bytes = ws;
 }
 

@@ -1,0 +1,178 @@
+// fc.hip -- the server's completion of a fully connected layer on additive shares
+// (section 3.1, the linear layers): after Pi_MatMul on the client's share X0 the
+// server holds Y1 with Y0 + Y1 = X0 W mod 2^l; it adds its own share's product
+// and the bias, Y1 <- Y1 + X1 W + b (mod 2^l), so that Y0 + Y1 = X W + b.
+//
+// X1 W is an integer product mod 2^l.  It runs on the FP64 unit, exactly: each
+// entry of X1 (read mod 2^l) is split as xh 2^S + xl with S = ceil(l / 2), the
+// weights are small signed integers, and both limb products are summed in
+// doubles.  Every partial sum is an integer of magnitude at most
+// r (2^S - 1) max|W|, which the call checks to be below 2^53, so the sums are
+// exact in any order (the split inner dimension is added with FP64 atomics).
+// The epilogue turns the two sums into integers and finishes mod 2^l.
+#include "common.h"
+
+namespace pimm {
+
+namespace {
+
+constexpr int kFcT = 64;   // output tile: 64 rows of X1 by 64 columns of W
+constexpr int kFcK = 16;   // inner step held in LDS
+constexpr int kFcKC = 64;  // inner extent of one workgroup (the inner dimension is split)
+
+__global__ void k_fc_zero(double *p, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+// acc[0][i][j] += sum_k xl[i][k] W[k][j], acc[1][i][j] += sum_k xh[i][k] W[k][j] over the
+// workgroup's inner range.  Thread (tx, ty) of 16 x 16 owns rows ty + 16 a and columns
+// tx + 16 b (a, b < 4) of the tile.
+__global__ __launch_bounds__(256) void k_fc_gemm(const uint64_t *__restrict__ X1,
+                                                 const double *__restrict__ Wd,
+                                                 double *__restrict__ acc, int n, int r, int m,
+                                                 int S, uint64_t xmask)
+{
+    __shared__ double xl[kFcK][kFcT + 1], xh[kFcK][kFcT + 1], wt[kFcK][kFcT];
+    const int tx = (int)threadIdx.x % 16, ty = (int)threadIdx.x / 16;
+    const int j0 = (int)blockIdx.x * kFcT, i0 = (int)blockIdx.y * kFcT;
+    const int k0 = (int)blockIdx.z * kFcKC;
+    const int k1 = k0 + kFcKC < r ? k0 + kFcKC : r;
+    const uint64_t lmask = ((uint64_t)1 << S) - 1;
+    double al[4][4], ah[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) al[a][b] = ah[a][b] = 0.0;
+
+    for (int kk = k0; kk < k1; kk += kFcK) {
+        for (int e = (int)threadIdx.x; e < kFcT * kFcK; e += 256) {
+            const int i = e / kFcK, k = e % kFcK;
+            const int gi = i0 + i, gk = kk + k;
+            const uint64_t v = (gi < n && gk < k1) ? X1[(size_t)gi * r + gk] & xmask : 0;
+            xl[k][i] = (double)(v & lmask);
+            xh[k][i] = (double)(v >> S);
+        }
+        for (int e = (int)threadIdx.x; e < kFcK * kFcT; e += 256) {
+            const int k = e / kFcT, j = e % kFcT;
+            const int gk = kk + k, gj = j0 + j;
+            wt[k][j] = (gk < k1 && gj < m) ? Wd[(size_t)gk * m + gj] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kFcK; ++k) {
+            double vl[4], vh[4], w[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                vl[a] = xl[k][ty + 16 * a];
+                vh[a] = xh[k][ty + 16 * a];
+            }
+#pragma unroll
+            for (int b = 0; b < 4; ++b) w[b] = wt[k][tx + 16 * b];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    al[a][b] = __builtin_fma(vl[a], w[b], al[a][b]);
+                    ah[a][b] = __builtin_fma(vh[a], w[b], ah[a][b]);
+                }
+        }
+        __syncthreads();
+    }
+    const size_t plane = (size_t)n * m;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = i0 + ty + 16 * a, j = j0 + tx + 16 * b;
+            if (i < n && j < m) {
+                atomicAdd(acc + (size_t)i * m + j, al[a][b]);
+                atomicAdd(acc + plane + (size_t)i * m + j, ah[a][b]);
+            }
+        }
+}
+
+// share[i][j] <- (share[i][j] + lo + hi 2^S + b[j]) mod 2^l, in uint64 wrap-around
+// arithmetic (exact mod 2^l); lo and hi are the exact integer sums.
+__global__ void k_fc_finish(const double *__restrict__ acc, const int64_t *__restrict__ bias,
+                            uint64_t *__restrict__ share, int n, int m, int S, uint64_t tmask)
+{
+    const size_t plane = (size_t)n * m;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < plane;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const uint64_t lo = (uint64_t)(int64_t)acc[idx];
+        const uint64_t hi = (uint64_t)(int64_t)acc[plane + idx];
+        uint64_t v = share[idx] + lo + (hi << S);
+        if (bias) v += (uint64_t)bias[idx % (size_t)m];
+        share[idx] = v & tmask;
+    }
+}
+
+__global__ void k_w_to_f64(const int64_t *__restrict__ W, double *__restrict__ Wd, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        Wd[i] = (double)W[i];
+}
+
+}  // namespace
+
+int weights_plain(const int64_t *W, double *Wd, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_w_to_f64, dim3(1024), dim3(256), 0, s, W, Wd, n);
+    return check_hip(hipGetLastError(), "weights copy launch");
+}
+
+// Bit split of X1's entries: S = ceil(l / 2).
+static int fc_split(int ell) { return (ell + 1) / 2; }
+
+bool fc_exact(const pimm_plan_info &f, int ell, uint64_t wmax)
+{
+    using u128 = unsigned __int128;
+    const int S = fc_split(ell);
+    const u128 bound = (u128)f.r * ((((u128)1) << S) - 1) * wmax;
+    return bound < ((u128)1 << 53);
+}
+
+}  // namespace pimm
+
+using namespace pimm;
+
+extern "C" {
+
+int pimm_fc_complete(const pimm_plan *plan, const pimm_weights *w, const uint64_t *x1,
+                     const int64_t *bias, uint64_t *share1, void *ws, size_t ws_bytes,
+                     void *stream)
+{
+    if (!plan || !w || !x1 || !share1) return set_error(PIMM_E_ARG, "pimm_fc_complete: NULL argument");
+    if (!weights_fit(w, plan))
+        return set_error(PIMM_E_ARG, "pimm_fc_complete: weights were made for another shape or block split");
+    const Ctx &c = *plan->ctx;
+    const pimm_plan_info &f = plan->info;
+    const int ell = (int)c.params.log2_t;
+    if (!fc_exact(f, ell, (uint64_t)w->wmax))
+        return set_error(PIMM_E_ARG,
+                         "pimm_fc_complete: r * max|W| * 2^%d reaches 2^53 (max|W| = %lld): the "
+                         "limb sums would not be exact",
+                         fc_split(ell), (long long)w->wmax);
+    const size_t need = (size_t)f.n * f.m * 2 * 8;
+    if (!ws || ws_bytes < need) return set_error(PIMM_E_WORKSPACE, "pimm_fc_complete: workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    int rc = check_hip(hipSetDevice(c.device), "hipSetDevice");
+    if (rc) return rc;
+    double *acc = (double *)ws;
+    const int S = fc_split(ell);
+    const uint64_t tmask = ell >= 64 ? ~0ull : (((uint64_t)1 << ell) - 1);
+    ProfScope prof("fc", s);
+    hipLaunchKernelGGL(k_fc_zero, dim3(1024), dim3(256), 0, s, acc, (size_t)f.n * f.m * 2);
+    const dim3 grid((f.m + kFcT - 1) / kFcT, (f.n + kFcT - 1) / kFcT, (f.r + kFcKC - 1) / kFcKC);
+    hipLaunchKernelGGL(k_fc_gemm, grid, dim3(256), 0, s, x1, (const double *)w->d_w_plain, acc,
+                       (int)f.n, (int)f.r, (int)f.m, S, tmask);
+    hipLaunchKernelGGL(k_fc_finish, dim3(1024), dim3(256), 0, s, (const double *)acc, bias, share1,
+                       (int)f.n, (int)f.m, S, tmask);
+    return check_hip(hipGetLastError(), "fc launch");
+}
+
+}  // extern "C"

@@ -313,6 +313,10 @@ int pimm_weights_create(const pimm_plan *plan, const int64_t *W, pimm_weights **
     w->wmax = (int64_t)h_max;
     rc = check_hip(hipMalloc((void **)&w->d_w_hat, f.weights_bytes), "hipMalloc weights");
     if (!rc)
+        rc = check_hip(hipMalloc((void **)&w->d_w_plain, (size_t)f.r * f.m * sizeof(double)),
+                       "hipMalloc plain weights");
+    if (!rc) rc = weights_plain(W, w->d_w_plain, (size_t)f.r * f.m, s);
+    if (!rc)
         rc = launch_fwd(c, LoadWeights{W, f.r, f.m, f.mb, f.rb, f.R, (int)c.params.L},
                         StoreWeightTiled{w->d_w_hat, c.dp.logN, (int)c.params.L, f.M, f.R},
                         (int)(f.Wb * c.params.L), s);
@@ -329,6 +333,7 @@ int pimm_weights_destroy(pimm_weights *w)
 {
     if (!w) return PIMM_OK;
     if (w->d_w_hat) (void)hipFree(w->d_w_hat);
+    if (w->d_w_plain) (void)hipFree(w->d_w_plain);
     delete w;
     return PIMM_OK;
 }

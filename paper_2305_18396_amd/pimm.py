@@ -37,6 +37,7 @@ EXPORTS = [
     "pimm_keygen", "pimm_sk_destroy", "pimm_encode_input", "pimm_encrypt", "pimm_decrypt",
     "pimm_weights_create", "pimm_weights_destroy", "pimm_matmul", "pimm_mask_share",
     "pimm_matmul_share",
+    "pimm_fc_complete",
     "pimm_batch_create", "pimm_batch_destroy", "pimm_batch_query", "pimm_batch_set_schedule",
     "pimm_batch_get_schedule",
     "pimm_batch_matmul", "pimm_batch_status",
@@ -114,6 +115,7 @@ def lib():
         "pimm_matmul": [vp, vp, vp, vp, vp, ctypes.c_size_t, vp],
         "pimm_mask_share": [vp, vp, vp, u32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp],
         "pimm_matmul_share": [vp, vp, vp, vp, u32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp],
+        "pimm_fc_complete": [vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp],
         "pimm_batch_create": [vp, u32, vp],
         "pimm_batch_destroy": [vp],
         "pimm_batch_query": [vp, vp, vp],
@@ -432,6 +434,20 @@ def matmul_share(plan: Plan, w: Weights, pk, seed: bytes, op_id: int, ct: torch.
                                    _ptr(c0s), _ptr(share), _ptr(ws), ws.numel() * 8,
                                    _stream(stream)))
     return c1, c0s, share
+
+
+def fc_complete(plan: Plan, w: Weights, x1: torch.Tensor, bias, share1: torch.Tensor, ws=None,
+                stream=None):
+    """pimm_fc_complete: share1 += x1 W + bias (mod 2^l), in place.  -> share1."""
+    f = plan.info
+    assert x1.dtype == torch.int64 and tuple(x1.shape) == (f.n, f.r)
+    assert share1.dtype == torch.int64 and tuple(share1.shape) == (f.n, f.m)
+    if bias is not None:
+        assert bias.dtype == torch.int64 and tuple(bias.shape) == (f.m,)
+    ws = plan.workspace() if ws is None else ws
+    _check(lib().pimm_fc_complete(plan.h, w.h, _ptr(x1), _ptr(bias) if bias is not None else None,
+                                  _ptr(share1), _ptr(ws), ws.numel() * 8, _stream(stream)))
+    return share1
 
 
 def decrypt(plan: Plan, sk: SecretKey, c1: torch.Tensor, c0s: torch.Tensor, share=None, ws=None,
