@@ -76,6 +76,7 @@ def lib():
         _lib.orc_negacyclic_mul_schoolbook.argtypes = [vp, vp, vp, u64, u64]
         _lib.orc_keygen.argtypes = [u64, u64, vp, vp, vp, vp, vp, vp]
         _lib.orc_encrypt.argtypes = [u64, u64, vp, vp, vp, vp, vp, u32, vp, vp, u64, vp]
+        _lib.orc_encrypt_seeded.argtypes = [u64, u64, vp, vp, vp, vp, vp, vp, u32, vp, vp, u64, vp]
         _lib.orc_ctpt_matmul.argtypes = [u64, u64, vp, vp, u64, u64, vp, vp, vp, u64, vp]
         _lib.orc_rerandomize.argtypes = [u64, u64, vp, vp, vp, vp, u32, vp, vp, u64, vp]
         _lib.orc_mask_extract.argtypes = [u64, u64, vp, vp, ctypes.c_uint, vp, u32, u64, u64, u64,
@@ -344,6 +345,37 @@ def encrypt(params: Params, s: np.ndarray, seed: bytes, op_id: int, pt: np.ndarr
                       _p(_key(seed)), op_id, _p(params.cdt_arr), _p(pt), count, _p(ct))
     return ct
 
+
+def encrypt_seeded(params: Params, s: np.ndarray, seed: bytes, a_seed: bytes, op_id: int,
+                   pt: np.ndarray) -> np.ndarray:
+    """Seed-compressed upload (a wire-format variant of Algorithm 1 step 2): the symmetric
+    encryption with c1 = a drawn from the public seed a_seed and e from the secret seed, so the
+    client sends c0 and a_seed.  -> [count][2][L][N]; with a_seed = seed it equals encrypt()."""
+    pt = _u64(pt)
+    count = pt.shape[0]
+    ct = np.zeros((count, 2, params.L, params.N), dtype=np.uint64)
+    lib().orc_encrypt_seeded(params.N, params.L, _p(params.q_arr), _p(params.psi_arr),
+                             _p(params.delta_arr), _p(np.ascontiguousarray(s, dtype=np.int64)),
+                             _p(_key(seed)), _p(_key(a_seed)), op_id, _p(params.cdt_arr), _p(pt),
+                             count, _p(ct))
+    return ct
+
+
+def expand_ct(params: Params, a_seed: bytes, op_id: int, c0: np.ndarray) -> np.ndarray:
+    """The server's side of the seed-compressed upload: ct[x][0] = c0[x] and
+    ct[x][1][l] = a_l regenerated from a_seed (stream tag 4, prime l, op_id, object x)."""
+    c0 = _u64(c0)
+    count = c0.shape[0]
+    ct = np.zeros((count, 2, params.L, params.N), dtype=np.uint64)
+    ct[:, 0] = c0
+    key = _key(a_seed)
+    for x in range(count):
+        for l in range(params.L):
+            a = np.zeros(params.N, dtype=np.uint64)
+            lib().orc_sample_poly(0, _p(key), TAG_ENC_A, l, op_id, x, params.N, int(params.q_arr[l]),
+                                  0, _p(params.cdt_arr), _p(a))
+            ct[x, 1, l] = a
+    return ct
 
 def matmul(params: Params, plan: Plan, ptA: np.ndarray, ct: np.ndarray, outs=None) -> np.ndarray:
     """Algorithm 1 step 3 ([[c]] = a * [[b]]) summed over the inner blocks, for the requested

@@ -380,6 +380,39 @@ void orc_encrypt(uint64_t n, uint64_t L, const uint64_t *q, const uint64_t *psi,
     }
 }
 
+/* Seed-compressed upload, a wire-format variant of Algorithm 1 step 2: the
+ * same symmetric encryption with a_l drawn from a public key (a_key, tag 4)
+ * and e from the secret key (e_key, tag 5), so that c1 can be regenerated by
+ * the server from a_key.  With a_key = e_key this is orc_encrypt. */
+void orc_encrypt_seeded(uint64_t n, uint64_t L, const uint64_t *q, const uint64_t *psi,
+                        const uint64_t *delta_l, const int64_t *s, const uint8_t e_key[32],
+                        const uint8_t a_key[32], uint32_t op, const uint64_t *cdt,
+                        const uint64_t *pt, uint64_t count, uint64_t *ct)
+{
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t xi = 0; xi < (int64_t)count; ++xi) {
+        uint64_t x = (uint64_t)xi;
+        int64_t *e = (int64_t *)malloc(n * sizeof(int64_t));
+        uint64_t *sl = (uint64_t *)malloc(n * sizeof(uint64_t));
+        uint64_t *as = (uint64_t *)malloc(n * sizeof(uint64_t));
+        orc_sample_poly(2, e_key, TAG_ENC_E, 0, op, (uint32_t)x, n, 0, 0, cdt, e);
+        for (uint64_t l = 0; l < L; ++l) {
+            uint64_t *c0 = ct + ((x * 2 + 0) * L + l) * n;
+            uint64_t *c1 = ct + ((x * 2 + 1) * L + l) * n;
+            orc_sample_poly(0, a_key, TAG_ENC_A, (uint32_t)l, op, (uint32_t)x, n, q[l], 0, cdt, c1);
+            for (uint64_t j = 0; j < n; ++j) sl[j] = lift(s[j], q[l]);
+            orc_negacyclic_mul(c1, sl, as, n, q[l], psi[l]);
+            for (uint64_t j = 0; j < n; ++j) {
+                uint64_t m = mulm(delta_l[l], pt[x * n + j] % q[l], q[l]);
+                c0[j] = subm(addm(m, lift(e[j], q[l]), q[l]), as[j], q[l]);
+            }
+        }
+        free(e);
+        free(sl);
+        free(as);
+    }
+}
+
 /* Ciphertext-plaintext product with accumulation over the inner blocks
  * (Algorithm 1, step 3, [[c]] = a * [[b]], summed over the blocks the inner
  * dimension was split into).  For each requested output ciphertext
