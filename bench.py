@@ -466,7 +466,7 @@ def main():
     cseed, sseed = workloads.seed("client", 1), workloads.seed("server", 1)
     sk, pk = pimm.keygen(ctx, cseed)
     state = []
-    useful = mac_bytes = slot_macs = butterflies = wire = cache = 0
+    useful = mac_bytes = slot_macs = butterflies = wire = wire_seeded = cache = 0
     for i, wl in enumerate(ops):
         n, r, m = wl.shape
         plan = pimm.Plan(ctx, n, r, m, d_fix=args.layer_d)
@@ -499,6 +499,7 @@ def main():
         slot_macs += 2 * L * N * fi.P
         butterflies += L * (N // 2) * (N.bit_length() - 1) * (2 * fi.I + 2 * fi.O)
         wire += fi.ct_bytes + fi.c1_bytes + fi.c0s_bytes
+        wire_seeded += fi.ct_bytes // 2 + 32 + fi.c1_bytes + fi.c0s_bytes
         cache += fi.weights_bytes
         log(f"{wl.name}: plan ({fi.mb},{fi.rb},{fi.nb}) I={fi.I} O={fi.O} Wb={fi.Wb} "
             f"weights {fi.weights_bytes / 1e9:.2f} GB")
@@ -576,6 +577,20 @@ def main():
     torch.cuda.synchronize()
     fc_s = (time.perf_counter() - t0) / args.steps
 
+    # Seed-compressed upload: the server's rebuild of the ciphertexts from c0 and the public
+    # seed (not part of the timed step, whose client uploads whole ciphertexts).
+    aseed = workloads.seed("public", 1)
+    for st in state:
+        st["c0"] = st["ct"][:, 0].contiguous()
+        st["ctx_"] = torch.empty_like(st["ct"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        for st in state:
+            pimm.ct_expand(st["plan"], aseed, st["op"], st["c0"], st["ctx_"])
+    torch.cuda.synchronize()
+    expand_s = (time.perf_counter() - t0) / args.steps
+
     if args.calib_copy_mb:
         src = torch.ones(args.calib_copy_mb << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -626,6 +641,8 @@ def main():
         "server_path_int_mac_per_s": useful / server_s,
         "fc_completion_ms": fc_s * 1e3,
         "fc_completion_int_mac_per_s": useful / fc_s,
+        "wire_bytes_per_step_seeded_upload": wire_seeded,
+        "seeded_upload_expand_ms": expand_s * 1e3,
         "slot_mac_per_s": slot_macs * args.steps / elapsed,
         "server_ntt_butterflies_per_s": butterflies * args.steps / elapsed,
         "wire_bytes_per_step": wire,

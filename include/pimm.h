@@ -179,6 +179,24 @@ int pimm_encode_input(const pimm_plan *plan, const uint64_t *X, uint64_t *pt, vo
 int pimm_encrypt(const pimm_plan *plan, const pimm_sk *sk, const uint8_t seed[32], uint32_t op_id,
                  const uint64_t *pt, uint64_t *ct, void *ws, size_t ws_bytes, void *stream);
 
+/* Seed-compressed upload, a wire-format variant of Algorithm 1 step 2.  c1 = a is
+ * public, so it can come from a public seed: pimm_encrypt_seeded draws a_l from
+ * the stream of a_seed (tag 4) and e from `seed` (tag 5), and the client sends
+ * c0 ([I][L][N], half the ciphertext bytes) with the 32-byte a_seed; the server
+ * rebuilds the ciphertexts with pimm_ct_expand.  a_seed must be independent of
+ * `seed` (a is public, e is not); with a_seed = seed the call is pimm_encrypt.
+ * ct: [I][2][L][N] (device); the client's c0 is ct[x][0]. */
+int pimm_encrypt_seeded(const pimm_plan *plan, const pimm_sk *sk, const uint8_t seed[32],
+                        const uint8_t a_seed[32], uint32_t op_id, const uint64_t *pt, uint64_t *ct,
+                        void *ws, size_t ws_bytes, void *stream);
+
+/* The server's side of the seed-compressed upload: ct[x][0] = c0[x] and
+ * ct[x][1][l] = a_l drawn from a_seed (tag 4, prime l, op_id, object x), so that
+ * ct equals what pimm_encrypt_seeded produced on the client.
+ * c0: [I][L][N], ct: [I][2][L][N] (device, not overlapping).  Allocates nothing. */
+int pimm_ct_expand(const pimm_plan *plan, const uint8_t a_seed[32], uint32_t op_id,
+                   const uint64_t *c0, uint64_t *ct, void *stream);
+
 /* Algorithm 1 step 4, client side: decrypt the decoded coefficients
  * (section 3.1.3: coefficient i of c0 + c1 s needs (c0)_i and all of c1),
  * x = CRT, v = floor((t x + floor(q/2)) / q) mod t, and place them by pi_C^{-1}:

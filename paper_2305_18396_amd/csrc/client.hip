@@ -1,4 +1,6 @@
 // client.hip -- the client's side of Pi_MatMul (Algorithm 1 steps 1, 2 and 4).
+#include <string.h>
+
 #include "common.h"
 #include "ntt.h"
 
@@ -221,10 +223,14 @@ int pimm_encode_input(const pimm_plan *plan, const uint64_t *X, uint64_t *pt, vo
 }
 
 // Workspace: a^ [I][L][N] doubles, then e [I][N] int64.
-int pimm_encrypt(const pimm_plan *plan, const pimm_sk *sk, const uint8_t seed[32], uint32_t op_id,
-                 const uint64_t *pt, uint64_t *ct, void *ws, size_t ws_bytes, void *stream)
+// Symmetric encryption with e drawn from `seed` and a from `a_seed` (the same
+// seed for pimm_encrypt).
+static int encrypt_with(const pimm_plan *plan, const pimm_sk *sk, const uint8_t seed[32],
+                        const uint8_t a_seed[32], uint32_t op_id, const uint64_t *pt, uint64_t *ct,
+                        void *ws, size_t ws_bytes, void *stream)
 {
-    if (!plan || !sk || !seed || !pt || !ct) return set_error(PIMM_E_ARG, "pimm_encrypt: NULL argument");
+    if (!plan || !sk || !seed || !a_seed || !pt || !ct)
+        return set_error(PIMM_E_ARG, "pimm_encrypt: NULL argument");
     const Ctx &c = *plan->ctx;
     if (sk->ctx != plan->ctx) return set_error(PIMM_E_ARG, "pimm_encrypt: key of another context");
     const pimm_plan_info &f = plan->info;
@@ -236,12 +242,25 @@ int pimm_encrypt(const pimm_plan *plan, const pimm_sk *sk, const uint8_t seed[32
     double *ah = (double *)ws;
     int64_t *e = (int64_t *)(ah + (size_t)f.I * L * N);
     const Key key = make_key(seed);
-    // c1 = a (uniform per prime, written straight into the ciphertexts) and e, in one launch.
-    SampleJobs js{};
-    js.n = 2;
-    js.job[0] = SampleJob{0, kTagEncA, 0, (int)f.I, 0, (int)L, ct + L * N, 2 * L * N, N, 0};
-    js.job[1] = SampleJob{2, kTagEncE, 0, (int)f.I, 0, 1, e, N, 0, 0};
-    int rc = launch_samples(c, key, op_id, js, s);
+    // c1 = a (uniform per prime, written straight into the ciphertexts) and e: one launch
+    // when both come from the same seed, else one per seed.
+    const SampleJob ja{0, kTagEncA, 0, (int)f.I, 0, (int)L, ct + L * N, 2 * L * N, N, 0};
+    const SampleJob je{2, kTagEncE, 0, (int)f.I, 0, 1, e, N, 0, 0};
+    int rc;
+    if (memcmp(seed, a_seed, 32) == 0) {
+        SampleJobs js{};
+        js.n = 2;
+        js.job[0] = ja;
+        js.job[1] = je;
+        rc = launch_samples(c, key, op_id, js, s);
+    } else {
+        SampleJobs js{};
+        js.n = 1;
+        js.job[0] = ja;
+        rc = launch_samples(c, make_key(a_seed), op_id, js, s);
+        js.job[0] = je;
+        if (!rc) rc = launch_samples(c, key, op_id, js, s);
+    }
     if (!rc)
         rc = launch_fwd(c, LoadCtComp{ct, lg, (int)L, 1}, StoreSlots{ah, lg}, (int)(f.I * L), s);
     if (!rc) {
@@ -250,6 +269,19 @@ int pimm_encrypt(const pimm_plan *plan, const pimm_sk *sk, const uint8_t seed[32
         rc = launch_inv(c, LoadSlotsMul{ah, sk->d_s_hat, lg, (int)L}, st, (int)(f.I * L), s);
     }
     return rc;
+}
+
+int pimm_encrypt(const pimm_plan *plan, const pimm_sk *sk, const uint8_t seed[32], uint32_t op_id,
+                 const uint64_t *pt, uint64_t *ct, void *ws, size_t ws_bytes, void *stream)
+{
+    return encrypt_with(plan, sk, seed, seed, op_id, pt, ct, ws, ws_bytes, stream);
+}
+
+int pimm_encrypt_seeded(const pimm_plan *plan, const pimm_sk *sk, const uint8_t seed[32],
+                        const uint8_t a_seed[32], uint32_t op_id, const uint64_t *pt, uint64_t *ct,
+                        void *ws, size_t ws_bytes, void *stream)
+{
+    return encrypt_with(plan, sk, seed, a_seed, op_id, pt, ct, ws, ws_bytes, stream);
 }
 
 // Workspace: c1^ [O][L][N] doubles, then cs [O][L][mb*nb] uint64.

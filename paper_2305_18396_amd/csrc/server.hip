@@ -439,4 +439,23 @@ int pimm_matmul_share(const pimm_plan *plan, const pimm_weights *w, const uint64
     return rc;
 }
 
+int pimm_ct_expand(const pimm_plan *plan, const uint8_t a_seed[32], uint32_t op_id,
+                   const uint64_t *c0, uint64_t *ct, void *stream)
+{
+    if (!plan || !a_seed || !c0 || !ct) return set_error(PIMM_E_ARG, "pimm_ct_expand: NULL argument");
+    const Ctx &c = *plan->ctx;
+    const pimm_plan_info &f = plan->info;
+    const size_t N = c.params.N, L = c.params.L;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = check_hip(hipSetDevice(c.device), "hipSetDevice");
+    if (!rc)
+        rc = check_hip(hipMemcpy2DAsync(ct, 2 * L * N * 8, c0, L * N * 8, L * N * 8, f.I,
+                                        hipMemcpyDeviceToDevice, s),
+                       "pimm_ct_expand: copy c0");
+    if (!rc)
+        rc = launch_sample(c, 0, make_key(a_seed), kTagEncA, op_id, 0, (int)f.I, 0, (int)L, ct + L * N,
+                           2 * L * N, N, s);
+    return rc;
+}
+
 }  // extern "C"

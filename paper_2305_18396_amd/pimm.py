@@ -38,6 +38,8 @@ EXPORTS = [
     "pimm_weights_create", "pimm_weights_destroy", "pimm_matmul", "pimm_mask_share",
     "pimm_matmul_share",
     "pimm_fc_complete",
+    "pimm_encrypt_seeded",
+    "pimm_ct_expand",
     "pimm_batch_create", "pimm_batch_destroy", "pimm_batch_query", "pimm_batch_set_schedule",
     "pimm_batch_get_schedule",
     "pimm_batch_matmul", "pimm_batch_status",
@@ -116,6 +118,8 @@ def lib():
         "pimm_mask_share": [vp, vp, vp, u32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp],
         "pimm_matmul_share": [vp, vp, vp, vp, u32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp],
         "pimm_fc_complete": [vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp],
+        "pimm_encrypt_seeded": [vp, vp, vp, vp, u32, vp, vp, vp, ctypes.c_size_t, vp],
+        "pimm_ct_expand": [vp, vp, u32, vp, vp, vp],
         "pimm_batch_create": [vp, u32, vp],
         "pimm_batch_destroy": [vp],
         "pimm_batch_query": [vp, vp, vp],
@@ -434,6 +438,29 @@ def matmul_share(plan: Plan, w: Weights, pk, seed: bytes, op_id: int, ct: torch.
                                    _ptr(c0s), _ptr(share), _ptr(ws), ws.numel() * 8,
                                    _stream(stream)))
     return c1, c0s, share
+
+
+def encrypt_seeded(plan: Plan, sk: SecretKey, seed: bytes, a_seed: bytes, op_id: int,
+                   pt: torch.Tensor, ct=None, ws=None, stream=None):
+    """pimm_encrypt_seeded: c1 = a from the public a_seed, e from seed.  -> ct [I][2][L][N]
+    (the upload is ct[:, 0] and a_seed)."""
+    f, c = plan.info, plan.ctx
+    if ct is None:
+        ct = torch.empty((f.I, 2, c.L, c.N), dtype=torch.int64, device=c.device)
+    ws = plan.workspace() if ws is None else ws
+    _check(lib().pimm_encrypt_seeded(plan.h, sk.h, _seed(seed), _seed(a_seed), op_id, _ptr(pt),
+                                     _ptr(ct), _ptr(ws), ws.numel() * 8, _stream(stream)))
+    return ct
+
+
+def ct_expand(plan: Plan, a_seed: bytes, op_id: int, c0: torch.Tensor, ct=None, stream=None):
+    """pimm_ct_expand: the server rebuilds [I][2][L][N] from c0 [I][L][N] and a_seed."""
+    f, c = plan.info, plan.ctx
+    assert c0.dtype == torch.int64 and tuple(c0.shape) == (f.I, c.L, c.N) and c0.is_contiguous()
+    if ct is None:
+        ct = torch.empty((f.I, 2, c.L, c.N), dtype=torch.int64, device=c.device)
+    _check(lib().pimm_ct_expand(plan.h, _seed(a_seed), op_id, _ptr(c0), _ptr(ct), _stream(stream)))
+    return ct
 
 
 def fc_complete(plan: Plan, w: Weights, x1: torch.Tensor, bias, share1: torch.Tensor, ws=None,
