@@ -29,7 +29,9 @@ Other workloads (each prints one JSON line of its own): --workload batch (64
 uneven products, one batched pass against one call per product), serve (a
 Poisson stream of requests through a 12-layer stack with continuous batching,
 p50/p99 per arrival rate), stack (the BERT-large-shaped 24-layer stack at
-N = 8192) and peak (the device's streaming and arithmetic ceilings).
+N = 8192), peak (the device's streaming and arithmetic ceilings) and pareto (the
+layer at several block areas: GPU time against wire bytes, the Pareto front and the
+block area that minimises step plus wire time for a few link speeds).
 """
 import argparse
 import collections
@@ -367,6 +369,92 @@ def bench_stack(args):
             "product_slot_mac_per_s": slot / mac_s if mac_s else None}
 
 
+def bench_pareto(args):
+    """Protocol-level plan selection: the BERT-base layer at each block area D (0 = the
+    fewest-wire plan), the GPU time of a whole step and of the server's part against the bytes
+    on the wire; the points no other point beats on both, and the D that minimises the step
+    time plus the wire time over links of a few speeds."""
+    import torch
+
+    from paper_2305_18396_amd import pimm, workloads
+
+    dev = torch.device("cuda", 0)
+    N, L, ell, f = 4096, 2, 37, 12
+    ctx = pimm.Context(N, L, ell, f, rerandomize=True, device=0)
+    ops = workloads.bert_base_layer(args.seq)
+    cseed, sseed = workloads.seed("client", 1), workloads.seed("server", 1)
+    sk, pk = pimm.keygen(ctx, cseed)
+    points = []
+    for D in args.pareto_d:
+        state, wire = [], 0
+        for i, wl in enumerate(ops):
+            n, r, m = wl.shape
+            plan = pimm.Plan(ctx, n, r, m, d_fix=D)
+            w = pimm.Weights(plan, pimm.to_device_u64(wl.W))
+            fi = plan.info
+            X = pimm.to_device_u64(wl.X)
+            ct = pimm.encrypt(plan, sk, cseed, i, pimm.encode_input(plan, X))
+            acc = torch.empty((fi.O, 2, L, N), dtype=torch.int64, device=dev)
+            plan.autotune(w, ct, acc, reps=2)
+            del acc
+            state.append(dict(plan=plan, w=w, X=X, ct=ct, op=i, ws=plan.workspace(),
+                              pt=torch.empty((fi.I, N), dtype=torch.int64, device=dev),
+                              c1=torch.empty((fi.O, L, N), dtype=torch.int64, device=dev),
+                              c0s=torch.empty((fi.O, L, fi.mb * fi.nb), dtype=torch.int64,
+                                              device=dev),
+                              y0=torch.empty((n, m), dtype=torch.int64, device=dev),
+                              y1=torch.empty((n, m), dtype=torch.int64, device=dev)))
+            wire += fi.ct_bytes + fi.c1_bytes + fi.c0s_bytes
+
+        def step(k, server_only=False):
+            for st in state:
+                p, op = st["plan"], k * 8 + st["op"]
+                if not server_only:
+                    pimm.encode_input(p, st["X"], st["pt"])
+                    pimm.encrypt(p, sk, cseed, op, st["pt"], st["ct"], st["ws"])
+                pimm.matmul_share(p, st["w"], pk, sseed, op, st["ct"], st["c1"], st["c0s"],
+                                  st["y1"], st["ws"])
+                if not server_only:
+                    pimm.decrypt(p, sk, st["c1"], st["c0s"], st["y0"], st["ws"])
+
+        times = {}
+        for mode in (False, True):
+            for k in range(args.warmup):
+                step(k, mode)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(args.steps):
+                step(args.warmup + k, mode)
+            torch.cuda.synchronize()
+            times[mode] = (time.perf_counter() - t0) / args.steps
+        pt = {"d": D or "fewest-wire", "plans": [[s["plan"].mb, s["plan"].rb, s["plan"].nb] for s in state],
+              "step_ms": times[False] * 1e3, "server_ms": times[True] * 1e3, "wire_bytes": wire,
+              "weight_cache_bytes": sum(s["plan"].info.weights_bytes for s in state)}
+        log(f"D={pt['d']}: step {pt['step_ms']:.2f} ms, server {pt['server_ms']:.2f} ms, "
+            f"wire {wire / 1e6:.0f} MB")
+        points.append(pt)
+        del state
+        torch.cuda.empty_cache()
+    for a in points:
+        a["pareto"] = not any(b is not a and b["server_ms"] <= a["server_ms"] and
+                              b["wire_bytes"] <= a["wire_bytes"] and
+                              (b["server_ms"] < a["server_ms"] or b["wire_bytes"] < a["wire_bytes"])
+                              for b in points)
+    # Link speed above which each point of the front beats the next one with fewer bytes.
+    front = sorted((q for q in points if q["pareto"]), key=lambda q: q["wire_bytes"])
+    for lo, hi in zip(front, front[1:]):
+        dt = lo["step_ms"] - hi["step_ms"]
+        hi["beats_previous_above_Gbit_per_s"] = (
+            (hi["wire_bytes"] - lo["wire_bytes"]) * 8 / (dt * 1e-3) / 1e9 if dt > 0 else None)
+    choice = {}
+    for gbps in (1, 10, 100, 400, 1600):
+        best = min(points, key=lambda q: q["step_ms"] + q["wire_bytes"] * 8 / (gbps * 1e9) * 1e3)
+        choice[f"{gbps}_Gbit_per_s"] = {"d": best["d"], "total_ms": best["step_ms"] +
+                                        best["wire_bytes"] * 8 / (gbps * 1e9) * 1e3}
+    return {"workload": f"BERT-base-shaped layer, seq {args.seq}, N=4096, 2 primes; block area "
+                        "swept", "points": points, "choice_by_link": choice}
+
+
 def bench_peak(args):
     """Sustained device rates next to the published peaks: the HBM read and copy
     bandwidth of plain streaming kernels (and of torch's own sum and copy), the FP64
@@ -415,11 +503,14 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the timed steps, copy a buffer of this many MiB device to device "
                          "(a known-size reference for hardware byte counters)")
-    ap.add_argument("--workload", choices=["layer", "batch", "serve", "peak", "stack"],
+    ap.add_argument("--workload", choices=["layer", "batch", "serve", "peak", "stack", "pareto"],
                     default="layer")
     ap.add_argument("--stack-layers", type=int, default=24)
     ap.add_argument("--serve-tile", type=lambda v: tuple(int(x) for x in v.split(",")),
                     default=(8, 4), help="serve: product tile 'rows,cols' of the batched launch")
+    ap.add_argument("--pareto-d", type=lambda v: [int(x) for x in v.split(",")],
+                    default=[0, 64, 128, 256, 1024],
+                    help="block areas of the pareto workload (0: the fewest-wire plan)")
     ap.add_argument("--layer-d", type=int, default=0,
                     help="layer workload: fixed block area m_b*r_b (0: the fewest-wire plan)")
     ap.add_argument("--schedules", default="",
@@ -457,6 +548,9 @@ def main():
         return
     if args.workload == "serve":
         print(json.dumps({"metric": METRIC, "serve": bench_serve(args)}), flush=True)
+        return
+    if args.workload == "pareto":
+        print(json.dumps({"metric": METRIC, "pareto": bench_pareto(args)}), flush=True)
         return
 
     dev = torch.device("cuda", 0)
