@@ -31,7 +31,8 @@ Poisson stream of requests through a 12-layer stack with continuous batching,
 p50/p99 per arrival rate), stack (the BERT-large-shaped 24-layer stack at
 N = 8192), peak (the device's streaming and arithmetic ceilings) and pareto (the
 layer at several block areas: GPU time against wire bytes, the Pareto front and the
-block area that minimises step plus wire time for a few link speeds).
+block area that minimises step plus wire time for a few link speeds) and attention
+(the cross terms of a BERT-base layer's attention, Pi_MatMul on uniform shares at N = 8192).
 """
 import argparse
 import collections
@@ -455,6 +456,81 @@ def bench_pareto(args):
                         "swept", "points": points, "choice_by_link": choice}
 
 
+def bench_attention(args):
+    """Attention cross terms of one BERT-base layer at seq `--seq` (Eq. 2): per head (12, head
+    dimension 64) the score terms Q0 K1^T and K0 Q1^T (seq x 64 x seq) and the value terms A0 V1
+    (seq x seq x 64) and V0^T A1^T (64 x seq x seq), each a Pi_MatMul whose plaintext operand is
+    the server's uniform share, at N = 8192 with three primes and t = 2^41.  A step runs all 48
+    products: the client's encode and encrypt, the server's re-encoding of its share into the
+    weight cache (no allocation, no synchronisation), the fused server step, the decryption."""
+    import numpy as np
+    import torch
+
+    from paper_2305_18396_amd import pimm, workloads
+
+    dev = torch.device("cuda", 0)
+    N, L, ell, f, heads, d = 8192, 3, 41, 14, 12, 64
+    n = args.seq
+    ctx = pimm.Context(N, L, ell, f, rerandomize=True, device=0)
+    cseed, sseed = workloads.seed("client", 5), workloads.seed("server", 5)
+    sk, pk = pimm.keygen(ctx, cseed)
+    rng = np.random.default_rng(20230529)
+    half = 1 << (ell - 1)
+    shapes = [(n, d, n), (n, d, n), (n, n, d), (d, n, n)]
+    state, useful, wire = [], 0, 0
+    for h in range(heads):
+        for t, (a, r, m) in enumerate(shapes):
+            plan = pimm.Plan(ctx, a, r, m)
+            fi = plan.info
+            X = pimm.to_device_u64(rng.integers(0, 1 << ell, (a, r), dtype=np.uint64))
+            W = torch.from_numpy(rng.integers(-half, half, (r, m), dtype=np.int64)).to(dev)
+            w = pimm.Weights(plan, W)
+            state.append(dict(plan=plan, w=w, X=X, W=W, op=h * 4 + t, ws=plan.workspace(),
+                              pt=torch.empty((fi.I, N), dtype=torch.int64, device=dev),
+                              ct=torch.empty((fi.I, 2, L, N), dtype=torch.int64, device=dev),
+                              c1=torch.empty((fi.O, L, N), dtype=torch.int64, device=dev),
+                              c0s=torch.empty((fi.O, L, fi.mb * fi.nb), dtype=torch.int64,
+                                              device=dev),
+                              y0=torch.empty((a, m), dtype=torch.int64, device=dev),
+                              y1=torch.empty((a, m), dtype=torch.int64, device=dev)))
+            useful += a * r * m
+            wire += fi.ct_bytes + fi.c1_bytes + fi.c0s_bytes
+    for st in state[:4]:
+        ct0 = pimm.encrypt(st["plan"], sk, cseed, 999, pimm.encode_input(st["plan"], st["X"]))
+        acc0 = torch.empty((st["plan"].info.O, 2, L, N), dtype=torch.int64, device=dev)
+        st["plan"].autotune(st["w"], ct0, acc0, reps=2)
+        del ct0, acc0
+    for st in state[4:]:
+        st["plan"].set_tuning(*state[st["op"] % 4]["plan"].tuning())
+
+    def step(k):
+        for st in state:
+            p, op = st["plan"], k * 64 + st["op"]
+            pimm.encode_input(p, st["X"], st["pt"])
+            pimm.encrypt(p, sk, cseed, op, st["pt"], st["ct"], st["ws"])
+            st["w"].update(st["W"], half)
+            pimm.matmul_share(p, st["w"], pk, sseed, op, st["ct"], st["c1"], st["c0s"], st["y1"],
+                              st["ws"])
+            pimm.decrypt(p, sk, st["c1"], st["c0s"], st["y0"], st["ws"])
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(args.warmup + k)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    log(f"attention cross terms: {sec * 1e3:.2f} ms per layer, {useful / sec / 1e9:.1f}e9 int-MAC/s")
+    return {"workload": f"BERT-base attention cross terms, seq {n}: 12 heads x (2 x {n}x64x{n} "
+                        f"+ {n}x{n}x64 + 64x{n}x{n}), plaintext operand a uniform share; "
+                        "RNS-BFV N=8192, 3x50-bit primes, t=2^41",
+            "plans": [[s["plan"].mb, s["plan"].rb, s["plan"].nb] for s in state[:4]],
+            "product_schedules": [list(s["plan"].tuning()) for s in state[:4]],
+            "ms_per_layer": sec * 1e3, "useful_macs_per_layer": useful,
+            "int_mac_per_s": useful / sec, "wire_bytes_per_layer": wire}
+
+
 def bench_peak(args):
     """Sustained device rates next to the published peaks: the HBM read and copy
     bandwidth of plain streaming kernels (and of torch's own sum and copy), the FP64
@@ -503,7 +579,8 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the timed steps, copy a buffer of this many MiB device to device "
                          "(a known-size reference for hardware byte counters)")
-    ap.add_argument("--workload", choices=["layer", "batch", "serve", "peak", "stack", "pareto"],
+    ap.add_argument("--workload", choices=["layer", "batch", "serve", "peak", "stack", "pareto",
+                                           "attention"],
                     default="layer")
     ap.add_argument("--stack-layers", type=int, default=24)
     ap.add_argument("--serve-tile", type=lambda v: tuple(int(x) for x in v.split(",")),
@@ -548,6 +625,9 @@ def main():
         return
     if args.workload == "serve":
         print(json.dumps({"metric": METRIC, "serve": bench_serve(args)}), flush=True)
+        return
+    if args.workload == "attention":
+        print(json.dumps({"metric": METRIC, "attention": bench_attention(args)}), flush=True)
         return
     if args.workload == "pareto":
         print(json.dumps({"metric": METRIC, "pareto": bench_pareto(args)}), flush=True)

@@ -210,10 +210,20 @@ int pimm_decrypt(const pimm_plan *plan, const pimm_sk *sk, const uint64_t *c1, c
  * pi_A per block, a[ib*R + jb][i*rb + rb-1-j] = W[jb*rb + j][ib*mb + i], lifted
  * centred (w < 0 -> q_l - |w|), kept on the device in NTT form.
  * W: [r][m] signed fixed-point integers (device).  Fails with PIMM_E_NOISE when
- * the worst-case noise bound of the reply breaks decryption.  Synchronises
- * `stream` (it reads max |W| back). */
+ * the worst-case noise bound of the reply breaks decryption, PIMM_E_ARG when
+ * max |W| > 2^48.  Synchronises `stream` (it reads max |W| back). */
 int pimm_weights_create(const pimm_plan *plan, const int64_t *W, pimm_weights **out, void *stream);
 int pimm_weights_destroy(pimm_weights *w);
+
+/* Re-encode new weights of the same shape into an existing weight cache, for a
+ * plaintext operand that changes from call to call (the attention cross terms of
+ * Eq. 2 multiply by the server's share).  The caller states a bound: every
+ * |W[k][j]| <= wmax (2^(l-1) for a centred share of Z_{2^l}); entries beyond it
+ * void the noise guarantee.  Fails with PIMM_E_NOISE when the bound breaks
+ * decryption, PIMM_E_ARG when wmax > 2^48.  Neither synchronises nor allocates;
+ * a product already queued on `stream` sees the old or the new weights in stream
+ * order. */
+int pimm_weights_update(pimm_weights *w, const int64_t *W, uint64_t wmax, void *stream);
 
 /* Algorithm 1 step 3, [[c]] = a [[b]], accumulated over the inner blocks:
  * acc[y = ib*K + kb][comp][l] = sum_jb a[ib*R + jb] * ct[jb*K + kb][comp][l]

@@ -22,6 +22,10 @@ namespace pimm {
 
 // Coefficient j of block w = ib*R + jb of pi_A(W^T), read straight from W [r][m]:
 // j = i*rb + rb - 1 - jj holds W[jb*rb + jj][ib*mb + i]; j >= mb*rb is zero.
+// Largest weight magnitude the transform takes: the weights enter the NTT as
+// balanced doubles, which must stay exact and below a few primes.
+constexpr unsigned long long kMaxWeight = 1ull << 48;
+
 struct LoadWeights {
     const int64_t *W;
     uint32_t r, m, mb, rb, R;
@@ -302,6 +306,8 @@ int pimm_weights_create(const pimm_plan *plan, const int64_t *W, pimm_weights **
     if (!rc) rc = check_hip(hipStreamSynchronize(s), "absmax synchronize");
     (void)hipFree(d_max);
     if (rc) return rc;
+    if (h_max > kMaxWeight)
+        return set_error(PIMM_E_ARG, "max |W| = %llu exceeds 2^48", h_max);
     if (!noise_ok(c, f, h_max))
         return set_error(PIMM_E_NOISE,
                          "max |W| = %llu: worst-case noise of the reply breaks decryption for "
@@ -327,6 +333,28 @@ int pimm_weights_create(const pimm_plan *plan, const int64_t *W, pimm_weights **
     }
     *out = w;
     return PIMM_OK;
+}
+
+int pimm_weights_update(pimm_weights *w, const int64_t *W, uint64_t wmax, void *stream)
+{
+    if (!w || !W) return set_error(PIMM_E_ARG, "pimm_weights_update: NULL argument");
+    const Ctx &c = *w->ctx;
+    const pimm_plan_info &f = w->info;
+    if (wmax > kMaxWeight) return set_error(PIMM_E_ARG, "pimm_weights_update: wmax exceeds 2^48");
+    if (!noise_ok(c, f, wmax))
+        return set_error(PIMM_E_NOISE,
+                         "pimm_weights_update: |W| <= %llu breaks decryption for these parameters "
+                         "and this plan",
+                         (unsigned long long)wmax);
+    hipStream_t s = (hipStream_t)stream;
+    int rc = check_hip(hipSetDevice(c.device), "hipSetDevice");
+    if (!rc) rc = weights_plain(W, w->d_w_plain, (size_t)f.r * f.m, s);
+    if (!rc)
+        rc = launch_fwd(c, LoadWeights{W, f.r, f.m, f.mb, f.rb, f.R, (int)c.params.L},
+                        StoreWeightTiled{w->d_w_hat, c.dp.logN, (int)c.params.L, f.M, f.R},
+                        (int)(f.Wb * c.params.L), s);
+    if (!rc) w->wmax = (int64_t)wmax;
+    return rc;
 }
 
 int pimm_weights_destroy(pimm_weights *w)

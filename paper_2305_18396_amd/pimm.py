@@ -38,6 +38,7 @@ EXPORTS = [
     "pimm_weights_create", "pimm_weights_destroy", "pimm_matmul", "pimm_mask_share",
     "pimm_matmul_share",
     "pimm_fc_complete",
+    "pimm_weights_update",
     "pimm_encrypt_seeded",
     "pimm_ct_expand",
     "pimm_batch_create", "pimm_batch_destroy", "pimm_batch_query", "pimm_batch_set_schedule",
@@ -118,6 +119,7 @@ def lib():
         "pimm_mask_share": [vp, vp, vp, u32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp],
         "pimm_matmul_share": [vp, vp, vp, vp, u32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp],
         "pimm_fc_complete": [vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp],
+        "pimm_weights_update": [vp, vp, u64, vp],
         "pimm_encrypt_seeded": [vp, vp, vp, vp, u32, vp, vp, vp, ctypes.c_size_t, vp],
         "pimm_ct_expand": [vp, vp, u32, vp, vp, vp],
         "pimm_batch_create": [vp, u32, vp],
@@ -347,6 +349,11 @@ class Weights:
         self.plan = plan
         self.h = ctypes.c_void_p()
         _check(lib().pimm_weights_create(plan.h, _ptr(W), ctypes.byref(self.h), _stream(stream)))
+
+    def update(self, W: torch.Tensor, wmax: int, stream=None):
+        """pimm_weights_update: new weights of the same shape, |W| <= wmax, no sync."""
+        assert W.dtype == torch.int64 and W.shape == (self.plan.info.r, self.plan.info.m)
+        _check(lib().pimm_weights_update(self.h, _ptr(W), int(wmax), _stream(stream)))
 
     def close(self):
         if self.h:
