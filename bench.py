@@ -522,13 +522,43 @@ def bench_attention(args):
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / args.steps
     log(f"attention cross terms: {sec * 1e3:.2f} ms per layer, {useful / sec / 1e9:.1f}e9 int-MAC/s")
+
+    # The same step captured once into a HIP graph (the calls allocate nothing and record no
+    # memset) and replayed; every replay is checked against the eager step with the same ids.
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cs):
+        step(900)
+    torch.cuda.synchronize()
+    ref = [(st["y0"].clone(), st["y1"].clone()) for st in state]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=cs):
+        step(900)
+    same = True
+    for _ in range(3):
+        for st in state:
+            st["y0"].zero_()
+            st["y1"].zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        same = same and all(torch.equal(st["y0"], a) and torch.equal(st["y1"], b)
+                            for st, (a, b) in zip(state, ref))
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    gsec = (time.perf_counter() - t0) / args.steps
+    log(f"  as a HIP graph: {gsec * 1e3:.2f} ms per layer (replays bit-exact: {same})")
     return {"workload": f"BERT-base attention cross terms, seq {n}: 12 heads x (2 x {n}x64x{n} "
                         f"+ {n}x{n}x64 + 64x{n}x{n}), plaintext operand a uniform share; "
                         "RNS-BFV N=8192, 3x50-bit primes, t=2^41",
             "plans": [[s["plan"].mb, s["plan"].rb, s["plan"].nb] for s in state[:4]],
             "product_schedules": [list(s["plan"].tuning()) for s in state[:4]],
             "ms_per_layer": sec * 1e3, "useful_macs_per_layer": useful,
-            "int_mac_per_s": useful / sec, "wire_bytes_per_layer": wire}
+            "int_mac_per_s": useful / sec, "wire_bytes_per_layer": wire,
+            "graph_ms_per_layer": gsec * 1e3, "graph_int_mac_per_s": useful / gsec,
+            "graph_replays_bitexact": bool(same)}
 
 
 def bench_peak(args):
