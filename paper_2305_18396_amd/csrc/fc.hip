@@ -157,6 +157,9 @@ int pimm_fc_complete(const pimm_plan *plan, const pimm_weights *w, const uint64_
                          "pimm_fc_complete: r * max|W| * 2^%d reaches 2^53 (max|W| = %lld): the "
                          "limb sums would not be exact",
                          fc_split(ell), (long long)w->wmax);
+    if ((f.n + kFcT - 1) / kFcT > 65535 || (f.r + kFcKC - 1) / kFcKC > 65535)
+        return set_error(PIMM_E_SHAPE, "pimm_fc_complete: n = %u or r = %u too large for one launch",
+                         f.n, f.r);
     const size_t need = (size_t)f.n * f.m * 2 * 8;
     if (!ws || ws_bytes < need) return set_error(PIMM_E_WORKSPACE, "pimm_fc_complete: workspace too small");
     hipStream_t s = (hipStream_t)stream;
