@@ -18,7 +18,7 @@ namespace {
 
 constexpr int kFcT = 64;   // output tile: 64 rows of X1 by 64 columns of W
 constexpr int kFcK = 16;   // inner step held in LDS
-constexpr int kFcKC = 64;  // inner extent of one workgroup (the inner dimension is split)
+constexpr int kFcKC = 64;  // granule of the inner extent of one workgroup
 
 __global__ void k_fc_zero(double *p, size_t n)
 {
@@ -33,13 +33,13 @@ __global__ void k_fc_zero(double *p, size_t n)
 __global__ __launch_bounds__(256) void k_fc_gemm(const uint64_t *__restrict__ X1,
                                                  const double *__restrict__ Wd,
                                                  double *__restrict__ acc, int n, int r, int m,
-                                                 int S, uint64_t xmask)
+                                                 int kc, int S, uint64_t xmask)
 {
     __shared__ double xl[kFcK][kFcT + 1], xh[kFcK][kFcT + 1], wt[kFcK][kFcT];
     const int tx = (int)threadIdx.x % 16, ty = (int)threadIdx.x / 16;
     const int j0 = (int)blockIdx.x * kFcT, i0 = (int)blockIdx.y * kFcT;
-    const int k0 = (int)blockIdx.z * kFcKC;
-    const int k1 = k0 + kFcKC < r ? k0 + kFcKC : r;
+    const int k0 = (int)blockIdx.z * kc;
+    const int k1 = k0 + kc < r ? k0 + kc : r;
     const uint64_t lmask = ((uint64_t)1 << S) - 1;
     double al[4][4], ah[4][4];
 #pragma unroll
@@ -157,7 +157,15 @@ int pimm_fc_complete(const pimm_plan *plan, const pimm_weights *w, const uint64_
                          "pimm_fc_complete: r * max|W| * 2^%d reaches 2^53 (max|W| = %lld): the "
                          "limb sums would not be exact",
                          fc_split(ell), (long long)w->wmax);
-    if ((f.n + kFcT - 1) / kFcT > 65535 || (f.r + kFcKC - 1) / kFcKC > 65535)
+    // Inner extent per workgroup: whole granules, as long as the grid keeps about two
+    // workgroups per compute unit (fewer pieces mean fewer atomic additions).
+    const uint64_t tiles = (uint64_t)((f.m + kFcT - 1) / kFcT) * ((f.n + kFcT - 1) / kFcT);
+    const uint64_t granules = (f.r + kFcKC - 1) / kFcKC;
+    uint64_t per = tiles * granules / 512;
+    if (per < 1) per = 1;
+    if (per > granules) per = granules;
+    const int kc = (int)(per * kFcKC);
+    if ((f.n + kFcT - 1) / kFcT > 65535 || (f.r + kc - 1) / kc > 65535)
         return set_error(PIMM_E_SHAPE, "pimm_fc_complete: n = %u or r = %u too large for one launch",
                          f.n, f.r);
     const size_t need = (size_t)f.n * f.m * 2 * 8;
@@ -170,9 +178,9 @@ int pimm_fc_complete(const pimm_plan *plan, const pimm_weights *w, const uint64_
     const uint64_t tmask = ell >= 64 ? ~0ull : (((uint64_t)1 << ell) - 1);
     ProfScope prof("fc", s);
     hipLaunchKernelGGL(k_fc_zero, dim3(1024), dim3(256), 0, s, acc, (size_t)f.n * f.m * 2);
-    const dim3 grid((f.m + kFcT - 1) / kFcT, (f.n + kFcT - 1) / kFcT, (f.r + kFcKC - 1) / kFcKC);
+    const dim3 grid((f.m + kFcT - 1) / kFcT, (f.n + kFcT - 1) / kFcT, (f.r + kc - 1) / kc);
     hipLaunchKernelGGL(k_fc_gemm, grid, dim3(256), 0, s, x1, (const double *)w->d_w_plain, acc,
-                       (int)f.n, (int)f.r, (int)f.m, S, tmask);
+                       (int)f.n, (int)f.r, (int)f.m, kc, S, tmask);
     hipLaunchKernelGGL(k_fc_finish, dim3(1024), dim3(256), 0, s, (const double *)acc, bias, share1,
                        (int)f.n, (int)f.m, S, tmask);
     return check_hip(hipGetLastError(), "fc launch");

@@ -67,9 +67,11 @@ def test_fc_complete_n8192_l41(orc):
     assert np.array_equal(got, want)
 
 
-def test_fc_complete_full_size_bert_base_qkv(orc):
-    """The QKV product of the BERT-base layer at seq 128 (128 x 768 x 2304), every entry."""
-    got, want = run_fc(orc, 4096, 2, 37, 12, (128, 768, 2304), seed=128, wrange=600)
+@pytest.mark.parametrize("shape", [(128, 768, 2304), (128, 3072, 768)])
+def test_fc_complete_full_size_bert_base(orc, shape):
+    """The QKV and FFN2 products of the BERT-base layer at seq 128, every entry (FFN2's inner
+    dimension is split into pieces of two granules per workgroup)."""
+    got, want = run_fc(orc, 4096, 2, 37, 12, shape, seed=shape[1], wrange=600)
     assert np.array_equal(got, want)
 
 
