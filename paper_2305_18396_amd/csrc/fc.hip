@@ -3,7 +3,7 @@
 // server holds Y1 with Y0 + Y1 = X0 W mod 2^l; it adds its own share's product
 // and the bias, Y1 <- Y1 + X1 W + b (mod 2^l), so that Y0 + Y1 = X W + b.
 //
-// X1 W is an integer product mod 2^l.  It runs on the FP64 unit, exactly: each
+// X1 W is an integer product mod 2^l.  It runs on the FP64 matrix cores, exactly: each
 // entry of X1 (read mod 2^l) is split as xh 2^S + xl with S = ceil(l / 2), the
 // weights are small signed integers, and both limb products are summed in
 // doubles.  Every partial sum is an integer of magnitude at most
@@ -28,24 +28,32 @@ __global__ void k_fc_zero(double *p, size_t n)
 }
 
 // acc[0][i][j] += sum_k xl[i][k] W[k][j], acc[1][i][j] += sum_k xh[i][k] W[k][j] over the
-// workgroup's inner range.  Thread (tx, ty) of 16 x 16 owns rows ty + 16 a and columns
-// tx + 16 b (a, b < 4) of the tile.
+// workgroup's inner range, on the FP64 matrix cores.  v_mfma_f64_16x16x4f64 takes, from lane
+// l of a wave, A[l % 16][l / 16] and B[l / 16][l % 16] of a 16x4 by 4x16 product and keeps
+// D[l / 16 + 4 t][l % 16] in value t of the lane's four accumulators.  Wave w of the
+// workgroup owns the 32 x 32 quarter (w / 2, w % 2) of the 64 x 64 tile: two row blocks by
+// two column blocks of 16, for both limbs.  The products of integers and their sums stay
+// exact (all below 2^53), so the matrix cores' rounding never acts.
+typedef double fc_v4d __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(256) void k_fc_gemm(const uint64_t *__restrict__ X1,
                                                  const double *__restrict__ Wd,
                                                  double *__restrict__ acc, int n, int r, int m,
                                                  int kc, int S, uint64_t xmask)
 {
-    __shared__ double xl[kFcK][kFcT + 1], xh[kFcK][kFcT + 1], wt[kFcK][kFcT];
-    const int tx = (int)threadIdx.x % 16, ty = (int)threadIdx.x / 16;
+    __shared__ double xl[kFcK][kFcT], xh[kFcK][kFcT], wt[kFcK][kFcT];
+    const int lane = (int)threadIdx.x % 64, wave = (int)threadIdx.x / 64;
     const int j0 = (int)blockIdx.x * kFcT, i0 = (int)blockIdx.y * kFcT;
     const int k0 = (int)blockIdx.z * kc;
     const int k1 = k0 + kc < r ? k0 + kc : r;
+    const int rbase = (wave / 2) * 32, cbase = (wave % 2) * 32;
+    const int li = lane % 16, lk = lane / 16;
     const uint64_t lmask = ((uint64_t)1 << S) - 1;
-    double al[4][4], ah[4][4];
+    fc_v4d dl[2][2], dh[2][2];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) al[a][b] = ah[a][b] = 0.0;
+        for (int b = 0; b < 2; ++b) dl[a][b] = dh[a][b] = fc_v4d{0.0, 0.0, 0.0, 0.0};
 
     for (int kk = k0; kk < k1; kk += kFcK) {
         for (int e = (int)threadIdx.x; e < kFcT * kFcK; e += 256) {
@@ -62,36 +70,39 @@ __global__ __launch_bounds__(256) void k_fc_gemm(const uint64_t *__restrict__ X1
         }
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < kFcK; ++k) {
-            double vl[4], vh[4], w[4];
+        for (int s4 = 0; s4 < kFcK; s4 += 4) {
+            const int k = s4 + lk;
+            double al[2], ah[2], bw[2];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                vl[a] = xl[k][ty + 16 * a];
-                vh[a] = xh[k][ty + 16 * a];
+            for (int a = 0; a < 2; ++a) {
+                al[a] = xl[k][rbase + 16 * a + li];
+                ah[a] = xh[k][rbase + 16 * a + li];
             }
 #pragma unroll
-            for (int b = 0; b < 4; ++b) w[b] = wt[k][tx + 16 * b];
+            for (int b = 0; b < 2; ++b) bw[b] = wt[k][cbase + 16 * b + li];
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    al[a][b] = __builtin_fma(vl[a], w[b], al[a][b]);
-                    ah[a][b] = __builtin_fma(vh[a], w[b], ah[a][b]);
+                for (int b = 0; b < 2; ++b) {
+                    dl[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(al[a], bw[b], dl[a][b], 0, 0, 0);
+                    dh[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ah[a], bw[b], dh[a][b], 0, 0, 0);
                 }
         }
         __syncthreads();
     }
     const size_t plane = (size_t)n * m;
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int i = i0 + ty + 16 * a, j = j0 + tx + 16 * b;
-            if (i < n && j < m) {
-                atomicAdd(acc + (size_t)i * m + j, al[a][b]);
-                atomicAdd(acc + plane + (size_t)i * m + j, ah[a][b]);
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int i = i0 + rbase + 16 * a + lk + 4 * t, j = j0 + cbase + 16 * b + li;
+                if (i < n && j < m) {
+                    atomicAdd(acc + (size_t)i * m + j, dl[a][b][t]);
+                    atomicAdd(acc + plane + (size_t)i * m + j, dh[a][b][t]);
+                }
             }
-        }
 }
 
 // share[i][j] <- (share[i][j] + lo + hi 2^S + b[j]) mod 2^l, in uint64 wrap-around
