@@ -635,8 +635,8 @@ def main():
                     help="serve: run only these arrival rates (comma-separated)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "sharding of Pi_MatMul is a design note, not part of this build.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); sharding Pi_MatMul "
+              "over several GPUs is described, not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -56,7 +56,7 @@ extern "C" {
 #define PIMM_E_NOISE (-4)       /* weights whose worst-case noise breaks decryption */
 #define PIMM_E_OOM (-5)         /* device allocation failed */
 #define PIMM_E_DEVICE (-6)      /* HIP runtime error */
-#define PIMM_E_UNSUPPORTED (-7) /* valid request this build does not implement */
+#define PIMM_E_UNSUPPORTED (-7) /* valid request the library does not implement */
 #define PIMM_E_WORKSPACE (-8)   /* workspace missing or smaller than required */
 
 typedef struct pimm_ctx pimm_ctx;
