@@ -262,6 +262,21 @@ bool weights_fit(const Weights *w, const Plan *plan);
 // X1 W stay exact for this shape, share width and weight bound.
 int weights_plain(const int64_t *W, double *Wd, size_t n, hipStream_t s);
 bool fc_exact(const pimm_plan_info &f, int ell, uint64_t wmax);
+
+// The FC completion's cut of the inner dimension: whole granules of 64 inner rows
+// per workgroup, as many pieces as keep about two workgroups per compute unit
+// over the 64 x 64 output tiles.  Each piece writes its own partial sums (two
+// limbs), so the workspace holds pieces * n * m * 2 doubles.
+inline void fc_cut(uint32_t n, uint32_t r, uint32_t m, uint32_t *kc, uint32_t *pieces)
+{
+    const uint64_t tiles = (uint64_t)((m + 63) / 64) * ((n + 63) / 64);
+    const uint64_t granules = (r + 63) / 64;
+    uint64_t per = tiles * granules / 512;
+    if (per < 1) per = 1;
+    if (per > granules) per = granules;
+    *kc = (uint32_t)(per * 64);
+    *pieces = (uint32_t)((r + *kc - 1) / *kc);
+}
 uint64_t fused_workspace_bytes(const Ctx &c, const pimm_plan_info &f);
 int plan_rule(const Ctx &c, uint32_t n, uint32_t r, uint32_t m, uint32_t mb, uint32_t rb, uint32_t nb,
               uint32_t d_fix, pimm_plan_info &f);

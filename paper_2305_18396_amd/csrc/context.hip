@@ -277,7 +277,9 @@ static void fill_info(const Ctx &c, pimm_plan_info &f)
     if (mm > ws) ws = mm;
     if (msk > ws) ws = msk;
     if (dec > ws) ws = dec;
-    const uint64_t fc = (uint64_t)f.n * f.m * 2 * 8;  // the FC completion's two limb sums
+    uint32_t fc_kc = 0, fc_pieces = 0;
+    fc_cut(f.n, f.r, f.m, &fc_kc, &fc_pieces);
+    const uint64_t fc = (uint64_t)fc_pieces * f.n * f.m * 2 * 8;  // the FC completion's partial sums
     if (fc > ws) ws = fc;
     f.workspace_bytes = ws;
 }

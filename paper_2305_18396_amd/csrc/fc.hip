@@ -8,7 +8,8 @@
 // weights are small signed integers, and both limb products are summed in
 // doubles.  Every partial sum is an integer of magnitude at most
 // r (2^S - 1) max|W|, which the call checks to be below 2^53, so the sums are
-// exact in any order (the split inner dimension is added with FP64 atomics).
+// exact in any order (each piece of the inner dimension writes its own partial
+// sums, which the epilogue adds).
 // The epilogue turns the two sums into integers and finishes mod 2^l.
 #include "common.h"
 
@@ -18,17 +19,9 @@ namespace {
 
 constexpr int kFcT = 64;   // output tile: 64 rows of X1 by 64 columns of W
 constexpr int kFcK = 16;   // inner step held in LDS
-constexpr int kFcKC = 64;  // granule of the inner extent of one workgroup
 
-__global__ void k_fc_zero(double *p, size_t n)
-{
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x)
-        p[i] = 0.0;
-}
-
-// acc[0][i][j] += sum_k xl[i][k] W[k][j], acc[1][i][j] += sum_k xh[i][k] W[k][j] over the
-// workgroup's inner range, on the FP64 matrix cores.  v_mfma_f64_16x16x4f64 takes, from lane
+// part[z][0][i][j] = sum_k xl[i][k] W[k][j] and part[z][1][i][j] = sum_k xh[i][k] W[k][j]
+// over piece z of the inner dimension, on the FP64 matrix cores.  v_mfma_f64_16x16x4f64 takes, from lane
 // l of a wave, A[l % 16][l / 16] and B[l / 16][l % 16] of a 16x4 by 4x16 product and keeps
 // D[l / 16 + 4 t][l % 16] in value t of the lane's four accumulators.  Wave w of the
 // workgroup owns the 32 x 32 quarter (w / 2, w % 2) of the 64 x 64 tile: two row blocks by
@@ -91,6 +84,7 @@ __global__ __launch_bounds__(256) void k_fc_gemm(const uint64_t *__restrict__ X1
         __syncthreads();
     }
     const size_t plane = (size_t)n * m;
+    double *part = acc + (size_t)blockIdx.z * 2 * plane;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -99,22 +93,28 @@ __global__ __launch_bounds__(256) void k_fc_gemm(const uint64_t *__restrict__ X1
             for (int t = 0; t < 4; ++t) {
                 const int i = i0 + rbase + 16 * a + lk + 4 * t, j = j0 + cbase + 16 * b + li;
                 if (i < n && j < m) {
-                    atomicAdd(acc + (size_t)i * m + j, dl[a][b][t]);
-                    atomicAdd(acc + plane + (size_t)i * m + j, dh[a][b][t]);
+                    part[(size_t)i * m + j] = dl[a][b][t];
+                    part[plane + (size_t)i * m + j] = dh[a][b][t];
                 }
             }
 }
 
 // share[i][j] <- (share[i][j] + lo + hi 2^S + b[j]) mod 2^l, in uint64 wrap-around
-// arithmetic (exact mod 2^l); lo and hi are the exact integer sums.
-__global__ void k_fc_finish(const double *__restrict__ acc, const int64_t *__restrict__ bias,
-                            uint64_t *__restrict__ share, int n, int m, int S, uint64_t tmask)
+// arithmetic (exact mod 2^l); lo and hi are the exact integer sums of the pieces.
+__global__ void k_fc_finish(const double *__restrict__ acc, int pieces,
+                            const int64_t *__restrict__ bias, uint64_t *__restrict__ share, int n,
+                            int m, int S, uint64_t tmask)
 {
     const size_t plane = (size_t)n * m;
     for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < plane;
          idx += (size_t)gridDim.x * blockDim.x) {
-        const uint64_t lo = (uint64_t)(int64_t)acc[idx];
-        const uint64_t hi = (uint64_t)(int64_t)acc[plane + idx];
+        double sl = 0.0, sh = 0.0;
+        for (int z = 0; z < pieces; ++z) {
+            sl += acc[(size_t)z * 2 * plane + idx];
+            sh += acc[(size_t)z * 2 * plane + plane + idx];
+        }
+        const uint64_t lo = (uint64_t)(int64_t)sl;
+        const uint64_t hi = (uint64_t)(int64_t)sh;
         uint64_t v = share[idx] + lo + (hi << S);
         if (bias) v += (uint64_t)bias[idx % (size_t)m];
         share[idx] = v & tmask;
@@ -168,18 +168,12 @@ int pimm_fc_complete(const pimm_plan *plan, const pimm_weights *w, const uint64_
                          "pimm_fc_complete: r * max|W| * 2^%d reaches 2^53 (max|W| = %lld): the "
                          "limb sums would not be exact",
                          fc_split(ell), (long long)w->wmax);
-    // Inner extent per workgroup: whole granules, as long as the grid keeps about two
-    // workgroups per compute unit (fewer pieces mean fewer atomic additions).
-    const uint64_t tiles = (uint64_t)((f.m + kFcT - 1) / kFcT) * ((f.n + kFcT - 1) / kFcT);
-    const uint64_t granules = (f.r + kFcKC - 1) / kFcKC;
-    uint64_t per = tiles * granules / 512;
-    if (per < 1) per = 1;
-    if (per > granules) per = granules;
-    const int kc = (int)(per * kFcKC);
-    if ((f.n + kFcT - 1) / kFcT > 65535 || (f.r + kc - 1) / kc > 65535)
+    uint32_t kc = 0, pieces = 0;
+    fc_cut(f.n, f.r, f.m, &kc, &pieces);
+    if ((f.n + kFcT - 1) / kFcT > 65535 || pieces > 65535)
         return set_error(PIMM_E_SHAPE, "pimm_fc_complete: n = %u or r = %u too large for one launch",
                          f.n, f.r);
-    const size_t need = (size_t)f.n * f.m * 2 * 8;
+    const size_t need = (size_t)pieces * f.n * f.m * 2 * 8;
     if (!ws || ws_bytes < need) return set_error(PIMM_E_WORKSPACE, "pimm_fc_complete: workspace too small");
     hipStream_t s = (hipStream_t)stream;
     int rc = check_hip(hipSetDevice(c.device), "hipSetDevice");
@@ -188,12 +182,11 @@ int pimm_fc_complete(const pimm_plan *plan, const pimm_weights *w, const uint64_
     const int S = fc_split(ell);
     const uint64_t tmask = ell >= 64 ? ~0ull : (((uint64_t)1 << ell) - 1);
     ProfScope prof("fc", s);
-    hipLaunchKernelGGL(k_fc_zero, dim3(1024), dim3(256), 0, s, acc, (size_t)f.n * f.m * 2);
-    const dim3 grid((f.m + kFcT - 1) / kFcT, (f.n + kFcT - 1) / kFcT, (f.r + kc - 1) / kc);
+    const dim3 grid((f.m + kFcT - 1) / kFcT, (f.n + kFcT - 1) / kFcT, pieces);
     hipLaunchKernelGGL(k_fc_gemm, grid, dim3(256), 0, s, x1, (const double *)w->d_w_plain, acc,
-                       (int)f.n, (int)f.r, (int)f.m, kc, S, tmask);
-    hipLaunchKernelGGL(k_fc_finish, dim3(1024), dim3(256), 0, s, (const double *)acc, bias, share1,
-                       (int)f.n, (int)f.m, S, tmask);
+                       (int)f.n, (int)f.r, (int)f.m, (int)kc, S, tmask);
+    hipLaunchKernelGGL(k_fc_finish, dim3(1024), dim3(256), 0, s, (const double *)acc, (int)pieces,
+                       bias, share1, (int)f.n, (int)f.m, S, tmask);
     return check_hip(hipGetLastError(), "fc launch");
 }
 
