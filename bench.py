@@ -523,6 +523,43 @@ def bench_attention(args):
     sec = (time.perf_counter() - t0) / args.steps
     log(f"attention cross terms: {sec * 1e3:.2f} ms per layer, {useful / sec / 1e9:.1f}e9 int-MAC/s")
 
+    # The products of each phase are independent (the 24 score terms, then after the softmax
+    # the 24 value terms): run each phase over four streams, joined before the next phase.
+    streams = [torch.cuda.Stream() for _ in range(4)]
+
+    def step_streams(k):
+        main = torch.cuda.current_stream()
+        for phase in (0, 1):
+            for q in streams:
+                q.wait_stream(main)
+            for st in state:
+                if (st["op"] % 4 >= 2) != bool(phase):
+                    continue
+                q = streams[(st["op"] // 4 + st["op"]) % 4]
+                p, op = st["plan"], k * 64 + st["op"]
+                pimm.encode_input(p, st["X"], st["pt"], stream=q)
+                pimm.encrypt(p, sk, cseed, op, st["pt"], st["ct"], st["ws"], stream=q)
+                st["w"].update(st["W"], half, stream=q)
+                pimm.matmul_share(p, st["w"], pk, sseed, op, st["ct"], st["c1"], st["c0s"],
+                                  st["y1"], st["ws"], stream=q)
+                pimm.decrypt(p, sk, st["c1"], st["c0s"], st["y0"], st["ws"], stream=q)
+            for q in streams:
+                main.wait_stream(q)
+
+    step_streams(800)
+    torch.cuda.synchronize()
+    ref_s = [(st["y0"].clone(), st["y1"].clone()) for st in state]
+    step(800)
+    torch.cuda.synchronize()
+    streams_same = all(torch.equal(st["y0"], a) and torch.equal(st["y1"], b)
+                       for st, (a, b) in zip(state, ref_s))
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step_streams(args.warmup + k)
+    torch.cuda.synchronize()
+    ssec = (time.perf_counter() - t0) / args.steps
+    log(f"  over four streams per phase: {ssec * 1e3:.2f} ms per layer (same shares: {streams_same})")
+
     # The same step captured once into a HIP graph (the calls allocate nothing and record no
     # memset) and replayed; every replay is checked against the eager step with the same ids.
     cs = torch.cuda.Stream()
@@ -558,7 +595,9 @@ def bench_attention(args):
             "ms_per_layer": sec * 1e3, "useful_macs_per_layer": useful,
             "int_mac_per_s": useful / sec, "wire_bytes_per_layer": wire,
             "graph_ms_per_layer": gsec * 1e3, "graph_int_mac_per_s": useful / gsec,
-            "graph_replays_bitexact": bool(same)}
+            "graph_replays_bitexact": bool(same),
+            "streams4_ms_per_layer": ssec * 1e3, "streams4_int_mac_per_s": useful / ssec,
+            "streams4_same_shares": bool(streams_same)}
 
 
 def bench_peak(args):
