@@ -524,8 +524,8 @@ def bench_attention(args):
     log(f"attention cross terms: {sec * 1e3:.2f} ms per layer, {useful / sec / 1e9:.1f}e9 int-MAC/s")
 
     # The products of each phase are independent (the 24 score terms, then after the softmax
-    # the 24 value terms): run each phase over four streams, joined before the next phase.
-    streams = [torch.cuda.Stream() for _ in range(4)]
+    # the 24 value terms): run each phase over --att-streams streams, joined before the next phase.
+    streams = [torch.cuda.Stream() for _ in range(args.att_streams)]
 
     def step_streams(k):
         main = torch.cuda.current_stream()
@@ -535,7 +535,7 @@ def bench_attention(args):
             for st in state:
                 if (st["op"] % 4 >= 2) != bool(phase):
                     continue
-                q = streams[(st["op"] // 4 + st["op"]) % 4]
+                q = streams[(st["op"] // 4 + st["op"]) % len(streams)]
                 p, op = st["plan"], k * 64 + st["op"]
                 pimm.encode_input(p, st["X"], st["pt"], stream=q)
                 pimm.encrypt(p, sk, cseed, op, st["pt"], st["ct"], st["ws"], stream=q)
@@ -558,7 +558,8 @@ def bench_attention(args):
         step_streams(args.warmup + k)
     torch.cuda.synchronize()
     ssec = (time.perf_counter() - t0) / args.steps
-    log(f"  over four streams per phase: {ssec * 1e3:.2f} ms per layer (same shares: {streams_same})")
+    log(f"  over {len(streams)} streams per phase: {ssec * 1e3:.2f} ms per layer "
+        f"(same shares: {streams_same})")
 
     # The same step captured once into a HIP graph (the calls allocate nothing and record no
     # memset) and replayed; every replay is checked against the eager step with the same ids.
@@ -596,8 +597,8 @@ def bench_attention(args):
             "int_mac_per_s": useful / sec, "wire_bytes_per_layer": wire,
             "graph_ms_per_layer": gsec * 1e3, "graph_int_mac_per_s": useful / gsec,
             "graph_replays_bitexact": bool(same),
-            "streams4_ms_per_layer": ssec * 1e3, "streams4_int_mac_per_s": useful / ssec,
-            "streams4_same_shares": bool(streams_same)}
+            "streams": len(streams), "streams_ms_per_layer": ssec * 1e3,
+            "streams_int_mac_per_s": useful / ssec, "streams_same_shares": bool(streams_same)}
 
 
 def bench_peak(args):
@@ -657,6 +658,8 @@ def main():
     ap.add_argument("--pareto-d", type=lambda v: [int(x) for x in v.split(",")],
                     default=[0, 64, 128, 256, 1024],
                     help="block areas of the pareto workload (0: the fewest-wire plan)")
+    ap.add_argument("--att-streams", type=int, default=8,
+                    help="streams per phase of the attention workload")
     ap.add_argument("--layer-d", type=int, default=0,
                     help="layer workload: fixed block area m_b*r_b (0: the fewest-wire plan)")
     ap.add_argument("--schedules", default="",
