@@ -855,6 +855,35 @@ def main():
         lat.append((time.perf_counter() - a) * 1e3)
     lat = np.array(lat)
 
+    # The same step captured once into a HIP graph and replayed (the calls allocate nothing
+    # and record no memset).  A replay repeats the captured operation ids, so it is reported
+    # beside the measured step, not as it; every checked replay equals the eager step.
+    gs = torch.cuda.Stream()
+    gs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(gs):
+        step(50_000)
+    torch.cuda.synchronize()
+    gref = [(st["y0"].clone(), st["y1"].clone()) for st in state]
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=gs):
+        step(50_000)
+    graph_same = True
+    for _ in range(3):
+        for st in state:
+            st["y0"].zero_()
+            st["y1"].zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        graph_same = graph_same and all(torch.equal(st["y0"], a) and torch.equal(st["y1"], b)
+                                        for st, (a, b) in zip(state, gref))
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    graph_s = (time.perf_counter() - t0) / args.steps
+    log(f"step as a HIP graph: {graph_s * 1e3:.3f} ms (replays bit-exact: {graph_same})")
+
     mac_avg_s = mac_ms / 1e3 / max(1, mac_cnt)
     bytes_per_launch = mac_bytes / len(state)
     achieved = bytes_per_launch / mac_avg_s / 1e9 if mac_cnt else 0.0
@@ -885,6 +914,8 @@ def main():
         },
         "server_path_ms": server_s * 1e3,
         "server_path_int_mac_per_s": useful / server_s,
+        "graph_replay_ms_per_step": graph_s * 1e3,
+        "graph_replays_bitexact": bool(graph_same),
         "fc_completion_ms": fc_s * 1e3,
         "fc_completion_int_mac_per_s": useful / fc_s,
         "wire_bytes_per_step_seeded_upload": wire_seeded,
