@@ -96,3 +96,40 @@ def test_weights_update_changes_operand(orc):
     with pytest.raises(pimm.PimmError) as e:
         w2.update(torch.zeros((r, m), dtype=torch.int64, device=small.device), 1 << 36)
     assert e.value.code == -4
+
+
+def test_cross_terms_over_streams_match_stream_order():
+    """Independent cross terms issued over several streams give the same shares as in stream
+    order (each product has its own buffers and workspace; the key material is shared)."""
+    ctx = context()
+    rng = np.random.default_rng(95)
+    cseed, sseed = workloads.seed("client", 95), workloads.seed("server", 95)
+    sk, pk = pimm.keygen(ctx, cseed)
+    half = 1 << (ELL - 1)
+    items = []
+    for t, (n, r, m) in enumerate([(128, 64, 128), (128, 64, 128), (128, 128, 64), (64, 128, 128)]):
+        plan = pimm.Plan(ctx, n, r, m)
+        X = pimm.to_device_u64(rng.integers(0, 1 << ELL, (n, r), dtype=np.uint64))
+        W = torch.from_numpy(rng.integers(-half, half, (r, m), dtype=np.int64)).to(ctx.device)
+        items.append(dict(plan=plan, X=X, W=W, w=pimm.Weights(plan, W), ws=plan.workspace(), op=t))
+
+    def run(streams):
+        out = []
+        for it in items:
+            q = streams[it["op"] % len(streams)] if streams else None
+            if q is not None:
+                q.wait_stream(torch.cuda.current_stream())
+            p = it["plan"]
+            with torch.cuda.stream(q) if q is not None else torch.cuda.stream(torch.cuda.current_stream()):
+                ct = pimm.encrypt(p, sk, cseed, it["op"], pimm.encode_input(p, it["X"]), ws=it["ws"])
+                it["w"].update(it["W"], half)
+                c1, c0s, y1 = pimm.matmul_share(p, it["w"], pk, sseed, it["op"], ct, ws=it["ws"])
+                y0 = pimm.decrypt(p, sk, c1, c0s, ws=it["ws"])
+            out.append((y0, y1))
+        torch.cuda.synchronize()
+        return [(pimm.to_host_u64(a), pimm.to_host_u64(b)) for a, b in out]
+
+    serial = run(None)
+    parallel = run([torch.cuda.Stream() for _ in range(3)])
+    for (a0, a1), (b0, b1) in zip(serial, parallel):
+        assert np.array_equal(a0, b0) and np.array_equal(a1, b1)
