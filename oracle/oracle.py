@@ -17,6 +17,11 @@ design notes): primes are the L largest primes below 2^50 congruent to 1 mod
 re-randomised by a public-key encryption of zero when requested; the mask is
 subtracted as Delta * s; the decrypt rounding is round-half-up (ties cannot
 occur since t = 2^l and q is odd).
+
+Parity unpinned: the block-plan rules (plan_comm, plan_fix) and the stream
+layout's choices (tag numbers, which nonce word holds what).  They are spec
+decisions the paper leaves open; only the protocol invariants (the shares add
+up to X W for any plan, the keystream is RFC 8439's) tie them to the paper.
 """
 from __future__ import annotations
 

@@ -92,9 +92,8 @@ def test_samplers_read_the_keystream(orc):
     assert sample(1, 1, 0, 5, 6).tolist() == [v % 3 - 1 for v in d]
 
 
-def test_cdt_table_against_mpmath(orc):
-    """T[k] = floor(2^63 P(|e| <= k)) for the Gaussian of width 3.2 cut at |e| <= 19,
-    recomputed with mpmath at 50 digits (the oracle uses Python's decimal module)."""
+def _cdt_mpmath():
+    """T[k] = floor(2^63 P(|e| <= k)), k = 0..18, for width 3.2 cut at |e| <= 19 (50 digits)."""
     mpmath = pytest.importorskip("mpmath")
     mpmath.mp.dps = 50
     s2 = 2 * mpmath.mpf("3.2") ** 2
@@ -104,6 +103,41 @@ def test_cdt_table_against_mpmath(orc):
     for k in range(19):
         want.append(int(mpmath.floor(acc / total * mpmath.mpf(2) ** 63)))
         acc += 2 * rho[k + 1]
+    return want
+
+
+@needs_openssl
+def test_gaussian_sampler_reads_the_keystream(orc):
+    """The error sampler's exact draw -> value rule, recomputed from the OpenSSL keystream and
+    an mpmath table: with d the 64-bit draw j and u = d mod 2^63 (its low 63 bits),
+    |e_j| = #{k : u >= T[k]} and e_j < 0 exactly when bit 63 of d is set.  A flipped sign, a
+    shifted 63-bit field or a table read off by one entry each change some of the 4096 values.
+    (Whether u = T[k] counts is unobservable on random draws: it has probability 19 / 2^63.)"""
+    key = bytes(range(60, 92))
+    k = np.frombuffer(key, dtype=np.uint8).copy()
+    n = 4096
+    T = _cdt_mpmath()
+    cdt = np.asarray(T, dtype=np.uint64)
+    got = np.zeros(n, dtype=np.int64)
+    orc.lib().orc_sample_poly(2, k.ctypes.data_as(ctypes.c_void_p), 5, 0, 7, 3, n, 0, 0,
+                              cdt.ctypes.data_as(ctypes.c_void_p),
+                              got.ctypes.data_as(ctypes.c_void_p))
+    ks = openssl_keystream(key, 0, nonce_bytes(5, 0, 7, 3), 8 * n)
+    want = []
+    for j in range(n):
+        d = int.from_bytes(ks[8 * j:8 * j + 8], "little")
+        u = d & ((1 << 63) - 1)
+        mag = sum(1 for t in T if u >= t)
+        want.append(-mag if d >> 63 else mag)
+    assert got.tolist() == want
+    # The draws exercise both signs and magnitudes across the table.
+    assert min(want) <= -6 and max(want) >= 6
+
+
+def test_cdt_table_against_mpmath(orc):
+    """T[k] = floor(2^63 P(|e| <= k)) for the Gaussian of width 3.2 cut at |e| <= 19,
+    recomputed with mpmath at 50 digits (the oracle uses Python's decimal module)."""
+    want = _cdt_mpmath()
     assert orc.cdt_table() == want
     assert all(a < b for a, b in zip(want, want[1:]))  # strictly increasing
     assert want[-1] < 2**63

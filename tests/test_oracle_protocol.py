@@ -279,3 +279,69 @@ def test_noise_under_bound(orc):
         assert orc.noise_ok(p, pl, 600)
     # A plaintext lifted uncentred (|w| ~ t) would break the budget: the bound says so.
     assert not orc.noise_ok(p, orc.plan_comm(4096, 128, 3072, 768), p.t // 2)
+
+
+def _negacyclic_np(a, b):
+    """Integer a * b mod (X^N + 1) by full convolution and the wrap X^N = -1 (small entries)."""
+    n = len(a)
+    c = np.convolve(np.asarray(a, np.int64), np.asarray(b, np.int64))
+    out = c[:n].copy()
+    out[:n - 1] -= c[n:]
+    return out
+
+
+def _sample(orc, kind, seed, tag, op, obj, p):
+    import ctypes
+    k = np.frombuffer(seed, np.uint8).copy()
+    out = np.zeros(p.N, np.int64)
+    orc.lib().orc_sample_poly(kind, k.ctypes.data_as(ctypes.c_void_p), tag, 0, op, obj, p.N, 0, 0,
+                              p.cdt_arr.ctypes.data_as(ctypes.c_void_p),
+                              out.ctypes.data_as(ctypes.c_void_p))
+    return out
+
+
+@pytest.mark.parametrize("N", [256, 4096])
+def test_rerandomisation_adds_an_encryption_of_zero_with_its_exact_noise(orc, N):
+    """The re-randomisation adds (u pk0 + e1, u pk1 + e2) with pk = (-a' s + e', a').  Under s
+    this decrypts to u e' + e1 + e2 s exactly (the a' s terms cancel), so the decryption of the
+    re-randomised reply minus that of the plain product must be that integer polynomial,
+    recomputed here by schoolbook from the pinned samplers' u, e', e1, e2 and s.  A flipped
+    sign of either product, a swapped component or a wrong stream changes it."""
+    p = orc.Params(N, 2, 30, 8)
+    rng = np.random.default_rng(29)
+    n, r, m = 4, 8, 4
+    X = rng.integers(0, p.t, (n, r), dtype=np.uint64)
+    W = rng.integers(-100, 100, (r, m))
+    plan = orc.plan_comm(p.N, n, r, m)
+    res = run_protocol(orc, p, plan, X, W, tag=6)
+    cseed, sseed = workloads.seed("client", 6), workloads.seed("server", 6)
+    s = _sample(orc, 1, cseed, orc.TAG_SK, 0, 0, p)
+    assert np.array_equal(s, res["s"])
+    e_pk = _sample(orc, 2, cseed, 3, 0, 0, p)  # pk error e' (tag 3)
+    Q = p.Q
+    coef = [(Q // q) * pow(Q // q, -1, q) for q in p.q]
+
+    def phase(ct):
+        """[c0 + c1 s]_q of every coefficient, centred, as Python integers."""
+        x = np.zeros((1, p.N, p.L), np.uint64)
+        import ctypes
+        orc.lib().orc_decrypt_full_residues(
+            p.N, p.L, p.q_arr.ctypes.data_as(ctypes.c_void_p),
+            p.psi_arr.ctypes.data_as(ctypes.c_void_p), s.ctypes.data_as(ctypes.c_void_p), 1,
+            np.ascontiguousarray(ct).ctypes.data_as(ctypes.c_void_p),
+            x.ctypes.data_as(ctypes.c_void_p))
+        out = []
+        for j in range(p.N):
+            v = sum(int(x[0, j, l]) * coef[l] for l in range(p.L)) % Q
+            out.append(v - Q if v > Q // 2 else v)
+        return out
+
+    for o, y in enumerate(res["outs"][:2]):
+        u = _sample(orc, 1, sseed, 6, 6, int(y), p)
+        e1 = _sample(orc, 2, sseed, 7, 6, int(y), p)
+        e2 = _sample(orc, 2, sseed, 8, 6, int(y), p)
+        want = _negacyclic_np(u, e_pk) + e1 + _negacyclic_np(e2, s)
+        got = [a - b for a, b in zip(phase(res["acc_rr"][o:o + 1]), phase(res["acc"][o:o + 1]))]
+        got = [((g + Q // 2) % Q) - Q // 2 for g in got]
+        assert got == want.tolist()
+        assert np.abs(want).max() > 0
