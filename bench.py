@@ -46,6 +46,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ct-pt MatMul int-MAC/s and layer-stack p50/p99 latency, batched vs plain"
 HBM_PEAK_GBS = 8000.0
+# Operation ids of the autotuners' trial encryptions: far above every step's ids, so that no
+# (seed, op_id) pair is used for two different inputs.
+AUTOTUNE_OP = 1 << 31
 
 
 def log(msg):
@@ -326,8 +329,8 @@ def bench_stack(args):
     # One schedule per product shape, tuned on layer 0's buffers.
     for i, plan in enumerate(plans):
         b = bufs[i]
-        pimm.encrypt(plan, sk, cseed, 90_000 + i, pimm.encode_input(plan, layers[0][i][1], b["pt"]),
-                     b["ct"])
+        pimm.encrypt(plan, sk, cseed, AUTOTUNE_OP + i,
+                     pimm.encode_input(plan, layers[0][i][1], b["pt"]), b["ct"])
         acc = torch.empty((plan.O, 2, L, N), dtype=torch.int64, device=dev)
         best = plan.autotune(layers[0][i][0], b["ct"], acc, reps=1)
         log(f"  {shapes[i][0]}: plan ({plan.mb},{plan.rb},{plan.nb}) K={plan.K} "
@@ -496,7 +499,10 @@ def bench_attention(args):
             useful += a * r * m
             wire += fi.ct_bytes + fi.c1_bytes + fi.c0s_bytes
     for st in state[:4]:
-        ct0 = pimm.encrypt(st["plan"], sk, cseed, 999, pimm.encode_input(st["plan"], st["X"]))
+        # Operation ids from 2^31 up are kept for the autotuner's encryptions, apart from
+        # the steps' ids, so that no (seed, op_id) pair serves two different inputs.
+        ct0 = pimm.encrypt(st["plan"], sk, cseed, AUTOTUNE_OP + st["op"],
+                           pimm.encode_input(st["plan"], st["X"]))
         acc0 = torch.empty((st["plan"].info.O, 2, L, N), dtype=torch.int64, device=dev)
         st["plan"].autotune(st["w"], ct0, acc0, reps=2)
         del ct0, acc0
@@ -733,7 +739,7 @@ def main():
             plan.set_tuning(*(int(v) for v in args.schedules.split(";")[i].split(",")))
         elif not args.no_autotune:
             # The product's schedule is picked by the library's autotuner on these buffers.
-            ct0 = pimm.encrypt(plan, sk, cseed, 10_000 + i, pimm.encode_input(plan, st["X"]))
+            ct0 = pimm.encrypt(plan, sk, cseed, AUTOTUNE_OP + i, pimm.encode_input(plan, st["X"]))
             acc0 = torch.empty((fi.O, 2, L, N), dtype=torch.int64, device=dev)
             best = plan.autotune(w, ct0, acc0, reps=2)
             st["tuning"] = plan.tuning()

@@ -26,9 +26,14 @@
  *     pimm_sync() or at a later call.  Calls that take a workspace use the
  *     caller's buffer `ws` of `ws_bytes` bytes (at least
  *     pimm_plan_info.workspace_bytes) and allocate nothing.
- *   - Contexts, plans, keys and weight caches are immutable after creation,
- *     so calls on different streams may share them; two calls in flight must
- *     not share a workspace or an output buffer.
+ *   - Contexts, plans and keys are immutable after creation, so calls on
+ *     different streams may share them; two calls in flight must not share a
+ *     workspace or an output buffer.  A weight cache is immutable too unless
+ *     pimm_weights_update rewrites it: that call enqueues the rewrite on its
+ *     own stream, so every later call that reads the cache (a product, a
+ *     batch, pimm_fc_complete) must be on the same stream or ordered after it
+ *     by an event, and no call that reads the cache may still be in flight on
+ *     another stream when the update is enqueued.
  *   - Output bytes depend only on (parameters, plan, inputs, seeds, op_id),
  *     never on batching, stream or launch order.
  *   - Residues are canonical integers in [0, q_l), stored as uint64.  Shares
@@ -38,6 +43,11 @@
  * keyed by the caller's 32-byte seed, nonce (tag | prime << 8, op_id,
  * object index), block counter from 0; the 64-bit draw j is keystream bytes
  * [8j, 8j+8) and the 128-bit draw j bytes [16j, 16j+16), little-endian.
+ * op_id is the only per-call nonce: a (seed, op_id) pair must never serve two
+ * different inputs (two encryptions of different plaintexts under one pair
+ * share a and e; two replies under one server pair share the mask).  Repeating
+ * a call on the same inputs with the same pair repeats its bytes, which is
+ * harmless.
  */
 #ifndef PIMM_H
 #define PIMM_H
@@ -220,9 +230,11 @@ int pimm_weights_destroy(pimm_weights *w);
  * Eq. 2 multiply by the server's share).  The caller states a bound: every
  * |W[k][j]| <= wmax (2^(l-1) for a centred share of Z_{2^l}); entries beyond it
  * void the noise guarantee.  Fails with PIMM_E_NOISE when the bound breaks
- * decryption, PIMM_E_ARG when wmax > 2^48.  Neither synchronises nor allocates;
- * a product already queued on `stream` sees the old or the new weights in stream
- * order. */
+ * decryption, PIMM_E_ARG when wmax > 2^48.  Neither synchronises nor allocates.
+ * The device words change in stream order on `stream` (a call queued earlier on
+ * `stream` sees the old weights, a later one the new); the bound wmax takes effect
+ * on the host at once, for the checks of the calls made after this one (the
+ * noise check here, the exactness check of pimm_fc_complete). */
 int pimm_weights_update(pimm_weights *w, const int64_t *W, uint64_t wmax, void *stream);
 
 /* Algorithm 1 step 3, [[c]] = a [[b]], accumulated over the inner blocks:

@@ -4,9 +4,11 @@ All arithmetic is integer, so the bar is bit-exact equality of every buffer that
 crosses the ABI (public key, plaintexts, ciphertexts, accumulators, the sparse
 reply, both shares), plus the user-level contract Y0 + Y1 = X W (mod 2^l)
 against a plain integer matrix product.  Small cases span several blocks with
-ragged edges; the full-size cases run the BERT-shaped layers at their real
-shapes, in the launch configuration the benchmark uses, and compare sampled
-ciphertexts with the oracle.
+ragged edges; the full-size cases run every BERT-shaped product of the
+benchmarks at its real shape and block plan, under the product schedule the
+library's autotuner picks on those buffers (as the benchmarks run them) and
+under fixed tiles, through the two-call and the fused server path, and compare
+sampled ciphertexts and the decrypted shares with the oracle.
 """
 import zlib
 
@@ -226,9 +228,12 @@ def test_error_paths():
                         torch.zeros((plan.O, 2, 2, 4096), dtype=torch.int64, device="cuda"))
 
 
-def check_layer_op(orc, ctx, pyp, wl, plan_kw, tag, nsample_out=2):
+def check_layer_op(orc, ctx, pyp, wl, plan_kw, tag, tunings=(None,), nsample_out=2):
     """One full-size product: the contract on every entry (or a sample) and bit-exact
-    ciphertexts / accumulators / reply for sampled output ciphertexts."""
+    ciphertexts / accumulators / reply for sampled output ciphertexts, under each product
+    schedule in `tunings` ("auto": the library's autotuner on these buffers, as the benchmark
+    runs it; a (rows, cols, waves) tuple; None: the plan's default), through both the two-call
+    server path and the fused call the benchmark times."""
     n, r, m = wl.shape
     plan = pimm.Plan(ctx, n, r, m, **plan_kw)
     oplan = orc.Plan(n, r, m, plan.mb, plan.rb, plan.nb, ctx.N)
@@ -241,56 +246,80 @@ def check_layer_op(orc, ctx, pyp, wl, plan_kw, tag, nsample_out=2):
     pt = pimm.encode_input(plan, Xd)
     ct = pimm.encrypt(plan, sk, cseed, tag, pt)
     w = pimm.Weights(plan, pimm.to_device_u64(wl.W))
-    acc = pimm.matmul(plan, w, ct)
     pimm.sync()
     outs = sorted({0, plan.O // 2, plan.O - 1})[:nsample_out + 1]
-    acc_s = u64(acc[outs])
-    c1, c0s, y1 = pimm.mask_share(plan, pk, sseed, tag, acc)
-    y0 = pimm.decrypt(plan, sk, c1, c0s)
-    pimm.sync()
-    Y0, Y1 = u64(y0), u64(y1)
-    t = np.uint64((1 << wl.ell) - 1)
-    if n * r * m <= 400_000_000:
-        assert np.array_equal((Y0 + Y1) & t, xw_mod(wl.X, wl.W, wl.ell))
-    else:
-        rng = np.random.default_rng(tag)
-        rows = rng.integers(0, n, 4000)
-        cols = rng.integers(0, m, 4000)
-        assert np.array_equal((Y0[rows, cols] + Y1[rows, cols]) & t,
-                              xw_sampled(wl.X, wl.W, wl.ell, rows, cols))
-    # Sampled bit-exactness against the oracle.
+    # The oracle's side, once per product: encoding, encryption, the sampled accumulators,
+    # re-randomisation, reply and decryption.
     pt_ref = orc.encode_input(oplan, wl.X)
     assert np.array_equal(u64(pt), pt_ref)
     ct_ref = orc.encrypt(pyp, s_ref, cseed, tag, pt_ref)
     assert np.array_equal(u64(ct), ct_ref)
     ptA = orc.encode_weights(oplan, wl.W)
     acc_ref = orc.matmul(pyp, oplan, ptA, ct_ref, outs)
-    assert np.array_equal(acc_s, acc_ref)
     acc_rr = orc.rerandomize(pyp, pk_ref, sseed, tag, acc_ref, outs)
     c1_ref, c0s_ref, sm_ref = orc.mask_extract(pyp, oplan, sseed, tag, acc_rr, outs)
-    assert np.array_equal(u64(c1[outs]), c1_ref)
-    assert np.array_equal(u64(c0s[outs]), c0s_ref)
-    assert np.array_equal(Y1, orc.place_shares(oplan, sm_ref, outs, out=Y1.copy()))
     y0_ref = orc.decrypt(pyp, oplan, s_ref, c1_ref, c0s_ref, outs)
-    sel = orc.place_shares(oplan, np.ones((len(outs), plan.mb * plan.nb), np.uint64), outs)
-    assert np.array_equal(Y0[sel == 1], y0_ref[sel == 1])
+    sel = orc.place_shares(oplan, np.ones((len(outs), plan.mb * plan.nb), np.uint64), outs) == 1
+    t = np.uint64((1 << wl.ell) - 1)
+    if n * r * m <= 400_000_000:
+        want_sum, pick = xw_mod(wl.X, wl.W, wl.ell), (slice(None), slice(None))
+    else:
+        rng = np.random.default_rng(tag)
+        rows = rng.integers(0, n, 4000)
+        cols = rng.integers(0, m, 4000)
+        want_sum, pick = xw_sampled(wl.X, wl.W, wl.ell, rows, cols), (rows, cols)
+    for tuning in tunings:
+        if tuning == "auto":
+            scratch = torch.empty((plan.O, 2, ctx.L, ctx.N), dtype=torch.int64, device="cuda")
+            plan.autotune(w, ct, scratch, reps=1)
+            del scratch
+        elif tuning is not None:
+            plan.set_tuning(*tuning)
+        log(f"  schedule {tuning} -> {plan.tuning()}")
+        acc = pimm.matmul(plan, w, ct)
+        pimm.sync()
+        assert np.array_equal(u64(acc[outs]), acc_ref), plan.tuning()
+        c1, c0s, y1 = pimm.mask_share(plan, pk, sseed, tag, acc)
+        del acc
+        y0 = pimm.decrypt(plan, sk, c1, c0s)
+        pimm.sync()
+        Y0, Y1 = u64(y0), u64(y1)
+        assert np.array_equal(((Y0 + Y1) & t)[pick], want_sum)
+        assert np.array_equal(u64(c1[outs]), c1_ref)
+        assert np.array_equal(u64(c0s[outs]), c0s_ref)
+        assert np.array_equal(Y1, orc.place_shares(oplan, sm_ref, outs, out=Y1.copy()))
+        assert np.array_equal(Y0[sel], y0_ref[sel])
+        # The fused server call (what the benchmark times) under the same schedule.
+        d1, d0s, z1 = pimm.matmul_share(plan, w, pk, sseed, tag, ct)
+        pimm.sync()
+        assert np.array_equal(u64(d1[outs]), c1_ref), plan.tuning()
+        assert np.array_equal(u64(d0s[outs]), c0s_ref), plan.tuning()
+        assert torch.equal(d1, c1) and torch.equal(d0s, c0s) and torch.equal(z1, y1)
+        del c1, c0s, y1, d1, d0s, z1
 
 
-def test_full_size_bert_base_layer(orc):
-    """One BERT-base-shaped layer at sequence 128 (the benchmark's workload), fewest-wire plan."""
+@pytest.mark.parametrize("layer_d,tunings", [(0, ("auto", (16, 1, 1), None)), (64, ("auto",)),
+                                             (128, ("auto",))])
+def test_full_size_bert_base_layer(orc, layer_d, tunings):
+    """One BERT-base-shaped layer at sequence 128 (the benchmark's workload): the fewest-wire plan
+    under the autotuned schedule the benchmark runs, 16x1 and the plan default; block areas 64
+    and 128 (the plans of the block-area sweep) under the autotuned schedule."""
     ctx = context(4096, 2, 37, 12, True)
     pyp = orc.Params(4096, 2, 37, 12)
     for i, wl in enumerate(workloads.bert_base_layer(128)):
-        check_layer_op(orc, ctx, pyp, wl, {}, 100 + i)
+        check_layer_op(orc, ctx, pyp, wl, dict(d_fix=layer_d), 100 + i + layer_d, tunings)
 
 
-def test_full_size_bert_large_op(orc):
-    """The largest BERT-large-shaped product (FFN2 4096x1024, seq 512) with N = 8192, three
-    primes, t = 2^41, blocks of area 1024."""
+@pytest.mark.parametrize("op", range(4))
+def test_full_size_bert_large_op(orc, op):
+    """Every BERT-large-shaped product of the stack (QKV 1024x3072, attn-out 1024x1024, FFN
+    1024x4096 and 4096x1024 at seq 512) with N = 8192, three primes, t = 2^41, blocks of area
+    1024: under the autotuned schedule the stack benchmark runs and the column-blocked tiles
+    4x8 and 8x4."""
     ctx = context(8192, 3, 41, 14, True)
     pyp = orc.Params(8192, 3, 41, 14)
-    wl = workloads.bert_large_layer(512)[3]
-    check_layer_op(orc, ctx, pyp, wl, dict(d_fix=1024), 200)
+    wl = workloads.bert_large_layer(512)[op]
+    check_layer_op(orc, ctx, pyp, wl, dict(d_fix=1024), 200 + op, ("auto", (4, 8, 1), (8, 4, 1)))
 
 
 TUNINGS = [(g, kb, wv) for g, kb in [(4, 1), (8, 1), (16, 1), (4, 2), (8, 2), (16, 2), (2, 4),
