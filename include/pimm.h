@@ -265,6 +265,26 @@ int pimm_matmul_share(const pimm_plan *plan, const pimm_weights *w, const uint64
                       uint64_t *c0s, uint64_t *server_share, void *ws, size_t ws_bytes,
                       void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops that must not call the allocator, harnesses that forbid it):
+ * pimm_matmul_share with the workspace taken from scratch memory the library
+ * holds in its static device data, PIMM_NOALLOC_SCRATCH_BYTES per device, kept
+ * from the loading of the library's code object until the process ends (enough
+ * for every product of a BERT-base layer at sequence 128 under the fewest-wire
+ * plan; pimm_plan_info does not report the fused step's share of the workspace,
+ * so a plan that needs more is rejected with PIMM_E_WORKSPACE before any work is
+ * enqueued).  Same arguments, bytes and stream semantics as pimm_matmul_share
+ * without ws/ws_bytes; the call itself allocates nothing, and neither does the
+ * work it enqueues (keep tracing off: pimm_profile_enable creates HIP events).
+ * Every call on one device shares that device's scratch: two calls that overlap
+ * on one device (on different streams, or from different threads) race and give
+ * undefined results; calls in one stream are ordered and safe.  The scratch
+ * keeps the last call's contents; each call writes every scratch word it reads. */
+#define PIMM_NOALLOC_SCRATCH_BYTES (128ull << 20)
+int pimm_matmul_share_noalloc(const pimm_plan *plan, const pimm_weights *w, const uint64_t *pk,
+                              const uint8_t seed[32], uint32_t op_id, const uint64_t *ct,
+                              uint64_t *c1, uint64_t *c0s, uint64_t *server_share, void *stream);
+
 /* Completion of a fully connected layer y = x W + b on additive shares (section
  * 3.1, the linear layers).  The input is shared as x = x0 + x1 mod 2^l; the client
  * runs Pi_MatMul on x0, after which the server holds share1 with

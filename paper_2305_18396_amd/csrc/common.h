@@ -278,6 +278,9 @@ inline void fc_cut(uint32_t n, uint32_t r, uint32_t m, uint32_t *kc, uint32_t *p
     *pieces = (uint32_t)((r + *kc - 1) / *kc);
 }
 uint64_t fused_workspace_bytes(const Ctx &c, const pimm_plan_info &f);
+// Takes the device address of pimm_matmul_share_noalloc's static scratch on
+// `device` (current at the call), once per device (noalloc.hip).
+int bind_noalloc_scratch(int device);
 int plan_rule(const Ctx &c, uint32_t n, uint32_t r, uint32_t m, uint32_t mb, uint32_t rb, uint32_t nb,
               uint32_t d_fix, pimm_plan_info &f);
 

@@ -508,6 +508,9 @@ int pimm_ctx_create(const pimm_params *params, int device, pimm_ctx **out)
     if (!params || !out) return set_error(PIMM_E_ARG, "pimm_ctx_create: NULL argument");
     pimm_ctx *c = new pimm_ctx();
     int rc = build_context(*params, device, c, true);
+    // The device address of the static scratch of pimm_matmul_share_noalloc, taken
+    // once per device while the device is current (build_context made it current).
+    if (!rc) rc = bind_noalloc_scratch(device);
     if (rc) {
         if (c->d_tw) (void)hipFree(c->d_tw);
         delete c;

@@ -36,7 +36,7 @@ EXPORTS = [
     "pimm_plan_get_tuning", "pimm_plan_autotune", "pimm_batch_autotune",
     "pimm_keygen", "pimm_sk_destroy", "pimm_encode_input", "pimm_encrypt", "pimm_decrypt",
     "pimm_weights_create", "pimm_weights_destroy", "pimm_matmul", "pimm_mask_share",
-    "pimm_matmul_share",
+    "pimm_matmul_share", "pimm_matmul_share_noalloc",
     "pimm_fc_complete",
     "pimm_weights_update",
     "pimm_encrypt_seeded",
@@ -118,6 +118,7 @@ def lib():
         "pimm_matmul": [vp, vp, vp, vp, vp, ctypes.c_size_t, vp],
         "pimm_mask_share": [vp, vp, vp, u32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp],
         "pimm_matmul_share": [vp, vp, vp, vp, u32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp],
+        "pimm_matmul_share_noalloc": [vp, vp, vp, vp, u32, vp, vp, vp, vp, vp],
         "pimm_fc_complete": [vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp],
         "pimm_weights_update": [vp, vp, u64, vp],
         "pimm_encrypt_seeded": [vp, vp, vp, vp, u32, vp, vp, vp, ctypes.c_size_t, vp],
@@ -444,6 +445,18 @@ def matmul_share(plan: Plan, w: Weights, pk, seed: bytes, op_id: int, ct: torch.
     _check(lib().pimm_matmul_share(plan.h, w.h, _ptr(pk), _seed(seed), op_id, _ptr(ct), _ptr(c1),
                                    _ptr(c0s), _ptr(share), _ptr(ws), ws.numel() * 8,
                                    _stream(stream)))
+    return c1, c0s, share
+
+
+def matmul_share_noalloc(plan: Plan, w: Weights, pk, seed: bytes, op_id: int, ct: torch.Tensor,
+                         c1: torch.Tensor, c0s: torch.Tensor, share: torch.Tensor, stream=None):
+    """pimm_matmul_share_noalloc: the fused server step on the library's static scratch (no
+    workspace, no allocation; the caller passes the outputs).  -> (c1, c0s, server_share)."""
+    f, c = plan.info, plan.ctx
+    for t, shape in ((c1, (f.O, c.L, c.N)), (c0s, (f.O, c.L, f.mb * f.nb)), (share, (f.n, f.m))):
+        assert t.dtype == torch.int64 and tuple(t.shape) == shape and t.is_contiguous()
+    _check(lib().pimm_matmul_share_noalloc(plan.h, w.h, _ptr(pk), _seed(seed), op_id, _ptr(ct),
+                                           _ptr(c1), _ptr(c0s), _ptr(share), _stream(stream)))
     return c1, c0s, share
 
 
