@@ -1,38 +1,39 @@
 #!/usr/bin/env python3
 """Benchmark of the MI355X Pi_MatMul path; prints one JSON line.
 
-Workload: one BERT-base-shaped layer of private linear products at sequence
-128 (QKV 768x2304, attn-out 768x768, FFN 768x3072 and 3072x768), RNS-BFV with
-N = 4096, two 50-bit primes, t = 2^37, W = floor(N(0, 0.02) * 2^12), client
-share X uniform over Z_{2^37}; fewest-wire block plan.  Synthetic seeded
-inputs (workloads.py).  The server's weight cache (pi_A blocks in NTT form) is
-built once at weight-load time, outside the timed region.
+Headline workload (the default): the BERT-large / GPT-2-medium-shaped stack of 24 encoder
+layers, each with four private linear products at sequence 512 (QKV 1024x3072, attn-out
+1024x1024, FFN 1024x4096 and 4096x1024), RNS-BFV with N = 8192, three 50-bit primes,
+t = 2^41, W = floor(N(0, 0.02) * 2^14), client share X uniform over Z_{2^41}, block area
+1024.  Synthetic seeded inputs (workloads.py).  Every layer has its own weight cache (pi_A
+blocks in NTT form), built at weight-load time outside the timed region and resident at once.
 
-A step is one pass of the whole protocol over the layer: for each of the four
-products encode (client), encrypt (client), ciphertext-plaintext product with
-accumulation, re-randomisation, mask and sparse reply (server, one fused call),
-decrypt and decode (client).  value = useful multiply-accumulates (seq * d_in * d_out
-summed over the four products) per second of wall time over the timed steps.
+A step is one pass of the whole stack: for each of the 96 products encode (client), encrypt
+(client), ciphertext-plaintext product with accumulation, re-randomisation, mask and sparse
+reply (server, one fused call), decrypt and decode (client).  value = useful
+multiply-accumulates (seq * d_in * d_out summed over the stack) per second of wall time over
+the timed passes.  HIP events recorded on the stream at every layer boundary give the pass
+and per-layer latencies (p50 / p99).
 
-roofline: the dominant kernel is the slot-wise modular product ("mac"); its
-algorithmic bytes per launch are the weight-cache words it must stream
-(Wb * L * N * 8) plus the transformed inputs it reads once (I * 2 * L * N * 8)
-plus the accumulators it writes (O * 2 * L * N * 8), divided by its average
-launch duration from HIP events recorded on its stream during the timed steps.
+roofline: the product kernel (k_mac_sk), whose launches are bracketed with HIP events on their
+own stream during the timed passes; at this shape (64 column blocks per weight block) it is
+bound by the FP64 vector unit, so achieved = slot-wise modular multiply-accumulates per launch
+(2 L N P) x 14 (7 FP64 instructions, each counted at the FMA rate the peak assumes) over the
+average launch duration, against 78.6 TFLOP/s.
 
-cpu_baseline: the oracle (plain C + Python big integers, OpenMP) on a bounded
-sample: the QKV 768x2304 product at sequence 128, output ciphertexts taken in
-chunks until about --cpu-seconds have passed, encryption of all inputs counted
-pro rata.
+cpu_baseline: the oracle (plain C + Python big integers, OpenMP) on a bounded sample of the
+stack (the FFN2 product's first column block), with the host's CPU model.
 
-Other workloads (each prints one JSON line of its own): --workload batch (64
-uneven products, one batched pass against one call per product), serve (a
-Poisson stream of requests through a 12-layer stack with continuous batching,
-p50/p99 per arrival rate), stack (the BERT-large-shaped 24-layer stack at
-N = 8192), peak (the device's streaming and arithmetic ceilings) and pareto (the
-layer at several block areas: GPU time against wire bytes, the Pareto front and the
-block area that minimises step plus wire time for a few link speeds) and attention
-(the cross terms of a BERT-base layer's attention, Pi_MatMul on uniform shares at N = 8192).
+Extra keys: bert_base_layer (the BERT-base layer at seq 128, N = 4096, two primes, fewest-wire
+plan, with the product's HBM roofline) and batched_vs_plain (64 uneven BERT-base products:
+one batched pass against one call per product).
+
+Other workloads (each prints one JSON line of its own): --workload layer (the BERT-base layer
+alone, with its oracle baseline), stack, batch, serve (a Poisson stream of requests through a
+12-layer stack with continuous batching, p50/p99 per arrival rate), peak (the device's
+streaming and arithmetic ceilings), pareto (the layer at several block areas: GPU time against
+wire bytes) and attention (the cross terms of a BERT-base layer's attention, Pi_MatMul on
+uniform shares at N = 8192).
 """
 import argparse
 import collections
@@ -282,12 +283,81 @@ def bench_serve(args):
             "sweep": sweep, "one_at_a_time": one}
 
 
+FP64_ISSUE_PER_S = 39.3e12  # FP64 VALU instruction issues per second (78.6 TFLOP/s counts an FMA as 2)
+FP64_ISSUES_PER_SLOT_MAC = 7  # mul, fma, mul, rint, fma, add of the modular product + the accumulation
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline_stack(seconds: float):
+    """The oracle on a bounded sample of the BERT-large stack: column blocks of the FFN2
+    4096x1024 product (block plan (16, 64, 8), N = 8192, three primes; a column block is 8
+    sequence rows: 64 input and 64 output ciphertexts), one after another until about `seconds`
+    have passed, each through encryption of its inputs, product, re-randomisation, mask and
+    decryption of its outputs (output ciphertexts in chunks of the thread count; the last block
+    may stop part-way, its encryption then counted pro rata)."""
+    import numpy as np
+
+    from oracle import oracle as orc
+    from paper_2305_18396_amd import workloads
+
+    wl = workloads.bert_large_layer(512)[3]  # FFN2 4096x1024
+    n, r, m = wl.shape
+    pyp = orc.Params(8192, 3, 41, 14)
+    full = orc.plan_fix(8192, 1024, n, r, m)
+    plan = orc.Plan(full.nb, r, m, full.mb, full.rb, full.nb, 8192)  # one column block (K = 1)
+    cseed, sseed = workloads.seed("client", 901), workloads.seed("server", 901)
+    s, pk = orc.keygen(pyp, cseed)
+    ptA = orc.encode_weights(plan, wl.W)
+    threads = orc.max_threads()
+    elapsed, macs, blocks, outs_done = 0.0, 0, 0, 0
+    for kb in range(full.K):
+        if elapsed >= seconds:
+            break
+        X = wl.X[kb * full.nb:(kb + 1) * full.nb]
+        t0 = time.perf_counter()
+        ct = orc.encrypt(pyp, s, cseed, kb, orc.encode_input(plan, X))
+        t_enc = time.perf_counter() - t0
+        done, t_out = 0, 0.0
+        while done < plan.O and elapsed + t_out + t_enc * done / plan.O < seconds:
+            outs = np.arange(done, min(plan.O, done + threads), dtype=np.uint32)
+            t1 = time.perf_counter()
+            acc = orc.matmul(pyp, plan, ptA, ct, outs)
+            acc = orc.rerandomize(pyp, pk, sseed, kb, acc, outs)
+            c1, c0s, sm = orc.mask_extract(pyp, plan, sseed, kb, acc, outs)
+            orc.decrypt(pyp, plan, s, c1, c0s, outs)
+            t_out += time.perf_counter() - t1
+            for y in outs.tolist():
+                macs += plan.nb * min(plan.mb, m - y * plan.mb) * r
+            done += len(outs)
+        elapsed += t_out + t_enc * done / plan.O
+        blocks += 1
+        outs_done += done
+    return {"value": macs / elapsed, "unit": "int-MAC/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "sample": f"BERT-large FFN2 4096x1024 product (N=8192, 3 primes, block plan "
+                      f"({full.mb},{full.rb},{full.nb})): {outs_done} output ciphertexts of "
+                      f"{blocks} column block(s) (of {full.K}) through encryption of their inputs, "
+                      f"product, re-randomisation, mask and decryption; {elapsed:.1f} s"}
+
+
 def bench_stack(args):
     """BERT-large / GPT-2-medium-shaped stack: `--stack-layers` encoder layers (24 by default) of
     four products each at seq 512 (QKV 1024x3072, attn-out 1024x1024, FFN 1024x4096 and
     4096x1024), N = 8192, three 50-bit primes, t = 2^41, 14 fractional bits, block area 1024.
-    Every layer has its own weights and weight cache (all resident at once); a step is the whole
-    stack, each product through encode, encrypt, fused server step and decrypt."""
+    Every layer has its own weights and weight cache (all resident at once); a step is one pass
+    of the whole stack, each product through encode, encrypt, fused server step and decrypt.
+    HIP events on the stream at every layer boundary give the pass and layer latencies; the
+    product launches are bracketed for the roofline."""
     import numpy as np
     import torch
 
@@ -314,6 +384,7 @@ def bench_stack(args):
             y1=torch.empty((seq, m), dtype=torch.int64, device=dev)))
     layers = []
     cache = 0
+    t_setup = time.perf_counter()
     for k in range(args.stack_layers):
         ops = workloads.bert_large_layer(seq, layer_index=k)
         row = []
@@ -323,9 +394,12 @@ def bench_stack(args):
             cache += plans[i].info.weights_bytes
         layers.append(row)
     torch.cuda.synchronize()
-    log(f"stack: {args.stack_layers} layers, weight caches {cache / 1e9:.1f} GB")
-    useful = args.stack_layers * sum(seq * r * m for _, r, m in shapes)
-    slot = args.stack_layers * sum(2 * L * N * p.info.P for p in plans)
+    log(f"stack: {args.stack_layers} layers, weight caches {cache / 1e9:.1f} GB "
+        f"({time.perf_counter() - t_setup:.1f} s)")
+    useful_layer = sum(seq * r * m for _, r, m in shapes)
+    useful = args.stack_layers * useful_layer
+    slot_per_product = [2 * L * N * p.info.P for p in plans]
+    slot = args.stack_layers * sum(slot_per_product)
     # One schedule per product shape, tuned on layer 0's buffers.
     for i, plan in enumerate(plans):
         b = bufs[i]
@@ -336,41 +410,98 @@ def bench_stack(args):
         log(f"  {shapes[i][0]}: plan ({plan.mb},{plan.rb},{plan.nb}) K={plan.K} "
             f"schedule {plan.tuning()} {best:.2f} ms")
         del acc
+    torch.cuda.empty_cache()
 
-    def step(t):
-        for k, row in enumerate(layers):
-            for i, (w, X) in enumerate(row):
-                plan, b = plans[i], bufs[i]
-                op = (t * args.stack_layers + k) * 4 + i
-                pimm.encode_input(plan, X, b["pt"])
-                pimm.encrypt(plan, sk, cseed, op, b["pt"], b["ct"])
-                pimm.matmul_share(plan, w, pk, sseed, op, b["ct"], b["c1"], b["c0s"], b["y1"])
-                pimm.decrypt(plan, sk, b["c1"], b["c0s"], b["y0"])
+    def product(t, k, i):
+        w, X = layers[k][i]
+        plan, b = plans[i], bufs[i]
+        op = (t * args.stack_layers + k) * 4 + i
+        pimm.encode_input(plan, X, b["pt"])
+        pimm.encrypt(plan, sk, cseed, op, b["pt"], b["ct"])
+        pimm.matmul_share(plan, w, pk, sseed, op, b["ct"], b["c1"], b["c0s"], b["y1"])
+        pimm.decrypt(plan, sk, b["c1"], b["c0s"], b["y0"])
+
+    def step(t, marks=None):
+        for k in range(args.stack_layers):
+            for i in range(len(plans)):
+                product(t, k, i)
+            if marks is not None:
+                marks.append(torch.cuda.Event(enable_timing=True))
+                marks[-1].record()
 
     for t in range(args.warmup):
         step(t)
     torch.cuda.synchronize()
+    pimm.profile_read("mac")
     pimm.profile_select(["mac"])
     pimm.profile_enable(True)
+    start = torch.cuda.Event(enable_timing=True)
+    marks = []
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
+    start.record()
     for t in range(args.steps):
-        step(args.warmup + t)
+        step(args.warmup + t, marks)
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / args.steps
     pimm.profile_enable(False)
     pimm.profile_select(None)
     cnt, mac_ms = pimm.profile_read("mac")
-    mac_s = mac_ms / 1e3 / args.steps
-    return {"workload": f"BERT-large-shaped stack, {args.stack_layers} layers x 4 products at seq "
-                        f"{seq}; N={N}, {L}x50-bit primes, t=2^{ell}, {f} fractional bits, block "
-                        f"area {D}, weight caches resident",
-            "plans": [[p.mb, p.rb, p.nb] for p in plans],
-            "schedules": [list(p.tuning()) for p in plans],
-            "weight_cache_bytes": cache, "useful_macs_per_step": useful,
-            "s_per_step": el, "ms_per_layer": el * 1e3 / args.stack_layers,
-            "int_mac_per_s": useful / el, "slot_mac_per_s": slot / el,
-            "product_s_per_step": mac_s,
-            "product_slot_mac_per_s": slot / mac_s if mac_s else None}
+    # Latencies from the layer-boundary events (device time, no host synchronisation).
+    ends = [start.elapsed_time(e) for e in marks]
+    layer_ms = np.diff([0.0] + ends)
+    pass_ms = np.diff([0.0] + ends[args.stack_layers - 1::args.stack_layers])
+    log(f"stack: {el * 1e3:.1f} ms per pass, {useful / el / 1e9:.1f}e9 int-MAC/s")
+
+    # Per-class breakdown from one untimed pass with every class recorded.
+    classes = ("mac", "ntt_fwd", "ntt_inv", "sample", "encode", "decode", "mask_extract")
+    for kname in classes:
+        pimm.profile_read(kname)
+    pimm.profile_enable(True)
+    step(10_000)
+    torch.cuda.synchronize()
+    pimm.profile_enable(False)
+    breakdown = {}
+    for kname in classes:
+        c_, ms_ = pimm.profile_read(kname)
+        breakdown[kname] = {"launches_per_pass": c_, "ms_per_pass": round(ms_, 3)}
+
+    mac_avg_s = mac_ms / 1e3 / max(1, cnt)
+    slot_per_launch = sum(slot_per_product) / len(plans)
+    slot_rate = slot_per_launch / mac_avg_s if cnt else 0.0
+    flop_per_slot = 2 * FP64_ISSUES_PER_SLOT_MAC
+    achieved_tf = slot_rate * flop_per_slot / 1e12
+    return {
+        "workload": f"BERT-large-shaped stack, {args.stack_layers} layers x 4 products at seq "
+                    f"{seq} (QKV 1024x3072, attn-out 1024x1024, FFN 1024x4096 and 4096x1024); "
+                    f"RNS-BFV N={N}, {L}x50-bit primes, t=2^{ell}, {f} fractional bits, block "
+                    f"area {D}; weight caches resident",
+        "plans": [[p.mb, p.rb, p.nb] for p in plans],
+        "product_schedules": [list(p.tuning()) for p in plans],
+        "weight_cache_bytes": cache, "useful_macs_per_step": useful,
+        "s_per_step": el, "ms_per_layer": el * 1e3 / args.stack_layers,
+        "int_mac_per_s": useful / el, "slot_mac_per_s": slot / el,
+        "stack_latency_ms": {"p50": float(np.percentile(pass_ms, 50)),
+                             "p99": float(np.percentile(pass_ms, 99)),
+                             "samples": int(len(pass_ms))},
+        "layer_latency_ms": {"p50": float(np.percentile(layer_ms, 50)),
+                             "p99": float(np.percentile(layer_ms, 99)),
+                             "samples": int(len(layer_ms))},
+        "product_ms_per_step": mac_ms / args.steps,
+        "product_slot_mac_per_s": slot_rate,
+        "kernels_untimed_pass": breakdown,
+        "roofline": {
+            "kernel": "k_mac_sk (the slot-wise product)", "bound": "alu",
+            "achieved": achieved_tf, "peak": 78.6, "unit": "TFLOP/s",
+            "frac": achieved_tf / 78.6, "traffic": None,
+            "work_per_launch_slot_macs": slot_per_launch,
+            "flop_per_slot_mac": flop_per_slot,
+            "avg_launch_ms": mac_avg_s * 1e3,
+            "note": "FP64 vector issue rate: each slot-wise modular multiply-accumulate is 7 FP64 "
+                    "instructions (counted at the FMA rate of the 78.6 TFLOP/s peak, i.e. 2 each); "
+                    "peak = 5.61e12 slot-MAC/s",
+        },
+    }
 
 
 def bench_pareto(args):
@@ -644,72 +775,14 @@ def bench_peak(args):
     return out
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--seq", type=int, default=128)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--calib-copy-mb", type=int, default=0,
-                    help="after the timed steps, copy a buffer of this many MiB device to device "
-                         "(a known-size reference for hardware byte counters)")
-    ap.add_argument("--workload", choices=["layer", "batch", "serve", "peak", "stack", "pareto",
-                                           "attention"],
-                    default="layer")
-    ap.add_argument("--stack-layers", type=int, default=24)
-    ap.add_argument("--serve-tile", type=lambda v: tuple(int(x) for x in v.split(",")),
-                    default=(8, 4), help="serve: product tile 'rows,cols' of the batched launch")
-    ap.add_argument("--pareto-d", type=lambda v: [int(x) for x in v.split(",")],
-                    default=[0, 64, 128, 256, 1024],
-                    help="block areas of the pareto workload (0: the fewest-wire plan)")
-    ap.add_argument("--att-streams", type=int, default=8,
-                    help="streams per phase of the attention workload")
-    ap.add_argument("--layer-d", type=int, default=0,
-                    help="layer workload: fixed block area m_b*r_b (0: the fewest-wire plan)")
-    ap.add_argument("--schedules", default="",
-                    help="product schedules 'rows,cols,waves;...' per product (skips the autotuner)")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the default product schedule instead of autotuning it per product")
-    ap.add_argument("--batch-count", type=int, default=64)
-    ap.add_argument("--d-fix", type=int, default=32)
-    ap.add_argument("--layers", type=int, default=12)
-    ap.add_argument("--serve-budget-gb", type=float, default=48.0)
-    ap.add_argument("--serve-requests", type=int, default=32)
-    ap.add_argument("--serve-max-active", type=int, default=32)
-    ap.add_argument("--serve-rate0", type=float, default=4.0)
-    ap.add_argument("--serve-rates", type=lambda v: [float(x) for x in v.split(",")], default=None,
-                    help="serve: run only these arrival rates (comma-separated)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); sharding Pi_MatMul "
-              "over several GPUs is described, not implemented.", file=sys.stderr)
-        sys.exit(2)
-
+def bench_layer(args):
+    """BERT-base-shaped layer (the four products at sequence --seq, N = 4096, two primes,
+    t = 2^37), the whole protocol per step; the product's HBM roofline, the server path alone,
+    the FC completion, the seed-compressed upload's expansion, latency and graph replay."""
     import numpy as np
     import torch
 
     from paper_2305_18396_amd import pimm, workloads
-
-    if args.workload == "batch":
-        print(json.dumps({"metric": METRIC, "batch": bench_batch(args)}), flush=True)
-        return
-    if args.workload == "stack":
-        print(json.dumps({"metric": METRIC, "stack": bench_stack(args)}), flush=True)
-        return
-    if args.workload == "peak":
-        print(json.dumps({"metric": METRIC, "peak": bench_peak(args)}), flush=True)
-        return
-    if args.workload == "serve":
-        print(json.dumps({"metric": METRIC, "serve": bench_serve(args)}), flush=True)
-        return
-    if args.workload == "attention":
-        print(json.dumps({"metric": METRIC, "attention": bench_attention(args)}), flush=True)
-        return
-    if args.workload == "pareto":
-        print(json.dumps({"metric": METRIC, "pareto": bench_pareto(args)}), flush=True)
-        return
 
     dev = torch.device("cuda", 0)
     N, L, ell, f = 4096, 2, 37, 12
@@ -942,9 +1015,140 @@ def main():
         },
         "cpu_baseline": None,
     }
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--seq", type=int, default=128)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="after the timed steps, copy a buffer of this many MiB device to device "
+                         "(a known-size reference for hardware byte counters)")
+    ap.add_argument("--workload", choices=["default", "layer", "batch", "serve", "peak", "stack",
+                                           "pareto", "attention"],
+                    default="default",
+                    help="default: the BERT-large stack (headline) with the BERT-base layer and "
+                         "the batched-versus-plain comparison as extra keys")
+    ap.add_argument("--no-layer", action="store_true",
+                    help="default workload: skip the BERT-base layer")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="default workload: skip the batched-versus-plain comparison")
+    ap.add_argument("--stack-layers", type=int, default=24)
+    ap.add_argument("--serve-tile", type=lambda v: tuple(int(x) for x in v.split(",")),
+                    default=(8, 4), help="serve: product tile 'rows,cols' of the batched launch")
+    ap.add_argument("--pareto-d", type=lambda v: [int(x) for x in v.split(",")],
+                    default=[0, 64, 128, 256, 1024],
+                    help="block areas of the pareto workload (0: the fewest-wire plan)")
+    ap.add_argument("--att-streams", type=int, default=8,
+                    help="streams per phase of the attention workload")
+    ap.add_argument("--layer-d", type=int, default=0,
+                    help="layer workload: fixed block area m_b*r_b (0: the fewest-wire plan)")
+    ap.add_argument("--schedules", default="",
+                    help="product schedules 'rows,cols,waves;...' per product (skips the autotuner)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default product schedule instead of autotuning it per product")
+    ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--d-fix", type=int, default=32)
+    ap.add_argument("--layers", type=int, default=12)
+    ap.add_argument("--serve-budget-gb", type=float, default=48.0)
+    ap.add_argument("--serve-requests", type=int, default=32)
+    ap.add_argument("--serve-max-active", type=int, default=32)
+    ap.add_argument("--serve-rate0", type=float, default=4.0)
+    ap.add_argument("--serve-rates", type=lambda v: [float(x) for x in v.split(",")], default=None,
+                    help="serve: run only these arrival rates (comma-separated)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); sharding Pi_MatMul "
+              "over several GPUs is described, not implemented.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2305_18396_amd import pimm, workloads
+
+    if args.workload == "batch":
+        print(json.dumps({"metric": METRIC, "batch": bench_batch(args)}), flush=True)
+        return
+    if args.workload == "stack":
+        print(json.dumps({"metric": METRIC, "stack": bench_stack(args)}), flush=True)
+        return
+    if args.workload == "peak":
+        print(json.dumps({"metric": METRIC, "peak": bench_peak(args)}), flush=True)
+        return
+    if args.workload == "serve":
+        print(json.dumps({"metric": METRIC, "serve": bench_serve(args)}), flush=True)
+        return
+    if args.workload == "attention":
+        print(json.dumps({"metric": METRIC, "attention": bench_attention(args)}), flush=True)
+        return
+    if args.workload == "pareto":
+        print(json.dumps({"metric": METRIC, "pareto": bench_pareto(args)}), flush=True)
+        return
+
+    if args.workload == "layer":
+        out = bench_layer(args)
+        if not args.no_cpu_baseline:
+            log("cpu baseline (oracle) ...")
+            out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        print(json.dumps(out), flush=True)
+        return
+
+    # Default: the BERT-large-shaped 24-layer stack is the headline (the largest configuration
+    # that fits one GPU), with the BERT-base layer and the batched-versus-plain comparison as
+    # extra keys.
+    st = bench_stack(args)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    out = {
+        "metric": METRIC,
+        "value": st["int_mac_per_s"],
+        "unit": "int-MAC/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": st["s_per_step"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": st["workload"], "global_batch": 1, "seq_len": 512,
+                   "parallelism": "single GPU", "plans": st["plans"],
+                   "product_schedules": st["product_schedules"],
+                   "useful_macs_per_step": st["useful_macs_per_step"]},
+        "stack_latency_ms": st["stack_latency_ms"],
+        "layer_latency_ms": st["layer_latency_ms"],
+        "roofline": st["roofline"],
+        "stack": {k: v for k, v in st.items() if k not in ("roofline", "workload", "plans",
+                                                           "product_schedules",
+                                                           "stack_latency_ms",
+                                                           "layer_latency_ms")},
+        "cpu_baseline": None,
+    }
+    if not args.no_layer:
+        lay = bench_layer(args)
+        out["bert_base_layer"] = {k: v for k, v in lay.items()
+                                  if k not in ("metric", "unit", "n_gpus", "higher_is_better",
+                                               "scaling", "vs_baseline", "dtype", "data",
+                                               "cpu_baseline")}
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    if not args.no_batch:
+        bsteps, args.steps = args.steps, min(args.steps, 5)
+        b = bench_batch(args)
+        args.steps = bsteps
+        out["batched_vs_plain"] = b
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        log("cpu baseline (oracle on a sample of the stack) ...")
+        out["cpu_baseline"] = cpu_baseline_stack(args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
