@@ -233,6 +233,8 @@ struct Ctx {
 struct Plan {
     Ctx *ctx = nullptr;
     pimm_plan_info info;
+    // Product schedule: mac_rows = 0 selects the matrix-core product (mfma.hip);
+    // otherwise the FP64 vector product with this tile.
     int mac_rows = 8;  // output rows per product thread
     int mac_cols = 1;  // output column blocks per product thread
     int waves = 1;     // product grid = waves x the workgroups the device holds at once
@@ -249,6 +251,7 @@ struct Weights {
     pimm_plan_info info;        // of the plan it was made for (r, m, mb, rb, M, R, Wb matter)
     double *d_w_hat = nullptr;  // [L][N/256][M][R][256] NTT slots, balanced
     double *d_w_plain = nullptr;  // [r][m] the weights as doubles (the FC completion's product)
+    void *d_w_dig = nullptr;      // digit form for the matrix-core product (mfma.h), or null
     int64_t wmax = 0;
 };
 
@@ -258,6 +261,8 @@ int check_hip(hipError_t e, const char *what);
 Key make_key(const uint8_t seed[32]);
 bool noise_ok(const Ctx &c, const pimm_plan_info &f, uint64_t wmax);
 bool weights_fit(const Weights *w, const Plan *plan);
+// PIMM_OK when the matrix-core product can run this plan on these weights.
+int mfma_ready(const Plan *plan, const Weights *w, const char *who);
 // FC completion (fc.hip): the weights as doubles, and whether the limb sums of
 // X1 W stay exact for this shape, share width and weight bound.
 int weights_plain(const int64_t *W, double *Wd, size_t n, hipStream_t s);
@@ -322,8 +327,11 @@ int launch_sample(const Ctx &c, int kind, const Key &key, uint32_t tag, uint32_t
 // Slot-wise products of one plan into zeroed-then-accumulated acc^ (mac.hip).
 // The fused server step after the product (server.hip), on a workspace laid out as
 // pimm_matmul_share's; pk may be NULL without re-randomisation.
+// run16: acc^ is in the matrix-core product's chunked layout [L][N/16][O][2][16]
+// instead of [O][2][L][N].
 int fused_tail(const pimm_plan *plan, const uint64_t *pk, const Key &key, uint32_t op_id,
-               double *ws, uint64_t *c1, uint64_t *c0s, uint64_t *server_share, hipStream_t s);
+               double *ws, uint64_t *c1, uint64_t *c0s, uint64_t *server_share, bool run16,
+               hipStream_t s);
 // The product of one plan (acc^ zeroed first unless `zeroed` says the caller did).
 int launch_mac(const Ctx &c, const pimm_plan_info &f, int G, int KB, int waves, const double *Wt,
                const double *Ct, double *Ah, bool zeroed, hipStream_t s);

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "common.h"
+#include "mfma.h"
 #include "ntt.h"
 
 extern "C" int pimm_host_cdt(int len, uint64_t *out);
@@ -266,6 +267,7 @@ static void fill_info(const Ctx &c, pimm_plan_info &f)
     f.c0s_bytes = (uint64_t)f.O * L * f.mb * f.nb * 8;
     f.share_bytes = (uint64_t)f.n * f.m * 8;
     f.weights_bytes = (uint64_t)f.Wb * L * N * 8;
+    if (mfma_eligible(f)) f.weights_bytes += digit_cache_bytes(c, f);  // digit form (mfma.h)
     // Scratch of each call (see the call's implementation for the layout).
     const uint64_t enc = (uint64_t)f.I * N * 8 * (L + 1);
     const uint64_t mm = ((uint64_t)f.I + f.O) * 2 * L * N * 8;

@@ -1,0 +1,52 @@
+// mfma.h -- the matrix-core form of the slot-wise products (mfma.hip) and the
+// 16-slot-chunk layouts its operands use.
+#pragma once
+
+#include "common.h"
+
+namespace pimm {
+
+// Plans the matrix-core product serves: at most 64 inner blocks (one 64-deep int8
+// product per digit pair) and at least 8 column blocks (16 columns with both
+// ciphertext components), where the product is bound by arithmetic.
+bool mfma_eligible(const pimm_plan_info &f);
+// Bytes of the digit form of a weight cache for plan f.
+uint64_t digit_cache_bytes(const Ctx &c, const pimm_plan_info &f);
+// Digit form [L][N][7][Mt][64][16 B] of the FP64 cache Wt [L][N/256][M][R][256].
+int build_weight_digits(const Ctx &c, const pimm_plan_info &f, const double *Wt, void *Wd,
+                        hipStream_t s);
+// acc^ [L][N/16][O][2][16] = the slot-wise products of c^ [L][N/16][I][2][16] with the
+// digit weight cache Wd.  Every accumulator is written once (no zeroing needed).
+int launch_mac_mfma(const Ctx &c, const pimm_plan_info &f, const void *Wd, const double *Ch,
+                    double *Ah, hipStream_t s);
+
+// Input transform storer for the chunked layout: polynomial (x*2 + comp)*L + l, slot z.
+struct StoreCtRun16 {
+    double *out;
+    uint32_t I2, NC;  // 2 * I, N / 16
+    int L;
+    __device__ void operator()(int poly, int l, int z, double v, double, double) const
+    {
+        const uint32_t xc = (uint32_t)(poly / L);
+        out[(((size_t)l * NC + (uint32_t)(z >> 4)) * I2 + xc) * 16 + (z & 15)] = v;
+    }
+};
+
+// Index of accumulator polynomial (o*2 + comp)*L + l, slot z, in [L][N/16][O][2][16].
+__device__ __forceinline__ size_t run16_index(int poly, int l, int z, int L, uint32_t O2, uint32_t NC)
+{
+    return (((size_t)l * NC + (uint32_t)(z >> 4)) * O2 + (uint32_t)(poly / L)) * 16 + (z & 15);
+}
+
+// Accumulators in the chunked layout, reduced (the plain pimm_matmul's inverse transform).
+struct LoadSlotsReduceRun16 {
+    const double *a;
+    uint32_t O2, NC;
+    int L;
+    __device__ double operator()(int poly, int l, int z, double p, double pinv) const
+    {
+        return reduce(a[run16_index(poly, l, z, L, O2, NC)], p, pinv);
+    }
+};
+
+}  // namespace pimm

@@ -422,7 +422,7 @@ int pimm_serve_run(pimm_server *sv, const pimm_request *reqs, uint32_t count,
             const pimm_plan *plan = &a->plans[a->step % sv->cfg.ops];
             const pimm_plan_info &f = plan->info;
             rc = fused_tail(plan, a->pk, make_key(a->req.server_seed), a->step, a->ws, a->c1, a->c0s,
-                            a->y1, s);
+                            a->y1, false, s);
             if (!rc) rc = pimm_decrypt(plan, &a->sk, a->c1, a->c0s, a->y0, a->ws, a->ws_bytes, s);
             if (!rc) {
                 hipLaunchKernelGGL(k_checksum, dim3(64), dim3(256), 0, s, a->y0, a->y1, f.n * f.m,

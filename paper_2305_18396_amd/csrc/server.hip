@@ -14,6 +14,7 @@
 
 #include "common.h"
 #include "mac.h"
+#include "mfma.h"
 #include "ntt.h"
 
 namespace pimm {
@@ -145,13 +146,16 @@ __global__ void k_mask_extract(Key key, uint32_t op, const uint64_t *acc, uint64
 
 // acc^ (reduced) plus, with re-randomisation, u^ pk^ (NTT domain) for polynomials [O][2][L].
 struct LoadAccRerand {
-    const double *ah;   // [O][2][L][N]
+    const double *ah;   // [O][2][L][N], or [L][N/16][O][2][16] with run16
     const double *uh;   // [O][L][N]
     const double *pkh;  // [2][L][N]
     int logn, L, rr;
+    int run16;
+    uint32_t O2, NC;  // 2 * O and N / 16 (run16 layout)
     __device__ double operator()(int poly, int l, int z, double p, double pinv) const
     {
-        double v = reduce(ah[((size_t)poly << logn) + z], p, pinv);
+        const size_t at = run16 ? run16_index(poly, l, z, L, O2, NC) : ((size_t)poly << logn) + z;
+        double v = reduce(ah[at], p, pinv);
         if (rr) {
             const size_t o = (size_t)(poly / (2 * L)), comp = (size_t)((poly / L) % 2);
             v += mulmod(uh[((o * L + l) << logn) + z], pkh[((comp * L + l) << logn) + z], p, pinv);
@@ -235,7 +239,8 @@ __global__ void k_mask_reply(Key key, uint32_t op, uint64_t *c0s, uint64_t *shar
 // re-randomisation draws and transforms, the inverse transform with the reply
 // epilogue, then the mask at the decoded positions and the server's share.
 int fused_tail(const pimm_plan *plan, const uint64_t *pk, const Key &key, uint32_t op_id,
-               double *ws, uint64_t *c1, uint64_t *c0s, uint64_t *server_share, hipStream_t s)
+               double *ws, uint64_t *c1, uint64_t *c0s, uint64_t *server_share, bool run16,
+               hipStream_t s)
 {
     const Ctx &c = *plan->ctx;
     const pimm_plan_info &f = plan->info;
@@ -255,7 +260,8 @@ int fused_tail(const pimm_plan *plan, const uint64_t *pk, const Key &key, uint32
             rc = launch_fwd(c, LoadPkU{pk, u, lg, (int)L}, StoreSlots{pkh, lg}, (int)((2 + f.O) * L), s);
     }
     if (!rc)
-        rc = launch_inv_lds(c, LoadAccRerand{ah, uh, pkh, lg, (int)L, rr},
+        rc = launch_inv_lds(c, LoadAccRerand{ah, uh, pkh, lg, (int)L, rr, run16 ? 1 : 0, 2 * f.O,
+                                             (uint32_t)(N / 16)},
                             ReplyOut{c1, c0s, e, FastDiv::make(f.mb), f.rb, f.nb, lg, (int)L, rr},
                             (int)(f.O * 2 * L), s);
     if (!rc) {
@@ -280,6 +286,22 @@ bool weights_fit(const Weights *w, const Plan *plan)
 {
     const pimm_plan_info &a = w->info, &b = plan->info;
     return w->ctx == plan->ctx && a.r == b.r && a.m == b.m && a.mb == b.mb && a.rb == b.rb;
+}
+
+// The matrix-core product needs an eligible plan and the digit form of the weights.
+int mfma_ready(const Plan *plan, const Weights *w, const char *who)
+{
+    if (!mfma_eligible(plan->info))
+        return set_error(PIMM_E_UNSUPPORTED,
+                         "%s: the matrix-core product needs at most 64 inner blocks and at least 8 "
+                         "column blocks (plan: R = %u, K = %u)",
+                         who, plan->info.R, plan->info.K);
+    if (!w->d_w_dig)
+        return set_error(PIMM_E_UNSUPPORTED,
+                         "%s: the weight cache has no digit form (it is built when the cache is "
+                         "made for a plan the matrix-core product serves)",
+                         who);
+    return PIMM_OK;
 }
 }  // namespace pimm
 
@@ -317,7 +339,10 @@ int pimm_weights_create(const pimm_plan *plan, const int64_t *W, pimm_weights **
     w->ctx = plan->ctx;
     w->info = plan->info;
     w->wmax = (int64_t)h_max;
-    rc = check_hip(hipMalloc((void **)&w->d_w_hat, f.weights_bytes), "hipMalloc weights");
+    const uint64_t f64_bytes = (uint64_t)f.Wb * c.params.L * c.params.N * 8;
+    rc = check_hip(hipMalloc((void **)&w->d_w_hat, f64_bytes), "hipMalloc weights");
+    if (!rc && mfma_eligible(f))
+        rc = check_hip(hipMalloc(&w->d_w_dig, digit_cache_bytes(c, f)), "hipMalloc weight digits");
     if (!rc)
         rc = check_hip(hipMalloc((void **)&w->d_w_plain, (size_t)f.r * f.m * sizeof(double)),
                        "hipMalloc plain weights");
@@ -326,6 +351,7 @@ int pimm_weights_create(const pimm_plan *plan, const int64_t *W, pimm_weights **
         rc = launch_fwd(c, LoadWeights{W, f.r, f.m, f.mb, f.rb, f.R, (int)c.params.L},
                         StoreWeightTiled{w->d_w_hat, c.dp.logN, (int)c.params.L, f.M, f.R},
                         (int)(f.Wb * c.params.L), s);
+    if (!rc && w->d_w_dig) rc = build_weight_digits(c, f, w->d_w_hat, w->d_w_dig, s);
     if (!rc) rc = check_hip(hipStreamSynchronize(s), "weights synchronize");
     if (rc) {
         pimm_weights_destroy(w);
@@ -353,6 +379,7 @@ int pimm_weights_update(pimm_weights *w, const int64_t *W, uint64_t wmax, void *
         rc = launch_fwd(c, LoadWeights{W, f.r, f.m, f.mb, f.rb, f.R, (int)c.params.L},
                         StoreWeightTiled{w->d_w_hat, c.dp.logN, (int)c.params.L, f.M, f.R},
                         (int)(f.Wb * c.params.L), s);
+    if (!rc && w->d_w_dig) rc = build_weight_digits(c, f, w->d_w_hat, w->d_w_dig, s);
     if (!rc) w->wmax = (int64_t)wmax;
     return rc;
 }
@@ -362,6 +389,7 @@ int pimm_weights_destroy(pimm_weights *w)
     if (!w) return PIMM_OK;
     if (w->d_w_hat) (void)hipFree(w->d_w_hat);
     if (w->d_w_plain) (void)hipFree(w->d_w_plain);
+    if (w->d_w_dig) (void)hipFree(w->d_w_dig);
     delete w;
     return PIMM_OK;
 }
@@ -382,8 +410,20 @@ int pimm_matmul(const pimm_plan *plan, const pimm_weights *w, const uint64_t *ct
     const int lg = c.dp.logN;
     double *ch = (double *)ws;
     double *ah = ch + (size_t)f.I * 2 * L * N;
-    int rc = launch_fwd_zero(c, LoadU64{ct, lg}, StoreCtTiled{ch, lg, (int)L, f.K, f.R},
-                             (int)(f.I * 2 * L), ah, (size_t)f.O * 2 * L * N, s);
+    int rc = PIMM_OK;
+    if (plan->mac_rows == 0) {
+        rc = mfma_ready(plan, w, "pimm_matmul");
+        if (!rc)
+            rc = launch_fwd(c, LoadU64{ct, lg}, StoreCtRun16{ch, 2 * f.I, (uint32_t)(N / 16), (int)L},
+                            (int)(f.I * 2 * L), s);
+        if (!rc) rc = launch_mac_mfma(c, f, w->d_w_dig, ch, ah, s);
+        if (!rc)
+            rc = launch_inv(c, LoadSlotsReduceRun16{ah, 2 * f.O, (uint32_t)(N / 16), (int)L},
+                            StoreU64{acc, lg}, (int)(f.O * 2 * L), s);
+        return rc;
+    }
+    rc = launch_fwd_zero(c, LoadU64{ct, lg}, StoreCtTiled{ch, lg, (int)L, f.K, f.R},
+                         (int)(f.I * 2 * L), ah, (size_t)f.O * 2 * L * N, s);
     if (!rc)
         rc = launch_mac(c, f, plan->mac_rows, plan->mac_cols, plan->waves, w->d_w_hat, ch, ah, true, s);
     if (!rc) rc = launch_inv(c, LoadSlotsReduce{ah, lg}, StoreU64{acc, lg}, (int)(f.O * 2 * L), s);
@@ -459,11 +499,23 @@ int pimm_matmul_share(const pimm_plan *plan, const pimm_weights *w, const uint64
     const int lg = c.dp.logN;
     double *ch = (double *)ws;
     double *ah = ch + (size_t)f.I * 2 * L * N;
-    int rc = launch_fwd_zero(c, LoadU64{ct, lg}, StoreCtTiled{ch, lg, (int)L, f.K, f.R},
+    const bool mx = plan->mac_rows == 0;
+    int rc = PIMM_OK;
+    if (mx) {
+        rc = mfma_ready(plan, w, "pimm_matmul_share");
+        if (!rc)
+            rc = launch_fwd(c, LoadU64{ct, lg}, StoreCtRun16{ch, 2 * f.I, (uint32_t)(N / 16), (int)L},
+                            (int)(f.I * 2 * L), s);
+        if (!rc) rc = launch_mac_mfma(c, f, w->d_w_dig, ch, ah, s);
+    } else {
+        rc = launch_fwd_zero(c, LoadU64{ct, lg}, StoreCtTiled{ch, lg, (int)L, f.K, f.R},
                              (int)(f.I * 2 * L), ah, (size_t)f.O * 2 * L * N, s);
+        if (!rc)
+            rc = launch_mac(c, f, plan->mac_rows, plan->mac_cols, plan->waves, w->d_w_hat, ch, ah,
+                            true, s);
+    }
     if (!rc)
-        rc = launch_mac(c, f, plan->mac_rows, plan->mac_cols, plan->waves, w->d_w_hat, ch, ah, true, s);
-    if (!rc) rc = fused_tail(plan, pk, make_key(seed), op_id, (double *)ws, c1, c0s, server_share, s);
+        rc = fused_tail(plan, pk, make_key(seed), op_id, (double *)ws, c1, c0s, server_share, mx, s);
     return rc;
 }
 

@@ -10,6 +10,7 @@
 #include "batch.h"
 #include "common.h"
 #include "mac.h"
+#include "mfma.h"
 
 using namespace pimm;
 
@@ -41,6 +42,15 @@ extern "C" {
 int pimm_plan_set_tuning(pimm_plan *plan, int mac_rows, int mac_cols, int waves)
 {
     if (!plan) return set_error(PIMM_E_ARG, "pimm_plan_set_tuning: NULL plan");
+    if (mac_rows == 0 && mac_cols == 0 && waves == 0) {  // the matrix-core product
+        if (!mfma_eligible(plan->info))
+            return set_error(PIMM_E_UNSUPPORTED,
+                             "the matrix-core product needs at most 64 inner blocks and at least 8 "
+                             "column blocks (plan: R = %u, K = %u)",
+                             plan->info.R, plan->info.K);
+        plan->mac_rows = plan->mac_cols = plan->waves = 0;
+        return PIMM_OK;
+    }
     if (!mac_shape_ok(mac_rows, mac_cols))
         return set_error(PIMM_E_ARG, "product tile %d rows x %d column blocks is not built",
                          mac_rows, mac_cols);
@@ -98,6 +108,22 @@ int pimm_plan_autotune(pimm_plan *plan, const pimm_weights *w, const uint64_t *c
                 bk = sh.kb;
                 bw = wv;
             }
+        }
+    }
+    if (w->d_w_dig && mfma_eligible(plan->info)) {
+        plan->mac_rows = plan->mac_cols = plan->waves = 0;
+        double ms = 0;
+        int rc = time_ms(s, reps,
+                         [&]() { return pimm_matmul(plan, w, ct, acc, ws, ws_bytes, stream); }, &ms);
+        if (rc) {
+            plan->mac_rows = bg;
+            plan->mac_cols = bk;
+            plan->waves = bw;
+            return rc;
+        }
+        if (ms < best) {
+            best = ms;
+            bg = bk = bw = 0;
         }
     }
     plan->mac_rows = bg;

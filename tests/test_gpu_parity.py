@@ -109,12 +109,14 @@ def test_poly_mul_bitexact(orc, N, L):
     assert np.array_equal(got[0, 0], shifted)
 
 
-def run_both(orc, N, L, ell, f, rr, X, W, plan_kw, tag):
+def run_both(orc, N, L, ell, f, rr, X, W, plan_kw, tag, tuning=None):
     """Run the protocol on the GPU and in the oracle; return both sets of buffers."""
     ctx = context(N, L, ell, f, rr)
     n, r = X.shape
     m = W.shape[1]
     plan = pimm.Plan(ctx, n, r, m, **plan_kw)
+    if tuning is not None:
+        plan.set_tuning(*tuning)
     pyp = orc.Params(N, L, ell, f, rerandomize=rr)
     oplan = orc.Plan(n, r, m, plan.mb, plan.rb, plan.nb, N)
     cseed, sseed = workloads.seed("client", tag), workloads.seed("server", tag)
@@ -314,12 +316,72 @@ def test_full_size_bert_base_layer(orc, layer_d, tunings):
 def test_full_size_bert_large_op(orc, op):
     """Every BERT-large-shaped product of the stack (QKV 1024x3072, attn-out 1024x1024, FFN
     1024x4096 and 4096x1024 at seq 512) with N = 8192, three primes, t = 2^41, blocks of area
-    1024: under the autotuned schedule the stack benchmark runs and the column-blocked tiles
-    4x8 and 8x4."""
+    1024: under the autotuned schedule the stack benchmark runs, the column-blocked tiles
+    4x8 and 8x4 and the matrix-core product (int8 digit products)."""
     ctx = context(8192, 3, 41, 14, True)
     pyp = orc.Params(8192, 3, 41, 14)
     wl = workloads.bert_large_layer(512)[op]
-    check_layer_op(orc, ctx, pyp, wl, dict(d_fix=1024), 200 + op, ("auto", (4, 8, 1), (8, 4, 1)))
+    check_layer_op(orc, ctx, pyp, wl, dict(d_fix=1024), 200 + op,
+                   ("auto", (4, 8, 1), (8, 4, 1), MATRIX_CORES))
+
+
+# Schedule (0, 0, 0): the slot-wise products on the matrix cores (exact int8 digit products).
+MATRIX_CORES = (0, 0, 0)
+
+
+@pytest.mark.parametrize("name,N,L,ell,f,shape,plan_kw", [
+    ("mx_ragged", 4096, 2, 37, 12, (200, 100, 70), dict(d_fix=256)),
+    ("mx_r64", 4096, 2, 37, 12, (520, 512, 40), dict(mb=8, rb=8, nb=64)),
+    ("mx_n8192", 8192, 3, 41, 14, (300, 96, 200), dict(d_fix=512)),
+    ("mx_m80", 4096, 2, 37, 12, (96, 64, 330), dict(mb=4, rb=2, nb=8))])
+def test_matrix_core_product_bitexact(orc, name, N, L, ell, f, shape, plan_kw):
+    """The matrix-core product (schedule (0, 0, 0)) gives the oracle's accumulators and reply,
+    through pimm_matmul and the fused call, with ragged row, column and inner tiles (M, K and R
+    not multiples of 16, 8 and 64; more than four row tiles)."""
+    n, r, m = shape
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    X = workloads.share(rng, n, r, ell)
+    W = workloads.weights(rng, r, m, f)
+    ctx = context(N, L, ell, f, True)
+    plan = pimm.Plan(ctx, n, r, m, **plan_kw)
+    assert plan.R <= 64 and plan.K >= 8, (plan.R, plan.K)
+    log(f"matrix cores {name}: plan=({plan.mb},{plan.rb},{plan.nb}) M={plan.M} R={plan.R} "
+        f"K={plan.K}")
+    gpu, ref, pyp = run_both(orc, N, L, ell, f, True, X, W, plan_kw, 300 + len(name),
+                             tuning=MATRIX_CORES)
+    for k in ("ct", "acc", "acc_rr", "c1", "c0s", "Y1", "Y0"):
+        assert np.array_equal(gpu[k], ref[k].view(np.uint64)), k
+    Y = (gpu["Y0"] + gpu["Y1"]) & np.uint64(pyp.t - 1)
+    assert np.array_equal(Y, xw_mod(X, W, ell))
+    # The fused call under the same schedule gives the same reply.
+    cs, ss = workloads.seed("client", 300 + len(name)), workloads.seed("server", 300 + len(name))
+    sk, pk = pimm.keygen(ctx, cs)
+    ct = pimm.to_device_u64(gpu["ct"])
+    w = pimm.Weights(plan, pimm.to_device_u64(W))
+    plan.set_tuning(*MATRIX_CORES)
+    d1, d0s, z1 = pimm.matmul_share(plan, w, pk, ss, 300 + len(name), ct)
+    assert np.array_equal(u64(d1), gpu["c1"]) and np.array_equal(u64(d0s), gpu["c0s"])
+    assert np.array_equal(u64(z1), gpu["Y1"])
+
+
+def test_matrix_core_product_refusals():
+    """Plans the matrix-core product does not serve (more than 64 inner blocks, fewer than 8
+    column blocks) are refused by pimm_plan_set_tuning; weights made for such a plan have no
+    digit form, so a matrix-core call on them is refused too."""
+    ctx = context(4096, 2, 37, 12, True)
+    wide = pimm.Plan(ctx, 128, 3072, 64, mb=4, rb=2, nb=8)  # R = 1536
+    with pytest.raises(pimm.PimmError, match="PIMM_E_UNSUPPORTED"):
+        wide.set_tuning(*MATRIX_CORES)
+    narrow = pimm.Plan(ctx, 16, 64, 64)  # K = 1
+    with pytest.raises(pimm.PimmError, match="PIMM_E_UNSUPPORTED"):
+        narrow.set_tuning(*MATRIX_CORES)
+    small = pimm.Plan(ctx, 4, 32, 64, d_fix=64)  # K = 1 at creation: no digit form
+    w = pimm.Weights(small, torch.ones((32, 64), dtype=torch.int64, device="cuda"))
+    long = pimm.Plan(ctx, 600, 32, 64, d_fix=64)  # K = 10: eligible, but w has no digits
+    long.set_tuning(*MATRIX_CORES)
+    ct = torch.zeros((long.I, 2, 2, 4096), dtype=torch.int64, device="cuda")
+    with pytest.raises(pimm.PimmError, match="PIMM_E_UNSUPPORTED"):
+        pimm.matmul(long, w, ct)
 
 
 TUNINGS = [(g, kb, wv) for g, kb in [(4, 1), (8, 1), (16, 1), (4, 2), (8, 2), (16, 2), (2, 4),
