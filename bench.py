@@ -60,19 +60,23 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mac_traffic_bert_base_seq128.md")
 MAC_SOURCES = [os.path.join(ROOT, "paper_2305_18396_amd", "csrc", f) for f in ("mac.h", "mac.hip")]
 
 
-def measured_traffic(schedules):
+STACK_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mac_mfma_traffic_bert_large_seq512.md")
+MFMA_SOURCES = [os.path.join(ROOT, "paper_2305_18396_amd", "csrc", f) for f in ("mfma.h", "mfma.hip")]
+
+
+def measured_traffic(schedules, path=TRAFFIC_FILE, sources=MAC_SOURCES):
     """HBM bytes per product launch from the committed counter summary, or None when the
     product's sources or schedules differ from the ones the counters were taken on."""
     import hashlib
 
-    if not os.path.exists(TRAFFIC_FILE):
+    if not os.path.exists(path):
         return None
     fields = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith(("|", "#", "`")):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    h = hashlib.sha256(b"".join(open(f, "rb").read() for f in MAC_SOURCES)).hexdigest()
+    h = hashlib.sha256(b"".join(open(f, "rb").read() for f in sources)).hexdigest()
     want = ";".join(",".join(str(v) for v in sch) for sch in schedules)
     if fields.get("mac_sources_sha256") != h or fields.get("product_schedules") != want:
         return None
@@ -400,8 +404,11 @@ def bench_stack(args):
     useful = args.stack_layers * useful_layer
     slot_per_product = [2 * L * N * p.info.P for p in plans]
     slot = args.stack_layers * sum(slot_per_product)
-    # One schedule per product shape, tuned on layer 0's buffers.
+    # One schedule per product shape, tuned on layer 0's buffers (or given by --schedules).
     for i, plan in enumerate(plans):
+        if args.schedules:
+            plan.set_tuning(*(int(v) for v in args.schedules.split(";")[i].split(",")))
+            continue
         b = bufs[i]
         pimm.encrypt(plan, sk, cseed, AUTOTUNE_OP + i,
                      pimm.encode_input(plan, layers[0][i][1], b["pt"]), b["ct"])
@@ -469,8 +476,53 @@ def bench_stack(args):
     mac_avg_s = mac_ms / 1e3 / max(1, cnt)
     slot_per_launch = sum(slot_per_product) / len(plans)
     slot_rate = slot_per_launch / mac_avg_s if cnt else 0.0
-    flop_per_slot = 2 * FP64_ISSUES_PER_SLOT_MAC
-    achieved_tf = slot_rate * flop_per_slot / 1e12
+    schedules = [p.tuning() for p in plans]
+    if all(sch == (0, 0, 0) for sch in schedules):
+        # Matrix-core product: the algorithmic bytes are the transformed inputs (FP64), the
+        # digit form of the weight fragments (7 bytes a residue, padded to 16 rows x 64 inner
+        # blocks) and the accumulators (FP64), each once; the int8 work is 49 digit-pair
+        # products of 2 x 16 x 16 x 64 operations per tile, slot and prime.
+        byts, ops = [], []
+        for p in plans:
+            fi = p.info
+            mt = (fi.M + 15) // 16
+            byts.append(16 * L * N * (fi.I + fi.O) + 7 * L * N * mt * 1024)
+            ops.append(L * N * mt * ((2 * fi.K + 15) // 16) * 49 * 2 * 16 * 16 * 64)
+        bytes_per_launch, ops_per_launch = sum(byts) / len(byts), sum(ops) / len(ops)
+        achieved = bytes_per_launch / mac_avg_s / 1e9 if cnt else 0.0
+        roofline = {
+            "kernel": "k_mac_mfma (the slot-wise product on the matrix cores)", "bound": "hbm",
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": measured_traffic(schedules, STACK_TRAFFIC_FILE, MFMA_SOURCES),
+            "alg_bytes_per_launch": bytes_per_launch, "avg_launch_ms": mac_avg_s * 1e3,
+            "int8_ops_per_launch": ops_per_launch,
+            "int8_TOPS": ops_per_launch / mac_avg_s / 1e12 if cnt else 0.0,
+            "int8_peak_TOPS": 5000.0,
+            "note": "HBM is the binding roofline: the launch's bytes at 8 TB/s take longer than "
+                    "its int8 operations at 5.0 POP/s",
+        }
+    else:
+        flop_per_slot = 2 * FP64_ISSUES_PER_SLOT_MAC
+        achieved_tf = slot_rate * flop_per_slot / 1e12
+        roofline = {
+            "kernel": "k_mac_sk (the slot-wise product)", "bound": "alu",
+            "achieved": achieved_tf, "peak": 78.6, "unit": "TFLOP/s",
+            "frac": achieved_tf / 78.6, "traffic": None,
+            "work_per_launch_slot_macs": slot_per_launch,
+            "flop_per_slot_mac": flop_per_slot,
+            "avg_launch_ms": mac_avg_s * 1e3,
+            "note": "FP64 vector issue rate: each slot-wise modular multiply-accumulate is 7 FP64 "
+                    "instructions (counted at the FMA rate of the 78.6 TFLOP/s peak, i.e. 2 each); "
+                    "peak = 5.61e12 slot-MAC/s",
+        }
+    if args.calib_copy_mb:
+        src = torch.ones(args.calib_copy_mb << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     return {
         "workload": f"BERT-large-shaped stack, {args.stack_layers} layers x 4 products at seq "
                     f"{seq} (QKV 1024x3072, attn-out 1024x1024, FFN 1024x4096 and 4096x1024); "
@@ -490,17 +542,7 @@ def bench_stack(args):
         "product_ms_per_step": mac_ms / args.steps,
         "product_slot_mac_per_s": slot_rate,
         "kernels_untimed_pass": breakdown,
-        "roofline": {
-            "kernel": "k_mac_sk (the slot-wise product)", "bound": "alu",
-            "achieved": achieved_tf, "peak": 78.6, "unit": "TFLOP/s",
-            "frac": achieved_tf / 78.6, "traffic": None,
-            "work_per_launch_slot_macs": slot_per_launch,
-            "flop_per_slot_mac": flop_per_slot,
-            "avg_launch_ms": mac_avg_s * 1e3,
-            "note": "FP64 vector issue rate: each slot-wise modular multiply-accumulate is 7 FP64 "
-                    "instructions (counted at the FMA rate of the 78.6 TFLOP/s peak, i.e. 2 each); "
-                    "peak = 5.61e12 slot-MAC/s",
-        },
+        "roofline": roofline,
     }
 
 
