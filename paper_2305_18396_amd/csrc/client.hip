@@ -46,7 +46,7 @@ struct LoadCtComp {
 // host data a kernel may read).
 struct StoreEncC0 {
     const uint64_t *pt;  // [I][N]
-    const int64_t *e;    // [I][N]
+    const int8_t *e;     // [I][N]
     uint64_t *ct;        // [I][2][L][N]
     uint64_t delta[kMaxL];
     int logn, L;
@@ -222,7 +222,7 @@ int pimm_encode_input(const pimm_plan *plan, const uint64_t *X, uint64_t *pt, vo
     return check_hip(hipGetLastError(), "encode_input launch");
 }
 
-// Workspace: a^ [I][L][N] doubles, then e [I][N] int64.
+// Workspace: a^ [I][L][N] doubles, then e [I][N] (one byte each, in an int64-sized region).
 // Symmetric encryption with e drawn from `seed` and a from `a_seed` (the same
 // seed for pimm_encrypt).
 static int encrypt_with(const pimm_plan *plan, const pimm_sk *sk, const uint8_t seed[32],
@@ -240,12 +240,12 @@ static int encrypt_with(const pimm_plan *plan, const pimm_sk *sk, const uint8_t 
     hipStream_t s = (hipStream_t)stream;
     const int lg = c.dp.logN;
     double *ah = (double *)ws;
-    int64_t *e = (int64_t *)(ah + (size_t)f.I * L * N);
+    int8_t *e = (int8_t *)(ah + (size_t)f.I * L * N);
     const Key key = make_key(seed);
     // c1 = a (uniform per prime, written straight into the ciphertexts) and e: one launch
     // when both come from the same seed, else one per seed.
     const SampleJob ja{0, kTagEncA, 0, (int)f.I, 0, (int)L, ct + L * N, 2 * L * N, N, 0};
-    const SampleJob je{2, kTagEncE, 0, (int)f.I, 0, 1, e, N, 0, 0};
+    const SampleJob je{kSampleGauss8, kTagEncE, 0, (int)f.I, 0, 1, e, N, 0, 0};
     int rc;
     if (memcmp(seed, a_seed, 32) == 0) {
         SampleJobs js{};

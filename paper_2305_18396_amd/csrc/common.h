@@ -302,6 +302,13 @@ class ProfScope {
     bool active_ = false;
 };
 
+// Sampler kinds: 0 uniform mod q_l (uint64), 1 ternary (int64), 2 Gaussian (int64),
+// 3 mask mod 2^l (uint64); the library's own scratch also takes ternary and Gaussian
+// values as one signed byte each (|value| <= 19), which every kernel that reads them
+// widens again.
+constexpr int kSampleTernary8 = 4;
+constexpr int kSampleGauss8 = 5;
+
 // One sampling job (see k_sample): `nobj` objects x `nprime` primes of draws
 // from stream (tag, prime, op, obj0 + o), written at out + o * obj_stride +
 // prime_index * prime_stride.

@@ -403,6 +403,16 @@ __device__ __forceinline__ void sample_block(const Key &key, uint32_t op, const 
         int64_t *dst = (int64_t *)jb.out + base;
 #pragma unroll
         for (int i = 0; i < 8; ++i) dst[i] = gauss_of(word64(w, i), dp.cdt);
+    } else if (KIND == kSampleTernary8 || KIND == kSampleGauss8) {
+        // The same values as kinds 1 and 2 (|value| <= 19), one byte each.
+        uint64_t packed = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int64_t v = KIND == kSampleTernary8 ? ternary_of(word64(w, i))
+                                                      : gauss_of(word64(w, i), dp.cdt);
+            packed |= (uint64_t)(uint8_t)(int8_t)v << (8 * i);
+        }
+        *(uint64_t *)((int8_t *)jb.out + base) = packed;
     } else {
         uint64_t *dst = (uint64_t *)jb.out + base;
 #pragma unroll
@@ -426,6 +436,8 @@ __global__ __launch_bounds__(256) void k_sample(Key key, uint32_t op, SampleJobs
     case 0: sample_block<0>(key, op, jb, gid, dp); break;
     case 1: sample_block<1>(key, op, jb, gid, dp); break;
     case 2: sample_block<2>(key, op, jb, gid, dp); break;
+    case kSampleTernary8: sample_block<kSampleTernary8>(key, op, jb, gid, dp); break;
+    case kSampleGauss8: sample_block<kSampleGauss8>(key, op, jb, gid, dp); break;
     default: sample_block<3>(key, op, jb, gid, dp); break;
     }
 }

@@ -222,12 +222,18 @@ __device__ __forceinline__ void ntt_inv_block(const Load &ld, const Store &st, c
     inv_pass<typename NP::A, T, false, true>(ld, st, poly, l, tw, p, pinv, ninv, lds);
 }
 
+// Polynomial of a workgroup: workgroups are dispatched round-robin over the XCDs, so the
+// transform kernels take xcd_local(blockIdx.x): neighbouring polynomials (the primes of one
+// ciphertext, the two components of one output) run on one XCD and the operands they share
+// (error and plaintext words, the re-randomisation term, the key) come from its L2.
+__device__ __forceinline__ int ntt_poly() { return (int)xcd_local(blockIdx.x, gridDim.x); }
+
 template <int LOGN, class Load, class Store>
 __global__ __launch_bounds__(ntt_threads<LOGN>()) void k_ntt_fwd(Load ld, Store st, DevParams dp)
 {
     constexpr int T = ntt_threads<LOGN>();
     __shared__ double lds[NttPasses<LOGN, T>::LDS];
-    ntt_fwd_block<LOGN, T>(ld, st, dp, (int)blockIdx.x, lds);
+    ntt_fwd_block<LOGN, T>(ld, st, dp, ntt_poly(), lds);
 }
 
 // Forward transform that also clears its share of another buffer (the
@@ -239,7 +245,7 @@ __global__ __launch_bounds__(ntt_threads<LOGN>()) void k_ntt_fwd_zero(Load ld, S
 {
     constexpr int T = ntt_threads<LOGN>();
     __shared__ double lds[NttPasses<LOGN, T>::LDS];
-    ntt_fwd_block<LOGN, T>(ld, st, dp, (int)blockIdx.x, lds);
+    ntt_fwd_block<LOGN, T>(ld, st, dp, ntt_poly(), lds);
     const size_t per = (zero_n + gridDim.x - 1) / gridDim.x;
     const size_t b = (size_t)blockIdx.x * per;
     const size_t e = b + per < zero_n ? b + per : zero_n;
@@ -251,7 +257,7 @@ __global__ __launch_bounds__(ntt_threads<LOGN>()) void k_ntt_inv(Load ld, Store 
 {
     constexpr int T = ntt_threads<LOGN>();
     __shared__ double lds[NttPasses<LOGN, T>::LDS];
-    ntt_inv_block<LOGN, T>(ld, st, dp, (int)blockIdx.x, lds);
+    ntt_inv_block<LOGN, T>(ld, st, dp, ntt_poly(), lds);
 }
 
 // Inverse transform whose result stays in the workgroup's LDS (natural order,
@@ -271,7 +277,7 @@ __global__ __launch_bounds__(ntt_threads<LOGN>()) void k_ntt_inv_lds(Load ld, Ep
 {
     constexpr int T = ntt_threads<LOGN>();
     __shared__ double lds[NttPasses<LOGN, T>::LDS];
-    const int poly = (int)blockIdx.x;
+    const int poly = ntt_poly();
     ntt_inv_block<LOGN, T>(ld, StoreLds{lds}, dp, poly, lds);
     __syncthreads();
     epi(poly, lds, dp);

@@ -62,14 +62,14 @@ __global__ void k_absmax(const int64_t *W, size_t n, unsigned long long *out)
 
 // The re-randomisation draws of every output ciphertext y in one launch: u_y
 // (ternary, stream RR_U) into u [O][N], e1_y and e2_y (Gaussian, RR_E1 / RR_E2)
-// into e [O][2][N].
-static SampleJobs rerand_jobs(uint32_t O, size_t N, int64_t *u, int64_t *e)
+// into e [O][2][N], one signed byte each.
+static SampleJobs rerand_jobs(uint32_t O, size_t N, int8_t *u, int8_t *e)
 {
     SampleJobs js{};
     js.n = 3;
-    js.job[0] = SampleJob{1, kTagRrU, 0, (int)O, 0, 1, u, N, 0, 0};
-    js.job[1] = SampleJob{2, kTagRrE1, 0, (int)O, 0, 1, e, 2 * N, 0, 0};
-    js.job[2] = SampleJob{2, kTagRrE2, 0, (int)O, 0, 1, e + N, 2 * N, 0, 0};
+    js.job[0] = SampleJob{kSampleTernary8, kTagRrU, 0, (int)O, 0, 1, u, N, 0, 0};
+    js.job[1] = SampleJob{kSampleGauss8, kTagRrE1, 0, (int)O, 0, 1, e, 2 * N, 0, 0};
+    js.job[2] = SampleJob{kSampleGauss8, kTagRrE2, 0, (int)O, 0, 1, e + N, 2 * N, 0, 0};
     return js;
 }
 
@@ -92,7 +92,7 @@ struct LoadRerand {
 // keeps prime poly % L in both parts (2L is a multiple of L).
 struct LoadPkU {
     const uint64_t *pk;
-    const int64_t *u;
+    const int8_t *u;
     int logn, L;
     __device__ double operator()(int poly, int, int j, double, double) const
     {
@@ -104,7 +104,7 @@ struct LoadPkU {
 // acc[o][comp][l][j] += (u pk_comp)_j + e_comp[j]  (mod q_l); e: [O][2][N].
 struct StoreAddErr {
     uint64_t *acc;
-    const int64_t *e;
+    const int8_t *e;
     int logn, L;
     __device__ void operator()(int poly, int l, int j, double v, double p, double pinv) const
     {
@@ -170,7 +170,7 @@ struct LoadAccRerand {
 // (component 0).
 struct ReplyOut {
     uint64_t *c1, *c0s;
-    const int64_t *e;  // [O][2][N]
+    const int8_t *e;  // [O][2][N]
     FastDiv mb;
     uint32_t rb, nb;
     int logn, L, rr;
@@ -180,7 +180,7 @@ struct ReplyOut {
         const uint32_t y = (uint32_t)(poly / (2 * L)), comp = (uint32_t)((poly / L) % 2);
         const double p = dp.p[l], pinv = dp.pinv[l];
         const uint64_t q = dp.q[l];
-        const int64_t *ey = e + (((size_t)y * 2 + comp) << logn);
+        const int8_t *ey = e + (((size_t)y * 2 + comp) << logn);
         const int n = 1 << logn;
         if (comp == 1) {
             uint64_t *dst = c1 + (((size_t)y * L + l) << logn);
@@ -250,8 +250,9 @@ int fused_tail(const pimm_plan *plan, const uint64_t *pk, const Key &key, uint32
     double *ah = ws + (size_t)f.I * 2 * L * N;
     double *pkh = ah + (size_t)f.O * 2 * L * N;
     double *uh = pkh + 2 * L * N;
-    int64_t *u = (int64_t *)(uh + (size_t)f.O * L * N);
-    int64_t *e = u + (size_t)f.O * N;
+    // u [O][N] and e [O][2][N], one byte each, at the start of their int64-sized regions.
+    int8_t *u = (int8_t *)(uh + (size_t)f.O * L * N);
+    int8_t *e = u + (size_t)f.O * N * 8;
     int rc = PIMM_OK;
     if (rr) {
         rc = launch_samples(c, key, op_id, rerand_jobs(f.O, N, u, e), s);
@@ -452,8 +453,8 @@ int pimm_mask_share(const pimm_plan *plan, const uint64_t *pk, const uint8_t see
             return set_error(PIMM_E_WORKSPACE, "pimm_mask_share: workspace too small");
         double *pkh = (double *)ws;
         double *uh = pkh + 2 * L * N;
-        int64_t *u = (int64_t *)(uh + (size_t)f.O * L * N);
-        int64_t *e = u + (size_t)f.O * N;
+        int8_t *u = (int8_t *)(uh + (size_t)f.O * L * N);
+        int8_t *e = u + (size_t)f.O * N * 8;
         rc = launch_samples(c, key, op_id, rerand_jobs(f.O, N, u, e), s);
         // pk^ and u^ in one launch: they are adjacent in the workspace.
         if (!rc)
