@@ -632,6 +632,38 @@ def bench_pareto(args):
                         "swept", "points": points, "choice_by_link": choice}
 
 
+def bench_select(args):
+    """Protocol-level plan selection as the library does it (pimm_plan_select): for each product
+    of the BERT-base layer at seq --seq and each link speed of --link-gbps, the block area among
+    --pareto-d (0 = the fewest-wire plan) that minimises the measured server step plus the time
+    the upload and the reply take on the link."""
+    import torch
+
+    from paper_2305_18396_amd import pimm, workloads
+
+    ctx = pimm.Context(4096, 2, 37, 12, rerandomize=True, device=0)
+    ops = workloads.bert_base_layer(args.seq)
+    out = {"workload": f"BERT-base-shaped layer, seq {args.seq}, N=4096, 2 primes; block area "
+                       "chosen per product and link speed by pimm_plan_select",
+           "candidates": args.pareto_d, "links": {}}
+    for gbps in args.link_gbps:
+        row = {"choice": [], "server_ms": [], "wire_bytes": [], "total_ms": 0.0}
+        for wl in ops:
+            n, r, m = wl.shape
+            best, ms, wire = pimm.plan_select(ctx, n, r, m, pimm.to_device_u64(wl.W), gbps * 1e9,
+                                              args.pareto_d, reps=2)
+            i = args.pareto_d.index(best)
+            row["choice"].append(best)
+            row["server_ms"].append(ms)
+            row["wire_bytes"].append(wire)
+            row["total_ms"] += ms[i] + wire[i] * 8 / (gbps * 1e9) * 1e3
+        log(f"select at {gbps} Gbit/s: block areas {row['choice']} "
+            f"(step + wire {row['total_ms']:.2f} ms)")
+        out["links"][f"{gbps:g}_Gbit_per_s"] = row
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_attention(args):
     """Attention cross terms of one BERT-base layer at seq `--seq` (Eq. 2): per head (12, head
     dimension 64) the score terms Q0 K1^T and K0 Q1^T (seq x 64 x seq) and the value terms A0 V1
@@ -1072,7 +1104,7 @@ def main():
                     help="after the timed steps, copy a buffer of this many MiB device to device "
                          "(a known-size reference for hardware byte counters)")
     ap.add_argument("--workload", choices=["default", "layer", "batch", "serve", "peak", "stack",
-                                           "pareto", "attention"],
+                                           "pareto", "attention", "select"],
                     default="default",
                     help="default: the BERT-large stack (headline) with the BERT-base layer and "
                          "the batched-versus-plain comparison as extra keys")
@@ -1086,6 +1118,9 @@ def main():
     ap.add_argument("--pareto-d", type=lambda v: [int(x) for x in v.split(",")],
                     default=[0, 64, 128, 256, 1024],
                     help="block areas of the pareto workload (0: the fewest-wire plan)")
+    ap.add_argument("--link-gbps", type=lambda v: [float(x) for x in v.split(",")],
+                    default=[1, 10, 100, 400, 1600],
+                    help="select: link speeds in Gbit/s")
     ap.add_argument("--att-streams", type=int, default=8,
                     help="streams per phase of the attention workload")
     ap.add_argument("--layer-d", type=int, default=0,
@@ -1131,6 +1166,11 @@ def main():
         return
     if args.workload == "pareto":
         print(json.dumps({"metric": METRIC, "pareto": bench_pareto(args)}), flush=True)
+        return
+    if args.workload == "select":
+        if args.pareto_d == [0, 64, 128, 256, 1024]:
+            args.pareto_d = [0, 64, 128, 256]
+        print(json.dumps({"metric": METRIC, "select": bench_select(args)}), flush=True)
         return
 
     if args.workload == "layer":

@@ -158,10 +158,29 @@ int pimm_plan_query(const pimm_plan *plan, pimm_plan_info *info);
  * 8x2, 16x2, 2x4, 4x4, 8x4, 2x8, 4x8), so that a weight word it loads serves mac_cols column
  * blocks (a ragged last column tile runs as narrower tiles);
  * the (tile, inner block) iterations are divided evenly over a grid of `waves`
- * (1, 2, 4) times the workgroups the device holds at once.  Any schedule gives
- * the same bytes. */
+ * (1, 2, 4) times the workgroups the device holds at once.
+ * (0, 0, 0) selects the matrix-core product instead: exact int8 products of signed 8-bit
+ * digits of the residues on the matrix instructions, for plans with R <= 64 inner blocks
+ * and K >= 8 column blocks (PIMM_E_UNSUPPORTED otherwise) and weight caches made for such
+ * a plan (they then also hold the digit form; pimm_matmul refuses the schedule with
+ * PIMM_E_UNSUPPORTED on a cache without it).  Any schedule gives the same bytes. */
 int pimm_plan_set_tuning(pimm_plan *plan, int mac_rows, int mac_cols, int waves);
 int pimm_plan_get_tuning(const pimm_plan *plan, int *mac_rows, int *mac_cols, int *waves);
+/* Protocol-level choice of the block split (section 3.1.1 leaves it open: larger
+ * matrices are split into blocks).  For each candidate block area d_candidates[i]
+ * (0 = the fewest-wire plan, otherwise mb*rb = d as pimm_plan_create's d_fix) the
+ * call builds the plan and a weight cache of W ([r][m] signed fixed point, device),
+ * autotunes the product, and times the server's part of Algorithm 1 (pimm_matmul_share:
+ * input transforms, slot-wise products, re-randomisation, mask, sparse reply) on random
+ * ciphertexts with HIP events on `stream` (`reps` timed runs after one untimed run).
+ * It writes the measured milliseconds to server_ms[i] and the bytes on the wire (client
+ * upload of whole ciphertexts + sparse reply) to wire_bytes[i] (either may be NULL), and
+ * the candidate minimising server_ms + wire_bytes * 8 / link_bits_per_s to *d_best.
+ * Allocates and frees device memory for each candidate (not for capture or tight loops);
+ * synchronises `stream`. */
+int pimm_plan_select(pimm_ctx *ctx, uint32_t n, uint32_t r, uint32_t m, const int64_t *W,
+                     double link_bits_per_s, const uint32_t *d_candidates, uint32_t count, int reps,
+                     void *stream, uint32_t *d_best, double *server_ms, uint64_t *wire_bytes);
 /* Time every (mac_rows, mac_cols, waves) on these buffers with HIP events on `stream`
  * (`reps` timed runs each) and keep the fastest on the plan; best_ms may be NULL. */
 int pimm_plan_autotune(pimm_plan *plan, const pimm_weights *w, const uint64_t *ct, uint64_t *acc,

@@ -33,7 +33,7 @@ EXPORTS = [
     "pimm_ctx_create", "pimm_ctx_destroy", "pimm_ctx_primes", "pimm_ctx_cdt",
     "pimm_params_primes", "pimm_cdt", "pimm_plan_rule", "pimm_noise_ok",
     "pimm_plan_create", "pimm_plan_destroy", "pimm_plan_query", "pimm_plan_set_tuning",
-    "pimm_plan_get_tuning", "pimm_plan_autotune", "pimm_batch_autotune",
+    "pimm_plan_get_tuning", "pimm_plan_autotune", "pimm_plan_select", "pimm_batch_autotune",
     "pimm_keygen", "pimm_sk_destroy", "pimm_encode_input", "pimm_encrypt", "pimm_decrypt",
     "pimm_weights_create", "pimm_weights_destroy", "pimm_matmul", "pimm_mask_share",
     "pimm_matmul_share", "pimm_matmul_share_noalloc",
@@ -107,6 +107,7 @@ def lib():
         "pimm_plan_set_tuning": [vp, i32, i32, i32],
         "pimm_plan_get_tuning": [vp, vp, vp],
         "pimm_plan_autotune": [vp, vp, vp, vp, vp, ctypes.c_size_t, i32, vp, vp],
+        "pimm_plan_select": [vp, u32, u32, u32, vp, ctypes.c_double, vp, u32, i32, vp, vp, vp, vp],
         "pimm_batch_autotune": [vp, vp, ctypes.c_size_t, i32, vp, vp],
         "pimm_keygen": [vp, vp, vp, vp, vp],
         "pimm_sk_destroy": [vp],
@@ -324,6 +325,22 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def plan_select(ctx: Context, n: int, r: int, m: int, W: torch.Tensor, link_bits_per_s: float,
+                d_candidates, reps: int = 2, stream=None):
+    """pimm_plan_select: time the server step for each candidate block area (0 = fewest-wire plan)
+    and pick the one minimising server time + wire time at this link speed.
+    -> (best d, [server ms per candidate], [wire bytes per candidate])."""
+    assert W.dtype == torch.int64 and tuple(W.shape) == (r, m) and W.is_contiguous()
+    cnt = len(d_candidates)
+    ds = (ctypes.c_uint32 * cnt)(*d_candidates)
+    ms = (ctypes.c_double * cnt)()
+    wire = (ctypes.c_uint64 * cnt)()
+    best = ctypes.c_uint32()
+    _check(lib().pimm_plan_select(ctx.h, n, r, m, _ptr(W), float(link_bits_per_s), ds, cnt, reps,
+                                  _stream(stream), ctypes.byref(best), ms, wire))
+    return best.value, list(ms), list(wire)
 
 
 class SecretKey:
