@@ -229,8 +229,8 @@ def bench_serve(args):
     """Served stream: Poisson arrivals of requests with prompt length log-uniform in [32, 512],
     each a 12-layer BERT-base-shaped stack of 4 products (block area d_fix), keys and
     ciphertexts resident on the device, admission by an HBM budget.  Sweeps the arrival rate on
-    a geometric grid until p99 latency saturates; also replays the lowest-load trace with one
-    request at a time."""
+    a geometric grid until p99 latency saturates; at every rate the same trace also runs in the
+    plain form, one request at a time in arrival order."""
     import numpy as np
     import torch
 
@@ -265,26 +265,33 @@ def bench_serve(args):
                 "p99_ms": float(np.percentile(lat, 99)), "int_mac_per_s": macs / wall,
                 "wall_s": wall, "max_active": max_active}
 
+    def both(rate):
+        """Continuous batching and the plain form (one request at a time, in arrival order) on
+        the same trace."""
+        cb = run(rate, args.serve_requests, args.serve_max_active)
+        plain = run(rate, args.serve_requests, 1)
+        log(f"serve rate {rate:.2f}/s: batched p50/p99 {cb['p50_ms']:.1f}/{cb['p99_ms']:.1f} ms "
+            f"{cb['int_mac_per_s'] / 1e9:.1f} G MAC/s; plain p50/p99 {plain['p50_ms']:.1f}/"
+            f"{plain['p99_ms']:.1f} ms {plain['int_mac_per_s'] / 1e9:.1f} G MAC/s")
+        return {"rate_per_s": rate, "batched": cb, "plain": plain}
+
     sweep = []
+    workload = (f"Poisson stream, prompt length log-uniform in [32, 512], {args.layers}-layer "
+                f"BERT-base linear stack, N=4096, 2 primes, block area {args.d_fix}")
     if args.serve_rates:
-        # Explicit rates only (no saturation search, no one-at-a-time replay).
+        # Explicit rates only (no saturation search).
         for rate in args.serve_rates:
-            sweep.append(run(rate, args.serve_requests, args.serve_max_active))
-        return {"product_tile": list(args.serve_tile), "sweep": sweep}
+            sweep.append(both(rate))
+        return {"product_tile": list(args.serve_tile), "workload": workload, "sweep": sweep}
     rate = args.serve_rate0
     while True:
-        r = run(rate, args.serve_requests, args.serve_max_active)
-        log(f"serve rate {rate:.2f}/s: p50 {r['p50_ms']:.1f} ms p99 {r['p99_ms']:.1f} ms "
-            f"{r['int_mac_per_s'] / 1e9:.1f} G MAC/s")
+        r = both(rate)
         sweep.append(r)
-        if len(sweep) >= 2 and (r["p99_ms"] > 4 * sweep[0]["p99_ms"] or len(sweep) >= 8):
+        if len(sweep) >= 2 and (r["batched"]["p99_ms"] > 4 * sweep[0]["batched"]["p99_ms"]
+                                or len(sweep) >= 6):
             break
         rate *= 2
-    one = run(sweep[0]["rate_per_s"], args.serve_requests, 1)
-    return {"product_tile": list(args.serve_tile),
-            "workload": f"Poisson stream, prompt length log-uniform in [32, 512], {args.layers}-layer "
-                        f"BERT-base linear stack, N=4096, 2 primes, block area {args.d_fix}",
-            "sweep": sweep, "one_at_a_time": one}
+    return {"product_tile": list(args.serve_tile), "workload": workload, "sweep": sweep}
 
 
 FP64_ISSUE_PER_S = 39.3e12  # FP64 VALU instruction issues per second (78.6 TFLOP/s counts an FMA as 2)
@@ -1114,7 +1121,7 @@ def main():
                     help="default workload: skip the batched-versus-plain comparison")
     ap.add_argument("--stack-layers", type=int, default=24)
     ap.add_argument("--serve-tile", type=lambda v: tuple(int(x) for x in v.split(",")),
-                    default=(8, 4), help="serve: product tile 'rows,cols' of the batched launch")
+                    default=(4, 8), help="serve: product tile 'rows,cols' of the batched launch")
     ap.add_argument("--pareto-d", type=lambda v: [int(x) for x in v.split(",")],
                     default=[0, 64, 128, 256, 1024],
                     help="block areas of the pareto workload (0: the fewest-wire plan)")
@@ -1133,7 +1140,7 @@ def main():
     ap.add_argument("--d-fix", type=int, default=32)
     ap.add_argument("--layers", type=int, default=12)
     ap.add_argument("--serve-budget-gb", type=float, default=48.0)
-    ap.add_argument("--serve-requests", type=int, default=32)
+    ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-max-active", type=int, default=32)
     ap.add_argument("--serve-rate0", type=float, default=4.0)
     ap.add_argument("--serve-rates", type=lambda v: [float(x) for x in v.split(",")], default=None,

@@ -409,9 +409,12 @@ int pimm_serve_destroy(pimm_server *server);
 /* Device bytes one request of length seq holds while it is in flight. */
 int pimm_serve_footprint(const pimm_server *server, uint32_t seq, uint64_t *bytes);
 /* Replay `count` requests in real time on `stream`: admit each at or after its
- * arrival when the budget has room (arrival order), run every admitted request's
- * next product at each tick, all of a tick's products in one batched launch, and
- * return when every request is done.  results[i] belongs to reqs[i]. */
+ * arrival when the budget has room (arrival order); at each tick run the step (layer,
+ * op) of the oldest admitted request for every admitted request at that step, their
+ * products in one batched launch that reads the step's weight cache once (a lone
+ * request takes the plain fused call); return when every request is done.  Requests
+ * admitted behind a running one gather at step 0 and then run as one cohort.
+ * results[i] belongs to reqs[i]. */
 int pimm_serve_run(pimm_server *server, const pimm_request *reqs, uint32_t count,
                    pimm_request_result *results, void *stream);
 

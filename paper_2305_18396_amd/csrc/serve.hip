@@ -12,15 +12,19 @@
 //   1. admits waiting requests in arrival order while the HBM budget has room
 //      for the request's buffers (key, ciphertexts, reply, shares and scratch,
 //      sized for its largest product) and fewer than max_active run;
-//   2. for every admitted request runs its next product: client share, encode,
-//      encrypt; one batched pass of forward transforms and slot-wise products
-//      over all requests (pimm_batch machinery, stopping at acc^); then per
-//      request the fused server tail (re-randomisation, inverse transform with
-//      the reply epilogue, mask) and decryption;
+//   2. takes the step (layer, op) of the oldest admitted request and runs it for
+//      every admitted request at that step: client share, encode, encrypt; one
+//      batched pass of forward transforms and slot-wise products over them
+//      (pimm_batch machinery, stopping at acc^), whose products share that step's
+//      weight cache and so read it once; then per request the fused server tail
+//      (re-randomisation, inverse transform with the reply epilogue, mask) and
+//      decryption.  A lone request at that step takes the plain fused call.
+//      Requests at other steps wait: the oldest request never does, and requests
+//      admitted behind it gather at step 0 and run as one cohort once it is done;
 //   3. waits for the device, then retires requests whose last product is done.
 // A request's key material and buffers stay in device memory from admission to
-// completion.  Requests admitted while others are running join the next tick,
-// so their work shares the batched launches with the running ones.
+// completion.  Requests admitted while others are running are admitted at once
+// (memory permitting) and share the batched launches of every tick at their step.
 //
 // Every product's two shares are folded into two order-independent checksums
 // per request: one over the (client, server) share pairs and one over their
@@ -331,6 +335,12 @@ int pimm_serve_run(pimm_server *sv, const pimm_request *reqs, uint32_t count,
                     delete a;
                     return fail(rc);
                 }
+                // Schedule of the plain fused call a lone request takes: one row per weight
+                // word per column block when there are few column blocks.
+                const uint32_t K = a->plans[o].info.K;
+                a->plans[o].mac_rows = K <= 1 ? 16 : 8;
+                a->plans[o].mac_cols = K <= 1 ? 1 : (K == 2 ? 2 : 4);
+                a->plans[o].waves = 1;
             }
             const Layout lay = layout_for(*sv, a->plans);
             if (lay.total > sv->arena_bytes - sv->counters_bytes) {
@@ -385,14 +395,16 @@ int pimm_serve_run(pimm_server *sv, const pimm_request *reqs, uint32_t count,
             if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(wait));
             continue;
         }
-        // 2. one product of every active request
-        std::vector<pimm_batch_item> items(active.size());
-        sv->batch.fixed_chat.resize(active.size());
-        sv->batch.fixed_ahat.resize(active.size());
-        for (size_t i = 0; i < active.size(); ++i) {
-            Active *a = active[i];
-            const uint32_t o = a->step % sv->cfg.ops;
-            const pimm_plan *plan = &a->plans[o];
+        // 2. one product for every active request at the oldest request's step: they
+        // share that step's weight cache, so the batched pass reads it once for all of them.
+        // Requests at other steps wait for a later tick (the oldest request never waits).
+        const uint32_t step_now = active.front()->step;
+        std::vector<Active *> tick;
+        for (Active *a : active)
+            if (a->step == step_now) tick.push_back(a);
+        const uint32_t o_now = step_now % sv->cfg.ops;
+        for (Active *a : tick) {
+            const pimm_plan *plan = &a->plans[o_now];
             const pimm_plan_info &f = plan->info;
             const Key ck = make_key(a->req.client_seed);
             const uint32_t cnt = f.n * f.r;
@@ -403,27 +415,44 @@ int pimm_serve_run(pimm_server *sv, const pimm_request *reqs, uint32_t count,
             if (!rc) rc = pimm_encrypt(plan, &a->sk, a->req.client_seed, a->step, a->pt, a->ct, a->ws,
                                        a->ws_bytes, s);
             if (rc) return fail(rc);
-            // No accumulator in coefficient form: the batched pass stops after the
-            // products and each request's fused tail reads acc^ from its workspace.
-            items[i] = pimm_batch_item{plan, sv->weights[a->step], a->ct, nullptr};
-            // The product's NTT forms live in the request's workspace (as pimm_matmul lays them).
-            const uint64_t ws_off = (uint64_t)((uint8_t *)a->ws - sv->arena_base) / 8;
-            sv->batch.fixed_chat[i] = ws_off;
-            sv->batch.fixed_ahat[i] = ws_off + (uint64_t)f.I * 2 * L * N;
         }
-        sv->batch.items = items;
-        rc = batch_rebuild(&sv->batch, true, s);
-        if (!rc && sv->batch.ws_bytes > sv->counters_bytes)
-            rc = set_error(PIMM_E_ARG, "serve: too many dependency counters for the reserve");
-        if (!rc) rc = batch_run(&sv->batch, sv->arena_base, s, false);
-        if (rc) return fail(rc);
-        for (size_t i = 0; i < active.size(); ++i) {
-            Active *a = active[i];
-            const pimm_plan *plan = &a->plans[a->step % sv->cfg.ops];
+        if (tick.size() == 1) {
+            // A lone request takes the plain fused server call (stream-K product).
+            Active *a = tick[0];
+            rc = pimm_matmul_share(&a->plans[o_now], sv->weights[a->step], a->pk, a->req.server_seed,
+                                   a->step, a->ct, a->c1, a->c0s, a->y1, a->ws, a->ws_bytes, s);
+            if (rc) return fail(rc);
+        } else {
+            std::vector<pimm_batch_item> items(tick.size());
+            sv->batch.fixed_chat.resize(tick.size());
+            sv->batch.fixed_ahat.resize(tick.size());
+            for (size_t i = 0; i < tick.size(); ++i) {
+                Active *a = tick[i];
+                const pimm_plan_info &f = a->plans[o_now].info;
+                // No accumulator in coefficient form: the batched pass stops after the
+                // products and each request's fused tail reads acc^ from its workspace.
+                items[i] = pimm_batch_item{&a->plans[o_now], sv->weights[a->step], a->ct, nullptr};
+                // The product's NTT forms live in the request's workspace (as pimm_matmul lays them).
+                const uint64_t ws_off = (uint64_t)((uint8_t *)a->ws - sv->arena_base) / 8;
+                sv->batch.fixed_chat[i] = ws_off;
+                sv->batch.fixed_ahat[i] = ws_off + (uint64_t)f.I * 2 * L * N;
+            }
+            sv->batch.items = items;
+            rc = batch_rebuild(&sv->batch, true, s);
+            if (!rc && sv->batch.ws_bytes > sv->counters_bytes)
+                rc = set_error(PIMM_E_ARG, "serve: too many dependency counters for the reserve");
+            if (!rc) rc = batch_run(&sv->batch, sv->arena_base, s, false);
+            if (rc) return fail(rc);
+            for (Active *a : tick) {
+                rc = fused_tail(&a->plans[o_now], a->pk, make_key(a->req.server_seed), a->step, a->ws,
+                                a->c1, a->c0s, a->y1, false, s);
+                if (rc) return fail(rc);
+            }
+        }
+        for (Active *a : tick) {
+            const pimm_plan *plan = &a->plans[o_now];
             const pimm_plan_info &f = plan->info;
-            rc = fused_tail(plan, a->pk, make_key(a->req.server_seed), a->step, a->ws, a->c1, a->c0s,
-                            a->y1, false, s);
-            if (!rc) rc = pimm_decrypt(plan, &a->sk, a->c1, a->c0s, a->y0, a->ws, a->ws_bytes, s);
+            rc = pimm_decrypt(plan, &a->sk, a->c1, a->c0s, a->y0, a->ws, a->ws_bytes, s);
             if (!rc) {
                 hipLaunchKernelGGL(k_checksum, dim3(64), dim3(256), 0, s, a->y0, a->y1, f.n * f.m,
                                    a->step, c.dp.ell, a->cs);
@@ -435,14 +464,14 @@ int pimm_serve_run(pimm_server *sv, const pimm_request *reqs, uint32_t count,
         // 3. wait, then retire finished requests
         rc = check_hip(hipStreamSynchronize(s), "serve tick synchronize");
         if (rc) return fail(rc);
-        if (sv->batch.schedule == kPersistent) {
+        if (tick.size() > 1 && sv->batch.schedule == kPersistent) {
             rc = pimm_batch_status(&sv->batch, sv->arena_base, s);
             if (rc) return fail(rc);
         }
         now = now_s(t0);
+        for (Active *a : tick) a->step += 1;
         std::vector<Active *> still;
         for (Active *a : active) {
-            a->step += 1;
             if (a->step < steps) {
                 still.push_back(a);
                 continue;
