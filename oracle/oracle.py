@@ -16,7 +16,9 @@ design notes): primes are the L largest primes below 2^50 congruent to 1 mod
 2N; encryption is symmetric; the plaintext A is lifted centred; the reply is
 re-randomised by a public-key encryption of zero when requested; the mask is
 subtracted as Delta * s; the decrypt rounding is round-half-up (ties cannot
-occur since t = 2^l and q is odd).
+occur since t = 2^l and q is odd).  Modulus switching of the reply (an
+optional wire format, not in the paper) rounds c q'/q to the nearest integer,
+q' the product of the first L - 1 primes.
 
 Parity unpinned: the block-plan rules (plan_comm, plan_fix) and the stream
 layout's choices (tag numbers, which nonce word holds what).  They are spec
@@ -567,3 +569,58 @@ def fc_complete(params: Params, X1: np.ndarray, W: np.ndarray, bias, Y1: np.ndar
     if bias is not None:
         out = out + np.asarray(bias, dtype=np.int64).astype(np.uint64)[None, :]
     return out & mask
+
+
+# ---------------------------------------------------------------------------
+# Modulus switching of the reply (a wire-format variant of the sparse reply of
+# section 3.1.3: fewer residues per coefficient on the wire; not in the paper)
+# ---------------------------------------------------------------------------
+
+def switched_params(params: Params) -> Params:
+    """Parameters of the reply after modulus switching: the first L - 1 primes,
+    q' = q_0 ... q_{L-2} (the last prime is dropped)."""
+    assert params.L >= 2
+    return Params(params.N, params.L - 1, params.ell, params.frac_bits, params.rerandomize,
+                  q=list(params.q[:-1]), psi=list(params.psi[:-1]), cdt=list(params.cdt))
+
+
+def mod_switch(params: Params, x: np.ndarray) -> np.ndarray:
+    """Modulus switching from q to q' = q / q_{L-1}, coefficient by coefficient, by its
+    definition: each coefficient c in [0, q) (reconstructed from its L residues by the CRT,
+    in exact integers) becomes round(c q' / q) = round(c / q_{L-1}) mod q' (never a tie:
+    q_{L-1} is odd).  x: [..., L, count] residues -> [..., L-1, count] residues mod the
+    first L-1 primes."""
+    x = np.asarray(x, dtype=np.uint64)
+    L = params.L
+    assert x.shape[-2] == L
+    Q = params.Q
+    qd = params.q[-1]
+    qs = Q // qd
+    coef = [(Q // q) * pow(Q // q, -1, q) for q in params.q]
+    lead = x.shape[:-2]
+    count = x.shape[-1]
+    flat = x.reshape(-1, L, count)
+    out = np.zeros((flat.shape[0], L - 1, count), dtype=np.uint64)
+    for o in range(flat.shape[0]):
+        for j in range(count):
+            c = sum(int(flat[o, l, j]) * coef[l] for l in range(L)) % Q
+            cp = ((2 * c + qd) // (2 * qd)) % qs  # nearest integer to c / q_{L-1}
+            for l in range(L - 1):
+                out[o, l, j] = cp % params.q[l]
+    return out.reshape(*lead, L - 1, count)
+
+
+def noise_bound_switched(params: Params, plan: Plan, wmax: int) -> int:
+    """Worst-case decryption noise of a switched reply coefficient: the reply's noise scaled
+    by q'/q (rounded up) plus the rounding of c0 and of the N terms of c1 s (each |e| <= 1/2,
+    |s_j| <= 1), i.e. ceil(E q'/q) + (N + 1) / 2 rounded up."""
+    E = noise_bound(params, plan, wmax)
+    qs = params.Q // params.q[-1]
+    return -(-E * qs // params.Q) + (params.N + 2) // 2
+
+
+def switch_ok(params: Params, plan: Plan, wmax: int) -> bool:
+    """A switched reply decrypts to the same share when 2 t (E' + 1) < q' (the message's
+    scale q' Delta / q differs from q'/t by less than one unit per t)."""
+    qs = params.Q // params.q[-1]
+    return 2 * params.t * (noise_bound_switched(params, plan, wmax) + 1) < qs
