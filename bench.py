@@ -391,8 +391,11 @@ def bench_stack(args):
             ct=torch.empty((fi.I, 2, L, N), dtype=torch.int64, device=dev),
             c1=torch.empty((fi.O, L, N), dtype=torch.int64, device=dev),
             c0s=torch.empty((fi.O, L, fi.mb * fi.nb), dtype=torch.int64, device=dev),
+            c1s=torch.empty((fi.O, L - 1, N), dtype=torch.int64, device=dev),
+            c0ss=torch.empty((fi.O, L - 1, fi.mb * fi.nb), dtype=torch.int64, device=dev),
             y0=torch.empty((seq, m), dtype=torch.int64, device=dev),
             y1=torch.empty((seq, m), dtype=torch.int64, device=dev)))
+    switched = args.reply == "switched"
     layers = []
     cache = 0
     t_setup = time.perf_counter()
@@ -433,7 +436,12 @@ def bench_stack(args):
         pimm.encode_input(plan, X, b["pt"])
         pimm.encrypt(plan, sk, cseed, op, b["pt"], b["ct"])
         pimm.matmul_share(plan, w, pk, sseed, op, b["ct"], b["c1"], b["c0s"], b["y1"])
-        pimm.decrypt(plan, sk, b["c1"], b["c0s"], b["y0"])
+        if switched:
+            # The reply crosses the wire with its last prime dropped.
+            pimm.mod_switch(plan, w, b["c1"], b["c0s"], b["c1s"], b["c0ss"])
+            pimm.decrypt_switched(plan, sk, b["c1s"], b["c0ss"], b["y0"])
+        else:
+            pimm.decrypt(plan, sk, b["c1"], b["c0s"], b["y0"])
 
     def step(t, marks=None):
         for k in range(args.stack_layers):
@@ -468,7 +476,8 @@ def bench_stack(args):
     log(f"stack: {el * 1e3:.1f} ms per pass, {useful / el / 1e9:.1f}e9 int-MAC/s")
 
     # Per-class breakdown from one untimed pass with every class recorded.
-    classes = ("mac", "ntt_fwd", "ntt_inv", "sample", "encode", "decode", "mask_extract")
+    classes = ("mac", "ntt_fwd", "ntt_inv", "sample", "encode", "decode", "mask_extract",
+               "mod_switch")
     for kname in classes:
         pimm.profile_read(kname)
     pimm.profile_enable(True)
@@ -548,6 +557,13 @@ def bench_stack(args):
                              "samples": int(len(layer_ms))},
         "product_ms_per_step": mac_ms / args.steps,
         "product_slot_mac_per_s": slot_rate,
+        "reply": ("switched: the last prime dropped before the reply is sent, decrypted with "
+                  f"{L - 1} primes" if switched else f"full: {L} primes"),
+        "wire_bytes_per_step": {
+            "upload": args.stack_layers * sum(p.info.ct_bytes for p in plans),
+            "reply_full": args.stack_layers * sum(p.info.c1_bytes + p.info.c0s_bytes for p in plans),
+            "reply_switched": args.stack_layers * sum(p.info.c1_bytes + p.info.c0s_bytes
+                                                      for p in plans) * (L - 1) // L},
         "kernels_untimed_pass": breakdown,
         "roofline": roofline,
     }
@@ -872,7 +888,8 @@ def bench_layer(args):
     cseed, sseed = workloads.seed("client", 1), workloads.seed("server", 1)
     sk, pk = pimm.keygen(ctx, cseed)
     state = []
-    useful = mac_bytes = slot_macs = butterflies = wire = wire_seeded = cache = 0
+    useful = mac_bytes = slot_macs = butterflies = wire = wire_seeded = wire_switched = cache = 0
+    switched = args.reply == "switched"
     for i, wl in enumerate(ops):
         n, r, m = wl.shape
         plan = pimm.Plan(ctx, n, r, m, d_fix=args.layer_d)
@@ -885,6 +902,8 @@ def bench_layer(args):
             acc=torch.empty((fi.O, 2, L, N), dtype=torch.int64, device=dev),
             c1=torch.empty((fi.O, L, N), dtype=torch.int64, device=dev),
             c0s=torch.empty((fi.O, L, fi.mb * fi.nb), dtype=torch.int64, device=dev),
+            c1s=torch.empty((fi.O, L - 1, N), dtype=torch.int64, device=dev),
+            c0ss=torch.empty((fi.O, L - 1, fi.mb * fi.nb), dtype=torch.int64, device=dev),
             y0=torch.empty((n, m), dtype=torch.int64, device=dev),
             y1=torch.empty((n, m), dtype=torch.int64, device=dev),
             ws=plan.workspace(), op=i)
@@ -906,6 +925,7 @@ def bench_layer(args):
         butterflies += L * (N // 2) * (N.bit_length() - 1) * (2 * fi.I + 2 * fi.O)
         wire += fi.ct_bytes + fi.c1_bytes + fi.c0s_bytes
         wire_seeded += fi.ct_bytes // 2 + 32 + fi.c1_bytes + fi.c0s_bytes
+        wire_switched += fi.ct_bytes + (fi.c1_bytes + fi.c0s_bytes) * (L - 1) // L
         cache += fi.weights_bytes
         log(f"{wl.name}: plan ({fi.mb},{fi.rb},{fi.nb}) I={fi.I} O={fi.O} Wb={fi.Wb} "
             f"weights {fi.weights_bytes / 1e9:.2f} GB")
@@ -918,13 +938,18 @@ def bench_layer(args):
             pimm.encrypt(p, sk, cseed, k * 8 + st["op"], st["pt"], st["ct"], st["ws"])
             pimm.matmul_share(p, st["w"], pk, sseed, k * 8 + st["op"], st["ct"], st["c1"],
                               st["c0s"], st["y1"], st["ws"])
-            pimm.decrypt(p, sk, st["c1"], st["c0s"], st["y0"], st["ws"])
+            if switched:
+                pimm.mod_switch(p, st["w"], st["c1"], st["c0s"], st["c1s"], st["c0ss"])
+                pimm.decrypt_switched(p, sk, st["c1s"], st["c0ss"], st["y0"], st["ws"])
+            else:
+                pimm.decrypt(p, sk, st["c1"], st["c0s"], st["y0"], st["ws"])
 
     for k in range(args.warmup):
         step(k)
     torch.cuda.synchronize()
     log(f"warmup done ({args.warmup} steps)")
-    classes = ("mac", "ntt_fwd", "ntt_inv", "sample", "encode", "decode", "mask_extract")
+    classes = ("mac", "ntt_fwd", "ntt_inv", "sample", "encode", "decode", "mask_extract",
+               "mod_switch")
     for kname in classes:
         pimm.profile_read(kname)
     # Timed region: HIP events bracket the product launches only (an event recorded
@@ -1079,6 +1104,9 @@ def bench_layer(args):
         "fc_completion_ms": fc_s * 1e3,
         "fc_completion_int_mac_per_s": useful / fc_s,
         "wire_bytes_per_step_seeded_upload": wire_seeded,
+        "reply": ("switched: the last prime dropped before the reply is sent, decrypted with "
+                  f"{L - 1} prime" if switched else f"full: {L} primes"),
+        "wire_bytes_per_step_switched_reply": wire_switched,
         "seeded_upload_expand_ms": expand_s * 1e3,
         "slot_mac_per_s": slot_macs * args.steps / elapsed,
         "server_ntt_butterflies_per_s": butterflies * args.steps / elapsed,
@@ -1120,6 +1148,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true",
                     help="default workload: skip the batched-versus-plain comparison")
     ap.add_argument("--stack-layers", type=int, default=24)
+    ap.add_argument("--reply", choices=["switched", "full"], default="switched",
+                    help="stack and layer: send the reply with its last prime dropped (modulus "
+                         "switching; the same shares) or with all primes")
     ap.add_argument("--serve-tile", type=lambda v: tuple(int(x) for x in v.split(",")),
                     default=(4, 8), help="serve: product tile 'rows,cols' of the batched launch")
     ap.add_argument("--pareto-d", type=lambda v: [int(x) for x in v.split(",")],

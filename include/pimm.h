@@ -137,6 +137,12 @@ int pimm_plan_rule(const pimm_params *params, uint32_t n, uint32_t r, uint32_t m
  * coefficient is E = R*D*wmax*19 + (q mod t)(r*wmax + 1) [+ 2*N*19 + 19 with
  * re-randomisation], D = mb*rb, and decryption is correct when 2 t (E + (q mod t)) < q. */
 int pimm_noise_ok(const pimm_params *params, const pimm_plan_info *info, uint64_t wmax);
+/* 1 if a reply made with weights of max |W| = wmax still decrypts to the same
+ * share after pimm_mod_switch, 0 if not, <0 on error (PIMM_E_UNSUPPORTED for
+ * L = 1).  With E the bound above and q' = q / q_{L-1}: the switched noise is at
+ * most E' = ceil(E / q_{L-1}) + (N + 2) / 2 (the scaled noise plus the rounding of
+ * c0 and of the N terms of c1 s), and the rule is 2 t (E' + 1) < q'. */
+int pimm_switch_ok(const pimm_params *params, const pimm_plan_info *info, uint64_t wmax);
 
 /* ---- plan ------------------------------------------------------------------ */
 
@@ -233,6 +239,15 @@ int pimm_ct_expand(const pimm_plan *plan, const uint8_t a_seed[32], uint32_t op_
 int pimm_decrypt(const pimm_plan *plan, const pimm_sk *sk, const uint64_t *c1, const uint64_t *c0s,
                  uint64_t *client_share, void *ws, size_t ws_bytes, void *stream);
 
+/* Decryption of a reply after pimm_mod_switch: as pimm_decrypt with the first
+ * L - 1 primes, q' = q_0 ... q_{L-2} and the rounding v = floor((t x + floor(q'/2))
+ * / q') mod t.  c1s: [O][L-1][N], c0ss: [O][L-1][mb*nb] (device).  The workspace
+ * of pimm_decrypt suffices (this call needs (L-1)/L of it).  PIMM_E_UNSUPPORTED
+ * for L = 1. */
+int pimm_decrypt_switched(const pimm_plan *plan, const pimm_sk *sk, const uint64_t *c1s,
+                          const uint64_t *c0ss, uint64_t *client_share, void *ws, size_t ws_bytes,
+                          void *stream);
+
 /* ---- server ---------------------------------------------------------------- */
 
 /* Algorithm 1 step 1, server side, plus the transform the product needs:
@@ -283,6 +298,20 @@ int pimm_matmul_share(const pimm_plan *plan, const pimm_weights *w, const uint64
                       const uint8_t seed[32], uint32_t op_id, const uint64_t *ct, uint64_t *c1,
                       uint64_t *c0s, uint64_t *server_share, void *ws, size_t ws_bytes,
                       void *stream);
+
+/* Modulus switching of the reply before it is sent, a wire-format variant of
+ * the sparse reply (section 3.1.3): every coefficient c of c1 and of the decoded
+ * c0 (residues mod q_0 .. q_{L-1}) becomes round(c / q_{L-1}) as residues mod the
+ * first L - 1 primes, so the reply crosses the wire with (L-1)/L of its bytes.
+ * c1: [O][L][N], c0s: [O][L][mb*nb] as pimm_mask_share / pimm_matmul_share wrote
+ * them; c1_out: [O][L-1][N], c0s_out: [O][L-1][mb*nb] (device; the outputs may
+ * not overlap the inputs or each other: PIMM_E_ARG).  w: the weights the reply
+ * was made with (their bound decides the noise): PIMM_E_NOISE when
+ * pimm_switch_ok fails for them, PIMM_E_UNSUPPORTED for L = 1.  One launch; no
+ * allocation, no synchronisation.  The client decrypts with
+ * pimm_decrypt_switched. */
+int pimm_mod_switch(const pimm_plan *plan, const pimm_weights *w, const uint64_t *c1,
+                    const uint64_t *c0s, uint64_t *c1_out, uint64_t *c0s_out, void *stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture,
  * serving loops that must not call the allocator, harnesses that forbid it):
@@ -439,7 +468,7 @@ int pimm_sample_poly(pimm_ctx *ctx, int kind, const uint8_t seed[32], uint32_t t
 /* on != 0: from now on bracket every kernel launch of the library with two HIP
  * events recorded on the launch's stream, filed under the kernel class
  * ("ntt_fwd", "ntt_inv", "mac", "sample", "encode", "decode", "mask_extract",
- * "fused").  Each recorded event delays the next dependent launch by a few
+ * "fused", "fc", "mod_switch").  Each recorded event delays the next dependent launch by a few
  * microseconds, so a timed region should record only the classes it reports. */
 int pimm_profile_enable(int on);
 /* Restrict recording to a comma-separated list of kernel classes (NULL or "":

@@ -15,7 +15,8 @@ LIB = os.path.join(HERE, "libpimm.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 HIP_SOURCES = ["context.hip", "client.hip", "server.hip", "mac.hip", "batch.hip", "serve.hip",
-               "tune.hip", "profile.hip", "probe.hip", "fc.hip", "noalloc.hip", "mfma.hip", "select.hip"]
+               "tune.hip", "profile.hip", "probe.hip", "fc.hip", "noalloc.hip", "mfma.hip", "select.hip",
+               "switch.hip"]
 HOST_SOURCES = ["cdt.cpp"]
 
 HIPCC_FLAGS = [

@@ -204,6 +204,36 @@ __global__ void k_decode(const uint64_t *c0s, const uint64_t *cs, uint64_t *shar
     share[(size_t)row * f.m + col] = crt_round(res, dp);
 }
 
+// Decryption of a reply under the moduli of `c` (the context's, or the first L - 1
+// primes after modulus switching): c1 to NTT form, times s^, back to coefficients
+// at the decoded positions only, then c0 + c1 s, CRT and rounding per coefficient.
+// Workspace: c1^ [O][L][N] doubles, then c1 s at the decoded positions [O][L][mb*nb].
+int decrypt_reply(const Ctx &c, const pimm_plan_info &f, const pimm_sk *sk, const uint64_t *c1,
+                  const uint64_t *c0s, uint64_t *client_share, void *ws, size_t ws_bytes,
+                  hipStream_t s, const char *who)
+{
+    const size_t N = c.dp.N, L = c.dp.L;
+    const size_t per = (size_t)f.mb * f.nb;
+    const size_t need = (size_t)f.O * L * N * 8 + (size_t)f.O * L * per * 8;
+    if (!ws || ws_bytes < need) return set_error(PIMM_E_WORKSPACE, "%s: workspace too small", who);
+    const int lg = c.dp.logN;
+    double *ch = (double *)ws;
+    uint64_t *cs = (uint64_t *)(ch + (size_t)f.O * L * N);
+    int rc = launch_fwd(c, LoadU64{c1, lg}, StoreSlots{ch, lg}, (int)(f.O * L), s);
+    if (!rc)
+        rc = launch_inv_lds(c, LoadSlotsMul{ch, sk->d_s_hat, lg, (int)L},
+                            DecodedOut{cs, FastDiv::make(f.mb), f.rb, f.nb}, (int)(f.O * L), s);
+    if (!rc) {
+        const size_t total = (size_t)f.O * per;
+        const int threads = 256;
+        ProfScope prof("decode", s);
+        hipLaunchKernelGGL(k_decode, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads),
+                           0, s, c0s, cs, client_share, f, c.dp);
+        rc = check_hip(hipGetLastError(), "decode launch");
+    }
+    return rc;
+}
+
 }  // namespace pimm
 
 using namespace pimm;
@@ -290,30 +320,9 @@ int pimm_decrypt(const pimm_plan *plan, const pimm_sk *sk, const uint64_t *c1, c
 {
     if (!plan || !sk || !c1 || !c0s || !client_share)
         return set_error(PIMM_E_ARG, "pimm_decrypt: NULL argument");
-    const Ctx &c = *plan->ctx;
     if (sk->ctx != plan->ctx) return set_error(PIMM_E_ARG, "pimm_decrypt: key of another context");
-    const pimm_plan_info &f = plan->info;
-    const size_t N = c.params.N, L = c.params.L;
-    const size_t per = (size_t)f.mb * f.nb;
-    const size_t need = (size_t)f.O * L * N * 8 + (size_t)f.O * L * per * 8;
-    if (!ws || ws_bytes < need) return set_error(PIMM_E_WORKSPACE, "pimm_decrypt: workspace too small");
-    hipStream_t s = (hipStream_t)stream;
-    const int lg = c.dp.logN;
-    double *ch = (double *)ws;
-    uint64_t *cs = (uint64_t *)(ch + (size_t)f.O * L * N);
-    int rc = launch_fwd(c, LoadU64{c1, lg}, StoreSlots{ch, lg}, (int)(f.O * L), s);
-    if (!rc)
-        rc = launch_inv_lds(c, LoadSlotsMul{ch, sk->d_s_hat, lg, (int)L},
-                            DecodedOut{cs, FastDiv::make(f.mb), f.rb, f.nb}, (int)(f.O * L), s);
-    if (!rc) {
-        const size_t total = (size_t)f.O * per;
-        const int threads = 256;
-        ProfScope prof("decode", s);
-        hipLaunchKernelGGL(k_decode, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads),
-                           0, s, c0s, cs, client_share, f, c.dp);
-        rc = check_hip(hipGetLastError(), "decode launch");
-    }
-    return rc;
+    return decrypt_reply(*plan->ctx, plan->info, sk, c1, c0s, client_share, ws, ws_bytes,
+                         (hipStream_t)stream, "pimm_decrypt");
 }
 
 }  // extern "C"

@@ -260,6 +260,15 @@ int set_error(int code, const char *fmt, ...);
 int check_hip(hipError_t e, const char *what);
 Key make_key(const uint8_t seed[32]);
 bool noise_ok(const Ctx &c, const pimm_plan_info &f, uint64_t wmax);
+// Modulus switching of the reply (the last prime dropped): whether the switched
+// reply still decrypts to the reply's value, and the parameters of the first L - 1
+// primes with q_{L-1}^{-1} mod q_l (balanced) for l < L - 1.
+bool switch_ok(const Ctx &c, const pimm_plan_info &f, uint64_t wmax);
+void switched_params(const Ctx &c, DevParams &d, double *qd_inv);
+// Decryption of a reply under the moduli of c (client.hip).
+int decrypt_reply(const Ctx &c, const pimm_plan_info &f, const pimm_sk *sk, const uint64_t *c1,
+                  const uint64_t *c0s, uint64_t *client_share, void *ws, size_t ws_bytes,
+                  hipStream_t s, const char *who);
 bool weights_fit(const Weights *w, const Plan *plan);
 // PIMM_OK when the matrix-core product can run this plan on these weights.
 int mfma_ready(const Plan *plan, const Weights *w, const char *who);

@@ -136,6 +136,22 @@ static void limbs_shr(const uint64_t *x, uint64_t *y, int n, int s)
     }
 }
 
+// q = q_0 ... q_{L-1} as limbs, floor(q/2), Delta = floor(q / 2^l) mod q_i and q as a
+// double, for the first L primes of q[].
+static void fill_modulus(DevParams &d, const uint64_t *q, int L, int log2_t)
+{
+    uint64_t Q[kMaxL + 1] = {1, 0, 0, 0, 0};
+    for (int l = 0; l < L; ++l) limbs_mul_small(Q, kMaxL + 1, q[l]);
+    memcpy(d.Q, Q, sizeof Q);
+    limbs_shr(Q, d.halfQ, kMaxL + 1, 1);
+    uint64_t Delta[kMaxL + 1];
+    limbs_shr(Q, Delta, kMaxL + 1, log2_t);
+    for (int l = 0; l < kMaxL; ++l) d.delta[l] = l < L ? limbs_mod_small(Delta, kMaxL + 1, q[l]) : 0;
+    long double qd = 0.0L;
+    for (int i = kMaxL; i >= 0; --i) qd = qd * 18446744073709551616.0L + (long double)Q[i];
+    d.Qd = (double)qd;
+}
+
 // ---- context -----------------------------------------------------------------
 
 static int build_context(const pimm_params &prm, int device, Ctx *c, bool upload)
@@ -188,17 +204,7 @@ static int build_context(const pimm_params &prm, int device, Ctx *c, bool upload
         d.pinv[l] = 1.0 / (double)c->q[l];
         d.n_inv[l] = balanced(h_inv((uint64_t)N, c->q[l]), c->q[l]);
     }
-    // q as limbs, floor(q/2), Delta = floor(q / 2^l) mod q_l.
-    uint64_t Q[kMaxL + 1] = {1, 0, 0, 0, 0};
-    for (int l = 0; l < L; ++l) limbs_mul_small(Q, kMaxL + 1, c->q[l]);
-    memcpy(d.Q, Q, sizeof Q);
-    limbs_shr(Q, d.halfQ, kMaxL + 1, 1);
-    uint64_t Delta[kMaxL + 1];
-    limbs_shr(Q, Delta, kMaxL + 1, (int)prm.log2_t);
-    for (int l = 0; l < L; ++l) d.delta[l] = limbs_mod_small(Delta, kMaxL + 1, c->q[l]);
-    long double qd = 0.0L;
-    for (int i = kMaxL; i >= 0; --i) qd = qd * 18446744073709551616.0L + (long double)Q[i];
-    d.Qd = (double)qd;
+    fill_modulus(d, c->q, L, (int)prm.log2_t);
     // Garner constants for the mixed-radix CRT.
     for (int l = 0; l < L; ++l) {
         uint64_t prod = 1 % c->q[l];
@@ -346,8 +352,7 @@ int plan_rule(const Ctx &c, uint32_t n, uint32_t r, uint32_t m, uint32_t mb, uin
 //   (q mod t)(r*wmax + 1) Delta*t = q - (q mod t): each multiple of t carried by
 //                         the integer product a*b and the mask's wrap past t,
 //   2*N*19 + 19           u*e' + e1 + e2*s of the re-randomisation (if on).
-// Decryption rounds correctly when 2 t (E + (q mod t)) < q.
-bool noise_ok(const Ctx &c, const pimm_plan_info &f, uint64_t wmax)
+static unsigned __int128 noise_bound(const Ctx &c, const pimm_plan_info &f, uint64_t wmax)
 {
     using u128 = unsigned __int128;
     const uint64_t t = 1ull << c.params.log2_t;
@@ -355,8 +360,26 @@ bool noise_ok(const Ctx &c, const pimm_plan_info &f, uint64_t wmax)
     const u128 D = (u128)f.mb * f.rb;
     u128 E = (u128)f.R * D * wmax * kCdtLen + (u128)qt * ((u128)f.r * wmax + 1);
     if (c.params.rerandomize) E += (u128)2 * c.params.N * kCdtLen + kCdtLen;
+    return E;
+}
+
+// lhs < Q for lhs < 2^128 and Q as kMaxL + 1 limbs.
+static bool u128_below(unsigned __int128 lhs, const uint64_t *Q)
+{
+    const uint64_t l[kMaxL + 1] = {(uint64_t)lhs, (uint64_t)(lhs >> 64), 0, 0, 0};
+    for (int i = kMaxL; i >= 0; --i)
+        if (l[i] != Q[i]) return l[i] < Q[i];
+    return false;
+}
+
+// Decryption rounds correctly when 2 t (E + (q mod t)) < q.
+bool noise_ok(const Ctx &c, const pimm_plan_info &f, uint64_t wmax)
+{
+    using u128 = unsigned __int128;
+    const uint64_t t = 1ull << c.params.log2_t;
+    const uint64_t qt = c.dp.Q[0] & (t - 1);
     // lhs = 2 t (E + qt) as limbs; compare with q.
-    const u128 a = E + qt;
+    const u128 a = noise_bound(c, f, wmax) + qt;
     uint64_t lhs[kMaxL + 1] = {0, 0, 0, 0, 0};
     const int sh = (int)c.params.log2_t + 1;  // 3 .. 49
     // a < 2^110, so a << sh < 2^160 spans three limbs.
@@ -368,6 +391,41 @@ bool noise_ok(const Ctx &c, const pimm_plan_info &f, uint64_t wmax)
         if (lhs[i] != c.dp.Q[i]) return lhs[i] < c.dp.Q[i];
     }
     return false;
+}
+
+// Modulus switching of the reply to q' = q / q_{L-1}.  Each coefficient c becomes
+// round(c / q_{L-1}); in c0 + c1 s the noise becomes E q'/q = E / q_{L-1} plus the
+// rounding of c0 and of the N products of c1 with the ternary key (each rounding at
+// most 1/2), so E' = ceil(E / q_{L-1}) + (N + 2) / 2.  The message's scale becomes
+// Delta q'/q, which is q'/t less (q mod t) q'/(q t) < 1, so decryption mod q' still
+// rounds to the reply's value when 2 t (E' + 1) < q'.
+bool switch_ok(const Ctx &c, const pimm_plan_info &f, uint64_t wmax)
+{
+    using u128 = unsigned __int128;
+    const int L = c.params.L;
+    if (L < 2) return false;
+    const uint64_t qd = c.q[L - 1];
+    const u128 E = noise_bound(c, f, wmax);
+    const u128 Es = (E + qd - 1) / qd + (c.params.N + 2) / 2;  // < 2^61
+    const u128 lhs = (u128)2 * (1ull << c.params.log2_t) * (Es + 1);  // < 2^104
+    uint64_t Qs[kMaxL + 1] = {1, 0, 0, 0, 0};
+    for (int l = 0; l < L - 1; ++l) limbs_mul_small(Qs, kMaxL + 1, c.q[l]);
+    return u128_below(lhs, Qs);
+}
+
+// The reply's parameters after the switch: the first L - 1 primes with their
+// transform and CRT tables as they are (the tables are per prime and the Garner
+// constants of prime l depend only on the primes before it), and q', floor(q'/2),
+// Delta' = floor(q' / t) and q' as a double.  qd_inv[l] = q_{L-1}^{-1} mod q_l,
+// balanced, for l < L - 1.
+void switched_params(const Ctx &c, DevParams &d, double *qd_inv)
+{
+    const int L = c.params.L;
+    d = c.dp;
+    d.L = L - 1;
+    fill_modulus(d, c.q, L - 1, (int)c.params.log2_t);
+    for (int l = 0; l < kMaxL; ++l)
+        qd_inv[l] = l < L - 1 ? balanced(h_inv(c.q[L - 1] % c.q[l], c.q[l]), c.q[l]) : 0.0;
 }
 
 // ---- sampling kernels --------------------------------------------------------
@@ -591,6 +649,17 @@ int pimm_noise_ok(const pimm_params *params, const pimm_plan_info *info, uint64_
     int rc = build_context(*params, 0, &c, false);
     if (rc) return rc;
     return noise_ok(c, *info, wmax) ? 1 : 0;
+}
+
+int pimm_switch_ok(const pimm_params *params, const pimm_plan_info *info, uint64_t wmax)
+{
+    if (!params || !info) return set_error(PIMM_E_ARG, "pimm_switch_ok: NULL argument");
+    Ctx c;
+    int rc = build_context(*params, 0, &c, false);
+    if (rc) return rc;
+    if (c.params.L < 2)
+        return set_error(PIMM_E_UNSUPPORTED, "pimm_switch_ok: one prime cannot be dropped");
+    return switch_ok(c, *info, wmax) ? 1 : 0;
 }
 
 int pimm_plan_create(pimm_ctx *ctx, uint32_t n, uint32_t r, uint32_t m, uint32_t mb, uint32_t rb,

@@ -3,7 +3,7 @@
 // When enabled, every kernel launch the library makes (or those of the
 // selected classes) is bracketed by two events recorded on the launch's own
 // stream, filed under the kernel's class name ("ntt_fwd", "ntt_inv", "mac",
-// "sample", "encode", "decode", "mask_extract", "fused").  pimm_profile_read
+// "sample", "encode", "decode", "mask_extract", "fused", "fc", "mod_switch").  pimm_profile_read
 // waits for the recorded events, returns the number of launches and their
 // summed duration, and forgets them.
 #include <map>

@@ -31,7 +31,7 @@ TAG_RR_U, TAG_RR_E1, TAG_RR_E2, TAG_MASK = 6, 7, 8, 9
 # Every function include/pimm.h and include/pimm_probe.h declare.
 EXPORTS = [
     "pimm_ctx_create", "pimm_ctx_destroy", "pimm_ctx_primes", "pimm_ctx_cdt",
-    "pimm_params_primes", "pimm_cdt", "pimm_plan_rule", "pimm_noise_ok",
+    "pimm_params_primes", "pimm_cdt", "pimm_plan_rule", "pimm_noise_ok", "pimm_switch_ok",
     "pimm_plan_create", "pimm_plan_destroy", "pimm_plan_query", "pimm_plan_set_tuning",
     "pimm_plan_get_tuning", "pimm_plan_autotune", "pimm_plan_select", "pimm_batch_autotune",
     "pimm_keygen", "pimm_sk_destroy", "pimm_encode_input", "pimm_encrypt", "pimm_decrypt",
@@ -41,6 +41,7 @@ EXPORTS = [
     "pimm_weights_update",
     "pimm_encrypt_seeded",
     "pimm_ct_expand",
+    "pimm_mod_switch", "pimm_decrypt_switched",
     "pimm_batch_create", "pimm_batch_destroy", "pimm_batch_query", "pimm_batch_set_schedule",
     "pimm_batch_get_schedule",
     "pimm_batch_matmul", "pimm_batch_status",
@@ -101,6 +102,9 @@ def lib():
         "pimm_cdt": [vp],
         "pimm_plan_rule": [vp, u32, u32, u32, u32, u32, u32, u32, vp],
         "pimm_noise_ok": [vp, vp, u64],
+        "pimm_switch_ok": [vp, vp, u64],
+        "pimm_mod_switch": [vp, vp, vp, vp, vp, vp, vp],
+        "pimm_decrypt_switched": [vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp],
         "pimm_plan_create": [vp, u32, u32, u32, u32, u32, u32, u32, vp],
         "pimm_plan_destroy": [vp],
         "pimm_plan_query": [vp, vp],
@@ -224,6 +228,10 @@ def plan_rule(params: Params, n, r, m, mb=0, rb=0, nb=0, d_fix=0) -> PlanInfo:
 
 def noise_ok(params: Params, info: PlanInfo, wmax: int) -> bool:
     return _check(lib().pimm_noise_ok(ctypes.byref(params), ctypes.byref(info), int(wmax))) == 1
+
+
+def switch_ok(params: Params, info: PlanInfo, wmax: int) -> bool:
+    return _check(lib().pimm_switch_ok(ctypes.byref(params), ctypes.byref(info), int(wmax))) == 1
 
 
 # ---------------------------------------------------------------------------
@@ -522,6 +530,34 @@ def decrypt(plan: Plan, sk: SecretKey, c1: torch.Tensor, c0s: torch.Tensor, shar
     ws = plan.workspace() if ws is None else ws
     _check(lib().pimm_decrypt(plan.h, sk.h, _ptr(c1), _ptr(c0s), _ptr(share), _ptr(ws),
                               ws.numel() * 8, _stream(stream)))
+    return share
+
+
+def mod_switch(plan: Plan, w: Weights, c1: torch.Tensor, c0s: torch.Tensor, c1_out=None,
+               c0s_out=None, stream=None):
+    """pimm_mod_switch: the reply with its last prime dropped.
+    -> (c1s [O][L-1][N], c0ss [O][L-1][mb*nb])."""
+    f, c = plan.info, plan.ctx
+    per = f.mb * f.nb
+    assert tuple(c1.shape) == (f.O, c.L, c.N) and tuple(c0s.shape) == (f.O, c.L, per)
+    if c1_out is None:
+        c1_out = torch.empty((f.O, c.L - 1, c.N), dtype=torch.int64, device=c.device)
+    if c0s_out is None:
+        c0s_out = torch.empty((f.O, c.L - 1, per), dtype=torch.int64, device=c.device)
+    _check(lib().pimm_mod_switch(plan.h, w.h, _ptr(c1), _ptr(c0s), _ptr(c1_out), _ptr(c0s_out),
+                                 _stream(stream)))
+    return c1_out, c0s_out
+
+
+def decrypt_switched(plan: Plan, sk: SecretKey, c1s: torch.Tensor, c0ss: torch.Tensor, share=None,
+                     ws=None, stream=None):
+    """pimm_decrypt_switched: the client's share from a switched reply."""
+    f, c = plan.info, plan.ctx
+    if share is None:
+        share = torch.empty((f.n, f.m), dtype=torch.int64, device=c.device)
+    ws = plan.workspace() if ws is None else ws
+    _check(lib().pimm_decrypt_switched(plan.h, sk.h, _ptr(c1s), _ptr(c0ss), _ptr(share), _ptr(ws),
+                                       ws.numel() * 8, _stream(stream)))
     return share
 
 

@@ -89,6 +89,40 @@ def test_noise_check_matches_oracle(orc):
         assert pimm.noise_ok(prm3, info, wmax) == orc.noise_ok(op3, plan, wmax)
 
 
+def _switch_edge(orc, op, plan):
+    """The largest wmax the oracle's switch rule accepts (bisection; it is monotone in wmax)."""
+    lo, hi = 0, 1 << 48
+    if not orc.switch_ok(op, plan, lo):
+        return -1
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        lo, hi = (mid, hi) if orc.switch_ok(op, plan, mid) else (lo, mid)
+    return lo
+
+
+@pytest.mark.parametrize("N,L,ell,f,shape,d", [
+    (4096, 2, 37, 12, (128, 768, 768), 0), (4096, 2, 37, 12, (128, 768, 3072), 64),
+    (4096, 2, 44, 12, (16, 64, 64), 0), (8192, 3, 41, 14, (512, 4096, 1024), 1024),
+    (8192, 3, 48, 14, (512, 4096, 1024), 1024),
+    (8192, 4, 41, 14, (512, 1024, 4096), 0)])
+def test_switch_check_matches_oracle(orc, N, L, ell, f, shape, d):
+    for rr in (True, False):
+        prm = pimm.make_params(N, L, ell, f, rr)
+        op = orc.Params(N, L, ell, f, rerandomize=rr)
+        info = pimm.plan_rule(prm, *shape, d_fix=d)
+        plan = orc.plan_fix(N, d, *shape) if d else orc.plan_comm(N, *shape)
+        edge = _switch_edge(orc, op, plan)
+        for wmax in {0, 1, 600, 2**20, 2**40, max(edge, 0), edge + 1}:
+            assert pimm.switch_ok(prm, info, wmax) == orc.switch_ok(op, plan, wmax), (rr, wmax, edge)
+
+
+def test_switch_check_refuses_one_prime():
+    prm = pimm.make_params(4096, 1, 20, 8)
+    info = pimm.plan_rule(prm, 16, 64, 64)
+    with pytest.raises(pimm.PimmError, match="PIMM_E_UNSUPPORTED"):
+        pimm.switch_ok(prm, info, 1)
+
+
 @pytest.mark.parametrize("bad,code", [
     (dict(N=1000), "PIMM_E_PARAMS"), (dict(N=2048), "PIMM_E_PARAMS"), (dict(L=0), "PIMM_E_PARAMS"),
     (dict(L=5), "PIMM_E_PARAMS"), (dict(log2_t=1), "PIMM_E_PARAMS"),
