@@ -69,7 +69,8 @@ template <int LOGN>
 __device__ __forceinline__ void run_out(const BatchItemDev &it, int poly, double *ws,
                                         const DevParams &dp, double *lds)
 {
-    ntt_inv_block<LOGN, kNttThreads>(LoadSlots{ws + it.ahat_off, LOGN}, StoreU64{it.acc, LOGN}, dp, poly, lds);
+    ntt_inv_block<LOGN, kNttThreads>(LoadSlotsReduce{ws + it.ahat_off, LOGN}, StoreU64{it.acc, LOGN}, dp,
+                                     poly, lds);
 }
 
 // mac unit t of an item -> (l, slot chunk, slot group, column tile, row-tile group), row-tile

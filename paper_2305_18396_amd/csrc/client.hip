@@ -34,30 +34,31 @@ __global__ void k_encode_input(const uint64_t *X, uint64_t *pt, pimm_plan_info f
 struct LoadCtComp {
     const uint64_t *ct;
     int logn, L, comp;
-    __device__ double operator()(int poly, int l, int j, double, double) const
+    __device__ double operator()(const PolyIx &pi, int j, double, double) const
     {
-        const size_t x = (size_t)(poly / L);
-        return (double)ct[(((x * 2 + comp) * L + l) << logn) + j];
+        const size_t x = (size_t)pi.x, l = (size_t)pi.l;
+        return f64_of(ct[(((x * 2 + comp) * L + l) << logn) + j]);
     }
 };
 
-// c0 = [Delta_l pt + e - a s]_{q_l} from the inverse NTT of a^ s^.
-// Delta_l travels by value inside the functor (kernel arguments are the only
+// c0 = [Delta_l pt + e - a s]_{q_l} from the inverse NTT of a^ s^, in balanced
+// doubles: Delta_l pt (|.| <= 0.6 q_l), e (|e| <= 19) and a s (|.| <= 0.6 q_l) add
+// to well under 2^52, and one reduction gives the canonical residue.  Delta_l
+// travels by value inside the functor, balanced (kernel arguments are the only
 // host data a kernel may read).
 struct StoreEncC0 {
-    const uint64_t *pt;  // [I][N]
+    const uint64_t *pt;  // [I][N], values < t
     const int8_t *e;     // [I][N]
     uint64_t *ct;        // [I][2][L][N]
-    uint64_t delta[kMaxL];
+    double delta[kMaxL];
     int logn, L;
-    __device__ void operator()(int poly, int l, int j, double v, double p, double pinv) const
+    __device__ void operator()(const PolyIx &pi, int j, double v, double p, double pinv) const
     {
-        const size_t x = (size_t)(poly / L);
-        const uint64_t q = (uint64_t)p;
-        const uint64_t as = to_canonical(v, p, pinv);
-        const uint64_t m = mul_mod(delta[l], pt[(x << logn) + j], p, pinv);
-        const uint64_t c0 = sub_mod(add_mod(m, lift_small(e[(x << logn) + j], q), q), as, q);
-        ct[(((x * 2) * L + l) << logn) + j] = c0;
+        const size_t x = (size_t)pi.x;
+        const int l = pi.l;
+        const double m = mulmod(delta[l], f64_of(pt[(x << logn) + j]), p, pinv);
+        const double c0 = m + (double)e[(x << logn) + j] - v;
+        ct[(((x * 2) * L + l) << logn) + j] = to_canonical(c0, p, pinv);
     }
 };
 
@@ -70,12 +71,13 @@ struct DecodedOut {
     uint64_t *cs;
     FastDiv mb;
     uint32_t rb, nb;
-    __device__ void operator()(int poly, const double *lds, const DevParams &dp) const
+    __device__ bool sparse(const PolyIx &) const { return true; }
+    __device__ void operator()(const PolyIx &pi, const double *lds, const DevParams &dp) const
     {
-        const int l = poly % dp.L;
+        const int l = pi.l;
         const double p = dp.p[l], pinv = dp.pinv[l];
         const uint32_t per = mb.d * nb;
-        uint64_t *dst = cs + (size_t)poly * per;
+        uint64_t *dst = cs + (size_t)pi.poly * per;
         for (uint32_t idx = threadIdx.x; idx < per; idx += blockDim.x) {
             const uint32_t k = mb.div(idx), i = idx - k * mb.d;
             const uint32_t j = (k * mb.d + i) * rb + rb - 1;
@@ -221,8 +223,9 @@ int decrypt_reply(const Ctx &c, const pimm_plan_info &f, const pimm_sk *sk, cons
     uint64_t *cs = (uint64_t *)(ch + (size_t)f.O * L * N);
     int rc = launch_fwd(c, LoadU64{c1, lg}, StoreSlots{ch, lg}, (int)(f.O * L), s);
     if (!rc)
-        rc = launch_inv_lds(c, LoadSlotsMul{ch, sk->d_s_hat, lg, (int)L},
-                            DecodedOut{cs, FastDiv::make(f.mb), f.rb, f.nb}, (int)(f.O * L), s);
+        rc = launch_inv_lds(c, LoadSlotsMul{ch, sk->d_s_hat, lg, 1},
+                            DecodedOut{cs, FastDiv::make(f.mb), f.rb, f.nb}, (int)(f.O * L),
+                            prune_factor(f.rb), s);
     if (!rc) {
         const size_t total = (size_t)f.O * per;
         const int threads = 256;
@@ -294,9 +297,12 @@ static int encrypt_with(const pimm_plan *plan, const pimm_sk *sk, const uint8_t 
     if (!rc)
         rc = launch_fwd(c, LoadCtComp{ct, lg, (int)L, 1}, StoreSlots{ah, lg}, (int)(f.I * L), s);
     if (!rc) {
-        StoreEncC0 st{pt, e, ct, {0, 0, 0, 0}, lg, (int)L};
-        for (size_t l = 0; l < L; ++l) st.delta[l] = c.dp.delta[l];
-        rc = launch_inv(c, LoadSlotsMul{ah, sk->d_s_hat, lg, (int)L}, st, (int)(f.I * L), s);
+        StoreEncC0 st{pt, e, ct, {0.0, 0.0, 0.0, 0.0}, lg, (int)L};
+        for (size_t l = 0; l < L; ++l) {
+            const uint64_t d = c.dp.delta[l], q = c.q[l];
+            st.delta[l] = d > q / 2 ? -(double)(q - d) : (double)d;
+        }
+        rc = launch_inv(c, LoadSlotsMul{ah, sk->d_s_hat, lg, 1}, st, (int)(f.I * L), s);
     }
     return rc;
 }

@@ -57,6 +57,18 @@ struct DevParams {
     const double *tw_inv;            // [L][N] psi^-bitrev(k), balanced
 };
 
+// Polynomial `poly` of a [..][L][N] buffer: its prime l = poly % L and x = poly / L
+// (the ciphertext, or ciphertext and component, it belongs to).
+struct PolyIx {
+    int poly, l, x;
+};
+
+__device__ __forceinline__ PolyIx poly_ix(int poly, int L)
+{
+    const int x = poly / L;
+    return PolyIx{poly, poly - x * L, x};
+}
+
 // 32-byte ChaCha20 key as little-endian words.
 struct Key {
     uint32_t w[8];
@@ -83,13 +95,26 @@ __device__ __forceinline__ double reduce(double x, double p, double pinv)
     return __builtin_fma(-__builtin_rint(x * pinv), p, x);
 }
 
-// Balanced double -> canonical residue in [0, p).
+// Exact conversions between integers in [0, 2^52) and doubles through the bit
+// pattern: 2^52 + v has exponent 52 and mantissa v, so setting the exponent bits
+// of v (or adding 2^52 to the double) and removing 2^52 again converts with one
+// floating-point and one integer operation.
+__device__ __forceinline__ double f64_of(uint64_t v)
+{
+    return __longlong_as_double((long long)(v | 0x4330000000000000ull)) - 4503599627370496.0;
+}
+__device__ __forceinline__ uint64_t u64_of(double x)
+{
+    return (uint64_t)__double_as_longlong(x + 4503599627370496.0) - 0x4330000000000000ull;
+}
+
+// Balanced double (|x| < 2^52) -> canonical residue in [0, p): the reduction
+// leaves |x| <= p/2 plus a few units, so one correction of the sign suffices.
 __device__ __forceinline__ uint64_t to_canonical(double x, double p, double pinv)
 {
     x = reduce(x, p, pinv);
     if (x < 0.0) x += p;
-    if (x >= p) x -= p;
-    return (uint64_t)x;
+    return u64_of(x);
 }
 
 // Canonical residues: exact add/sub for values < 2^63.
@@ -108,10 +133,10 @@ __device__ __forceinline__ uint64_t lift_small(int64_t x, uint64_t q)
 {
     return x >= 0 ? (uint64_t)x : q - (uint64_t)(-x);
 }
-// Canonical product through the FP64 path.
+// Canonical product through the FP64 path (a, b < 2^52).
 __device__ __forceinline__ uint64_t mul_mod(uint64_t a, uint64_t b, double p, double pinv)
 {
-    return to_canonical(mulmod((double)a, (double)b, p, pinv), p, pinv);
+    return to_canonical(mulmod(f64_of(a), f64_of(b), p, pinv), p, pinv);
 }
 
 // n / d for n * d < 2^32 by one multiply-high: M = ceil(2^32 / d) (d = 1 is kept apart,

@@ -533,11 +533,11 @@ struct StorePk0 {
     const int64_t *e;
     uint64_t *pk0;  // [L][N]
     int logn;
-    __device__ void operator()(int poly, int l, int j, double v, double p, double pinv) const
+    __device__ void operator()(const PolyIx &pi, int j, double v, double p, double pinv) const
     {
         const uint64_t q = (uint64_t)p;
         const uint64_t as = to_canonical(v, p, pinv);
-        pk0[((size_t)poly << logn) + j] = sub_mod(lift_small(e[j], q), as, q);
+        pk0[((size_t)pi.poly << logn) + j] = sub_mod(lift_small(e[j], q), as, q);
     }
 };
 
@@ -549,14 +549,14 @@ int keygen_into(const Ctx &c, const Key &key, int64_t *s, double *s_hat, uint64_
 {
     const int N = (int)c.params.N, L = (int)c.params.L, lg = c.dp.logN;
     int rc = launch_sample(c, 1, key, kTagSK, 0, 0, 1, 0, 1, s, 0, 0, st);
-    if (!rc) rc = launch_fwd(c, LoadI64Shared{s, lg, L}, StoreSlots{s_hat, lg}, L, st);
+    if (!rc) rc = launch_fwd(c, LoadI64Shared{s, lg}, StoreSlots{s_hat, lg}, L, st);
     if (rc || !pk || !c.params.rerandomize) return rc;
     uint64_t *pk1 = pk + (size_t)L * N;
     rc = launch_sample(c, 0, key, kTagPkA, 0, 0, 1, 0, L, pk1, 0, (size_t)N, st);
     if (!rc) rc = launch_sample(c, 2, key, kTagPkE, 0, 0, 1, 0, 1, e, 0, 0, st);
     if (!rc) rc = launch_fwd(c, LoadU64{pk1, lg}, StoreSlots{tmp, lg}, L, st);
     if (!rc)
-        rc = launch_inv(c, LoadSlotsMul{tmp, s_hat, lg, L}, StorePk0{e, pk, lg}, L, st);
+        rc = launch_inv(c, LoadSlotsMul{tmp, s_hat, lg, 1}, StorePk0{e, pk, lg}, L, st);
     return rc;
 }
 
@@ -757,7 +757,7 @@ int pimm_poly_mul(pimm_ctx *ctx, const uint64_t *a, const uint64_t *b, uint64_t 
     double *ah = (double *)ws, *bh = ah + ((size_t)np << lg);
     int rc = launch_fwd(*ctx, LoadU64{a, lg}, StoreSlots{ah, lg}, np, s);
     if (!rc) rc = launch_fwd(*ctx, LoadU64{b, lg}, StoreSlots{bh, lg}, np, s);
-    if (!rc) rc = launch_inv(*ctx, LoadSlotsMul{ah, bh, lg, np}, StoreU64{c, lg}, np, s);
+    if (!rc) rc = launch_inv(*ctx, LoadSlotsMul{ah, bh, lg, 0}, StoreU64{c, lg}, np, s);
     return rc;
 }
 

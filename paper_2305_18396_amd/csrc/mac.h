@@ -221,9 +221,9 @@ struct StoreWeightTiled {
     double *out;
     int logn, L;
     uint32_t M, R;
-    __device__ void operator()(int poly, int l, int z, double v, double, double) const
+    __device__ void operator()(const PolyIx &pi, int z, double v, double, double) const
     {
-        const uint32_t w = (uint32_t)(poly / L);
+        const uint32_t w = (uint32_t)pi.x, l = (uint32_t)pi.l;
         const uint32_t ib = w / R, jb = w % R;
         const size_t chunks = (size_t)1 << (logn - 8);
         const size_t zc = (size_t)(z >> 8), zz = (size_t)(z & 255);
@@ -236,10 +236,9 @@ struct StoreCtTiled {
     double *out;
     int logn, L;
     uint32_t K, R;
-    __device__ void operator()(int poly, int l, int z, double v, double, double) const
+    __device__ void operator()(const PolyIx &pi, int z, double v, double, double) const
     {
-        const uint32_t x = (uint32_t)(poly / (2 * L));
-        const uint32_t c = (uint32_t)((poly / L) % 2);
+        const uint32_t x = (uint32_t)(pi.x >> 1), c = (uint32_t)(pi.x & 1), l = (uint32_t)pi.l;
         const uint32_t jb = x / K, kb = x % K;
         const size_t chunks = (size_t)1 << (logn - 8);
         const size_t zc = (size_t)(z >> 8), zz = (size_t)(z & 255);
@@ -251,9 +250,9 @@ struct StoreCtTiled {
 struct LoadSlotsReduce {
     const double *a;
     int logn;
-    __device__ double operator()(int poly, int, int z, double p, double pinv) const
+    __device__ double operator()(const PolyIx &pi, int z, double p, double pinv) const
     {
-        return reduce(a[((size_t)poly << logn) + z], p, pinv);
+        return reduce(a[((size_t)pi.poly << logn) + z], p, pinv);
     }
 };
 

@@ -25,17 +25,16 @@ struct StoreCtRun16 {
     double *out;
     uint32_t I2, NC;  // 2 * I, N / 16
     int L;
-    __device__ void operator()(int poly, int l, int z, double v, double, double) const
+    __device__ void operator()(const PolyIx &pi, int z, double v, double, double) const
     {
-        const uint32_t xc = (uint32_t)(poly / L);
-        out[(((size_t)l * NC + (uint32_t)(z >> 4)) * I2 + xc) * 16 + (z & 15)] = v;
+        out[(((size_t)pi.l * NC + (uint32_t)(z >> 4)) * I2 + (uint32_t)pi.x) * 16 + (z & 15)] = v;
     }
 };
 
 // Index of accumulator polynomial (o*2 + comp)*L + l, slot z, in [L][N/16][O][2][16].
-__device__ __forceinline__ size_t run16_index(int poly, int l, int z, int L, uint32_t O2, uint32_t NC)
+__device__ __forceinline__ size_t run16_index(const PolyIx &pi, int z, uint32_t O2, uint32_t NC)
 {
-    return (((size_t)l * NC + (uint32_t)(z >> 4)) * O2 + (uint32_t)(poly / L)) * 16 + (z & 15);
+    return (((size_t)pi.l * NC + (uint32_t)(z >> 4)) * O2 + (uint32_t)pi.x) * 16 + (z & 15);
 }
 
 // Accumulators in the chunked layout, reduced (the plain pimm_matmul's inverse transform).
@@ -43,9 +42,9 @@ struct LoadSlotsReduceRun16 {
     const double *a;
     uint32_t O2, NC;
     int L;
-    __device__ double operator()(int poly, int l, int z, double p, double pinv) const
+    __device__ double operator()(const PolyIx &pi, int z, double p, double pinv) const
     {
-        return reduce(a[run16_index(poly, l, z, L, O2, NC)], p, pinv);
+        return reduce(a[run16_index(pi, z, O2, NC)], p, pinv);
     }
 };
 

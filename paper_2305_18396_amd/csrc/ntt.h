@@ -16,14 +16,16 @@
 // last forward pass writes element c of set S to slot c * NSETS + S, which
 // makes its global stores coalesced; the inverse's first pass reads the same.
 //
-// Loaders produce a double of magnitude <= p for (poly, prime, index);
-// storers consume a balanced double.  Poly index p of a [..][L][N] buffer
-// belongs to prime p % L.
+// Loaders produce a double of magnitude <= p for (polynomial, index); storers
+// consume a balanced double.  Poly index p of a [..][L][N] buffer belongs to
+// prime p % L; the workgroup works out the prime and the quotient p / L once
+// (PolyIx) and hands them to its loader and storer.
 #pragma once
 
 #include "common.h"
 
 namespace pimm {
+
 
 // Workgroup size of the batch kernels (and of every N = 4096 transform).
 constexpr int kNttThreads = 256;
@@ -58,6 +60,31 @@ constexpr int ntt_threads()
 // LDS slot of element j, padded by one double every 32 to break bank aliasing
 // of the strided pass patterns.
 __device__ __forceinline__ int lds_idx(int j) { return j + (j >> 5); }
+
+// Output pruning of the inverse transform.  When only the coefficients j with
+// j % G == G - 1 are read afterwards (G a power of two <= 16: the decoded
+// positions of a reply, j = t * r_b + r_b - 1, with G dividing r_b), the first
+// inverse pass -- the four stages that combine elements differing in the low four
+// index bits -- computes only the butterfly outputs those coefficients depend on,
+// and the later passes run only on the sets whose elements have those low bits.
+// prune_mask<PS, G>(sp): bit c set when register c of a set is still needed after
+// inverse stage sp (the stages run PS - 1 down to 0; stage sp pairs c with
+// c + (2^PS >> (sp + 1))).
+template <int PS, int G>
+__host__ __device__ constexpr uint32_t prune_mask(int sp)
+{
+    uint32_t m = 0;
+    for (int c = 0; c < (1 << PS); ++c)
+        if (c % G == G - 1) m |= 1u << c;
+    for (int st = 1; st <= sp; ++st) {
+        const int h = (1 << PS) >> st;  // the pair distance of stage st - 1
+        uint32_t n = m;
+        for (int c = 0; c < (1 << PS); ++c)
+            if ((m >> (c ^ h)) & 1u) n |= 1u << c;
+        m = n;
+    }
+    return m;
+}
 
 template <int LOGN, int S0, int PS, int T>
 struct Pass {
@@ -94,7 +121,37 @@ struct Pass {
         }
     }
 
-    // Inverse stages S0+PS-1 .. S0 on the registers of set S.
+    // Inverse stages S0+PS-1 .. S0 of set S computing only the registers that
+    // prune_mask<PS, G> keeps.
+    template <int G>
+    __device__ static __forceinline__ void inv_pruned(double *x, int S, const double *tw, double p,
+                                                      double pinv)
+    {
+        const int hi = S / STRIDE;
+#pragma unroll
+        for (int sp = PS - 1; sp >= 0; --sp) {
+            const int half = E >> (sp + 1);
+            const uint32_t need = prune_mask<PS, G>(sp);
+#pragma unroll
+            for (int c = 0; c < E; ++c) {
+                if (c & half) continue;
+                const bool lo = (need >> c) & 1u, up = (need >> (c + half)) & 1u;
+                if (!lo && !up) continue;
+                const double u = x[c], v = x[c + half];
+                if (lo) x[c] = (sp & 1) ? u + v : reduce(u + v, p, pinv);
+                if (up) {
+                    const double w = tw[(1 << (S0 + sp)) + (hi << sp) + (c >> (PS - sp))];
+                    x[c + half] = mulmod(u - v, w, p, pinv);
+                }
+            }
+        }
+    }
+
+    // Inverse stages S0+PS-1 .. S0 on the registers of set S.  The sums are
+    // reduced after the even stages only: with inputs within 1.1 p (every
+    // loader's bound) the registers stay within 2.7 p between reductions, so the
+    // differences that enter mulmod stay within 5.3 p (its result within 1.5 p,
+    // exact), and the pass ends with every register reduced.
     __device__ static __forceinline__ void inv(double *x, int S, const double *tw, double p,
                                                double pinv)
     {
@@ -107,7 +164,7 @@ struct Pass {
                 if (c & half) continue;
                 const double w = tw[(1 << (S0 + sp)) + (hi << sp) + (c >> (PS - sp))];
                 const double u = x[c], v = x[c + half];
-                x[c] = reduce(u + v, p, pinv);
+                x[c] = (sp & 1) ? u + v : reduce(u + v, p, pinv);
                 x[c + half] = mulmod(u - v, w, p, pinv);
             }
         }
@@ -131,7 +188,7 @@ struct NttPasses {
 // loader for the first pass), write to LDS (or the storer, in slot order, for
 // the last pass).
 template <class P, int T, bool FIRST, bool LAST, class Load, class Store>
-__device__ __forceinline__ void fwd_pass(const Load &ld, const Store &st, int poly, int l,
+__device__ __forceinline__ void fwd_pass(const Load &ld, const Store &st, const PolyIx &pi,
                                          const double *tw, double p, double pinv, double *lds)
 {
 #pragma unroll
@@ -140,12 +197,12 @@ __device__ __forceinline__ void fwd_pass(const Load &ld, const Store &st, int po
         double x[P::E];
 #pragma unroll
         for (int c = 0; c < P::E; ++c)
-            x[c] = FIRST ? ld(poly, l, P::elem(S, c), p, pinv) : lds[lds_idx(P::elem(S, c))];
+            x[c] = FIRST ? ld(pi, P::elem(S, c), p, pinv) : lds[lds_idx(P::elem(S, c))];
         P::fwd(x, S, tw, p, pinv);
 #pragma unroll
         for (int c = 0; c < P::E; ++c) {
             if (LAST)
-                st(poly, l, c * P::NSETS + S, reduce(x[c], p, pinv), p, pinv);
+                st(pi, c * P::NSETS + S, reduce(x[c], p, pinv), p, pinv);
             else
                 lds[lds_idx(P::elem(S, c))] = reduce(x[c], p, pinv);
         }
@@ -155,23 +212,64 @@ __device__ __forceinline__ void fwd_pass(const Load &ld, const Store &st, int po
 // Inverse stages of pass P (the mirror of fwd_pass: the first inverse pass reads
 // the loader in slot order, the last one multiplies by N^-1 and calls the storer
 // in natural order).
-template <class P, int T, bool FIRST, bool LAST, class Load, class Store>
-__device__ __forceinline__ void inv_pass(const Load &ld, const Store &st, int poly, int l,
+//
+// With G > 1 (output pruning, see prune_mask) the first pass loads every element
+// but keeps only the registers the needed coefficients depend on, and the other
+// passes run only on the sets S with S % G == G - 1 (their elements are the ones
+// whose low four index bits are G - 1 mod G), packed onto the first threads.
+template <class P, int T, bool FIRST, bool LAST, int G = 1, class Load, class Store>
+__device__ __forceinline__ void inv_pass(const Load &ld, const Store &st, const PolyIx &pi,
                                          const double *tw, double p, double pinv, double ninv,
                                          double *lds)
 {
+    if constexpr (G > 1 && FIRST) {
+        static_assert(P::STRIDE == 1 && P::E == 16 && !LAST, "pruned first pass: 16 adjacent elements");
+#pragma unroll
+        for (int k = 0; k < P::PER_THREAD; ++k) {
+            const int S = (int)threadIdx.x + k * T;
+            double x[P::E];
+#pragma unroll
+            for (int c = 0; c < P::E; ++c) x[c] = ld(pi, c * P::NSETS + S, p, pinv);
+            P::template inv_pruned<G>(x, S, tw, p, pinv);
+#pragma unroll
+            for (int c = 0; c < P::E; ++c)
+                if (c % G == G - 1) lds[lds_idx(P::elem(S, c))] = reduce(x[c], p, pinv);
+        }
+        return;
+    }
+    if constexpr (G > 1) {
+        constexpr int NEED = P::NSETS / G;
+#pragma unroll
+        for (int k = 0; k < (NEED + T - 1) / T; ++k) {
+            const int u = (int)threadIdx.x + k * T;
+            if (u >= NEED) break;
+            const int S = u * G + (G - 1);
+            double x[P::E];
+#pragma unroll
+            for (int c = 0; c < P::E; ++c) x[c] = lds[lds_idx(P::elem(S, c))];
+            P::inv(x, S, tw, p, pinv);
+#pragma unroll
+            for (int c = 0; c < P::E; ++c) {
+                if (LAST)
+                    st(pi, P::elem(S, c), mulmod(x[c], ninv, p, pinv), p, pinv);
+                else
+                    lds[lds_idx(P::elem(S, c))] = reduce(x[c], p, pinv);
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < P::PER_THREAD; ++k) {
         const int S = (int)threadIdx.x + k * T;
         double x[P::E];
 #pragma unroll
         for (int c = 0; c < P::E; ++c)
-            x[c] = FIRST ? ld(poly, l, c * P::NSETS + S, p, pinv) : lds[lds_idx(P::elem(S, c))];
+            x[c] = FIRST ? ld(pi, c * P::NSETS + S, p, pinv) : lds[lds_idx(P::elem(S, c))];
         P::inv(x, S, tw, p, pinv);
 #pragma unroll
         for (int c = 0; c < P::E; ++c) {
             if (LAST)
-                st(poly, l, P::elem(S, c), mulmod(x[c], ninv, p, pinv), p, pinv);
+                st(pi, P::elem(S, c), mulmod(x[c], ninv, p, pinv), p, pinv);
             else
                 lds[lds_idx(P::elem(S, c))] = reduce(x[c], p, pinv);
         }
@@ -186,40 +284,43 @@ __device__ __forceinline__ void ntt_fwd_block(const Load &ld, const Store &st, c
 {
     using NP = NttPasses<LOGN, T>;
     constexpr bool FOUR = NP::S::P3 > 0;
-    const int l = poly % dp.L;
+    const PolyIx pi = poly_ix(poly, dp.L);
+    const int l = pi.l;
     const double p = dp.p[l], pinv = dp.pinv[l];
     const double *tw = dp.tw_fwd + ((size_t)l << LOGN);
-    fwd_pass<typename NP::A, T, true, false>(ld, st, poly, l, tw, p, pinv, lds);
+    fwd_pass<typename NP::A, T, true, false>(ld, st, pi, tw, p, pinv, lds);
     __syncthreads();
-    fwd_pass<typename NP::B, T, false, false>(ld, st, poly, l, tw, p, pinv, lds);
+    fwd_pass<typename NP::B, T, false, false>(ld, st, pi, tw, p, pinv, lds);
     __syncthreads();
-    fwd_pass<typename NP::C, T, false, !FOUR>(ld, st, poly, l, tw, p, pinv, lds);
+    fwd_pass<typename NP::C, T, false, !FOUR>(ld, st, pi, tw, p, pinv, lds);
     if constexpr (FOUR) {
         __syncthreads();
-        fwd_pass<typename NP::D, T, false, true>(ld, st, poly, l, tw, p, pinv, lds);
+        fwd_pass<typename NP::D, T, false, true>(ld, st, pi, tw, p, pinv, lds);
     }
 }
 
-// Inverse negacyclic NTT (including the factor N^-1) of polynomial `poly`.
-template <int LOGN, int T, class Load, class Store>
+// Inverse negacyclic NTT (including the factor N^-1) of polynomial `poly`; with
+// G > 1 only the coefficients j with j % G == G - 1 are produced.
+template <int LOGN, int T, int G = 1, class Load, class Store>
 __device__ __forceinline__ void ntt_inv_block(const Load &ld, const Store &st, const DevParams &dp,
                                               int poly, double *lds)
 {
     using NP = NttPasses<LOGN, T>;
     constexpr bool FOUR = NP::S::P3 > 0;
-    const int l = poly % dp.L;
+    const PolyIx pi = poly_ix(poly, dp.L);
+    const int l = pi.l;
     const double p = dp.p[l], pinv = dp.pinv[l];
     const double *tw = dp.tw_inv + ((size_t)l << LOGN);
     const double ninv = dp.n_inv[l];
     if constexpr (FOUR) {
-        inv_pass<typename NP::D, T, true, false>(ld, st, poly, l, tw, p, pinv, ninv, lds);
+        inv_pass<typename NP::D, T, true, false, G>(ld, st, pi, tw, p, pinv, ninv, lds);
         __syncthreads();
     }
-    inv_pass<typename NP::C, T, !FOUR, false>(ld, st, poly, l, tw, p, pinv, ninv, lds);
+    inv_pass<typename NP::C, T, !FOUR, false, G>(ld, st, pi, tw, p, pinv, ninv, lds);
     __syncthreads();
-    inv_pass<typename NP::B, T, false, false>(ld, st, poly, l, tw, p, pinv, ninv, lds);
+    inv_pass<typename NP::B, T, false, false, G>(ld, st, pi, tw, p, pinv, ninv, lds);
     __syncthreads();
-    inv_pass<typename NP::A, T, false, true>(ld, st, poly, l, tw, p, pinv, ninv, lds);
+    inv_pass<typename NP::A, T, false, true, G>(ld, st, pi, tw, p, pinv, ninv, lds);
 }
 
 // Polynomial of a workgroup: workgroups are dispatched round-robin over the XCDs, so the
@@ -263,25 +364,36 @@ __global__ __launch_bounds__(ntt_threads<LOGN>()) void k_ntt_inv(Load ld, Store 
 // Inverse transform whose result stays in the workgroup's LDS (natural order,
 // lds_idx layout), followed by an epilogue that reads it with the whole
 // workgroup: epi(poly, lds, dp).  The last pass's storer writes exactly the
-// elements its thread has just read, so no barrier is needed before it.
+// elements its thread has just read, so no barrier is needed before it.  With
+// G > 1, the polynomials for which epi.sparse(pi) holds are transformed with
+// output pruning (only j % G == G - 1 is produced; the epilogue reads no other
+// coefficient of them).
 struct StoreLds {
     double *lds;
-    __device__ void operator()(int, int, int j, double v, double, double) const
+    __device__ void operator()(const PolyIx &, int j, double v, double, double) const
     {
         lds[lds_idx(j)] = v;
     }
 };
 
-template <int LOGN, class Load, class Epi>
+template <int LOGN, int G, class Load, class Epi>
 __global__ __launch_bounds__(ntt_threads<LOGN>()) void k_ntt_inv_lds(Load ld, Epi epi, DevParams dp)
 {
     constexpr int T = ntt_threads<LOGN>();
     __shared__ double lds[NttPasses<LOGN, T>::LDS];
     const int poly = ntt_poly();
-    ntt_inv_block<LOGN, T>(ld, StoreLds{lds}, dp, poly, lds);
+    const PolyIx pi = poly_ix(poly, dp.L);
+    if (G > 1 && epi.sparse(pi))
+        ntt_inv_block<LOGN, T, G>(ld, StoreLds{lds}, dp, poly, lds);
+    else
+        ntt_inv_block<LOGN, T, 1>(ld, StoreLds{lds}, dp, poly, lds);
     __syncthreads();
-    epi(poly, lds, dp);
+    epi(pi, lds, dp);
 }
+
+// The output pruning an epilogue that reads the decoded positions t * rb + rb - 1
+// allows: the largest of 16, 4 and 1 that divides rb.
+inline int prune_factor(uint32_t rb) { return rb % 16 == 0 ? 16 : rb % 4 == 0 ? 4 : 1; }
 
 // ---- loaders ----------------------------------------------------------------
 
@@ -289,30 +401,31 @@ __global__ __launch_bounds__(ntt_threads<LOGN>()) void k_ntt_inv_lds(Load ld, Ep
 struct LoadU64 {
     const uint64_t *in;
     int logn;
-    __device__ double operator()(int poly, int, int j, double, double) const
+    __device__ double operator()(const PolyIx &pi, int j, double, double) const
     {
-        return (double)in[((size_t)poly << logn) + j];
+        return f64_of(in[((size_t)pi.poly << logn) + j]);
     }
 };
 
 // Small signed integers shared by the L primes: source poly = poly / L.
 struct LoadI64Shared {
     const int64_t *in;
-    int logn, L;
-    __device__ double operator()(int poly, int, int j, double, double) const
+    int logn;
+    __device__ double operator()(const PolyIx &pi, int j, double, double) const
     {
-        return (double)in[((size_t)(poly / L) << logn) + j];
+        return (double)in[((size_t)pi.x << logn) + j];
     }
 };
 
-// Pointwise product of two NTT-form operands: a[poly] * b[poly % bmod].
+// Pointwise product of two NTT-form operands: a[poly] times b[l] (an operand per
+// prime, such as the key) or b[poly] (by_prime = 0).
 struct LoadSlotsMul {
     const double *a, *b;
-    int logn, bmod;
-    __device__ double operator()(int poly, int, int z, double p, double pinv) const
+    int logn, by_prime;
+    __device__ double operator()(const PolyIx &pi, int z, double p, double pinv) const
     {
-        return mulmod(a[((size_t)poly << logn) + z], b[((size_t)(poly % bmod) << logn) + z], p,
-                      pinv);
+        return mulmod(a[((size_t)pi.poly << logn) + z],
+                      b[((size_t)(by_prime ? pi.l : pi.poly) << logn) + z], p, pinv);
     }
 };
 
@@ -320,9 +433,9 @@ struct LoadSlotsMul {
 struct LoadSlots {
     const double *a;
     int logn;
-    __device__ double operator()(int poly, int, int z, double, double) const
+    __device__ double operator()(const PolyIx &pi, int z, double, double) const
     {
-        return a[((size_t)poly << logn) + z];
+        return a[((size_t)pi.poly << logn) + z];
     }
 };
 
@@ -331,18 +444,18 @@ struct LoadSlots {
 struct StoreSlots {
     double *out;
     int logn;
-    __device__ void operator()(int poly, int, int z, double v, double, double) const
+    __device__ void operator()(const PolyIx &pi, int z, double v, double, double) const
     {
-        out[((size_t)poly << logn) + z] = v;
+        out[((size_t)pi.poly << logn) + z] = v;
     }
 };
 
 struct StoreU64 {
     uint64_t *out;
     int logn;
-    __device__ void operator()(int poly, int, int j, double v, double p, double pinv) const
+    __device__ void operator()(const PolyIx &pi, int j, double v, double p, double pinv) const
     {
-        out[((size_t)poly << logn) + j] = to_canonical(v, p, pinv);
+        out[((size_t)pi.poly << logn) + j] = to_canonical(v, p, pinv);
     }
 };
 
@@ -390,17 +503,30 @@ int launch_inv(const Ctx &c, Load ld, Store st, int npoly, hipStream_t s)
     return check_hip(hipGetLastError(), "ntt_inv launch");
 }
 
+template <int LOGN, class Load, class Epi>
+void launch_inv_lds_g(int g, Load ld, Epi epi, int npoly, const DevParams &dp, hipStream_t s)
+{
+    if (g == 16)
+        hipLaunchKernelGGL((k_ntt_inv_lds<LOGN, 16, Load, Epi>), dim3(npoly), dim3(ntt_threads<LOGN>()),
+                           0, s, ld, epi, dp);
+    else if (g == 4)
+        hipLaunchKernelGGL((k_ntt_inv_lds<LOGN, 4, Load, Epi>), dim3(npoly), dim3(ntt_threads<LOGN>()),
+                           0, s, ld, epi, dp);
+    else
+        hipLaunchKernelGGL((k_ntt_inv_lds<LOGN, 1, Load, Epi>), dim3(npoly), dim3(ntt_threads<LOGN>()),
+                           0, s, ld, epi, dp);
+}
+
+// g: output pruning factor (prune_factor) for the polynomials epi.sparse marks.
 template <class Load, class Epi>
-int launch_inv_lds(const Ctx &c, Load ld, Epi epi, int npoly, hipStream_t s)
+int launch_inv_lds(const Ctx &c, Load ld, Epi epi, int npoly, int g, hipStream_t s)
 {
     if (npoly <= 0) return PIMM_OK;
     ProfScope prof("ntt_inv", s);
     if (c.dp.logN == 12)
-        hipLaunchKernelGGL((k_ntt_inv_lds<12, Load, Epi>), dim3(npoly), dim3(ntt_threads<12>()), 0, s, ld,
-                           epi, c.dp);
+        launch_inv_lds_g<12>(g, ld, epi, npoly, c.dp, s);
     else
-        hipLaunchKernelGGL((k_ntt_inv_lds<13, Load, Epi>), dim3(npoly), dim3(ntt_threads<13>()), 0, s, ld,
-                           epi, c.dp);
+        launch_inv_lds_g<13>(g, ld, epi, npoly, c.dp, s);
     return check_hip(hipGetLastError(), "ntt_inv launch");
 }
 

@@ -31,11 +31,11 @@ struct LoadWeights {
     const int64_t *W;
     uint32_t r, m, mb, rb, R;
     int L;
-    __device__ double operator()(int poly, int, int j, double, double) const
+    __device__ double operator()(const PolyIx &pi, int j, double, double) const
     {
         const uint32_t uj = (uint32_t)j;
         if (uj >= mb * rb) return 0.0;
-        const uint32_t w = (uint32_t)(poly / L);
+        const uint32_t w = (uint32_t)pi.x;
         const uint32_t ib = w / R, jb = w % R;
         const uint32_t i = uj / rb, jj = rb - 1 - uj % rb;
         const uint32_t row = jb * rb + jj, col = ib * mb + i;
@@ -78,10 +78,9 @@ struct LoadRerand {
     const double *uh;   // [O][L][N]
     const double *pkh;  // [2][L][N]
     int logn, L;
-    __device__ double operator()(int poly, int l, int z, double p, double pinv) const
+    __device__ double operator()(const PolyIx &pi, int z, double p, double pinv) const
     {
-        const size_t o = (size_t)(poly / (2 * L));
-        const size_t comp = (size_t)((poly / L) % 2);
+        const size_t o = (size_t)(pi.x >> 1), comp = (size_t)(pi.x & 1), l = (size_t)pi.l;
         return mulmod(uh[((o * L + l) << logn) + z], pkh[((comp * L + l) << logn) + z], p, pinv);
     }
 };
@@ -94,10 +93,10 @@ struct LoadPkU {
     const uint64_t *pk;
     const int8_t *u;
     int logn, L;
-    __device__ double operator()(int poly, int, int j, double, double) const
+    __device__ double operator()(const PolyIx &pi, int j, double, double) const
     {
-        if (poly < 2 * L) return (double)pk[((size_t)poly << logn) + j];
-        return (double)u[((size_t)((poly - 2 * L) / L) << logn) + j];
+        if (pi.x < 2) return f64_of(pk[((size_t)pi.poly << logn) + j]);
+        return (double)u[((size_t)(pi.x - 2) << logn) + j];
     }
 };
 
@@ -106,12 +105,12 @@ struct StoreAddErr {
     uint64_t *acc;
     const int8_t *e;
     int logn, L;
-    __device__ void operator()(int poly, int l, int j, double v, double p, double pinv) const
+    __device__ void operator()(const PolyIx &pi, int j, double v, double p, double pinv) const
     {
         const uint64_t q = (uint64_t)p;
-        const size_t at = ((size_t)poly << logn) + j;
+        const size_t at = ((size_t)pi.poly << logn) + j;
         const uint64_t up = to_canonical(v, p, pinv);
-        const uint64_t ee = lift_small(e[((size_t)(poly / L) << logn) + j], q);
+        const uint64_t ee = lift_small(e[((size_t)pi.x << logn) + j], q);
         acc[at] = add_mod(add_mod(acc[at], up, q), ee, q);
     }
 };
@@ -152,12 +151,12 @@ struct LoadAccRerand {
     int logn, L, rr;
     int run16;
     uint32_t O2, NC;  // 2 * O and N / 16 (run16 layout)
-    __device__ double operator()(int poly, int l, int z, double p, double pinv) const
+    __device__ double operator()(const PolyIx &pi, int z, double p, double pinv) const
     {
-        const size_t at = run16 ? run16_index(poly, l, z, L, O2, NC) : ((size_t)poly << logn) + z;
+        const size_t at = run16 ? run16_index(pi, z, O2, NC) : ((size_t)pi.poly << logn) + z;
         double v = reduce(ah[at], p, pinv);
         if (rr) {
-            const size_t o = (size_t)(poly / (2 * L)), comp = (size_t)((poly / L) % 2);
+            const size_t o = (size_t)(pi.x >> 1), comp = (size_t)(pi.x & 1), l = (size_t)pi.l;
             v += mulmod(uh[((o * L + l) << logn) + z], pkh[((comp * L + l) << logn) + z], p, pinv);
         }
         return v;
@@ -174,21 +173,20 @@ struct ReplyOut {
     FastDiv mb;
     uint32_t rb, nb;
     int logn, L, rr;
-    __device__ void operator()(int poly, const double *lds, const DevParams &dp) const
+    // Component 0 is read at the decoded positions only.
+    __device__ bool sparse(const PolyIx &pi) const { return (pi.x & 1) == 0; }
+    __device__ void operator()(const PolyIx &pi, const double *lds, const DevParams &dp) const
     {
-        const int l = poly % L;
-        const uint32_t y = (uint32_t)(poly / (2 * L)), comp = (uint32_t)((poly / L) % 2);
+        const int l = pi.l;
+        const uint32_t y = (uint32_t)(pi.x >> 1), comp = (uint32_t)(pi.x & 1);
         const double p = dp.p[l], pinv = dp.pinv[l];
-        const uint64_t q = dp.q[l];
         const int8_t *ey = e + (((size_t)y * 2 + comp) << logn);
         const int n = 1 << logn;
+        // The transform's output (within 1.5 q_l) plus the error (|e| <= 19), reduced once.
         if (comp == 1) {
             uint64_t *dst = c1 + (((size_t)y * L + l) << logn);
-            for (int j = threadIdx.x; j < n; j += (int)blockDim.x) {
-                uint64_t x = to_canonical(lds[lds_idx(j)], p, pinv);
-                if (rr) x = add_mod(x, lift_small(ey[j], q), q);
-                dst[j] = x;
-            }
+            for (int j = threadIdx.x; j < n; j += (int)blockDim.x)
+                dst[j] = to_canonical(lds[lds_idx(j)] + (rr ? (double)ey[j] : 0.0), p, pinv);
             return;
         }
         const uint32_t per = mb.d * nb;
@@ -196,9 +194,7 @@ struct ReplyOut {
         for (uint32_t idx = threadIdx.x; idx < per; idx += blockDim.x) {
             const uint32_t k = mb.div(idx), i = idx - k * mb.d;
             const uint32_t j = (k * mb.d + i) * rb + rb - 1;
-            uint64_t x = to_canonical(lds[lds_idx((int)j)], p, pinv);
-            if (rr) x = add_mod(x, lift_small(ey[j], q), q);
-            dst[idx] = x;
+            dst[idx] = to_canonical(lds[lds_idx((int)j)] + (rr ? (double)ey[j] : 0.0), p, pinv);
         }
     }
 };
@@ -264,7 +260,7 @@ int fused_tail(const pimm_plan *plan, const uint64_t *pk, const Key &key, uint32
         rc = launch_inv_lds(c, LoadAccRerand{ah, uh, pkh, lg, (int)L, rr, run16 ? 1 : 0, 2 * f.O,
                                              (uint32_t)(N / 16)},
                             ReplyOut{c1, c0s, e, FastDiv::make(f.mb), f.rb, f.nb, lg, (int)L, rr},
-                            (int)(f.O * 2 * L), s);
+                            (int)(f.O * 2 * L), prune_factor(f.rb), s);
     if (!rc) {
         const uint32_t blocks = (f.mb * f.rb * f.nb + 7) / 8;
         const size_t total = (size_t)f.O * blocks;

@@ -48,7 +48,7 @@ __global__ __launch_bounds__(256) void k_mod_switch(SwitchArgs a, DevParams dp)
     const double r = rd > qd / 2 ? -(double)(qd - rd) : (double)rd;  // |r| < q_{L-1}/2
     for (int l = 0; l < L - 1; ++l) {
         // |c_l - r| < 1.5 * 2^50: exact as a double, and within the mulmod's range.
-        const double v = mulmod((double)x[(size_t)l * cnt] - r, a.qd_inv[l], dp.p[l], dp.pinv[l]);
+        const double v = mulmod(f64_of(x[(size_t)l * cnt]) - r, a.qd_inv[l], dp.p[l], dp.pinv[l]);
         y[(size_t)l * cnt] = to_canonical(v, dp.p[l], dp.pinv[l]);
     }
 }
