@@ -74,7 +74,6 @@ def lib():
         _lib.orc_chacha20_block.argtypes = [vp, u32, vp, vp]
         _lib.orc_draw64.argtypes = [vp, u32, u32, u32, u32, u64]
         _lib.orc_draw64.restype = u64
-        _lib.orc_draw128.argtypes = [vp, u32, u32, u32, u32, u64, vp, vp]
         _lib.orc_sample_poly.argtypes = [ctypes.c_int, vp, u32, u32, u32, u32, u64, u64,
                                          ctypes.c_uint, vp, vp]
         _lib.orc_ntt_negacyclic.argtypes = [vp, vp, u64, u64, u64]

@@ -24,8 +24,9 @@
  *   key     = the party's 32-byte seed,
  *   nonce   = (tag | prime_index << 8, op_id, object_index) as LE words,
  *   counter = block number, starting at 0.
- * The 64-bit draw number j is keystream bytes [8j, 8j+8) read little-endian
- * and the 128-bit draw number j is bytes [16j, 16j+16).
+ * The 64-bit draw number j is keystream bytes [8j, 8j+8) read little-endian.
+ * A uniform residue that the first draw cannot give (rejection) comes from the
+ * stream's fallback stream, whose tag word has bit 31 set.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -123,30 +124,26 @@ uint64_t orc_draw64(const uint8_t key[32], uint32_t tag, uint32_t prime, uint32_
     return (uint64_t)b[w] | ((uint64_t)b[w + 1] << 32);
 }
 
-/* 128-bit draw number j of stream (tag, prime, op, obj), as (lo, hi). */
-void orc_draw128(const uint8_t key[32], uint32_t tag, uint32_t prime, uint32_t op, uint32_t obj,
-                 uint64_t j, uint64_t *lo, uint64_t *hi)
-{
-    uint32_t n[3], b[16];
-    stream_nonce(tag, prime, op, obj, n);
-    orc_chacha20_block(key, (uint32_t)(j / 4), n, b);
-    int w = (int)(4 * (j % 4));
-    *lo = (uint64_t)b[w] | ((uint64_t)b[w + 1] << 32);
-    *hi = (uint64_t)b[w + 2] | ((uint64_t)b[w + 3] << 32);
-}
-
 /* ------------------------------------------------------------------ */
 /* Samplers                                                            */
 /* ------------------------------------------------------------------ */
 
-/* Uniform residue mod q: the 128-bit draw reduced mod q. */
+/* The fallback stream of (tag, prime, op, obj): bit 31 of the tag word set. */
+#define FALLBACK_TAG 0x80000000u
+
+/* Uniform residue mod q (q < 2^50) by rejection: x = the low 50 bits of draw j,
+ * kept when x < q; otherwise x' = the low 50 bits of draw j of the fallback
+ * stream, reduced mod q.  For the primes of the parameter rule (within 2^21 of
+ * 2^50) a draw is rejected with probability below 2^-29, and the residue is
+ * uniform up to a statistical distance below 2^-58. */
 static uint64_t sample_uniform(const uint8_t key[32], uint32_t tag, uint32_t prime, uint32_t op,
                                uint32_t obj, uint64_t j, uint64_t q)
 {
-    uint64_t lo, hi;
-    orc_draw128(key, tag, prime, op, obj, j, &lo, &hi);
-    u128 v = ((u128)hi << 64) | lo;
-    return (uint64_t)(v % q);
+    const uint64_t m50 = (1ull << 50) - 1;
+    uint64_t x = orc_draw64(key, tag, prime, op, obj, j) & m50;
+    if (x < q) return x;
+    x = orc_draw64(key, tag | FALLBACK_TAG, prime, op, obj, j) & m50;
+    return x % q;
 }
 
 /* Ternary value in {-1, 0, 1}: (64-bit draw mod 3) - 1. */

@@ -3,8 +3,8 @@
 ChaCha20 (RFC 8439 section 2.3) is checked against the OpenSSL command-line
 cipher, which takes a 16-byte IV = 32-bit LE block counter || 96-bit nonce and
 XORs the keystream into its input (all-zero input gives the keystream).  The
-stream layout (draw j = keystream bytes [8j, 8j+8) or [16j, 16j+16)) is checked
-against the same keystream.  Samplers are checked against distributions fixed
+stream layout (draw j = keystream bytes [8j, 8j+8)) is checked against the same
+keystream.  Samplers are checked against distributions fixed
 independently: the cumulative table against a 50-digit mpmath recomputation,
 and sample statistics against the exact probabilities.
 """
@@ -56,11 +56,6 @@ def test_draw_layout_is_the_keystream(orc):
     for j in [0, 1, 7, 8, 9, 31, 79]:
         want = int.from_bytes(ks[8 * j:8 * j + 8], "little")
         assert orc.lib().orc_draw64(kp, tag, prime, op, obj, j) == want
-    lo, hi = ctypes.c_uint64(), ctypes.c_uint64()
-    for j in [0, 3, 4, 5, 39]:
-        orc.lib().orc_draw128(kp, tag, prime, op, obj, j, ctypes.byref(lo), ctypes.byref(hi))
-        want = int.from_bytes(ks[16 * j:16 * j + 16], "little")
-        assert (hi.value << 64) | lo.value == want
 
 
 @needs_openssl
@@ -72,16 +67,29 @@ def test_samplers_read_the_keystream(orc):
     q = 1125899906826241
     cdt = np.asarray(orc.cdt_table(), dtype=np.uint64)
 
-    def sample(kind, tag, prime, op, obj, ell=37):
+    def sample(kind, tag, prime, op, obj, ell=37, q_=q):
         out = np.zeros(n, dtype=np.uint64 if kind in (0, 3) else np.int64)
         orc.lib().orc_sample_poly(kind, k.ctypes.data_as(ctypes.c_void_p), tag, prime, op, obj, n,
-                                  q, ell, cdt.ctypes.data_as(ctypes.c_void_p),
+                                  q_, ell, cdt.ctypes.data_as(ctypes.c_void_p),
                                   out.ctypes.data_as(ctypes.c_void_p))
         return out
 
-    ks = openssl_keystream(key, 0, nonce_bytes(4, 1, 5, 6), 16 * n)
-    want = [int.from_bytes(ks[16 * j:16 * j + 16], "little") % q for j in range(n)]
-    assert sample(0, 4, 1, 5, 6).tolist() == want
+    # Uniform mod q: the low 50 bits of draw j if below q, else the low 50 bits of draw j of
+    # the fallback stream (bit 31 of the tag word set) mod q.  A q just above 2^49 rejects
+    # about half the draws, so both streams are read; the parameter rule's q takes the first.
+    m50 = (1 << 50) - 1
+    ks = openssl_keystream(key, 0, nonce_bytes(4, 1, 5, 6), 8 * n)
+    fb = openssl_keystream(key, 0, nonce_bytes(4 | (1 << 31), 1, 5, 6), 8 * n)
+    for qq in (q, (1 << 49) + 9):
+        want, rejected = [], 0
+        for j in range(n):
+            x = int.from_bytes(ks[8 * j:8 * j + 8], "little") & m50
+            if x >= qq:
+                rejected += 1
+                x = (int.from_bytes(fb[8 * j:8 * j + 8], "little") & m50) % qq
+            want.append(x)
+        assert sample(0, 4, 1, 5, 6, q_=qq).tolist() == want
+        assert (rejected == 0) if qq == q else (10 < rejected < 54)
 
     ks = openssl_keystream(key, 0, nonce_bytes(9, 0, 5, 6), 8 * n)
     d = [int.from_bytes(ks[8 * j:8 * j + 8], "little") for j in range(n)]
