@@ -42,7 +42,9 @@
  * Randomness (encryption noise and masks): ChaCha20 (RFC 8439, section 2.3)
  * keyed by the caller's 32-byte seed, nonce (tag | prime << 8, op_id,
  * object index), block counter from 0; the 64-bit draw j is keystream bytes
- * [8j, 8j+8) and the 128-bit draw j bytes [16j, 16j+16), little-endian.
+ * [8j, 8j+8), little-endian.  A uniform residue mod q_l is the low 50 bits x of
+ * draw j when x < q_l, else the low 50 bits of draw j of the fallback stream
+ * (bit 31 of the tag word set) mod q_l.
  * op_id is the only per-call nonce: a (seed, op_id) pair must never serve two
  * different inputs (two encryptions of different plaintexts under one pair
  * share a and e; two replies under one server pair share the mask).  Repeating

@@ -191,24 +191,9 @@ __device__ __forceinline__ void chacha_block(const Key &k, uint32_t counter, uin
 
 // Nonce word 0 of a stream.
 __device__ __forceinline__ uint32_t nonce0(uint32_t tag, uint32_t prime) { return tag | (prime << 8); }
-
-// (hi 2^64 + lo) mod q for q < 2^50: Horner over 32-bit words, each step
-// (r 2^32 + w) mod q with r 2^32 formed exactly as a double.
-__device__ __forceinline__ uint64_t mod_u128(uint64_t lo, uint64_t hi, uint64_t q, double p,
-                                             double pinv)
-{
-    const uint32_t w[4] = {(uint32_t)(hi >> 32), (uint32_t)hi, (uint32_t)(lo >> 32), (uint32_t)lo};
-    int64_t r = (int64_t)w[0];
-#pragma unroll
-    for (int i = 1; i < 4; ++i) {
-        const double h = (double)r * 4294967296.0;
-        int64_t t = (int64_t)reduce(h, p, pinv) + (int64_t)w[i];
-        if (t < 0) t += (int64_t)q;
-        if (t >= (int64_t)q) t -= (int64_t)q;
-        r = t;
-    }
-    return (uint64_t)r;
-}
+// Bit of the first nonce word that selects a stream's fallback stream (the draws
+// that replace rejected uniform residues).
+constexpr uint32_t kFallbackTag = 0x80000000u;
 
 __device__ __forceinline__ int64_t ternary_of(uint64_t v) { return (int64_t)(v % 3u) - 1; }
 

@@ -431,13 +431,13 @@ void switched_params(const Ctx &c, DevParams &d, double *qd_inv)
 // ---- sampling kernels --------------------------------------------------------
 
 // One thread per ChaCha20 block of stream (tag, prime, op, obj0 + o):
-// KIND 0 writes four uniform residues mod q_prime (uint64), 1 eight ternary
+// KIND 0 writes eight uniform residues mod q_prime (uint64), 1 eight ternary
 // values (int64), 2 eight Gaussian values (int64), 3 eight Z_{2^l} values (uint64).
 template <int KIND>
 __device__ __forceinline__ void sample_block(const Key &key, uint32_t op, const SampleJob &jb,
                                              long gid, const DevParams &dp)
 {
-    const int per = KIND == 0 ? 4 : 8;
+    constexpr int per = 8;
     const int nblk = dp.N / per;
     if (gid >= (long)nblk * jb.nprime * jb.nobj) return;
     const int b = (int)(gid % nblk);
@@ -449,10 +449,28 @@ __device__ __forceinline__ void sample_block(const Key &key, uint32_t op, const 
                  jb.obj0 + (uint32_t)o, w);
     const size_t base = (size_t)o * jb.obj_stride + (size_t)li * jb.prime_stride + (size_t)b * per;
     if (KIND == 0) {
+        // Uniform mod q_l: the low 50 bits of the draw when below q_l; the rare
+        // rejected draws (probability below 2^-29) take the same draw of the
+        // fallback stream, whose residue below 2^50 < 2 q_l is reduced by one
+        // subtraction.
+        const uint64_t m50 = (1ull << 50) - 1, q = dp.q[l];
         uint64_t *dst = (uint64_t *)jb.out + base;
+        uint32_t rejected = 0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            dst[i] = mod_u128(word64(w, 2 * i), word64(w, 2 * i + 1), dp.q[l], dp.p[l], dp.pinv[l]);
+        for (int i = 0; i < 8; ++i) {
+            const uint64_t x = word64(w, i) & m50;
+            dst[i] = x;
+            rejected |= (x >= q ? 1u : 0u) << i;
+        }
+        if (rejected) {
+            chacha_block(key, (uint32_t)b, nonce0(jb.tag, (uint32_t)l) | kFallbackTag, op,
+                         jb.obj0 + (uint32_t)o, w);
+            for (int i = 0; i < 8; ++i) {
+                if (!((rejected >> i) & 1u)) continue;
+                const uint64_t x = word64(w, i) & m50;
+                dst[i] = x >= q ? x - q : x;
+            }
+        }
     } else if (KIND == 1) {
         int64_t *dst = (int64_t *)jb.out + base;
 #pragma unroll
@@ -507,7 +525,7 @@ int launch_samples(const Ctx &c, const Key &key, uint32_t op, SampleJobs js, hip
     unsigned grid = 0;
     for (int k = 0; k < js.n; ++k) {
         SampleJob &jb = js.job[k];
-        const int per = jb.kind == 0 ? 4 : 8;
+        const int per = 8;
         const long total = jb.nobj > 0 ? (long)(c.dp.N / per) * jb.nprime * jb.nobj : 0;
         jb.blocks = (uint32_t)((total + threads - 1) / threads);
         grid += jb.blocks;

@@ -79,6 +79,28 @@ def test_samplers_bitexact(orc, kind, tag, prime):
     assert np.array_equal(got, want.view(np.uint64))
 
 
+def test_uniform_fallback_bitexact(orc):
+    """A stream whose draw j the rejection rule refuses (tests/golden/uniform_fallback.json, found
+    with the oracle's sampler): the GPU sampler takes the fallback stream there, as the oracle."""
+    import ctypes
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "uniform_fallback.json")))
+    log(f"uniform fallback at N={g['N']} prime {g['prime']} obj {g['obj']} draw {g['j']}")
+    ctx = context(g["N"], g["L"], 41, 14, True)
+    assert int(ctx.primes()[g["prime"]]) == g["q"]
+    seed = workloads.seed("client", g["request"])
+    got = u64(pimm.sample_poly(ctx, 0, seed, g["tag"], g["prime"], g["op"], g["obj"]))
+    pyp = orc.Params(g["N"], g["L"], 41, 14)
+    k = np.frombuffer(seed, np.uint8).copy()
+    want = np.zeros(g["N"], np.uint64)
+    orc.lib().orc_sample_poly(0, k.ctypes.data_as(ctypes.c_void_p), g["tag"], g["prime"], g["op"],
+                              g["obj"], g["N"], g["q"], 41, pyp.cdt_arr.ctypes.data_as(ctypes.c_void_p),
+                              want.ctypes.data_as(ctypes.c_void_p))
+    assert int(want[g["j"]]) != g["first_draw_low50"]
+    assert np.array_equal(got, want)
+
+
 @pytest.mark.parametrize("N,L", [(4096, 2), (8192, 3)])
 def test_poly_mul_bitexact(orc, N, L):
     import ctypes

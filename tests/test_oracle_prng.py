@@ -100,6 +100,35 @@ def test_samplers_read_the_keystream(orc):
     assert sample(1, 1, 0, 5, 6).tolist() == [v % 3 - 1 for v in d]
 
 
+def test_uniform_fallback_fixture(orc):
+    """The stored stream position (tests/golden/uniform_fallback.json, written by its script from
+    the oracle's sampler) has a rejected first draw: the sampler returns the fallback stream's draw
+    there, read back through the 64-bit draw function, and the first draw everywhere else."""
+    import json
+    import os
+
+    from paper_2305_18396_amd import workloads
+
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "uniform_fallback.json")))
+    p = orc.Params(g["N"], g["L"], 41, 14)
+    q = int(p.q[g["prime"]])
+    assert q == g["q"]
+    key = np.frombuffer(workloads.seed("client", g["request"]), np.uint8).copy()
+    kp = key.ctypes.data_as(ctypes.c_void_p)
+    out = np.zeros(g["N"], np.uint64)
+    orc.lib().orc_sample_poly(0, kp, g["tag"], g["prime"], g["op"], g["obj"], g["N"], q, 41,
+                              p.cdt_arr.ctypes.data_as(ctypes.c_void_p),
+                              out.ctypes.data_as(ctypes.c_void_p))
+    m50 = (1 << 50) - 1
+    first = [orc.lib().orc_draw64(kp, g["tag"], g["prime"], g["op"], g["obj"], j) & m50
+             for j in range(g["N"])]
+    j = g["j"]
+    assert first[j] == g["first_draw_low50"] and first[j] >= q
+    fb = orc.lib().orc_draw64(kp, g["tag"] | (1 << 31), g["prime"], g["op"], g["obj"], j) & m50
+    assert int(out[j]) == fb % q != first[j]
+    assert [int(v) for i, v in enumerate(out) if i != j] == [v for i, v in enumerate(first) if i != j]
+
+
 def _cdt_mpmath():
     """T[k] = floor(2^63 P(|e| <= k)), k = 0..18, for width 3.2 cut at |e| <= 19 (50 digits)."""
     mpmath = pytest.importorskip("mpmath")
