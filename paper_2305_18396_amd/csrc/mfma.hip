@@ -171,37 +171,38 @@ __global__ __launch_bounds__(kMfmaThreads, 2) void k_mac_mfma(MfmaArgs g, DevPar
 
     // Inputs: thread (q, j) takes inner blocks 4q .. 4q+3 of column j for the 8 slots.  All
     // loads are issued before any is used (absent blocks read a valid line and are zeroed
-    // afterwards), so their latencies overlap.
-    {
-        const int j = tid & 15, q = tid >> 4;
-        const int col = ct * 16 + j, kb = col >> 1, comp = col & 1;
-        double2 v[4][kMfmaSlots / 2];
-        bool ok[4];
+    // afterwards), so their latencies overlap.  The first half of the slots is split into
+    // digits and its products start while the second half's loads are still arriving; the
+    // second half goes to LDS before slot kMfmaSlots / 2.
+    const int jq = tid & 15, qq = tid >> 4;
+    const int colq = ct * 16 + jq, kbq = colq >> 1, compq = colq & 1;
+    double2 v[4][kMfmaSlots / 2];
+    bool ok[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int jb = 4 * qq + r;
+        ok[r] = jb < g.R && kbq < g.K;
+        const double2 *src = (const double2 *)(g.Ch +
+            (ok[r] ? ((line0 + (size_t)jb * g.K + kbq) * 2 + compq) * 16 + h * 8 : 0));
+#pragma unroll
+        for (int s2 = 0; s2 < kMfmaSlots / 2; ++s2) v[r][s2] = src[s2];
+    }
+    uint32_t *ld32 = (uint32_t *)lds;
+    const int grpq = (qq >> 2) ^ ((jq >> 2) & 3);
+    auto to_lds = [&](int s) {
+        uint64_t w[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int jb = 4 * q + r;
-            ok[r] = jb < g.R && kb < g.K;
-            const double2 *src = (const double2 *)(g.Ch +
-                (ok[r] ? ((line0 + (size_t)jb * g.K + kb) * 2 + comp) * 16 + h * 8 : 0));
-#pragma unroll
-            for (int s2 = 0; s2 < kMfmaSlots / 2; ++s2) v[r][s2] = src[s2];
+            const double x = (s & 1) ? v[r][s >> 1].y : v[r][s >> 1].x;
+            w[r] = ok[r] ? digits7(x) : 0;
         }
-        uint32_t *ld32 = (uint32_t *)lds;
-        const int grp = (q >> 2) ^ ((j >> 2) & 3);
 #pragma unroll
-        for (int s = 0; s < kMfmaSlots; ++s) {
-            uint64_t w[4];
+        for (int b = 0; b < 7; ++b)
+            ld32[s * kSlotLds * 4 + (b * 16 + jq) * 16 + grpq * 4 + (qq & 3)] =
+                gather_byte(w[0], w[1], w[2], w[3], b);
+    };
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const double x = (s & 1) ? v[r][s >> 1].y : v[r][s >> 1].x;
-                w[r] = ok[r] ? digits7(x) : 0;
-            }
-#pragma unroll
-            for (int b = 0; b < 7; ++b)
-                ld32[s * kSlotLds * 4 + (b * 16 + j) * 16 + grp * 4 + (q & 3)] =
-                    gather_byte(w[0], w[1], w[2], w[3], b);
-        }
-    }
+    for (int s = 0; s < kMfmaSlots / 2; ++s) to_lds(s);
     __syncthreads();
 
     const int wv = tid >> 6, lane = tid & 63;
@@ -226,6 +227,12 @@ __global__ __launch_bounds__(kMfmaThreads, 2) void k_mac_mfma(MfmaArgs g, DevPar
     }
 #pragma unroll
     for (int s = 0; s < kMfmaSlots; ++s) {
+        if (s == kMfmaSlots / 2) {
+            // Second half of the slots: their regions are untouched by the first half's results.
+#pragma unroll
+            for (int s1 = kMfmaSlots / 2; s1 < kMfmaSlots; ++s1) to_lds(s1);
+            __syncthreads();
+        }
         v4i T[13];
         if (active) {
             v4i B[7];
