@@ -553,6 +553,32 @@ def pi_matmul(params: Params, plan: Plan, X: np.ndarray, W: np.ndarray, client_s
                 smask=sm, Y0=Y0, Y1=Y1, outs=outs)
 
 
+def pi_matmul_grouped(params: Params, plan: Plan, Xs, Ws, client_seed: bytes, server_seed: bytes,
+                      op_id: int = 0, keys=None):
+    """G products of one shape (one plan), Y_p = X_p W_p, run as one protocol call: the G
+    inputs are encrypted together, input ciphertext x of product p being ciphertext p*I + x of
+    the group, and output ciphertext y of product p being p*O + y of the group (the objects of
+    the re-randomisation and mask streams).  Each product follows Algorithm 1 on its own
+    blocks; only the stream objects tie them together.
+    -> dict with the group's ct, acc, acc_rr, c1, c0s (stacked, product-major) and the shares
+    Y0, Y1 [G][n][m]."""
+    G = len(Xs)
+    s, pk = keys if keys is not None else keygen(params, client_seed)
+    pt = np.concatenate([encode_input(plan, X) for X in Xs])
+    ct = encrypt(params, s, client_seed, op_id, pt)
+    local = np.arange(plan.O, dtype=np.uint32)
+    acc = np.concatenate([matmul(params, plan, encode_weights(plan, W), ct[p * plan.I:(p + 1) * plan.I],
+                                 local) for p, W in enumerate(Ws)])
+    group = np.arange(G * plan.O, dtype=np.uint32)
+    acc_rr = rerandomize(params, pk, server_seed, op_id, acc, group) if params.rerandomize else acc
+    c1, c0s, sm = mask_extract(params, plan, server_seed, op_id, acc_rr, group)
+    v = crt_round(params, decrypt_residues(params, plan, s, c1, c0s))
+    Y0 = np.stack([place_shares(plan, v[p * plan.O:(p + 1) * plan.O], local) for p in range(G)])
+    Y1 = np.stack([place_shares(plan, sm[p * plan.O:(p + 1) * plan.O], local) for p in range(G)])
+    return dict(s=s, pk=pk, pt=pt, ct=ct, acc=acc, acc_rr=acc_rr, c1=c1, c0s=c0s, smask=sm,
+                Y0=Y0, Y1=Y1)
+
+
 def fc_complete(params: Params, X1: np.ndarray, W: np.ndarray, bias, Y1: np.ndarray) -> np.ndarray:
     """Server side of a fully connected layer y = x W + b on additive shares (section 3.1, the
     linear layers).  The input x is shared as X0 (client) + X1 (server) mod 2^l; Pi_MatMul on
