@@ -105,12 +105,18 @@ typedef struct {
  *                                     entry k*mb + i for position k*mb*rb + i*rb + rb-1
  *   share     [n][m]          uint64  one party's share of Y
  *   weights   device bytes held by a weight cache for this plan
- *   workspace bytes of scratch that encrypt, matmul, mask_share and decrypt need */
+ *   workspace bytes of scratch that encrypt, matmul, mask_share and decrypt need
+ * groups: G >= 1 products of this one shape run as one (pimm_plan_create_grouped;
+ * 1 otherwise).  Then I = G*R*K, O = G*M*K, Wb = G*M*R, P = G*M*R*K and every byte
+ * size count all G products: input ciphertext x of product p is ciphertext
+ * p*R*K + x of the plan, output y of product p is p*M*K + y, and X, W and the
+ * shares are [G][n][r], [G][r][m] and [G][n][m].  M, R and K stay per product. */
 typedef struct {
     uint32_t n, r, m, mb, rb, nb, M, R, K, I, O, Wb;
     uint64_t P;
     uint64_t pt_bytes, ct_bytes, acc_bytes, c1_bytes, c0s_bytes, share_bytes;
     uint64_t weights_bytes, workspace_bytes;
+    uint32_t groups;
 } pimm_plan_info;
 
 /* ---- context -------------------------------------------------------------- */
@@ -159,6 +165,20 @@ int pimm_switch_ok(const pimm_params *params, const pimm_plan_info *info, uint64
  *                        nb = min(n, N/(mb rb)); ties to larger nb, then larger mb. */
 int pimm_plan_create(pimm_ctx *ctx, uint32_t n, uint32_t r, uint32_t m, uint32_t mb, uint32_t rb,
                      uint32_t nb, uint32_t d_fix, pimm_plan **out);
+/* G independent products of one shape, Y_p[n][m] = X_p[n][r] W_p[r][m], run as one:
+ * every call on the plan does the work of all G in the same launches (many small
+ * products, such as the attention cross terms of Eq. 2 -- the 24 products of one
+ * phase of a BERT-base layer -- otherwise leave most of the device idle).  The
+ * block plan is pimm_plan_create's for one product; the layouts are in
+ * pimm_plan_info.  Each product follows Algorithm 1 on its own blocks; the group
+ * shares op_id, and the stream objects of the products are disjoint (ciphertext
+ * p*R*K + x, output p*M*K + y).  Grouped plans take the FP64 vector product with
+ * one column block per thread (tiles 4x1, 8x1, 16x1); pimm_fc_complete, pimm_batch_*
+ * and the matrix-core schedule refuse them (PIMM_E_UNSUPPORTED).  groups in
+ * [1, 65536]; groups = 1 is pimm_plan_create. */
+int pimm_plan_create_grouped(pimm_ctx *ctx, uint32_t n, uint32_t r, uint32_t m, uint32_t mb,
+                             uint32_t rb, uint32_t nb, uint32_t d_fix, uint32_t groups,
+                             pimm_plan **out);
 int pimm_plan_destroy(pimm_plan *plan);
 int pimm_plan_query(const pimm_plan *plan, pimm_plan_info *info);
 /* Schedule of pimm_matmul's slot-wise products: each thread owns mac_rows output

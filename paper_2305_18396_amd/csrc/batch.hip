@@ -61,7 +61,7 @@ template <int LOGN>
 __device__ __forceinline__ void run_in(const BatchItemDev &it, int poly, double *ws,
                                        const DevParams &dp, double *lds)
 {
-    ntt_fwd_block<LOGN, kNttThreads>(LoadU64{it.ct, LOGN}, StoreCtTiled{ws + it.chat_off, LOGN, dp.L, it.K, it.R},
+    ntt_fwd_block<LOGN, kNttThreads>(LoadU64{it.ct, LOGN}, StoreCtTiled{ws + it.chat_off, LOGN, dp.L, it.K, it.R, 1u},
                         dp, poly, lds);
 }
 
@@ -141,6 +141,7 @@ struct ColsGroup {
     {
         return (size_t)items[cols[j].item].K * 2 * L * N;
     }
+    __device__ __forceinline__ int row_end(const MacShape &sh) const { return sh.M; }
 };
 
 // Phased product: one unit per (prime, slot chunk, slot group, column tile, row-tile
@@ -510,6 +511,8 @@ int pimm_batch_create(const pimm_batch_item *items, uint32_t count, pimm_batch *
             return set_error(PIMM_E_ARG, "pimm_batch_create: items on different contexts");
         if (!weights_fit(it.weights, it.plan))
             return set_error(PIMM_E_ARG, "pimm_batch_create: item %u weights do not fit its plan", i);
+        if (it.plan->info.groups > 1)
+            return set_error(PIMM_E_UNSUPPORTED, "pimm_batch_create: item %u has a grouped plan", i);
     }
     pimm_batch *b = new pimm_batch();
     b->ctx = ctx;

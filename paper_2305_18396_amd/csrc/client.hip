@@ -15,8 +15,11 @@ __global__ void k_encode_input(const uint64_t *X, uint64_t *pt, pimm_plan_info f
     const size_t N = (size_t)1 << logn;
     const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= (size_t)f.I * N) return;
-    const uint32_t x = (uint32_t)(gid >> logn);
+    const uint32_t xg = (uint32_t)(gid >> logn);
     const uint32_t jcoef = (uint32_t)(gid & (N - 1));
+    // Input x of product g of a grouped plan reads X[g].
+    const uint32_t I1 = f.R * f.K, g = xg / I1, x = xg - g * I1;
+    X += (size_t)g * f.n * f.r;
     const uint32_t jb = x / f.K, kb = x % f.K;
     const uint32_t D = f.mb * f.rb;
     uint64_t v = 0;
@@ -195,15 +198,15 @@ __global__ void k_decode(const uint64_t *c0s, const uint64_t *cs, uint64_t *shar
     if (gid >= (size_t)f.O * per) return;
     const uint32_t o = (uint32_t)(gid / per), idx = (uint32_t)(gid % per);
     const uint32_t k = idx / f.mb, i = idx % f.mb;
-    const uint32_t ib = o / f.K, kb = o % f.K;
-    const uint32_t row = kb * f.nb + k, col = ib * f.mb + i;
+    const OutPos op = out_pos(o, f);
+    const uint32_t row = op.kb * f.nb + k, col = op.ib * f.mb + i;
     if (row >= f.n || col >= f.m) return;
     uint64_t res[kMaxL];
     for (int l = 0; l < dp.L; ++l) {
         const size_t at = ((size_t)o * dp.L + l) * per + idx;
         res[l] = add_mod(c0s[at], cs[at], dp.q[l]);
     }
-    share[(size_t)row * f.m + col] = crt_round(res, dp);
+    share[(size_t)op.g * f.n * f.m + (size_t)row * f.m + col] = crt_round(res, dp);
 }
 
 // Decryption of a reply under the moduli of `c` (the context's, or the first L - 1

@@ -69,6 +69,17 @@ __device__ __forceinline__ PolyIx poly_ix(int poly, int L)
     return PolyIx{poly, poly - x * L, x};
 }
 
+// Output ciphertext y of a plan (of a grouped plan too): y = (g*M + ib)*K + kb for
+// product g, block row ib and block column kb; its share entries go to share + g*n*m.
+struct OutPos {
+    uint32_t g, ib, kb;
+};
+__host__ __device__ __forceinline__ OutPos out_pos(uint32_t y, const pimm_plan_info &f)
+{
+    const uint32_t rowblk = y / f.K;
+    return OutPos{rowblk / f.M, rowblk % f.M, y - rowblk * f.K};
+}
+
 // 32-byte ChaCha20 key as little-endian words.
 struct Key {
     uint32_t w[8];

@@ -259,19 +259,21 @@ uint64_t fused_workspace_bytes(const Ctx &c, const pimm_plan_info &f)
 static void fill_info(const Ctx &c, pimm_plan_info &f)
 {
     const uint64_t N = c.params.N, L = c.params.L;
+    if (f.groups < 1) f.groups = 1;
+    const uint32_t G = f.groups;
     f.M = (uint32_t)ceil_div(f.m, f.mb);
     f.R = (uint32_t)ceil_div(f.r, f.rb);
     f.K = (uint32_t)ceil_div(f.n, f.nb);
-    f.I = f.R * f.K;
-    f.O = f.M * f.K;
-    f.Wb = f.M * f.R;
-    f.P = (uint64_t)f.M * f.R * f.K;
+    f.I = G * f.R * f.K;
+    f.O = G * f.M * f.K;
+    f.Wb = G * f.M * f.R;
+    f.P = (uint64_t)G * f.M * f.R * f.K;
     f.pt_bytes = (uint64_t)f.I * N * 8;
     f.ct_bytes = (uint64_t)f.I * 2 * L * N * 8;
     f.acc_bytes = (uint64_t)f.O * 2 * L * N * 8;
     f.c1_bytes = (uint64_t)f.O * L * N * 8;
     f.c0s_bytes = (uint64_t)f.O * L * f.mb * f.nb * 8;
-    f.share_bytes = (uint64_t)f.n * f.m * 8;
+    f.share_bytes = (uint64_t)G * f.n * f.m * 8;
     f.weights_bytes = (uint64_t)f.Wb * L * N * 8;
     if (mfma_eligible(f)) f.weights_bytes += digit_cache_bytes(c, f);  // digit form (mfma.h)
     // Scratch of each call (see the call's implementation for the layout).
@@ -285,10 +287,12 @@ static void fill_info(const Ctx &c, pimm_plan_info &f)
     if (mm > ws) ws = mm;
     if (msk > ws) ws = msk;
     if (dec > ws) ws = dec;
-    uint32_t fc_kc = 0, fc_pieces = 0;
-    fc_cut(f.n, f.r, f.m, &fc_kc, &fc_pieces);
-    const uint64_t fc = (uint64_t)fc_pieces * f.n * f.m * 2 * 8;  // the FC completion's partial sums
-    if (fc > ws) ws = fc;
+    if (G == 1) {
+        uint32_t fc_kc = 0, fc_pieces = 0;
+        fc_cut(f.n, f.r, f.m, &fc_kc, &fc_pieces);
+        const uint64_t fc = (uint64_t)fc_pieces * f.n * f.m * 2 * 8;  // the FC completion's partial sums
+        if (fc > ws) ws = fc;
+    }
     f.workspace_bytes = ws;
 }
 
@@ -688,6 +692,31 @@ int pimm_plan_create(pimm_ctx *ctx, uint32_t n, uint32_t r, uint32_t m, uint32_t
     pimm_plan_info f;
     int rc = plan_rule(*ctx, n, r, m, mb, rb, nb, d_fix, f);
     if (rc) return rc;
+    pimm_plan *p = new pimm_plan();
+    p->ctx = ctx;
+    p->info = f;
+    *out = p;
+    return PIMM_OK;
+}
+
+int pimm_plan_create_grouped(pimm_ctx *ctx, uint32_t n, uint32_t r, uint32_t m, uint32_t mb,
+                             uint32_t rb, uint32_t nb, uint32_t d_fix, uint32_t groups,
+                             pimm_plan **out)
+{
+    if (!ctx || !out) return set_error(PIMM_E_ARG, "pimm_plan_create_grouped: NULL argument");
+    if (groups < 1 || groups > 65536)
+        return set_error(PIMM_E_ARG, "pimm_plan_create_grouped: groups = %u not in [1, 65536]", groups);
+    if (!n || !r || !m) return set_error(PIMM_E_SHAPE, "empty matrix %u x %u x %u", n, r, m);
+    pimm_plan_info f;
+    int rc = plan_rule(*ctx, n, r, m, mb, rb, nb, d_fix, f);
+    if (rc) return rc;
+    f.groups = groups;
+    fill_info(*ctx, f);
+    const uint64_t L = ctx->params.L;
+    if ((uint64_t)groups * f.M * f.R * L >= (1ull << 31) ||
+        (uint64_t)groups * f.R * f.K * 2 * L >= (1ull << 31) ||
+        (uint64_t)groups * f.M * f.K * 2 * L >= (1ull << 31))
+        return set_error(PIMM_E_SHAPE, "grouped plan has too many blocks for one launch");
     pimm_plan *p = new pimm_plan();
     p->ctx = ctx;
     p->info = f;

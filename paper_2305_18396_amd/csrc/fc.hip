@@ -162,6 +162,8 @@ int pimm_fc_complete(const pimm_plan *plan, const pimm_weights *w, const uint64_
         return set_error(PIMM_E_ARG, "pimm_fc_complete: weights were made for another shape or block split");
     const Ctx &c = *plan->ctx;
     const pimm_plan_info &f = plan->info;
+    if (f.groups > 1 || !w->d_w_plain)
+        return set_error(PIMM_E_UNSUPPORTED, "pimm_fc_complete: grouped plans are not supported");
     const int ell = (int)c.params.log2_t;
     if (!fc_exact(f, ell, (uint64_t)w->wmax))
         return set_error(PIMM_E_ARG,

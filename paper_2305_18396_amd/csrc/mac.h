@@ -55,6 +55,30 @@ struct ColsOne {
         return Ah + ((size_t)col * 2 * L + l) * N + z;
     }
     __device__ __forceinline__ size_t arow(int) const { return (size_t)s.K * 2 * L * N; }
+    // One past the last weight row this tile may use.
+    __device__ __forceinline__ int row_end(const MacShape &sh) const { return sh.M; }
+};
+
+// Columns of product g of a grouped plan (G products of one shape): the input layout
+// holds the columns of all G products (g*K1 + kb), and the accumulators are
+// [G*M1*K1][2][L][N] with weight rows g*M1 + ib.  The shape passed with it has M = G*M1
+// rows and K = G*K1 columns (the strides of the weight and input layouts).
+struct ColsGrouped {
+    const double *Ct;  // c^ [L][chunks][G*K1][R][2][256]
+    double *Ah;        // acc^ [G*M1*K1][2][L][N]
+    MacShape s;
+    int L, N, K1, g, M1;
+    __device__ __forceinline__ int ncols() const { return K1; }
+    __device__ __forceinline__ const double *c(int col, int l, int zc, int zz) const
+    {
+        return Ct + c_tile_base(s, l, zc, g * K1 + col) + zz;
+    }
+    __device__ __forceinline__ double *a(int col, int l, int z) const
+    {
+        return Ah + ((size_t)col * 2 * L + l) * N + z;
+    }
+    __device__ __forceinline__ size_t arow(int) const { return (size_t)K1 * 2 * L * N; }
+    __device__ __forceinline__ int row_end(const MacShape &) const { return (g + 1) * M1; }
 };
 
 // Inner blocks [jb0, jb1) of one tile of G rows (ib0 ..) and KB columns (kb0 ..
@@ -69,7 +93,8 @@ __device__ __forceinline__ void mac_range(const double *__restrict__ Wt, const C
 {
     const int L = dp.L, N = dp.N;
     const double p = dp.p[l], pinv = dp.pinv[l];
-    const int rows = s.M - ib0 < G ? s.M - ib0 : G;
+    const int re = cs.row_end(s);
+    const int rows = re - ib0 < G ? re - ib0 : G;
     const int cols = cs.ncols() - kb0 < KB ? cs.ncols() - kb0 : KB;
     const double *wp = Wt + w_tile_base(s, l, zc) + ((size_t)ib0 * s.R + jb0) * 256 + zz;
     const size_t wrow = (size_t)s.R * 256;
@@ -231,18 +256,21 @@ struct StoreWeightTiled {
     }
 };
 
-// Input ciphertext x = jb*K + kb, component c, prime l: poly = (x*2 + c)*L + l.
+// Input ciphertext g*R*K + jb*K + kb (product g of G, inner block jb, column block kb),
+// component c, prime l: poly = (x*2 + c)*L + l.  The layout has G*K columns, column
+// g*K + kb for product g.
 struct StoreCtTiled {
     double *out;
     int logn, L;
-    uint32_t K, R;
+    uint32_t K, R, G;
     __device__ void operator()(const PolyIx &pi, int z, double v, double, double) const
     {
-        const uint32_t x = (uint32_t)(pi.x >> 1), c = (uint32_t)(pi.x & 1), l = (uint32_t)pi.l;
-        const uint32_t jb = x / K, kb = x % K;
+        const uint32_t xg = (uint32_t)(pi.x >> 1), c = (uint32_t)(pi.x & 1), l = (uint32_t)pi.l;
+        const uint32_t g = xg / (K * R), x = xg - g * (K * R);
+        const uint32_t jb = x / K, kb = g * K + x % K;
         const size_t chunks = (size_t)1 << (logn - 8);
         const size_t zc = (size_t)(z >> 8), zz = (size_t)(z & 255);
-        out[(((((size_t)l * chunks + zc) * K + kb) * R + jb) * 2 + c) * 256 + zz] = v;
+        out[(((((size_t)l * chunks + zc) * ((size_t)G * K) + kb) * R + jb) * 2 + c) * 256 + zz] = v;
     }
 };
 

@@ -48,6 +48,30 @@ __global__ __launch_bounds__(256) void k_mac_sk(const double *__restrict__ Wt,
     }
 }
 
+// Grouped plans (G products of one shape): one workgroup per (prime, chunk, product g,
+// column block, row tile of GR rows within the product), the whole inner dimension,
+// sums stored (no split tiles, no zeroing).  The 256 threads take the chunk's 256
+// slots.  Logical index t = (((l * chunks + zc) * G + g) * K1 + kb) * mt1 + ibt.
+template <int GR>
+__global__ __launch_bounds__(256) void k_mac_grouped(const double *__restrict__ Wt,
+                                                     const double *__restrict__ Ct,
+                                                     double *__restrict__ Ah, MacShape sh, int M1,
+                                                     int K1, int mt1, DevParams dp)
+{
+    uint32_t t = xcd_local(blockIdx.x, gridDim.x);
+    const int ibt = (int)(t % (uint32_t)mt1);
+    t /= (uint32_t)mt1;
+    const int kb = (int)(t % (uint32_t)K1);
+    t /= (uint32_t)K1;
+    const uint32_t groups = (uint32_t)(sh.M / M1);
+    const int g = (int)(t % groups);
+    t /= groups;
+    const int zc = (int)(t % (uint32_t)sh.chunks);
+    const int l = (int)(t / (uint32_t)sh.chunks);
+    mac_tile<GR, 1>(Wt, ColsGrouped{Ct, Ah, sh, dp.L, dp.N, K1, g, M1}, sh, dp, l, zc,
+                    (int)threadIdx.x, kb, g * M1 + ibt * GR, 0, sh.R, 0);
+}
+
 __global__ void k_fill_zero(double *p, size_t n)
 {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -82,9 +106,30 @@ int launch_mac_gk(const Ctx &c, const pimm_plan_info &f, int waves, const double
     return check_hip(hipGetLastError(), "mac launch");
 }
 
+template <int GR>
+int launch_mac_grouped(const Ctx &c, const pimm_plan_info &f, const double *Wt, const double *Ct,
+                       double *Ah, hipStream_t s)
+{
+    const MacShape sh{(int)(f.groups * f.M), (int)f.R, (int)(f.groups * f.K), (int)(c.params.N >> 8)};
+    const int mt1 = (int)((f.M + GR - 1) / GR);
+    const uint64_t grid = (uint64_t)c.params.L * sh.chunks * f.groups * f.K * mt1;
+    if (grid > 0x7fffffffull) return set_error(PIMM_E_SHAPE, "grouped product grid too large");
+    ProfScope prof("mac", s);
+    hipLaunchKernelGGL((k_mac_grouped<GR>), dim3((unsigned)grid), dim3(256), 0, s, Wt, Ct, Ah, sh,
+                       (int)f.M, (int)f.K, mt1, c.dp);
+    return check_hip(hipGetLastError(), "grouped mac launch");
+}
+
 int launch_mac(const Ctx &c, const pimm_plan_info &f, int G, int KB, int waves, const double *Wt,
                const double *Ct, double *Ah, bool zeroed, hipStream_t s)
 {
+    if (f.groups > 1) {
+        // Every accumulator is stored by exactly one workgroup: no zeroing needed.
+        if (KB == 1 && G == 4) return launch_mac_grouped<4>(c, f, Wt, Ct, Ah, s);
+        if (KB == 1 && G == 8) return launch_mac_grouped<8>(c, f, Wt, Ct, Ah, s);
+        if (KB == 1 && G == 16) return launch_mac_grouped<16>(c, f, Wt, Ct, Ah, s);
+        return set_error(PIMM_E_UNSUPPORTED, "grouped plans take product tiles 4x1, 8x1 or 16x1");
+    }
 #define PIMM_LAUNCH_MAC(g, kb) \
     if (G == g && KB == kb) return launch_mac_gk<g, kb>(c, f, waves, Wt, Ct, Ah, zeroed, s);
     PIMM_MAC_SHAPES(PIMM_LAUNCH_MAC)

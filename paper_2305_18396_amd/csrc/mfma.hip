@@ -281,7 +281,7 @@ static double balanced_pow2(uint64_t q, int e)
     return v > q / 2 ? -(double)(q - v) : (double)v;
 }
 
-bool mfma_eligible(const pimm_plan_info &f) { return f.R <= 64 && f.K >= 8; }
+bool mfma_eligible(const pimm_plan_info &f) { return f.R <= 64 && f.K >= 8 && f.groups <= 1; }
 
 uint64_t digit_cache_bytes(const Ctx &c, const pimm_plan_info &f)
 {

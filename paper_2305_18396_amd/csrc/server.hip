@@ -27,16 +27,18 @@ namespace pimm {
 // balanced doubles, which must stay exact and below a few primes.
 constexpr unsigned long long kMaxWeight = 1ull << 48;
 
+// Weight block w = (g*M + ib)*R + jb of product g (W: [G][r][m]).
 struct LoadWeights {
     const int64_t *W;
-    uint32_t r, m, mb, rb, R;
+    uint32_t r, m, mb, rb, R, M;
     int L;
     __device__ double operator()(const PolyIx &pi, int j, double, double) const
     {
         const uint32_t uj = (uint32_t)j;
         if (uj >= mb * rb) return 0.0;
         const uint32_t w = (uint32_t)pi.x;
-        const uint32_t ib = w / R, jb = w % R;
+        const uint32_t rowblk = w / R, jb = w % R, g = rowblk / M, ib = rowblk % M;
+        const int64_t *W = this->W + (size_t)g * r * m;
         const uint32_t i = uj / rb, jj = rb - 1 - uj % rb;
         const uint32_t row = jb * rb + jj, col = ib * mb + i;
         if (row >= r || col >= m) return 0.0;
@@ -136,9 +138,9 @@ __global__ void k_mask_extract(Key key, uint32_t op, const uint64_t *acc, uint64
         const uint64_t a0 = acc[(((size_t)y * 2 + 0) * L + l) * N + pos];
         c0s[((size_t)y * L + l) * per + idx] = sub_mod(a0, mul_mod(dp.delta[l], sm, dp.p[l], dp.pinv[l]), q);
     }
-    const uint32_t ib = y / f.K, kb = y % f.K;
-    const uint32_t row = kb * f.nb + k, col = ib * f.mb + i;
-    if (row < f.n && col < f.m) share[(size_t)row * f.m + col] = sm;
+    const OutPos yp = out_pos(y, f);
+    const uint32_t row = yp.kb * f.nb + k, col = yp.ib * f.mb + i;
+    if (row < f.n && col < f.m) share[(size_t)yp.g * f.n * f.m + (size_t)row * f.m + col] = sm;
 }
 
 // ---- fused server step: product, re-randomisation, mask and reply ----------------
@@ -212,7 +214,8 @@ __global__ void k_mask_reply(Key key, uint32_t op, uint64_t *c0s, uint64_t *shar
     uint32_t w[16];
     chacha_block(key, b, nonce0(kTagMask, 0), op, y, w);
     const uint32_t per = f.mb * f.nb;
-    const uint32_t ib = y / f.K, kb = y % f.K;
+    const OutPos yp = out_pos(y, f);
+    share += (size_t)yp.g * f.n * f.m;
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
         const uint32_t pos = b * 8 + t;
@@ -224,7 +227,7 @@ __global__ void k_mask_reply(Key key, uint32_t op, uint64_t *c0s, uint64_t *shar
             uint64_t *dst = c0s + ((size_t)y * dp.L + l) * per + k * f.mb + i;
             *dst = sub_mod(*dst, mul_mod(dp.delta[l], sm, dp.p[l], dp.pinv[l]), dp.q[l]);
         }
-        const uint32_t row = kb * f.nb + k, col = ib * f.mb + i;
+        const uint32_t row = yp.kb * f.nb + k, col = yp.ib * f.mb + i;
         if (row < f.n && col < f.m) share[(size_t)row * f.m + col] = sm;
     }
 }
@@ -282,7 +285,8 @@ namespace pimm {
 bool weights_fit(const Weights *w, const Plan *plan)
 {
     const pimm_plan_info &a = w->info, &b = plan->info;
-    return w->ctx == plan->ctx && a.r == b.r && a.m == b.m && a.mb == b.mb && a.rb == b.rb;
+    return w->ctx == plan->ctx && a.r == b.r && a.m == b.m && a.mb == b.mb && a.rb == b.rb &&
+           a.groups == b.groups;
 }
 
 // The matrix-core product needs an eligible plan and the digit form of the weights.
@@ -317,7 +321,8 @@ int pimm_weights_create(const pimm_plan *plan, const int64_t *W, pimm_weights **
     if (rc) return rc;
     rc = check_hip(hipMemsetAsync(d_max, 0, sizeof *d_max, s), "memset absmax");
     if (!rc) {
-        hipLaunchKernelGGL(k_absmax, dim3(1024), dim3(256), 0, s, W, (size_t)f.r * f.m, d_max);
+        hipLaunchKernelGGL(k_absmax, dim3(1024), dim3(256), 0, s, W, (size_t)f.groups * f.r * f.m,
+                           d_max);
         rc = check_hip(hipGetLastError(), "absmax launch");
     }
     if (!rc) rc = check_hip(hipMemcpyAsync(&h_max, d_max, sizeof h_max, hipMemcpyDeviceToHost, s),
@@ -340,13 +345,14 @@ int pimm_weights_create(const pimm_plan *plan, const int64_t *W, pimm_weights **
     rc = check_hip(hipMalloc((void **)&w->d_w_hat, f64_bytes), "hipMalloc weights");
     if (!rc && mfma_eligible(f))
         rc = check_hip(hipMalloc(&w->d_w_dig, digit_cache_bytes(c, f)), "hipMalloc weight digits");
-    if (!rc)
+    // The FC completion's copy of W as doubles (plans of one product only).
+    if (!rc && f.groups == 1)
         rc = check_hip(hipMalloc((void **)&w->d_w_plain, (size_t)f.r * f.m * sizeof(double)),
                        "hipMalloc plain weights");
-    if (!rc) rc = weights_plain(W, w->d_w_plain, (size_t)f.r * f.m, s);
+    if (!rc && w->d_w_plain) rc = weights_plain(W, w->d_w_plain, (size_t)f.r * f.m, s);
     if (!rc)
-        rc = launch_fwd(c, LoadWeights{W, f.r, f.m, f.mb, f.rb, f.R, (int)c.params.L},
-                        StoreWeightTiled{w->d_w_hat, c.dp.logN, (int)c.params.L, f.M, f.R},
+        rc = launch_fwd(c, LoadWeights{W, f.r, f.m, f.mb, f.rb, f.R, f.M, (int)c.params.L},
+                        StoreWeightTiled{w->d_w_hat, c.dp.logN, (int)c.params.L, f.groups * f.M, f.R},
                         (int)(f.Wb * c.params.L), s);
     if (!rc && w->d_w_dig) rc = build_weight_digits(c, f, w->d_w_hat, w->d_w_dig, s);
     if (!rc) rc = check_hip(hipStreamSynchronize(s), "weights synchronize");
@@ -371,10 +377,10 @@ int pimm_weights_update(pimm_weights *w, const int64_t *W, uint64_t wmax, void *
                          (unsigned long long)wmax);
     hipStream_t s = (hipStream_t)stream;
     int rc = check_hip(hipSetDevice(c.device), "hipSetDevice");
-    if (!rc) rc = weights_plain(W, w->d_w_plain, (size_t)f.r * f.m, s);
+    if (!rc && w->d_w_plain) rc = weights_plain(W, w->d_w_plain, (size_t)f.r * f.m, s);
     if (!rc)
-        rc = launch_fwd(c, LoadWeights{W, f.r, f.m, f.mb, f.rb, f.R, (int)c.params.L},
-                        StoreWeightTiled{w->d_w_hat, c.dp.logN, (int)c.params.L, f.M, f.R},
+        rc = launch_fwd(c, LoadWeights{W, f.r, f.m, f.mb, f.rb, f.R, f.M, (int)c.params.L},
+                        StoreWeightTiled{w->d_w_hat, c.dp.logN, (int)c.params.L, f.groups * f.M, f.R},
                         (int)(f.Wb * c.params.L), s);
     if (!rc && w->d_w_dig) rc = build_weight_digits(c, f, w->d_w_hat, w->d_w_dig, s);
     if (!rc) w->wmax = (int64_t)wmax;
@@ -419,7 +425,7 @@ int pimm_matmul(const pimm_plan *plan, const pimm_weights *w, const uint64_t *ct
                             StoreU64{acc, lg}, (int)(f.O * 2 * L), s);
         return rc;
     }
-    rc = launch_fwd_zero(c, LoadU64{ct, lg}, StoreCtTiled{ch, lg, (int)L, f.K, f.R},
+    rc = launch_fwd_zero(c, LoadU64{ct, lg}, StoreCtTiled{ch, lg, (int)L, f.K, f.R, f.groups},
                          (int)(f.I * 2 * L), ah, (size_t)f.O * 2 * L * N, s);
     if (!rc)
         rc = launch_mac(c, f, plan->mac_rows, plan->mac_cols, plan->waves, w->d_w_hat, ch, ah, true, s);
@@ -505,7 +511,7 @@ int pimm_matmul_share(const pimm_plan *plan, const pimm_weights *w, const uint64
                             (int)(f.I * 2 * L), s);
         if (!rc) rc = launch_mac_mfma(c, f, w->d_w_dig, ch, ah, s);
     } else {
-        rc = launch_fwd_zero(c, LoadU64{ct, lg}, StoreCtTiled{ch, lg, (int)L, f.K, f.R},
+        rc = launch_fwd_zero(c, LoadU64{ct, lg}, StoreCtTiled{ch, lg, (int)L, f.K, f.R, f.groups},
                              (int)(f.I * 2 * L), ah, (size_t)f.O * 2 * L * N, s);
         if (!rc)
             rc = launch_mac(c, f, plan->mac_rows, plan->mac_cols, plan->waves, w->d_w_hat, ch, ah,

@@ -54,6 +54,8 @@ int pimm_plan_set_tuning(pimm_plan *plan, int mac_rows, int mac_cols, int waves)
     if (!mac_shape_ok(mac_rows, mac_cols))
         return set_error(PIMM_E_ARG, "product tile %d rows x %d column blocks is not built",
                          mac_rows, mac_cols);
+    if (plan->info.groups > 1 && mac_cols != 1)
+        return set_error(PIMM_E_UNSUPPORTED, "grouped plans take product tiles 4x1, 8x1 or 16x1");
     if (waves != 1 && waves != 2 && waves != 4)
         return set_error(PIMM_E_ARG, "waves %d is not 1, 2 or 4", waves);
     plan->mac_rows = mac_rows;
@@ -86,10 +88,13 @@ int pimm_plan_autotune(pimm_plan *plan, const pimm_weights *w, const uint64_t *c
     const int K = (int)plan->info.K;
     double best = DBL_MAX;
     int bg = plan->mac_rows, bk = plan->mac_cols, bw = plan->waves;
+    const bool grouped = plan->info.groups > 1;
     for (const Shape &sh : shapes) {
         // Column blocking only pays when there are columns to share a weight word.
         if (sh.kb > 1 && sh.kb > 2 * K - 1) continue;
+        if (grouped && sh.kb != 1) continue;  // the grouped product's tiles
         for (int wv : waves) {
+            if (grouped && wv != 1) continue;  // one workgroup per tile: no grid to size
             plan->mac_rows = sh.g;
             plan->mac_cols = sh.kb;
             plan->waves = wv;

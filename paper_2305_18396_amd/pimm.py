@@ -32,7 +32,7 @@ TAG_RR_U, TAG_RR_E1, TAG_RR_E2, TAG_MASK = 6, 7, 8, 9
 EXPORTS = [
     "pimm_ctx_create", "pimm_ctx_destroy", "pimm_ctx_primes", "pimm_ctx_cdt",
     "pimm_params_primes", "pimm_cdt", "pimm_plan_rule", "pimm_noise_ok", "pimm_switch_ok",
-    "pimm_plan_create", "pimm_plan_destroy", "pimm_plan_query", "pimm_plan_set_tuning",
+    "pimm_plan_create", "pimm_plan_create_grouped", "pimm_plan_destroy", "pimm_plan_query", "pimm_plan_set_tuning",
     "pimm_plan_get_tuning", "pimm_plan_autotune", "pimm_plan_select", "pimm_batch_autotune",
     "pimm_keygen", "pimm_sk_destroy", "pimm_encode_input", "pimm_encrypt", "pimm_decrypt",
     "pimm_weights_create", "pimm_weights_destroy", "pimm_matmul", "pimm_mask_share",
@@ -74,7 +74,8 @@ class PlanInfo(ctypes.Structure):
                  ("n", "r", "m", "mb", "rb", "nb", "M", "R", "K", "I", "O", "Wb")] +
                 [(n, ctypes.c_uint64) for n in
                  ("P", "pt_bytes", "ct_bytes", "acc_bytes", "c1_bytes", "c0s_bytes",
-                  "share_bytes", "weights_bytes", "workspace_bytes")])
+                  "share_bytes", "weights_bytes", "workspace_bytes")] +
+                [("groups", ctypes.c_uint32)])
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -106,6 +107,7 @@ def lib():
         "pimm_mod_switch": [vp, vp, vp, vp, vp, vp, vp],
         "pimm_decrypt_switched": [vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp],
         "pimm_plan_create": [vp, u32, u32, u32, u32, u32, u32, u32, vp],
+        "pimm_plan_create_grouped": [vp, u32, u32, u32, u32, u32, u32, u32, u32, vp],
         "pimm_plan_destroy": [vp],
         "pimm_plan_query": [vp, vp],
         "pimm_plan_set_tuning": [vp, i32, i32, i32],
@@ -283,12 +285,17 @@ class Context:
 
 
 class Plan:
-    """pimm_plan: block plan and buffer sizes of Y[n][m] = X[n][r] W[r][m]."""
+    """pimm_plan: block plan and buffer sizes of Y[n][m] = X[n][r] W[r][m]; with groups = G > 1,
+    G products of that shape run as one (X, W and the shares gain a leading dimension G)."""
 
-    def __init__(self, ctx: Context, n: int, r: int, m: int, mb=0, rb=0, nb=0, d_fix=0):
+    def __init__(self, ctx: Context, n: int, r: int, m: int, mb=0, rb=0, nb=0, d_fix=0, groups=1):
         self.ctx = ctx
         self.h = ctypes.c_void_p()
-        _check(lib().pimm_plan_create(ctx.h, n, r, m, mb, rb, nb, d_fix, ctypes.byref(self.h)))
+        if groups == 1:
+            _check(lib().pimm_plan_create(ctx.h, n, r, m, mb, rb, nb, d_fix, ctypes.byref(self.h)))
+        else:
+            _check(lib().pimm_plan_create_grouped(ctx.h, n, r, m, mb, rb, nb, d_fix, groups,
+                                                  ctypes.byref(self.h)))
         info = PlanInfo()
         _check(lib().pimm_plan_query(self.h, ctypes.byref(info)))
         self.info = info
@@ -299,6 +306,15 @@ class Plan:
         if info is not None and k in dict(PlanInfo._fields_):
             return getattr(info, k)
         raise AttributeError(k)
+
+    def share_shape(self):
+        """Shape of a share (and of X, W with (n, r), (r, m)): (n, m), or (G, n, m) when grouped."""
+        f = self.info
+        return (f.n, f.m) if f.groups == 1 else (f.groups, f.n, f.m)
+
+    def lead(self, *shape):
+        """shape with the group dimension in front when the plan is grouped."""
+        return tuple(shape) if self.info.groups == 1 else (self.info.groups, *shape)
 
     def set_tuning(self, mac_rows: int = 8, mac_cols: int = 1, waves: int = 1):
         _check(lib().pimm_plan_set_tuning(self.h, mac_rows, mac_cols, waves))
@@ -371,14 +387,15 @@ class Weights:
     """pimm_weights: the server's weight cache (pi_A blocks in NTT form) for one plan."""
 
     def __init__(self, plan: Plan, W: torch.Tensor, stream=None):
-        assert W.dtype == torch.int64 and W.shape == (plan.info.r, plan.info.m)
+        assert W.dtype == torch.int64 and tuple(W.shape) == plan.lead(plan.info.r, plan.info.m)
         self.plan = plan
         self.h = ctypes.c_void_p()
         _check(lib().pimm_weights_create(plan.h, _ptr(W), ctypes.byref(self.h), _stream(stream)))
 
     def update(self, W: torch.Tensor, wmax: int, stream=None):
         """pimm_weights_update: new weights of the same shape, |W| <= wmax, no sync."""
-        assert W.dtype == torch.int64 and W.shape == (self.plan.info.r, self.plan.info.m)
+        assert W.dtype == torch.int64 and tuple(W.shape) == self.plan.lead(self.plan.info.r,
+                                                                           self.plan.info.m)
         _check(lib().pimm_weights_update(self.h, _ptr(W), int(wmax), _stream(stream)))
 
     def close(self):
@@ -447,7 +464,7 @@ def mask_share(plan: Plan, pk: torch.Tensor | None, seed: bytes, op_id: int, acc
     if c0s is None:
         c0s = torch.empty((f.O, c.L, f.mb * f.nb), dtype=torch.int64, device=dev)
     if share is None:
-        share = torch.empty((f.n, f.m), dtype=torch.int64, device=dev)
+        share = torch.empty(plan.share_shape(), dtype=torch.int64, device=dev)
     ws = plan.workspace() if ws is None else ws
     _check(lib().pimm_mask_share(plan.h, _ptr(pk), _seed(seed), op_id, _ptr(acc), _ptr(c1),
                                  _ptr(c0s), _ptr(share), _ptr(ws), ws.numel() * 8,
@@ -465,7 +482,7 @@ def matmul_share(plan: Plan, w: Weights, pk, seed: bytes, op_id: int, ct: torch.
     if c0s is None:
         c0s = torch.empty((f.O, c.L, f.mb * f.nb), dtype=torch.int64, device=dev)
     if share is None:
-        share = torch.empty((f.n, f.m), dtype=torch.int64, device=dev)
+        share = torch.empty(plan.share_shape(), dtype=torch.int64, device=dev)
     ws = plan.workspace() if ws is None else ws
     _check(lib().pimm_matmul_share(plan.h, w.h, _ptr(pk), _seed(seed), op_id, _ptr(ct), _ptr(c1),
                                    _ptr(c0s), _ptr(share), _ptr(ws), ws.numel() * 8,
@@ -478,7 +495,7 @@ def matmul_share_noalloc(plan: Plan, w: Weights, pk, seed: bytes, op_id: int, ct
     """pimm_matmul_share_noalloc: the fused server step on the library's static scratch (no
     workspace, no allocation; the caller passes the outputs).  -> (c1, c0s, server_share)."""
     f, c = plan.info, plan.ctx
-    for t, shape in ((c1, (f.O, c.L, c.N)), (c0s, (f.O, c.L, f.mb * f.nb)), (share, (f.n, f.m))):
+    for t, shape in ((c1, (f.O, c.L, c.N)), (c0s, (f.O, c.L, f.mb * f.nb)), (share, plan.share_shape())):
         assert t.dtype == torch.int64 and tuple(t.shape) == shape and t.is_contiguous()
     _check(lib().pimm_matmul_share_noalloc(plan.h, w.h, _ptr(pk), _seed(seed), op_id, _ptr(ct),
                                            _ptr(c1), _ptr(c0s), _ptr(share), _stream(stream)))
@@ -526,7 +543,7 @@ def decrypt(plan: Plan, sk: SecretKey, c1: torch.Tensor, c0s: torch.Tensor, shar
             stream=None):
     f, c = plan.info, plan.ctx
     if share is None:
-        share = torch.empty((f.n, f.m), dtype=torch.int64, device=c.device)
+        share = torch.empty(plan.share_shape(), dtype=torch.int64, device=c.device)
     ws = plan.workspace() if ws is None else ws
     _check(lib().pimm_decrypt(plan.h, sk.h, _ptr(c1), _ptr(c0s), _ptr(share), _ptr(ws),
                               ws.numel() * 8, _stream(stream)))
@@ -554,7 +571,7 @@ def decrypt_switched(plan: Plan, sk: SecretKey, c1s: torch.Tensor, c0ss: torch.T
     """pimm_decrypt_switched: the client's share from a switched reply."""
     f, c = plan.info, plan.ctx
     if share is None:
-        share = torch.empty((f.n, f.m), dtype=torch.int64, device=c.device)
+        share = torch.empty(plan.share_shape(), dtype=torch.int64, device=c.device)
     ws = plan.workspace() if ws is None else ws
     _check(lib().pimm_decrypt_switched(plan.h, sk.h, _ptr(c1s), _ptr(c0ss), _ptr(share), _ptr(ws),
                                        ws.numel() * 8, _stream(stream)))
