@@ -822,6 +822,61 @@ def bench_attention(args):
     torch.cuda.synchronize()
     gsec = (time.perf_counter() - t0) / args.steps
     log(f"  as a HIP graph: {gsec * 1e3:.2f} ms per layer (replays bit-exact: {same})")
+
+    # Grouped: the products of one shape in a phase as one grouped plan (the 24 score terms;
+    # the 12 A0 V1 and the 12 V0^T A1^T terms), every call doing all of them in one set of
+    # launches.  Operation ids from 2^30 up keep its randomness apart from the steps above.
+    terms = [[0, 1], [2], [3]]
+    gstate = []
+    for gi, ts in enumerate(terms):
+        members = [st for st in state if st["op"] % 4 in ts]
+        a, r, m = shapes[ts[0]]
+        G = len(members)
+        plan = pimm.Plan(ctx, a, r, m, groups=G)
+        fi = plan.info
+        Xg = torch.stack([st["X"] for st in members]).contiguous()
+        Wg = torch.stack([st["W"] for st in members]).contiguous()
+        w = pimm.Weights(plan, Wg)
+        g = dict(plan=plan, w=w, X=Xg, W=Wg, members=members, ws=plan.workspace(),
+                 pt=torch.empty((fi.I, N), dtype=torch.int64, device=dev),
+                 ct=torch.empty((fi.I, 2, L, N), dtype=torch.int64, device=dev),
+                 c1=torch.empty((fi.O, L, N), dtype=torch.int64, device=dev),
+                 c0s=torch.empty((fi.O, L, fi.mb * fi.nb), dtype=torch.int64, device=dev),
+                 y0=torch.empty((G, a, m), dtype=torch.int64, device=dev),
+                 y1=torch.empty((G, a, m), dtype=torch.int64, device=dev))
+        pimm.encrypt(plan, sk, cseed, AUTOTUNE_OP + 100 + gi, pimm.encode_input(plan, Xg, g["pt"]), g["ct"])
+        acc0 = torch.empty((fi.O, 2, L, N), dtype=torch.int64, device=dev)
+        plan.autotune(w, g["ct"], acc0, reps=2)
+        del acc0
+        gstate.append(g)
+
+    def gstep(k):
+        for gi, g in enumerate(gstate):
+            p, op = g["plan"], (1 << 30) + k * 8 + gi
+            pimm.encode_input(p, g["X"], g["pt"])
+            pimm.encrypt(p, sk, cseed, op, g["pt"], g["ct"], g["ws"])
+            g["w"].update(g["W"], half)
+            pimm.matmul_share(p, g["w"], pk, sseed, op, g["ct"], g["c1"], g["c0s"], g["y1"], g["ws"])
+            pimm.decrypt(p, sk, g["c1"], g["c0s"], g["y0"], g["ws"])
+
+    # The grouped shares add up to the same products as the per-product shares of step 800.
+    step(800)
+    gstep(800)
+    torch.cuda.synchronize()
+    mask = (1 << ell) - 1
+    grouped_same = all(
+        torch.equal((g["y0"][i] + g["y1"][i]) & mask, (st["y0"] + st["y1"]) & mask)
+        for g in gstate for i, st in enumerate(g["members"]))
+    for k in range(args.warmup):
+        gstep(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        gstep(args.warmup + k)
+    torch.cuda.synchronize()
+    grsec = (time.perf_counter() - t0) / args.steps
+    log(f"  grouped (3 plans of 24, 12, 12 products): {grsec * 1e3:.2f} ms per layer, "
+        f"{useful / grsec / 1e9:.1f}e9 int-MAC/s (same products: {grouped_same})")
     return {"workload": f"BERT-base attention cross terms, seq {n}: 12 heads x (2 x {n}x64x{n} "
                         f"+ {n}x{n}x64 + 64x{n}x{n}), plaintext operand a uniform share; "
                         "RNS-BFV N=8192, 3x50-bit primes, t=2^41",
@@ -832,7 +887,12 @@ def bench_attention(args):
             "graph_ms_per_layer": gsec * 1e3, "graph_int_mac_per_s": useful / gsec,
             "graph_replays_bitexact": bool(same),
             "streams": len(streams), "streams_ms_per_layer": ssec * 1e3,
-            "streams_int_mac_per_s": useful / ssec, "streams_same_shares": bool(streams_same)}
+            "streams_int_mac_per_s": useful / ssec, "streams_same_shares": bool(streams_same),
+            "grouped_ms_per_layer": grsec * 1e3, "grouped_int_mac_per_s": useful / grsec,
+            "grouped_plans": [[g["plan"].groups, g["plan"].mb, g["plan"].rb, g["plan"].nb]
+                              for g in gstate],
+            "grouped_product_schedules": [list(g["plan"].tuning()) for g in gstate],
+            "grouped_same_products": bool(grouped_same)}
 
 
 def bench_peak(args):
