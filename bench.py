@@ -251,7 +251,7 @@ def bench_serve(args):
     def run(rate, count, max_active):
         srv = pimm.Server(ctx, args.layers, shapes, weights, args.d_fix, budget, max_active,
                           schedule=pimm.PHASED, mac_rows=args.serve_tile[0],
-                          mac_cols=args.serve_tile[1])
+                          mac_cols=args.serve_tile[1], min_batch=args.serve_min_batch)
         trace = workloads.poisson_trace(rate, count)
         reqs = [(q.rid, q.seq, q.arrival_s, workloads.seed("client", 7000 + q.rid),
                  workloads.seed("server", 7000 + q.rid)) for q in trace]
@@ -282,7 +282,8 @@ def bench_serve(args):
         # Explicit rates only (no saturation search).
         for rate in args.serve_rates:
             sweep.append(both(rate))
-        return {"product_tile": list(args.serve_tile), "workload": workload, "sweep": sweep}
+        return {"product_tile": list(args.serve_tile), "min_batch": args.serve_min_batch,
+                "workload": workload, "sweep": sweep}
     rate = args.serve_rate0
     while True:
         r = both(rate)
@@ -291,7 +292,8 @@ def bench_serve(args):
                                 or len(sweep) >= 6):
             break
         rate *= 2
-    return {"product_tile": list(args.serve_tile), "workload": workload, "sweep": sweep}
+    return {"product_tile": list(args.serve_tile), "min_batch": args.serve_min_batch,
+            "workload": workload, "sweep": sweep}
 
 
 FP64_ISSUE_PER_S = 39.3e12  # FP64 VALU instruction issues per second (78.6 TFLOP/s counts an FMA as 2)
@@ -1232,6 +1234,8 @@ def main():
     ap.add_argument("--layers", type=int, default=12)
     ap.add_argument("--serve-budget-gb", type=float, default=48.0)
     ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-min-batch", type=int, default=8,
+                    help="serve: fewest requests at one step that run as one batched pass")
     ap.add_argument("--serve-max-active", type=int, default=32)
     ap.add_argument("--serve-rate0", type=float, default=4.0)
     ap.add_argument("--serve-rates", type=lambda v: [float(x) for x in v.split(",")], default=None,

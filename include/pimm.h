@@ -421,7 +421,9 @@ int pimm_batch_status(const pimm_batch *batch, const void *ws, void *stream);
  * hbm_budget: device bytes the server allocates once and hands to requests
  * (key, ciphertexts, accumulators, reply, scratch); max_active: most requests in
  * flight; schedule / mac_rows / mac_cols: the batched product's schedule (as
- * pimm_batch_set_schedule; mac_rows 0 means 8, mac_cols 0 means 1). */
+ * pimm_batch_set_schedule; mac_rows 0 means 8, mac_cols 0 means 1); min_batch: the
+ * fewest requests at one step that run together as one batched pass (with fewer, the
+ * oldest runs alone through the plain fused call; 0 means 8). */
 typedef struct {
     uint32_t layers, ops;
     const uint32_t *d_in, *d_out;
@@ -431,6 +433,7 @@ typedef struct {
     uint32_t max_active;
     int32_t schedule;
     uint32_t mac_rows, mac_cols;
+    uint32_t min_batch;
 } pimm_serve_config;
 
 /* A request: unique id, sequence length, arrival time in seconds from the start of
@@ -462,8 +465,9 @@ int pimm_serve_footprint(const pimm_server *server, uint32_t seq, uint64_t *byte
 /* Replay `count` requests in real time on `stream`: admit each at or after its
  * arrival when the budget has room (arrival order); at each tick run the step (layer,
  * op) of the oldest admitted request for every admitted request at that step, their
- * products in one batched launch that reads the step's weight cache once (a lone
- * request takes the plain fused call); return when every request is done.  Requests
+ * products in one batched launch that reads the step's weight cache once, when at
+ * least min_batch are at that step (otherwise the oldest request runs alone through
+ * the plain fused call); return when every request is done.  Requests
  * admitted behind a running one gather at step 0 and then run as one cohort.
  * results[i] belongs to reqs[i]. */
 int pimm_serve_run(pimm_server *server, const pimm_request *reqs, uint32_t count,

@@ -12,13 +12,14 @@
 //   1. admits waiting requests in arrival order while the HBM budget has room
 //      for the request's buffers (key, ciphertexts, reply, shares and scratch,
 //      sized for its largest product) and fewer than max_active run;
-//   2. takes the step (layer, op) of the oldest admitted request and runs it for
-//      every admitted request at that step: client share, encode, encrypt; one
-//      batched pass of forward transforms and slot-wise products over them
-//      (pimm_batch machinery, stopping at acc^), whose products share that step's
-//      weight cache and so read it once; then per request the fused server tail
-//      (re-randomisation, inverse transform with the reply epilogue, mask) and
-//      decryption.  A lone request at that step takes the plain fused call.
+//   2. takes the step (layer, op) of the oldest admitted request and, when at least
+//      min_batch admitted requests are at that step, runs it for all of them: client
+//      share, encode, encrypt; one batched pass of forward transforms and slot-wise
+//      products over them (pimm_batch machinery, stopping at acc^), whose products
+//      share that step's weight cache and so read it once; then per request the fused
+//      server tail (re-randomisation, inverse transform with the reply epilogue, mask)
+//      and decryption.  With fewer, the oldest request runs alone through the plain
+//      fused call, so light load is served in arrival order, one request at a time.
 //      Requests at other steps wait: the oldest request never does, and requests
 //      admitted behind it gather at step 0 and run as one cohort once it is done;
 //   3. waits for the device, then retires requests whose last product is done.
@@ -335,7 +336,7 @@ int pimm_serve_run(pimm_server *sv, const pimm_request *reqs, uint32_t count,
                     delete a;
                     return fail(rc);
                 }
-                // Schedule of the plain fused call a lone request takes: one row per weight
+                // Schedule of the plain fused call a request outside a batch takes: one row per weight
                 // word per column block when there are few column blocks.
                 const uint32_t K = a->plans[o].info.K;
                 a->plans[o].mac_rows = K <= 1 ? 16 : 8;
@@ -402,6 +403,11 @@ int pimm_serve_run(pimm_server *sv, const pimm_request *reqs, uint32_t count,
         std::vector<Active *> tick;
         for (Active *a : active)
             if (a->step == step_now) tick.push_back(a);
+        // Fewer than min_batch at that step: the oldest request runs alone (requests are
+        // then served in arrival order, as one at a time would serve them); interleaving a
+        // small cohort without the batched pass would only delay its first members.
+        const size_t min_batch = sv->cfg.min_batch ? sv->cfg.min_batch : 8;
+        if (tick.size() < min_batch) tick.resize(1);
         const uint32_t o_now = step_now % sv->cfg.ops;
         for (Active *a : tick) {
             const pimm_plan *plan = &a->plans[o_now];
@@ -416,8 +422,9 @@ int pimm_serve_run(pimm_server *sv, const pimm_request *reqs, uint32_t count,
                                        a->ws_bytes, s);
             if (rc) return fail(rc);
         }
-        if (tick.size() == 1) {
-            // A lone request takes the plain fused server call (stream-K product).
+        const bool batched = tick.size() > 1;
+        if (!batched) {
+            // One request: the plain fused server call (stream-K product).
             Active *a = tick[0];
             rc = pimm_matmul_share(&a->plans[o_now], sv->weights[a->step], a->pk, a->req.server_seed,
                                    a->step, a->ct, a->c1, a->c0s, a->y1, a->ws, a->ws_bytes, s);
@@ -464,7 +471,7 @@ int pimm_serve_run(pimm_server *sv, const pimm_request *reqs, uint32_t count,
         // 3. wait, then retire finished requests
         rc = check_hip(hipStreamSynchronize(s), "serve tick synchronize");
         if (rc) return fail(rc);
-        if (tick.size() > 1 && sv->batch.schedule == kPersistent) {
+        if (batched && sv->batch.schedule == kPersistent) {
             rc = pimm_batch_status(&sv->batch, sv->arena_base, s);
             if (rc) return fail(rc);
         }

@@ -659,7 +659,7 @@ class ServeConfig(ctypes.Structure):
                 ("weights", ctypes.POINTER(ctypes.c_void_p)), ("d_fix", ctypes.c_uint32),
                 ("hbm_budget", ctypes.c_uint64), ("max_active", ctypes.c_uint32),
                 ("schedule", ctypes.c_int32), ("mac_rows", ctypes.c_uint32),
-                ("mac_cols", ctypes.c_uint32)]
+                ("mac_cols", ctypes.c_uint32), ("min_batch", ctypes.c_uint32)]
 
 
 class Request(ctypes.Structure):
@@ -681,14 +681,15 @@ class Server:
     shapes: [(d_in, d_out)] per op; weights: [layers * ops] Weights made with block area d_fix."""
 
     def __init__(self, ctx: Context, layers: int, shapes, weights, d_fix: int, hbm_budget: int,
-                 max_active: int, schedule: int = PHASED, mac_rows: int = 8, mac_cols: int = 1):
+                 max_active: int, schedule: int = PHASED, mac_rows: int = 8, mac_cols: int = 1,
+                 min_batch: int = 0):
         self.ctx, self.weights = ctx, list(weights)
         ops = len(shapes)
         self._d_in = (ctypes.c_uint32 * ops)(*[r for r, _ in shapes])
         self._d_out = (ctypes.c_uint32 * ops)(*[m for _, m in shapes])
         self._w = (ctypes.c_void_p * len(self.weights))(*[w.h.value for w in self.weights])
         cfg = ServeConfig(layers, ops, self._d_in, self._d_out, self._w, d_fix, int(hbm_budget),
-                          max_active, schedule, mac_rows, mac_cols)
+                          max_active, schedule, mac_rows, mac_cols, min_batch)
         self.h = ctypes.c_void_p()
         _check(lib().pimm_serve_create(ctx.h, ctypes.byref(cfg), ctypes.byref(self.h)))
 

@@ -49,12 +49,15 @@ def stack():
     return ctx, shapes, layers, D, Ws, weights, reqs
 
 
-@pytest.mark.parametrize("schedule,tile", [(pimm.PHASED, (8, 1)), (pimm.PERSISTENT, (8, 1)),
-                                           (pimm.PHASED, (8, 4)), (pimm.PERSISTENT, (4, 2))])
-def test_mix_equals_solo_and_xw(stack, orc, schedule, tile):
+@pytest.mark.parametrize("schedule,tile,min_batch", [
+    (pimm.PHASED, (8, 1), 2), (pimm.PERSISTENT, (8, 1), 2), (pimm.PHASED, (8, 4), 2),
+    (pimm.PERSISTENT, (4, 2), 2), (pimm.PHASED, (4, 8), 0)])
+def test_mix_equals_solo_and_xw(stack, orc, schedule, tile, min_batch):
+    """min_batch 2: every step with two or more requests takes the batched pass; 0: the
+    server's default (eight)."""
     ctx, shapes, layers, D, Ws, weights, reqs = stack
     srv = pimm.Server(ctx, layers, shapes, weights, D, 4 << 30, 8, schedule=schedule,
-                      mac_rows=tile[0], mac_cols=tile[1])
+                      mac_rows=tile[0], mac_cols=tile[1], min_batch=min_batch)
     mix = srv.run(reqs)
     for rq, res in zip(reqs, mix):
         assert res["steps"] == layers * len(shapes)
@@ -138,7 +141,7 @@ def test_served_shares_equal_the_oracle(orc, D, ops):
     reqs = [(700 + i, s, 0.001 * i, workloads.seed("client", 700 + i),
              workloads.seed("server", 700 + i)) for i, s in enumerate([32, 77, 45])]
     srv = pimm.Server(ctx, 1, shapes, weights, D, 8 << 30, 8, schedule=pimm.PHASED,
-                      mac_rows=8, mac_cols=4)
+                      mac_rows=8, mac_cols=4, min_batch=2)
     res = srv.run(reqs)
     pyp = orc.Params(4096, 2, 37, 12)
     for i in (0, 2):
