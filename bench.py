@@ -212,6 +212,32 @@ def bench_batch(args):
     graph_t = timed(g.replay, args.steps)
     batch.status(ws=ws)
     sched = dict(zip(("schedule", "mac_rows", "mac_cols", "xcd_map", "grid"), batch.get_schedule()))
+    # Roofline of the phased pass's product (k_batch_mac): each weight cache is read once per
+    # column tile of its group (the products sharing it line up their column blocks), every
+    # input and accumulator word once.
+    L, N = 2, 4096
+    groups = collections.defaultdict(list)
+    for plan, w, ct, acc in rows:
+        groups[id(w)].append(plan)
+    KB = max(1, sched["mac_cols"])
+    mac_bytes = 0
+    for plans in groups.values():
+        cols = sum(p.K for p in plans)
+        mac_bytes += plans[0].Wb * L * N * 8 * (-(-cols // KB))
+        mac_bytes += sum((2 * p.I + 2 * p.O) * L * N * 8 for p in plans)
+    mac_s = batch_phases["mac"] / 1e3
+    achieved = mac_bytes / mac_s / 1e9 if mac_s > 0 else 0.0
+    # The persistent single launch on the same tile, and the bytes its per-product units read
+    # (each product reads its weight cache itself, once per column tile of its own).
+    persistent_ms = None
+    persistent_bytes = sum(p.Wb * L * N * 8 * (-(-p.K // KB)) + (2 * p.I + 2 * p.O) * L * N * 8
+                           for p, *_ in rows)
+    if sched["schedule"] == pimm.PHASED:
+        batch.set_schedule(pimm.PERSISTENT, sched["mac_rows"], sched["mac_cols"], sched["xcd_map"], 0)
+        persistent_ms = timed(batch.run, args.steps) * 1e3
+        batch.status()
+        batch.set_schedule(pimm.PHASED, sched["mac_rows"], sched["mac_cols"], sched["xcd_map"],
+                           sched["grid"])
     return {"workload": f"{len(rows)} products, seq uniform in [16, 512], BERT-base shapes, "
                         f"N=4096, 2 primes, block area {args.d_fix}",
             "useful_macs": useful, "slot_macs": slot, "wire_bytes": wire,
@@ -222,7 +248,12 @@ def bench_batch(args):
             "schedule": sched, "bitexact_vs_plain": bool(same),
             "plain_schedule_counts": {",".join(map(str, t)): c for t, c in
                                       collections.Counter(tuned.values()).most_common()},
-            "plain_kernel_ms": plain_phases, "batched_kernel_ms": batch_phases}
+            "plain_kernel_ms": plain_phases, "batched_kernel_ms": batch_phases,
+            "persistent_ms": persistent_ms, "persistent_product_alg_bytes": persistent_bytes,
+            "roofline": {"kernel": "k_batch_mac (the phased pass's product)", "bound": "hbm",
+                         "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "alg_bytes_per_pass": mac_bytes,
+                         "product_ms_per_pass": batch_phases["mac"]}}
 
 
 def bench_serve(args):
