@@ -139,27 +139,31 @@ __device__ __forceinline__ double combine(const v4i *T, int v, double p, double 
     return reduce(g0 + r1 + mulmod(g2, c64, p, pinv), p, pinv);
 }
 
-constexpr int kMfmaSlots = 8;    // slots per workgroup (half a 16-slot chunk)
+constexpr int kMfmaSlots = 4;    // slots per workgroup (a quarter of a 16-slot chunk)
+constexpr int kMfmaParts = 16 / kMfmaSlots;  // workgroups per 16-slot chunk
 constexpr int kMfmaThreads = 256;  // 4 waves, one 16-row tile each
 constexpr int kSlotLds = 512;      // v4i per slot region (8 KiB)
+constexpr int kMfmaPerCu = 16 / kMfmaSlots;  // workgroups per compute unit (128 KiB of LDS)
 
-// Workgroup: prime l, slots zc*16 + h*8 .. +7, column tile ct (16 columns), row tiles
+// Workgroup: prime l, slots zc*16 + h*4 .. +3, column tile ct (16 columns), row tiles
 // rg*4 .. rg*4+3 (one per wave).  LDS holds one 8 KiB region per slot: first the slot's
 // B fragments ([digit][column][4 x 16 B], the 16-byte groups of column j rotated by
 // (j / 4) % 4 so that the 16 lanes of a group hit distinct banks), then, once every wave
 // has issued its products for the slot, the slot's results ([wave][row v][lane] doubles).
-// At the end each lane writes its 4 rows x 8 slots as 64-byte runs (the other half of each
-// 128-byte line is the sibling workgroup's, h).  64 KiB per workgroup: two share a compute
-// unit, so one's loads overlap the other's matrix instructions.  Logical index (from
-// xcd_local, so that the two halves and the column tiles of a chunk run side by side on
-// one XCD and share its L2)
-//     lb = (((l * NC + zc) * RG + rg) * CT + ct) * 2 + h.
-__global__ __launch_bounds__(kMfmaThreads, 2) void k_mac_mfma(MfmaArgs g, DevParams dp)
+// At the end each lane writes its 4 rows x 4 slots as 32-byte runs (the other three
+// quarters of each 128-byte line are the sibling workgroups', h).  32 KiB of LDS and at
+// most 128 registers per lane: four workgroups (16 waves) share a compute unit, so the
+// loads of some overlap the matrix instructions of others; with 8 slots (64 KiB) only two
+// fit and the waves spend most of their time waiting on memory.  Logical index (from
+// xcd_local, so that the quarters and the column tiles of a chunk run side by side on one
+// XCD and share its L2)
+//     lb = (((l * NC + zc) * RG + rg) * CT + ct) * 4 + h.
+__global__ __launch_bounds__(kMfmaThreads, kMfmaPerCu) void k_mac_mfma(MfmaArgs g, DevParams dp)
 {
     __shared__ v4i lds[kMfmaSlots * kSlotLds];
     uint32_t lb = xcd_local(blockIdx.x, gridDim.x);
-    const int h = (int)(lb & 1);
-    lb >>= 1;
+    const int h = (int)(lb % kMfmaParts);
+    lb /= kMfmaParts;
     const int ct = (int)(lb % g.CT);
     lb /= g.CT;
     const int rg = (int)(lb % g.RG);
@@ -169,7 +173,7 @@ __global__ __launch_bounds__(kMfmaThreads, 2) void k_mac_mfma(MfmaArgs g, DevPar
     const int tid = (int)threadIdx.x;
     const size_t line0 = ((size_t)l * g.NC + zc) * g.I;  // first line of the chunk (c^)
 
-    // Inputs: thread (q, j) takes inner blocks 4q .. 4q+3 of column j for the 8 slots.  All
+    // Inputs: thread (q, j) takes inner blocks 4q .. 4q+3 of column j for the workgroup's slots.  All
     // loads are issued before any is used (absent blocks read a valid line and are zeroed
     // afterwards), so their latencies overlap.  The first half of the slots is split into
     // digits and its products start while the second half's loads are still arriving; the
@@ -183,7 +187,7 @@ __global__ __launch_bounds__(kMfmaThreads, 2) void k_mac_mfma(MfmaArgs g, DevPar
         const int jb = 4 * qq + r;
         ok[r] = jb < g.R && kbq < g.K;
         const double2 *src = (const double2 *)(g.Ch +
-            (ok[r] ? ((line0 + (size_t)jb * g.K + kbq) * 2 + compq) * 16 + h * 8 : 0));
+            (ok[r] ? ((line0 + (size_t)jb * g.K + kbq) * 2 + compq) * 16 + h * kMfmaSlots : 0));
 #pragma unroll
         for (int s2 = 0; s2 < kMfmaSlots / 2; ++s2) v[r][s2] = src[s2];
     }
@@ -214,7 +218,7 @@ __global__ __launch_bounds__(kMfmaThreads, 2) void k_mac_mfma(MfmaArgs g, DevPar
     const size_t fstride = (size_t)g.Mt * 64;  // v4i between the digits of one slot
     const size_t sstride = 7 * fstride;        // v4i between consecutive slots
     const int bgrp = gq ^ ((jl >> 2) & 3);
-    const size_t z0 = (size_t)zc * 16 + h * 8;
+    const size_t z0 = (size_t)zc * 16 + h * kMfmaSlots;
     // Weight fragment x of slot s + 1 is requested as soon as the 7 products that use
     // fragment x of slot s are issued, so its latency hides behind the rest of the slot.
     // Plain (cached) loads: the workgroups of the other column tiles of the chunk read the
@@ -264,7 +268,7 @@ __global__ __launch_bounds__(kMfmaThreads, 2) void k_mac_mfma(MfmaArgs g, DevPar
         if (ib >= g.M) continue;
         const double *src = (const double *)lds + (size_t)wv * 4 * 64 + vv * 64 + lane;
         double2 *dst = (double2 *)(g.Ah +
-            ((((size_t)l * g.NC + zc) * g.O + (size_t)ib * g.K + kb) * 2 + comp) * 16 + h * 8);
+            ((((size_t)l * g.NC + zc) * g.O + (size_t)ib * g.K + kb) * 2 + comp) * 16 + h * kMfmaSlots);
 #pragma unroll
         for (int s2 = 0; s2 < kMfmaSlots / 2; ++s2)
             dst[s2] = double2{src[(2 * s2) * kSlotLds * 2], src[(2 * s2 + 1) * kSlotLds * 2]};
@@ -321,7 +325,7 @@ int launch_mac_mfma(const Ctx &c, const pimm_plan_info &f, const void *Wd, const
     g.NC = (int)(c.params.N / 16);
     g.logn = c.dp.logN;
     for (uint32_t l = 0; l < c.params.L; ++l) g.c64[l] = balanced_pow2(c.q[l], 64);
-    const uint64_t blocks = (uint64_t)c.params.L * g.NC * g.RG * g.CT * 2;
+    const uint64_t blocks = (uint64_t)c.params.L * g.NC * g.RG * g.CT * kMfmaParts;
     if (blocks > 0x7fffffffull) return set_error(PIMM_E_SHAPE, "matrix-core product grid too large");
     ProfScope prof("mac", s);
     hipLaunchKernelGGL(k_mac_mfma, dim3((unsigned)blocks), dim3(kMfmaThreads), 0, s, g, c.dp);
