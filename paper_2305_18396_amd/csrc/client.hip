@@ -55,12 +55,23 @@ struct StoreEncC0 {
     uint64_t *ct;        // [I][2][L][N]
     double delta[kMaxL];
     int logn, L;
-    __device__ void operator()(const PolyIx &pi, int j, double v, double p, double pinv) const
+    // The plaintext and error words, read ahead of the transform's last pass.
+    struct Pre {
+        uint64_t m;
+        int e;
+    };
+    __device__ Pre pre(const PolyIx &pi, int j) const
+    {
+        const size_t at = ((size_t)pi.x << logn) + j;
+        return Pre{pt[at], (int)e[at]};
+    }
+    __device__ void operator()(const PolyIx &pi, int j, double v, double p, double pinv,
+                               const Pre &pr) const
     {
         const size_t x = (size_t)pi.x;
         const int l = pi.l;
-        const double m = mulmod(delta[l], f64_of(pt[(x << logn) + j]), p, pinv);
-        const double c0 = m + (double)e[(x << logn) + j] - v;
+        const double m = mulmod(delta[l], f64_of(pr.m), p, pinv);
+        const double c0 = m + (double)pr.e - v;
         ct[(((x * 2) * L + l) << logn) + j] = to_canonical(c0, p, pinv);
     }
 };
@@ -75,7 +86,8 @@ struct DecodedOut {
     FastDiv mb;
     uint32_t rb, nb;
     __device__ bool sparse(const PolyIx &) const { return true; }
-    __device__ void operator()(const PolyIx &pi, const double *lds, const DevParams &dp) const
+    template <int LOGN, int T>
+    __device__ void run(const PolyIx &pi, const double *lds, const DevParams &dp) const
     {
         const int l = pi.l;
         const double p = dp.p[l], pinv = dp.pinv[l];

@@ -555,11 +555,14 @@ struct StorePk0 {
     const int64_t *e;
     uint64_t *pk0;  // [L][N]
     int logn;
-    __device__ void operator()(const PolyIx &pi, int j, double v, double p, double pinv) const
+    // The error word, read ahead of the transform's last pass.
+    using Pre = int64_t;
+    __device__ Pre pre(const PolyIx &, int j) const { return e[j]; }
+    __device__ void operator()(const PolyIx &pi, int j, double v, double p, double pinv, Pre ej) const
     {
         const uint64_t q = (uint64_t)p;
         const uint64_t as = to_canonical(v, p, pinv);
-        pk0[((size_t)pi.poly << logn) + j] = sub_mod(lift_small(e[j], q), as, q);
+        pk0[((size_t)pi.poly << logn) + j] = sub_mod(lift_small(ej, q), as, q);
     }
 };
 

@@ -22,6 +22,8 @@
 // (PolyIx) and hands them to its loader and storer.
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace pimm {
@@ -101,24 +103,48 @@ struct Pass {
         return (S / STRIDE) * (N >> S0) + (S % STRIDE) + c * STRIDE;
     }
 
-    // Forward stages S0 .. S0+PS-1 on the registers of set S.
-    __device__ static __forceinline__ void fwd(double *x, int S, const double *tw, double p,
-                                               double pinv)
+    // Twiddles set S uses, stage by stage: w[2^sp - 1 + j] is the factor of the
+    // butterflies of stage S0 + sp whose lower index c has c >> (PS - sp) == j.
+    static constexpr int NTW = E - 1;
+    __device__ static __forceinline__ void load_tw(int S, const double *tw, double *w)
     {
         const int hi = S / STRIDE;
+#pragma unroll
+        for (int sp = 0; sp < PS; ++sp)
+#pragma unroll
+            for (int j = 0; j < (1 << sp); ++j) w[(1 << sp) - 1 + j] = tw[(1 << (S0 + sp)) + (hi << sp) + j];
+    }
+
+    // Set of element e (the inverse of elem).
+    __host__ __device__ static constexpr int set_of(int e)
+    {
+        return (e / (N >> S0)) * STRIDE + (e % (N >> S0)) % STRIDE;
+    }
+
+    // Forward stages S0 .. S0+PS-1 on the registers of a set whose twiddles are w.
+    __device__ static __forceinline__ void fwd_w(double *x, const double *w, double p, double pinv)
+    {
 #pragma unroll
         for (int sp = 0; sp < PS; ++sp) {
             const int half = E >> (sp + 1);
 #pragma unroll
             for (int c = 0; c < E; ++c) {
                 if (c & half) continue;
-                const double w = tw[(1 << (S0 + sp)) + (hi << sp) + (c >> (PS - sp))];
                 const double u = x[c];
-                const double v = mulmod(x[c + half], w, p, pinv);
+                const double v = mulmod(x[c + half], w[(1 << sp) - 1 + (c >> (PS - sp))], p, pinv);
                 x[c] = u + v;
                 x[c + half] = u - v;
             }
         }
+    }
+
+    // Forward stages S0 .. S0+PS-1 on the registers of set S.
+    __device__ static __forceinline__ void fwd(double *x, int S, const double *tw, double p,
+                                               double pinv)
+    {
+        double w[NTW];
+        load_tw(S, tw, w);
+        fwd_w(x, w, p, pinv);
     }
 
     // Inverse stages S0+PS-1 .. S0 of set S computing only the registers that
@@ -181,28 +207,120 @@ struct NttPasses {
     using D = Pass<LOGN, S::P0 + S::P1 + S::P2, (S::P3 > 0 ? S::P3 : 1), T>;
     static_assert(S::P0 + S::P1 + S::P2 + S::P3 == LOGN, "schedule covers every stage");
     static constexpr int N = 1 << LOGN;
-    static constexpr int LDS = N + (N >> 5);
+    // The pass that touches global memory in slot order (the forward's last, the inverse's
+    // first) and its size.
+    static constexpr int PL = S::P3 > 0 ? S::P3 : S::P2;
+    // LDS: the N elements (padded, lds_idx), then the twiddles of every other pass
+    // (factor indices below N >> PL), copied from global memory once per transform so that
+    // those passes read them from LDS.
+    static constexpr int DATA = N + (N >> 5);
+    static constexpr int TWL = N >> PL;
+    static constexpr int LDS = DATA + TWL;
 };
+
+// Copy of the twiddle factors with index below TWL into the LDS table (visible after the
+// next barrier).
+template <int LOGN, int T>
+__device__ __forceinline__ void load_tw_table(const double *tw, double *lds)
+{
+    using NP = NttPasses<LOGN, T>;
+#pragma unroll
+    for (int i = (int)threadIdx.x; i < NP::TWL; i += T) lds[NP::DATA + i] = tw[i];
+}
+
+// True when every element written by pass P (thread of set S: S % T) is read in pass Q by
+// a thread of the same wave: the exchange between the two passes then needs no workgroup
+// barrier, only ordering within the wave.
+template <class P, class Q, int T>
+__host__ __device__ constexpr bool exchange_in_wave()
+{
+    for (int e = 0; e < P::N; ++e)
+        if ((P::set_of(e) % T) / 64 != (Q::set_of(e) % T) / 64) return false;
+    return true;
+}
+
+// Orders the LDS writes of the calling wave before its later LDS reads (the lanes of a
+// wave see each other's writes in program order; this keeps the compiler from moving
+// them).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// A storer whose value needs global inputs of its own (the plaintext and error words of
+// an encryption) declares `Pre`, reads them in `pre(pi, j)` and takes them back as the
+// last argument of its call operator.  The last pass reads every element's inputs before
+// its butterflies, so the reads overlap each other and the arithmetic; without this the
+// stores in between would order every read after the previous store.
+template <class St, class = void>
+struct has_pre : std::false_type {};
+template <class St>
+struct has_pre<St, std::void_t<typename St::Pre>> : std::true_type {};
+
+// Pre-read inputs of a storer without any (keeps the call sites uniform).
+struct NoPre {};
+
+template <class St, bool = has_pre<St>::value>
+struct pre_of {
+    using type = NoPre;
+};
+template <class St>
+struct pre_of<St, true> {
+    using type = typename St::Pre;
+};
+template <class Store>
+using pre_t = typename pre_of<Store>::type;
+
+template <class Store>
+__device__ __forceinline__ pre_t<Store> store_pre(const Store &st, const PolyIx &pi, int j)
+{
+    if constexpr (has_pre<Store>::value)
+        return st.pre(pi, j);
+    else
+        return NoPre{};
+}
+
+template <class Store>
+__device__ __forceinline__ void store_val(const Store &st, const PolyIx &pi, int j, double v, double p,
+                                          double pinv, const pre_t<Store> &pr)
+{
+    if constexpr (has_pre<Store>::value)
+        st(pi, j, v, p, pinv, pr);
+    else
+        st(pi, j, v, p, pinv);
+}
 
 // Forward stages of pass P on every set the thread owns: read from LDS (or the
 // loader for the first pass), write to LDS (or the storer, in slot order, for
-// the last pass).
+// the last pass).  With w given (one set per thread), the set's twiddles are
+// those already loaded there; otherwise they come from tw.
 template <class P, int T, bool FIRST, bool LAST, class Load, class Store>
 __device__ __forceinline__ void fwd_pass(const Load &ld, const Store &st, const PolyIx &pi,
-                                         const double *tw, double p, double pinv, double *lds)
+                                         const double *tw, double p, double pinv, double *lds,
+                                         const double *w = nullptr)
 {
 #pragma unroll
     for (int k = 0; k < P::PER_THREAD; ++k) {
         const int S = (int)threadIdx.x + k * T;
+        pre_t<Store> pr[P::E];
+        if constexpr (LAST && has_pre<Store>::value) {
+#pragma unroll
+            for (int c = 0; c < P::E; ++c) pr[c] = store_pre(st, pi, c * P::NSETS + S);
+        }
         double x[P::E];
 #pragma unroll
         for (int c = 0; c < P::E; ++c)
             x[c] = FIRST ? ld(pi, P::elem(S, c), p, pinv) : lds[lds_idx(P::elem(S, c))];
-        P::fwd(x, S, tw, p, pinv);
+        if (w)
+            P::fwd_w(x, w, p, pinv);
+        else
+            P::fwd(x, S, tw, p, pinv);
 #pragma unroll
         for (int c = 0; c < P::E; ++c) {
             if (LAST)
-                st(pi, c * P::NSETS + S, reduce(x[c], p, pinv), p, pinv);
+                store_val(st, pi, c * P::NSETS + S, reduce(x[c], p, pinv), p, pinv, pr[c]);
             else
                 lds[lds_idx(P::elem(S, c))] = reduce(x[c], p, pinv);
         }
@@ -244,6 +362,11 @@ __device__ __forceinline__ void inv_pass(const Load &ld, const Store &st, const 
             const int u = (int)threadIdx.x + k * T;
             if (u >= NEED) break;
             const int S = u * G + (G - 1);
+            pre_t<Store> pr[P::E];
+            if constexpr (LAST && has_pre<Store>::value) {
+#pragma unroll
+                for (int c = 0; c < P::E; ++c) pr[c] = store_pre(st, pi, P::elem(S, c));
+            }
             double x[P::E];
 #pragma unroll
             for (int c = 0; c < P::E; ++c) x[c] = lds[lds_idx(P::elem(S, c))];
@@ -251,7 +374,7 @@ __device__ __forceinline__ void inv_pass(const Load &ld, const Store &st, const 
 #pragma unroll
             for (int c = 0; c < P::E; ++c) {
                 if (LAST)
-                    st(pi, P::elem(S, c), mulmod(x[c], ninv, p, pinv), p, pinv);
+                    store_val(st, pi, P::elem(S, c), mulmod(x[c], ninv, p, pinv), p, pinv, pr[c]);
                 else
                     lds[lds_idx(P::elem(S, c))] = reduce(x[c], p, pinv);
             }
@@ -261,6 +384,11 @@ __device__ __forceinline__ void inv_pass(const Load &ld, const Store &st, const 
 #pragma unroll
     for (int k = 0; k < P::PER_THREAD; ++k) {
         const int S = (int)threadIdx.x + k * T;
+        pre_t<Store> pr[P::E];
+        if constexpr (LAST && has_pre<Store>::value) {
+#pragma unroll
+            for (int c = 0; c < P::E; ++c) pr[c] = store_pre(st, pi, P::elem(S, c));
+        }
         double x[P::E];
 #pragma unroll
         for (int c = 0; c < P::E; ++c)
@@ -269,7 +397,7 @@ __device__ __forceinline__ void inv_pass(const Load &ld, const Store &st, const 
 #pragma unroll
         for (int c = 0; c < P::E; ++c) {
             if (LAST)
-                st(pi, P::elem(S, c), mulmod(x[c], ninv, p, pinv), p, pinv);
+                store_val(st, pi, P::elem(S, c), mulmod(x[c], ninv, p, pinv), p, pinv, pr[c]);
             else
                 lds[lds_idx(P::elem(S, c))] = reduce(x[c], p, pinv);
         }
@@ -277,7 +405,10 @@ __device__ __forceinline__ void inv_pass(const Load &ld, const Store &st, const 
 }
 
 // Forward negacyclic NTT of polynomial `poly` by the calling workgroup of T
-// threads, with `lds` holding NttPasses<LOGN, T>::LDS doubles.
+// threads, with `lds` holding NttPasses<LOGN, T>::LDS doubles.  The first pass
+// reads its few twiddles from global memory, the middle ones from the LDS table;
+// the last pass's twiddles (one set per thread) are requested before the pass
+// ahead of it, so their latency hides behind that pass.
 template <int LOGN, int T, class Load, class Store>
 __device__ __forceinline__ void ntt_fwd_block(const Load &ld, const Store &st, const DevParams &dp,
                                               int poly, double *lds)
@@ -288,19 +419,53 @@ __device__ __forceinline__ void ntt_fwd_block(const Load &ld, const Store &st, c
     const int l = pi.l;
     const double p = dp.p[l], pinv = dp.pinv[l];
     const double *tw = dp.tw_fwd + ((size_t)l << LOGN);
+    const double *twl = lds + NP::DATA;
+    load_tw_table<LOGN, T>(tw, lds);
     fwd_pass<typename NP::A, T, true, false>(ld, st, pi, tw, p, pinv, lds);
     __syncthreads();
-    fwd_pass<typename NP::B, T, false, false>(ld, st, pi, tw, p, pinv, lds);
-    __syncthreads();
-    fwd_pass<typename NP::C, T, false, !FOUR>(ld, st, pi, tw, p, pinv, lds);
     if constexpr (FOUR) {
+        using PC = typename NP::C;
+        using PD = typename NP::D;
+        fwd_pass<typename NP::B, T, false, false>(ld, st, pi, twl, p, pinv, lds);
         __syncthreads();
-        fwd_pass<typename NP::D, T, false, true>(ld, st, pi, tw, p, pinv, lds);
+        if constexpr (PD::PER_THREAD == 1) {
+            double w[PD::NTW];
+            PD::load_tw((int)threadIdx.x, tw, w);
+            fwd_pass<PC, T, false, false>(ld, st, pi, twl, p, pinv, lds);
+            if constexpr (exchange_in_wave<PC, PD, T>())
+                wave_sync();
+            else
+                __syncthreads();
+            fwd_pass<PD, T, false, true>(ld, st, pi, tw, p, pinv, lds, w);
+        } else {
+            fwd_pass<PC, T, false, false>(ld, st, pi, twl, p, pinv, lds);
+            __syncthreads();
+            fwd_pass<PD, T, false, true>(ld, st, pi, tw, p, pinv, lds);
+        }
+    } else {
+        using PB = typename NP::B;
+        using PC = typename NP::C;
+        if constexpr (PC::PER_THREAD == 1) {
+            double w[PC::NTW];
+            PC::load_tw((int)threadIdx.x, tw, w);
+            fwd_pass<PB, T, false, false>(ld, st, pi, twl, p, pinv, lds);
+            if constexpr (exchange_in_wave<PB, PC, T>())
+                wave_sync();
+            else
+                __syncthreads();
+            fwd_pass<PC, T, false, true>(ld, st, pi, tw, p, pinv, lds, w);
+        } else {
+            fwd_pass<PB, T, false, false>(ld, st, pi, twl, p, pinv, lds);
+            __syncthreads();
+            fwd_pass<PC, T, false, true>(ld, st, pi, tw, p, pinv, lds);
+        }
     }
 }
 
 // Inverse negacyclic NTT (including the factor N^-1) of polynomial `poly`; with
-// G > 1 only the coefficients j with j % G == G - 1 are produced.
+// G > 1 only the coefficients j with j % G == G - 1 are produced.  The first pass
+// reads its twiddles from global memory (with its inputs), the others from the
+// LDS table.
 template <int LOGN, int T, int G = 1, class Load, class Store>
 __device__ __forceinline__ void ntt_inv_block(const Load &ld, const Store &st, const DevParams &dp,
                                               int poly, double *lds)
@@ -311,16 +476,21 @@ __device__ __forceinline__ void ntt_inv_block(const Load &ld, const Store &st, c
     const int l = pi.l;
     const double p = dp.p[l], pinv = dp.pinv[l];
     const double *tw = dp.tw_inv + ((size_t)l << LOGN);
+    const double *twl = lds + NP::DATA;
     const double ninv = dp.n_inv[l];
+    load_tw_table<LOGN, T>(tw, lds);
     if constexpr (FOUR) {
         inv_pass<typename NP::D, T, true, false, G>(ld, st, pi, tw, p, pinv, ninv, lds);
         __syncthreads();
     }
-    inv_pass<typename NP::C, T, !FOUR, false, G>(ld, st, pi, tw, p, pinv, ninv, lds);
+    if constexpr (FOUR)
+        inv_pass<typename NP::C, T, false, false, G>(ld, st, pi, twl, p, pinv, ninv, lds);
+    else
+        inv_pass<typename NP::C, T, true, false, G>(ld, st, pi, tw, p, pinv, ninv, lds);
     __syncthreads();
-    inv_pass<typename NP::B, T, false, false, G>(ld, st, pi, tw, p, pinv, ninv, lds);
+    inv_pass<typename NP::B, T, false, false, G>(ld, st, pi, twl, p, pinv, ninv, lds);
     __syncthreads();
-    inv_pass<typename NP::A, T, false, true, G>(ld, st, pi, tw, p, pinv, ninv, lds);
+    inv_pass<typename NP::A, T, false, true, G>(ld, st, pi, twl, p, pinv, ninv, lds);
 }
 
 // Polynomial of a workgroup: workgroups are dispatched round-robin over the XCDs, so the
@@ -335,6 +505,22 @@ __global__ __launch_bounds__(ntt_threads<LOGN>()) void k_ntt_fwd(Load ld, Store 
     constexpr int T = ntt_threads<LOGN>();
     __shared__ double lds[NttPasses<LOGN, T>::LDS];
     ntt_fwd_block<LOGN, T>(ld, st, dp, ntt_poly(), lds);
+}
+
+// Forward transform of two polynomial lists in one launch: polynomials below n1 read
+// through ld1, the rest through ld2.  The choice is per workgroup, so each loader's
+// reads stay free of branches (a branch between reads would make each wait for the last).
+template <int LOGN, class Load1, class Load2, class Store>
+__global__ __launch_bounds__(ntt_threads<LOGN>()) void k_ntt_fwd2(Load1 ld1, Load2 ld2, int n1, Store st,
+                                                                   DevParams dp)
+{
+    constexpr int T = ntt_threads<LOGN>();
+    __shared__ double lds[NttPasses<LOGN, T>::LDS];
+    const int poly = ntt_poly();
+    if (poly < n1)
+        ntt_fwd_block<LOGN, T>(ld1, st, dp, poly, lds);
+    else
+        ntt_fwd_block<LOGN, T>(ld2, st, dp, poly, lds);
 }
 
 // Forward transform that also clears its share of another buffer (the
@@ -363,7 +549,7 @@ __global__ __launch_bounds__(ntt_threads<LOGN>()) void k_ntt_inv(Load ld, Store 
 
 // Inverse transform whose result stays in the workgroup's LDS (natural order,
 // lds_idx layout), followed by an epilogue that reads it with the whole
-// workgroup: epi(poly, lds, dp).  The last pass's storer writes exactly the
+// workgroup: epi.run<LOGN, T>(poly, lds, dp).  The last pass's storer writes exactly the
 // elements its thread has just read, so no barrier is needed before it.  With
 // G > 1, the polynomials for which epi.sparse(pi) holds are transformed with
 // output pruning (only j % G == G - 1 is produced; the epilogue reads no other
@@ -388,7 +574,7 @@ __global__ __launch_bounds__(ntt_threads<LOGN>()) void k_ntt_inv_lds(Load ld, Ep
     else
         ntt_inv_block<LOGN, T, 1>(ld, StoreLds{lds}, dp, poly, lds);
     __syncthreads();
-    epi(pi, lds, dp);
+    epi.template run<LOGN, T>(pi, lds, dp);
 }
 
 // The output pruning an epilogue that reads the decoded positions t * rb + rb - 1
@@ -471,6 +657,20 @@ int launch_fwd(const Ctx &c, Load ld, Store st, int npoly, hipStream_t s)
     else
         hipLaunchKernelGGL((k_ntt_fwd<13, Load, Store>), dim3(npoly), dim3(ntt_threads<13>()), 0, s, ld,
                            st, c.dp);
+    return check_hip(hipGetLastError(), "ntt_fwd launch");
+}
+
+template <class Load1, class Load2, class Store>
+int launch_fwd2(const Ctx &c, Load1 ld1, Load2 ld2, int n1, Store st, int npoly, hipStream_t s)
+{
+    if (npoly <= 0) return PIMM_OK;
+    ProfScope prof("ntt_fwd", s);
+    if (c.dp.logN == 12)
+        hipLaunchKernelGGL((k_ntt_fwd2<12, Load1, Load2, Store>), dim3(npoly), dim3(ntt_threads<12>()), 0,
+                           s, ld1, ld2, n1, st, c.dp);
+    else
+        hipLaunchKernelGGL((k_ntt_fwd2<13, Load1, Load2, Store>), dim3(npoly), dim3(ntt_threads<13>()), 0,
+                           s, ld1, ld2, n1, st, c.dp);
     return check_hip(hipGetLastError(), "ntt_fwd launch");
 }
 

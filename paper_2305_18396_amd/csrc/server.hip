@@ -88,32 +88,41 @@ struct LoadRerand {
 };
 
 // Inputs of the re-randomisation transforms as one polynomial list: the 2L
-// polynomials of pk (canonical residues, [2][L][N]) then, for each output
-// ciphertext, u shared by the L primes (int64 [O][N]).  Polynomial index poly
-// keeps prime poly % L in both parts (2L is a multiple of L).
-struct LoadPkU {
-    const uint64_t *pk;
+// polynomials of pk (canonical residues, [2][L][N], LoadU64) then, for each output
+// ciphertext, u shared by the L primes (one signed byte per coefficient, [O][N]):
+// polynomial index poly keeps prime poly % L in both parts (2L is a multiple of L), and
+// u's polynomial is poly / L - x0 with x0 = 2.
+struct LoadI8Shared {
     const int8_t *u;
-    int logn, L;
+    int logn;
+    uint32_t x0;
     __device__ double operator()(const PolyIx &pi, int j, double, double) const
     {
-        if (pi.x < 2) return f64_of(pk[((size_t)pi.poly << logn) + j]);
-        return (double)u[((size_t)(pi.x - 2) << logn) + j];
+        return (double)u[((size_t)(pi.x - x0) << logn) + j];
     }
 };
 
-// acc[o][comp][l][j] += (u pk_comp)_j + e_comp[j]  (mod q_l); e: [O][2][N].
+// acc[o][comp][l][j] += (u pk_comp)_j + e_comp[j]  (mod q_l); e: [O][2][N].  The
+// accumulator and error words are read ahead of the transform's last pass (Pre).
 struct StoreAddErr {
     uint64_t *acc;
     const int8_t *e;
     int logn, L;
-    __device__ void operator()(const PolyIx &pi, int j, double v, double p, double pinv) const
+    struct Pre {
+        uint64_t a;
+        int e;
+    };
+    __device__ Pre pre(const PolyIx &pi, int j) const
+    {
+        return Pre{acc[((size_t)pi.poly << logn) + j], (int)e[((size_t)pi.x << logn) + j]};
+    }
+    __device__ void operator()(const PolyIx &pi, int j, double v, double p, double pinv,
+                               const Pre &pr) const
     {
         const uint64_t q = (uint64_t)p;
-        const size_t at = ((size_t)pi.poly << logn) + j;
         const uint64_t up = to_canonical(v, p, pinv);
-        const uint64_t ee = lift_small(e[((size_t)pi.x << logn) + j], q);
-        acc[at] = add_mod(add_mod(acc[at], up, q), ee, q);
+        const uint64_t ee = lift_small((int64_t)pr.e, q);
+        acc[((size_t)pi.poly << logn) + j] = add_mod(add_mod(pr.a, up, q), ee, q);
     }
 };
 
@@ -145,19 +154,21 @@ __global__ void k_mask_extract(Key key, uint32_t op, const uint64_t *acc, uint64
 
 // ---- fused server step: product, re-randomisation, mask and reply ----------------
 
-// acc^ (reduced) plus, with re-randomisation, u^ pk^ (NTT domain) for polynomials [O][2][L].
+// acc^ (reduced) plus, with re-randomisation (RR), u^ pk^ (NTT domain) for polynomials
+// [O][2][L]; RUN16: acc^ in the matrix-core product's chunked layout.  Both choices are
+// compile-time, so the reads of a pass carry no branches and are issued together.
+template <bool RR, bool RUN16>
 struct LoadAccRerand {
-    const double *ah;   // [O][2][L][N], or [L][N/16][O][2][16] with run16
+    const double *ah;   // [O][2][L][N], or [L][N/16][O][2][16] with RUN16
     const double *uh;   // [O][L][N]
     const double *pkh;  // [2][L][N]
-    int logn, L, rr;
-    int run16;
-    uint32_t O2, NC;  // 2 * O and N / 16 (run16 layout)
+    int logn, L;
+    uint32_t O2, NC;  // 2 * O and N / 16 (RUN16 layout)
     __device__ double operator()(const PolyIx &pi, int z, double p, double pinv) const
     {
-        const size_t at = run16 ? run16_index(pi, z, O2, NC) : ((size_t)pi.poly << logn) + z;
+        const size_t at = RUN16 ? run16_index(pi, z, O2, NC) : ((size_t)pi.poly << logn) + z;
         double v = reduce(ah[at], p, pinv);
-        if (rr) {
+        if constexpr (RR) {
             const size_t o = (size_t)(pi.x >> 1), comp = (size_t)(pi.x & 1), l = (size_t)pi.l;
             v += mulmod(uh[((o * L + l) << logn) + z], pkh[((comp * L + l) << logn) + z], p, pinv);
         }
@@ -166,37 +177,57 @@ struct LoadAccRerand {
 };
 
 // The reply of output ciphertext y from its coefficient form in LDS: add the
-// re-randomisation error, then write c1 (component 1, every coefficient) or
+// re-randomisation error (RR), then write c1 (component 1, every coefficient) or
 // the unmasked c0 at the m_b n_b decoded positions k*mb*rb + i*rb + rb - 1
-// (component 0).
+// (component 0).  A thread reads all its error bytes before its first store.
+template <bool RR>
 struct ReplyOut {
     uint64_t *c1, *c0s;
     const int8_t *e;  // [O][2][N]
     FastDiv mb;
     uint32_t rb, nb;
-    int logn, L, rr;
+    int logn, L;
     // Component 0 is read at the decoded positions only.
     __device__ bool sparse(const PolyIx &pi) const { return (pi.x & 1) == 0; }
-    __device__ void operator()(const PolyIx &pi, const double *lds, const DevParams &dp) const
+    template <int LOGN, int T>
+    __device__ void run(const PolyIx &pi, const double *lds, const DevParams &dp) const
     {
         const int l = pi.l;
         const uint32_t y = (uint32_t)(pi.x >> 1), comp = (uint32_t)(pi.x & 1);
         const double p = dp.p[l], pinv = dp.pinv[l];
-        const int8_t *ey = e + (((size_t)y * 2 + comp) << logn);
-        const int n = 1 << logn;
+        const int8_t *ey = e + (((size_t)y * 2 + comp) << LOGN);
         // The transform's output (within 1.5 q_l) plus the error (|e| <= 19), reduced once.
         if (comp == 1) {
-            uint64_t *dst = c1 + (((size_t)y * L + l) << logn);
-            for (int j = threadIdx.x; j < n; j += (int)blockDim.x)
-                dst[j] = to_canonical(lds[lds_idx(j)] + (rr ? (double)ey[j] : 0.0), p, pinv);
+            constexpr int PER = (1 << LOGN) / T;
+            uint64_t *dst = c1 + (((size_t)y * L + l) << LOGN);
+            double ev[PER];
+#pragma unroll
+            for (int k = 0; k < PER; ++k) ev[k] = RR ? (double)ey[(int)threadIdx.x + k * T] : 0.0;
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int j = (int)threadIdx.x + k * T;
+                dst[j] = to_canonical(lds[lds_idx(j)] + ev[k], p, pinv);
+            }
             return;
         }
         const uint32_t per = mb.d * nb;
         uint64_t *dst = c0s + ((size_t)y * L + l) * per;
-        for (uint32_t idx = threadIdx.x; idx < per; idx += blockDim.x) {
-            const uint32_t k = mb.div(idx), i = idx - k * mb.d;
-            const uint32_t j = (k * mb.d + i) * rb + rb - 1;
-            dst[idx] = to_canonical(lds[lds_idx((int)j)] + (rr ? (double)ey[j] : 0.0), p, pinv);
+        constexpr int B = 4;  // positions per round: their error bytes are read together
+        for (uint32_t idx0 = threadIdx.x; idx0 < per; idx0 += B * T) {
+            uint32_t jj[B];
+            double ev[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const uint32_t idx = idx0 + b * T;
+                const uint32_t k = mb.div(idx), i = idx - k * mb.d;
+                jj[b] = (k * mb.d + i) * rb + rb - 1;
+                ev[b] = (RR && idx < per) ? (double)ey[jj[b]] : 0.0;
+            }
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const uint32_t idx = idx0 + b * T;
+                if (idx < per) dst[idx] = to_canonical(lds[lds_idx((int)jj[b])] + ev[b], p, pinv);
+            }
         }
     }
 };
@@ -232,6 +263,19 @@ __global__ void k_mask_reply(Key key, uint32_t op, uint64_t *c0s, uint64_t *shar
     }
 }
 
+// The reply transform of every output polynomial: acc^ (+ u^ pk^), inverse transform,
+// + error, then c1 and the decoded positions of c0.
+template <bool RR, bool RUN16>
+static int reply_transform(const Ctx &c, const pimm_plan_info &f, const double *ah, const double *uh,
+                           const double *pkh, uint64_t *c1, uint64_t *c0s, const int8_t *e, hipStream_t s)
+{
+    const int lg = c.dp.logN;
+    const int L = (int)c.params.L;
+    return launch_inv_lds(c, LoadAccRerand<RR, RUN16>{ah, uh, pkh, lg, L, 2 * f.O, (uint32_t)(c.params.N / 16)},
+                          ReplyOut<RR>{c1, c0s, e, FastDiv::make(f.mb), f.rb, f.nb, lg, L},
+                          (int)(f.O * 2 * L), prune_factor(f.rb), s);
+}
+
 // The fused step after the product, on the workspace laid out as
 // c^ [I][2][L][N], acc^ [O][2][L][N], pk^ [2][L][N], u^ [O][L][N] (doubles),
 // u [O][N], e [O][2][N] (int64), acc^ already summed over the inner blocks:
@@ -257,13 +301,17 @@ int fused_tail(const pimm_plan *plan, const uint64_t *pk, const Key &key, uint32
         rc = launch_samples(c, key, op_id, rerand_jobs(f.O, N, u, e), s);
         // pk^ and u^ in one launch: they are adjacent in the workspace.
         if (!rc)
-            rc = launch_fwd(c, LoadPkU{pk, u, lg, (int)L}, StoreSlots{pkh, lg}, (int)((2 + f.O) * L), s);
+            rc = launch_fwd2(c, LoadU64{pk, lg}, LoadI8Shared{u, lg, 2u}, (int)(2 * L), StoreSlots{pkh, lg},
+                             (int)((2 + f.O) * L), s);
     }
-    if (!rc)
-        rc = launch_inv_lds(c, LoadAccRerand{ah, uh, pkh, lg, (int)L, rr, run16 ? 1 : 0, 2 * f.O,
-                                             (uint32_t)(N / 16)},
-                            ReplyOut{c1, c0s, e, FastDiv::make(f.mb), f.rb, f.nb, lg, (int)L, rr},
-                            (int)(f.O * 2 * L), prune_factor(f.rb), s);
+    if (!rc) {
+        if (rr)
+            rc = run16 ? reply_transform<true, true>(c, f, ah, uh, pkh, c1, c0s, e, s)
+                       : reply_transform<true, false>(c, f, ah, uh, pkh, c1, c0s, e, s);
+        else
+            rc = run16 ? reply_transform<false, true>(c, f, ah, uh, pkh, c1, c0s, e, s)
+                       : reply_transform<false, false>(c, f, ah, uh, pkh, c1, c0s, e, s);
+    }
     if (!rc) {
         const uint32_t blocks = (f.mb * f.rb * f.nb + 7) / 8;
         const size_t total = (size_t)f.O * blocks;
@@ -460,7 +508,8 @@ int pimm_mask_share(const pimm_plan *plan, const uint64_t *pk, const uint8_t see
         rc = launch_samples(c, key, op_id, rerand_jobs(f.O, N, u, e), s);
         // pk^ and u^ in one launch: they are adjacent in the workspace.
         if (!rc)
-            rc = launch_fwd(c, LoadPkU{pk, u, lg, (int)L}, StoreSlots{pkh, lg}, (int)((2 + f.O) * L), s);
+            rc = launch_fwd2(c, LoadU64{pk, lg}, LoadI8Shared{u, lg, 2u}, (int)(2 * L), StoreSlots{pkh, lg},
+                             (int)((2 + f.O) * L), s);
         if (!rc)
             rc = launch_inv(c, LoadRerand{uh, pkh, lg, (int)L}, StoreAddErr{acc, e, lg, (int)L},
                             (int)(f.O * 2 * L), s);
