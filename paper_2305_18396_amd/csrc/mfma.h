@@ -27,14 +27,18 @@ struct StoreCtRun16 {
     int L;
     __device__ void operator()(const PolyIx &pi, int z, double v, double, double) const
     {
-        out[(((size_t)pi.l * NC + (uint32_t)(z >> 4)) * I2 + (uint32_t)pi.x) * 16 + (z & 15)] = v;
+        // The workgroup's base (uniform) plus run z / 16 of stride 16 I2: one 32 x 32 -> 64-bit
+        // multiply-add per element.
+        const size_t base = ((size_t)pi.l * NC * I2 + (uint32_t)pi.x) * 16 + ((uint32_t)z & 15u);
+        out[(size_t)((uint32_t)z >> 4) * (I2 * 16u) + base] = v;
     }
 };
 
 // Index of accumulator polynomial (o*2 + comp)*L + l, slot z, in [L][N/16][O][2][16].
 __device__ __forceinline__ size_t run16_index(const PolyIx &pi, int z, uint32_t O2, uint32_t NC)
 {
-    return (((size_t)pi.l * NC + (uint32_t)(z >> 4)) * O2 + (uint32_t)pi.x) * 16 + (z & 15);
+    const size_t base = ((size_t)pi.l * NC * O2 + (uint32_t)pi.x) * 16 + ((uint32_t)z & 15u);
+    return (size_t)((uint32_t)z >> 4) * (O2 * 16u) + base;
 }
 
 // Accumulators in the chunked layout, reduced (the plain pimm_matmul's inverse transform).

@@ -61,7 +61,7 @@ constexpr int ntt_threads()
 
 // LDS slot of element j, padded by one double every 32 to break bank aliasing
 // of the strided pass patterns.
-__device__ __forceinline__ int lds_idx(int j) { return j + (j >> 5); }
+__host__ __device__ constexpr int lds_idx(int j) { return j + (j >> 5); }
 
 // Output pruning of the inverse transform.  When only the coefficients j with
 // j % G == G - 1 are read afterwards (G a power of two <= 16: the decoded
@@ -98,9 +98,22 @@ struct Pass {
     static_assert(PER_THREAD >= 1 && NSETS % T == 0, "pass shape");
 
     // Element index of member c of set S.
-    __device__ static __forceinline__ int elem(int S, int c)
+    __host__ __device__ static constexpr int elem(int S, int c)
     {
         return (S / STRIDE) * (N >> S0) + (S % STRIDE) + c * STRIDE;
+    }
+
+    // LDS slot of member c relative to member 0: the members of a set are STRIDE apart
+    // and never cross a padding boundary differently from member 0's offset
+    // (lds_split_ok), so a pass computes one address per set and the rest are
+    // instruction offsets.
+    __host__ __device__ static constexpr int lds_off(int c) { return lds_idx(c * STRIDE); }
+    static constexpr bool lds_split_ok()
+    {
+        for (int S = 0; S < NSETS; ++S)
+            for (int c = 0; c < E; ++c)
+                if (lds_idx(elem(S, c)) != lds_idx(elem(S, 0)) + lds_off(c)) return false;
+        return true;
     }
 
     // Twiddles set S uses, stage by stage: w[2^sp - 1 + j] is the factor of the
@@ -206,6 +219,15 @@ struct NttPasses {
     // Fourth pass (only when P3 > 0; otherwise a placeholder that is never used).
     using D = Pass<LOGN, S::P0 + S::P1 + S::P2, (S::P3 > 0 ? S::P3 : 1), T>;
     static_assert(S::P0 + S::P1 + S::P2 + S::P3 == LOGN, "schedule covers every stage");
+    static constexpr bool d_split_ok()
+    {
+        if constexpr (S::P3 > 0)
+            return D::lds_split_ok();
+        else
+            return true;
+    }
+    static_assert(A::lds_split_ok() && B::lds_split_ok() && C::lds_split_ok() && d_split_ok(),
+                  "per-set LDS addressing");
     static constexpr int N = 1 << LOGN;
     // The pass that touches global memory in slot order (the forward's last, the inverse's
     // first) and its size.
@@ -248,6 +270,16 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+
+// Storer of a transform whose result stays in the workgroup's LDS (natural order,
+// lds_idx layout).
+struct StoreLds {
+    double *lds;
+    __device__ void operator()(const PolyIx &, int j, double v, double, double) const
+    {
+        lds[lds_idx(j)] = v;
+    }
+};
 
 // A storer whose value needs global inputs of its own (the plaintext and error words of
 // an encryption) declares `Pre`, reads them in `pre(pi, j)` and takes them back as the
@@ -304,6 +336,7 @@ __device__ __forceinline__ void fwd_pass(const Load &ld, const Store &st, const 
 #pragma unroll
     for (int k = 0; k < P::PER_THREAD; ++k) {
         const int S = (int)threadIdx.x + k * T;
+        const int b0 = lds_idx(P::elem(S, 0));
         pre_t<Store> pr[P::E];
         if constexpr (LAST && has_pre<Store>::value) {
 #pragma unroll
@@ -312,7 +345,7 @@ __device__ __forceinline__ void fwd_pass(const Load &ld, const Store &st, const 
         double x[P::E];
 #pragma unroll
         for (int c = 0; c < P::E; ++c)
-            x[c] = FIRST ? ld(pi, P::elem(S, c), p, pinv) : lds[lds_idx(P::elem(S, c))];
+            x[c] = FIRST ? ld(pi, P::elem(S, c), p, pinv) : lds[b0 + P::lds_off(c)];
         if (w)
             P::fwd_w(x, w, p, pinv);
         else
@@ -322,7 +355,7 @@ __device__ __forceinline__ void fwd_pass(const Load &ld, const Store &st, const 
             if (LAST)
                 store_val(st, pi, c * P::NSETS + S, reduce(x[c], p, pinv), p, pinv, pr[c]);
             else
-                lds[lds_idx(P::elem(S, c))] = reduce(x[c], p, pinv);
+                lds[b0 + P::lds_off(c)] = reduce(x[c], p, pinv);
         }
     }
 }
@@ -345,13 +378,14 @@ __device__ __forceinline__ void inv_pass(const Load &ld, const Store &st, const 
 #pragma unroll
         for (int k = 0; k < P::PER_THREAD; ++k) {
             const int S = (int)threadIdx.x + k * T;
+            const int b0 = lds_idx(P::elem(S, 0));
             double x[P::E];
 #pragma unroll
             for (int c = 0; c < P::E; ++c) x[c] = ld(pi, c * P::NSETS + S, p, pinv);
             P::template inv_pruned<G>(x, S, tw, p, pinv);
 #pragma unroll
             for (int c = 0; c < P::E; ++c)
-                if (c % G == G - 1) lds[lds_idx(P::elem(S, c))] = reduce(x[c], p, pinv);
+                if (c % G == G - 1) lds[b0 + P::lds_off(c)] = reduce(x[c], p, pinv);
         }
         return;
     }
@@ -362,6 +396,7 @@ __device__ __forceinline__ void inv_pass(const Load &ld, const Store &st, const 
             const int u = (int)threadIdx.x + k * T;
             if (u >= NEED) break;
             const int S = u * G + (G - 1);
+            const int b0 = lds_idx(P::elem(S, 0));
             pre_t<Store> pr[P::E];
             if constexpr (LAST && has_pre<Store>::value) {
 #pragma unroll
@@ -369,14 +404,16 @@ __device__ __forceinline__ void inv_pass(const Load &ld, const Store &st, const 
             }
             double x[P::E];
 #pragma unroll
-            for (int c = 0; c < P::E; ++c) x[c] = lds[lds_idx(P::elem(S, c))];
+            for (int c = 0; c < P::E; ++c) x[c] = lds[b0 + P::lds_off(c)];
             P::inv(x, S, tw, p, pinv);
 #pragma unroll
             for (int c = 0; c < P::E; ++c) {
-                if (LAST)
+                if constexpr (LAST && std::is_same<Store, StoreLds>::value)
+                    lds[b0 + P::lds_off(c)] = mulmod(x[c], ninv, p, pinv);
+                else if (LAST)
                     store_val(st, pi, P::elem(S, c), mulmod(x[c], ninv, p, pinv), p, pinv, pr[c]);
                 else
-                    lds[lds_idx(P::elem(S, c))] = reduce(x[c], p, pinv);
+                    lds[b0 + P::lds_off(c)] = reduce(x[c], p, pinv);
             }
         }
         return;
@@ -384,6 +421,7 @@ __device__ __forceinline__ void inv_pass(const Load &ld, const Store &st, const 
 #pragma unroll
     for (int k = 0; k < P::PER_THREAD; ++k) {
         const int S = (int)threadIdx.x + k * T;
+        const int b0 = lds_idx(P::elem(S, 0));
         pre_t<Store> pr[P::E];
         if constexpr (LAST && has_pre<Store>::value) {
 #pragma unroll
@@ -392,14 +430,16 @@ __device__ __forceinline__ void inv_pass(const Load &ld, const Store &st, const 
         double x[P::E];
 #pragma unroll
         for (int c = 0; c < P::E; ++c)
-            x[c] = FIRST ? ld(pi, c * P::NSETS + S, p, pinv) : lds[lds_idx(P::elem(S, c))];
+            x[c] = FIRST ? ld(pi, c * P::NSETS + S, p, pinv) : lds[b0 + P::lds_off(c)];
         P::inv(x, S, tw, p, pinv);
 #pragma unroll
         for (int c = 0; c < P::E; ++c) {
-            if (LAST)
+            if constexpr (LAST && std::is_same<Store, StoreLds>::value)
+                lds[b0 + P::lds_off(c)] = mulmod(x[c], ninv, p, pinv);
+            else if (LAST)
                 store_val(st, pi, P::elem(S, c), mulmod(x[c], ninv, p, pinv), p, pinv, pr[c]);
             else
-                lds[lds_idx(P::elem(S, c))] = reduce(x[c], p, pinv);
+                lds[b0 + P::lds_off(c)] = reduce(x[c], p, pinv);
         }
     }
 }
@@ -554,14 +594,6 @@ __global__ __launch_bounds__(ntt_threads<LOGN>()) void k_ntt_inv(Load ld, Store 
 // G > 1, the polynomials for which epi.sparse(pi) holds are transformed with
 // output pruning (only j % G == G - 1 is produced; the epilogue reads no other
 // coefficient of them).
-struct StoreLds {
-    double *lds;
-    __device__ void operator()(const PolyIx &, int j, double v, double, double) const
-    {
-        lds[lds_idx(j)] = v;
-    }
-};
-
 template <int LOGN, int G, class Load, class Epi>
 __global__ __launch_bounds__(ntt_threads<LOGN>()) void k_ntt_inv_lds(Load ld, Epi epi, DevParams dp)
 {
