@@ -350,6 +350,7 @@ struct SampleJob {
     void *out;
     size_t obj_stride, prime_stride;
     uint32_t blocks;  // workgroups of this job (set by launch_samples)
+    FastDiv pdiv;     // division by nprime (set by launch_samples)
 };
 struct SampleJobs {
     SampleJob job[kMaxSampleJobs];

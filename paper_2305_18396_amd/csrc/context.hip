@@ -439,15 +439,17 @@ void switched_params(const Ctx &c, DevParams &d, double *qd_inv)
 // values (int64), 2 eight Gaussian values (int64), 3 eight Z_{2^l} values (uint64).
 template <int KIND>
 __device__ __forceinline__ void sample_block(const Key &key, uint32_t op, const SampleJob &jb,
-                                             long gid, const DevParams &dp)
+                                             uint32_t gid, const DevParams &dp)
 {
     constexpr int per = 8;
-    const int nblk = dp.N / per;
-    if (gid >= (long)nblk * jb.nprime * jb.nobj) return;
-    const int b = (int)(gid % nblk);
-    const int li = (int)((gid / nblk) % jb.nprime);
-    const int l = jb.prime0 + li;
-    const int o = (int)(gid / ((long)nblk * jb.nprime));
+    // gid = (o * nprime + li) * (N / 8) + b; the host keeps every job below 2^31 threads.
+    const int lognb = dp.logN - 3;
+    const uint32_t rest = gid >> lognb;
+    if (rest >= (uint32_t)jb.nprime * (uint32_t)jb.nobj) return;
+    const uint32_t b = gid & ((1u << lognb) - 1u);
+    const uint32_t o = jb.pdiv.div(rest);
+    const uint32_t li = rest - o * (uint32_t)jb.nprime;
+    const int l = jb.prime0 + (int)li;
     uint32_t w[16];
     chacha_block(key, (uint32_t)b, nonce0(jb.tag, KIND == 0 ? (uint32_t)l : 0u), op,
                  jb.obj0 + (uint32_t)o, w);
@@ -511,7 +513,7 @@ __global__ __launch_bounds__(256) void k_sample(Key key, uint32_t op, SampleJobs
         ++k;
     }
     const SampleJob &jb = js.job[k];
-    const long gid = (long)b * blockDim.x + threadIdx.x;
+    const uint32_t gid = b * blockDim.x + threadIdx.x;
     switch (jb.kind) {
     case 0: sample_block<0>(key, op, jb, gid, dp); break;
     case 1: sample_block<1>(key, op, jb, gid, dp); break;
@@ -531,7 +533,10 @@ int launch_samples(const Ctx &c, const Key &key, uint32_t op, SampleJobs js, hip
         SampleJob &jb = js.job[k];
         const int per = 8;
         const long total = jb.nobj > 0 ? (long)(c.dp.N / per) * jb.nprime * jb.nobj : 0;
+        if (total >= (1l << 31) || jb.nprime < 1)
+            return set_error(PIMM_E_SHAPE, "launch_samples: job %d has %ld blocks of draws", k, total);
         jb.blocks = (uint32_t)((total + threads - 1) / threads);
+        jb.pdiv = FastDiv::make((uint32_t)jb.nprime);
         grid += jb.blocks;
     }
     if (!grid) return PIMM_OK;

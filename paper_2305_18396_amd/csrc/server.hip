@@ -142,11 +142,15 @@ __global__ void k_mask_extract(Key key, uint32_t op, const uint64_t *acc, uint64
     chacha_block(key, pos / 8, nonce0(kTagMask, 0), op, y, w);
     const uint64_t sm = mask_of(word64(w, (int)(pos % 8)), dp.ell);
     const size_t N = (size_t)dp.N, L = (size_t)dp.L;
-    for (int l = 0; l < dp.L; ++l) {
-        const uint64_t q = dp.q[l];
-        const uint64_t a0 = acc[(((size_t)y * 2 + 0) * L + l) * N + pos];
-        c0s[((size_t)y * L + l) * per + idx] = sub_mod(a0, mul_mod(dp.delta[l], sm, dp.p[l], dp.pinv[l]), q);
-    }
+    uint64_t a0[kMaxL];  // every prime's word read before the first store
+#pragma unroll
+    for (int l = 0; l < kMaxL; ++l)
+        if (l < dp.L) a0[l] = acc[(((size_t)y * 2 + 0) * L + l) * N + pos];
+#pragma unroll
+    for (int l = 0; l < kMaxL; ++l)
+        if (l < dp.L)
+            c0s[((size_t)y * L + l) * per + idx] =
+                sub_mod(a0[l], mul_mod(dp.delta[l], sm, dp.p[l], dp.pinv[l]), dp.q[l]);
     const OutPos yp = out_pos(y, f);
     const uint32_t row = yp.kb * f.nb + k, col = yp.ib * f.mb + i;
     if (row < f.n && col < f.m) share[(size_t)yp.g * f.n * f.m + (size_t)row * f.m + col] = sm;
@@ -232,10 +236,45 @@ struct ReplyOut {
     }
 };
 
-// The mask of output ciphertext y over Z_t: one thread per ChaCha20 block b of
-// stream (MASK, 0, op, y), i.e. coefficient positions 8b .. 8b+7; at each decoded
-// position pos = k*mb*rb + i*rb + rb-1: c0s[y][l][k*mb + i] -= Delta_l s (all
-// primes) and the server's share is s.
+// The mask of output ciphertext y over Z_t at its decoded positions
+// pos = k*mb*rb + i*rb + rb-1: s = mask draw number pos of stream (MASK, 0, op, y);
+// c0s[y][l][k*mb + i] -= Delta_l s (every prime) and the server's share is s.
+// Two thread layouts compute the same values: with rb >= 8 a ChaCha20 block holds at
+// most one decoded position, so one thread per decoded position (no block computed for
+// nothing); with rb < 8 one thread per block takes the block's 8 / rb positions.
+__device__ __forceinline__ void mask_one(uint64_t *c0s, uint64_t *share, uint32_t y, uint32_t idx,
+                                         uint64_t sm, const pimm_plan_info &f, const DevParams &dp)
+{
+    const uint32_t per = f.mb * f.nb;
+    uint64_t *dst = c0s + (size_t)y * dp.L * per + idx;
+    uint64_t cur[kMaxL];
+#pragma unroll
+    for (int l = 0; l < kMaxL; ++l)
+        if (l < dp.L) cur[l] = dst[(size_t)l * per];
+#pragma unroll
+    for (int l = 0; l < kMaxL; ++l)
+        if (l < dp.L)
+            dst[(size_t)l * per] = sub_mod(cur[l], mul_mod(dp.delta[l], sm, dp.p[l], dp.pinv[l]), dp.q[l]);
+    const OutPos yp = out_pos(y, f);
+    const uint32_t k = idx / f.mb, i = idx - k * f.mb;
+    const uint32_t row = yp.kb * f.nb + k, col = yp.ib * f.mb + i;
+    if (row < f.n && col < f.m) share[(size_t)yp.g * f.n * f.m + (size_t)row * f.m + col] = sm;
+}
+
+__global__ void k_mask_reply_pos(Key key, uint32_t op, uint64_t *c0s, uint64_t *share, pimm_plan_info f,
+                                 DevParams dp)
+{
+    const uint32_t per = f.mb * f.nb;
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (size_t)f.O * per) return;
+    const uint32_t y = (uint32_t)(gid / per), idx = (uint32_t)(gid % per);
+    const uint32_t k = idx / f.mb, i = idx - k * f.mb;
+    const uint32_t pos = (k * f.mb + i) * f.rb + f.rb - 1;
+    uint32_t w[16];
+    chacha_block(key, pos / 8, nonce0(kTagMask, 0), op, y, w);
+    mask_one(c0s, share, y, idx, mask_of(word64(w, (int)(pos % 8)), dp.ell), f, dp);
+}
+
 __global__ void k_mask_reply(Key key, uint32_t op, uint64_t *c0s, uint64_t *share, uint32_t blocks,
                              pimm_plan_info f, DevParams dp)
 {
@@ -244,22 +283,13 @@ __global__ void k_mask_reply(Key key, uint32_t op, uint64_t *c0s, uint64_t *shar
     const uint32_t y = (uint32_t)(gid / blocks), b = (uint32_t)(gid % blocks);
     uint32_t w[16];
     chacha_block(key, b, nonce0(kTagMask, 0), op, y, w);
-    const uint32_t per = f.mb * f.nb;
-    const OutPos yp = out_pos(y, f);
-    share += (size_t)yp.g * f.n * f.m;
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
         const uint32_t pos = b * 8 + t;
         if (pos % f.rb != f.rb - 1) continue;
         const uint32_t k = pos / (f.mb * f.rb), i = (pos / f.rb) % f.mb;
         if (k >= f.nb) continue;
-        const uint64_t sm = mask_of(word64(w, t), dp.ell);
-        for (int l = 0; l < dp.L; ++l) {
-            uint64_t *dst = c0s + ((size_t)y * dp.L + l) * per + k * f.mb + i;
-            *dst = sub_mod(*dst, mul_mod(dp.delta[l], sm, dp.p[l], dp.pinv[l]), dp.q[l]);
-        }
-        const uint32_t row = yp.kb * f.nb + k, col = yp.ib * f.mb + i;
-        if (row < f.n && col < f.m) share[(size_t)row * f.m + col] = sm;
+        mask_one(c0s, share, y, k * f.mb + i, mask_of(word64(w, t), dp.ell), f, dp);
     }
 }
 
@@ -313,11 +343,17 @@ int fused_tail(const pimm_plan *plan, const uint64_t *pk, const Key &key, uint32
                        : reply_transform<false, false>(c, f, ah, uh, pkh, c1, c0s, e, s);
     }
     if (!rc) {
-        const uint32_t blocks = (f.mb * f.rb * f.nb + 7) / 8;
-        const size_t total = (size_t)f.O * blocks;
         ProfScope prof("mask_extract", s);
-        hipLaunchKernelGGL(k_mask_reply, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, key,
-                           op_id, c0s, server_share, blocks, f, c.dp);
+        if (f.rb >= 8) {
+            const size_t total = (size_t)f.O * f.mb * f.nb;
+            hipLaunchKernelGGL(k_mask_reply_pos, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, key,
+                               op_id, c0s, server_share, f, c.dp);
+        } else {
+            const uint32_t blocks = (f.mb * f.rb * f.nb + 7) / 8;
+            const size_t total = (size_t)f.O * blocks;
+            hipLaunchKernelGGL(k_mask_reply, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, key,
+                               op_id, c0s, server_share, blocks, f, c.dp);
+        }
         rc = check_hip(hipGetLastError(), "mask_reply launch");
     }
     return rc;
