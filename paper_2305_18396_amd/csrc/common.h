@@ -365,10 +365,10 @@ int launch_sample(const Ctx &c, int kind, const Key &key, uint32_t tag, uint32_t
 // Slot-wise products of one plan into zeroed-then-accumulated acc^ (mac.hip).
 // The fused server step after the product (server.hip), on a workspace laid out as
 // pimm_matmul_share's; pk may be NULL without re-randomisation.
-// run16: acc^ is in the matrix-core product's chunked layout [L][N/16][O][2][16]
+// mx_layout: acc^ is in the matrix-core product's layout (acc_run_index)
 // instead of [O][2][L][N].
 int fused_tail(const pimm_plan *plan, const uint64_t *pk, const Key &key, uint32_t op_id,
-               double *ws, uint64_t *c1, uint64_t *c0s, uint64_t *server_share, bool run16,
+               double *ws, uint64_t *c1, uint64_t *c0s, uint64_t *server_share, bool mx_layout,
                hipStream_t s);
 // The product of one plan (acc^ zeroed first unless `zeroed` says the caller did).
 int launch_mac(const Ctx &c, const pimm_plan_info &f, int G, int KB, int waves, const double *Wt,

@@ -15,7 +15,7 @@ uint64_t digit_cache_bytes(const Ctx &c, const pimm_plan_info &f);
 // Digit form [L][N][7][Mt][64][16 B] of the FP64 cache Wt [L][N/256][M][R][256].
 int build_weight_digits(const Ctx &c, const pimm_plan_info &f, const double *Wt, void *Wd,
                         hipStream_t s);
-// acc^ [L][N/16][O][2][16] = the slot-wise products of c^ [L][N/16][I][2][16] with the
+// acc^ [L][N/kAccRun][O][2][kAccRun] = the slot-wise products of c^ [L][N/16][I][2][16] with the
 // digit weight cache Wd.  Every accumulator is written once (no zeroing needed).
 int launch_mac_mfma(const Ctx &c, const pimm_plan_info &f, const void *Wd, const double *Ch,
                     double *Ah, hipStream_t s);
@@ -34,21 +34,24 @@ struct StoreCtRun16 {
     }
 };
 
-// Index of accumulator polynomial (o*2 + comp)*L + l, slot z, in [L][N/16][O][2][16].
-__device__ __forceinline__ size_t run16_index(const PolyIx &pi, int z, uint32_t O2, uint32_t NC)
+// Accumulators of the matrix-core product in runs of the kAccRun slots one workgroup
+// computes: polynomial (o*2 + comp)*L + l, slot z at [L][N/kAccRun][O][2][kAccRun] (a
+// wave's stores then cover whole lines).  NR = N / kAccRun.
+constexpr int kAccRun = 8;
+__device__ __forceinline__ size_t acc_run_index(const PolyIx &pi, int z, uint32_t O2, uint32_t NR)
 {
-    const size_t base = ((size_t)pi.l * NC * O2 + (uint32_t)pi.x) * 16 + ((uint32_t)z & 15u);
-    return (size_t)((uint32_t)z >> 4) * (O2 * 16u) + base;
+    const size_t base = ((size_t)pi.l * NR * O2 + (uint32_t)pi.x) * kAccRun + ((uint32_t)z % kAccRun);
+    return (size_t)((uint32_t)z / kAccRun) * (O2 * (uint32_t)kAccRun) + base;
 }
 
-// Accumulators in the chunked layout, reduced (the plain pimm_matmul's inverse transform).
-struct LoadSlotsReduceRun16 {
+// Accumulators in that layout, reduced (the plain pimm_matmul's inverse transform).
+struct LoadSlotsReduceRun {
     const double *a;
-    uint32_t O2, NC;
+    uint32_t O2, NR;
     int L;
     __device__ double operator()(const PolyIx &pi, int z, double p, double pinv) const
     {
-        return reduce(a[run16_index(pi, z, O2, NC)], p, pinv);
+        return reduce(a[acc_run_index(pi, z, O2, NR)], p, pinv);
     }
 };
 

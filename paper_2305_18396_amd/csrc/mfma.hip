@@ -30,11 +30,15 @@
 // of its 16 bytes; the 16 x 16 int32 result has row 4 (t / 16) + v, column t % 16
 // in element v of lane t.
 //
-// Layouts (slots in chunks of 16, so that a chunk of one polynomial is one
-// 128-byte line):
+// Layouts:
 //   digit weight cache  [L][N][7][Mt][64 lanes][16 B]   (A fragments, Mt = ceil(M/16))
-//   c^   (f64)          [L][N/16][I][2][16]             (written by the input transform)
-//   acc^ (f64)          [L][N/16][O][2][16]             (read by the output transform)
+//   c^   (f64)          [L][N/16][I][2][16]             (written by the input transform: a
+//                                                        chunk of 16 slots of one polynomial
+//                                                        is one 128-byte line)
+//   acc^ (f64)          [L][N/8][O][2][8]               (read by the output transform; a
+//                                                        tile's 4 slots are half a run, so
+//                                                        its stores cover half lines and the
+//                                                        transform's reads 64-byte runs)
 #include "common.h"
 #include "mfma.h"
 
@@ -149,14 +153,14 @@ constexpr int kMfmaPerCu = 16 / kMfmaSlots;  // workgroups per compute unit (128
 // rg*4 .. rg*4+3 (one per wave).  LDS holds one 8 KiB region per slot: first the slot's
 // B fragments ([digit][column][4 x 16 B], the 16-byte groups of column j rotated by
 // (j / 4) % 4 so that the 16 lanes of a group hit distinct banks), then, once every wave
-// has issued its products for the slot, the slot's results ([wave][row v][lane] doubles).
-// At the end each lane writes its 4 rows x 4 slots as 32-byte runs (the other three
-// quarters of each 128-byte line are the sibling workgroups', h).  32 KiB of LDS and at
-// most 128 registers per lane: four workgroups (16 waves) share a compute unit, so the
-// loads of some overlap the matrix instructions of others; with 8 slots (64 KiB) only two
-// fit and the waves spend most of their time waiting on memory.  Logical index (from
-// xcd_local, so that the quarters and the column tiles of a chunk run side by side on one
-// XCD and share its L2)
+// has issued its products for the slot, the slot's results ([wave][row v][lane] doubles),
+// which the wave finally writes out with lanes remapped so that each row's 16 columns x
+// 4 slots go out as 16 contiguous 32-byte pieces of the accumulator runs (acc_run_index;
+// the sibling tile h ^ 1 writes the other halves).  32 KiB of LDS and at most 128
+// registers per lane: four workgroups (16 waves) share a compute unit, so the loads of
+// some overlap the matrix instructions of others; with 8 slots (64 KiB) only two fit.
+// Logical index (from xcd_local, so that the quarters and the column tiles of a chunk
+// run side by side on one XCD and share its L2)
 //     lb = (((l * NC + zc) * RG + rg) * CT + ct) * 4 + h.
 __global__ __launch_bounds__(kMfmaThreads, kMfmaPerCu) void k_mac_mfma(MfmaArgs g, DevParams dp)
 {
@@ -260,18 +264,26 @@ __global__ __launch_bounds__(kMfmaThreads, kMfmaPerCu) void k_mac_mfma(MfmaArgs 
         }
     }
     if (!active) return;
-    const int col = ct * 16 + jl, kb = col >> 1, comp = col & 1;
-    if (kb >= g.K) return;
+    // Lane k of a store instruction writes 2 slots (16 bytes) of one (row, column): the 8 S
+    // lanes of a row cover its 16 columns x S slots as one contiguous run, and an
+    // instruction covers 8 / S rows.
+    constexpr int LPR = 8 * kMfmaSlots, RPI = 64 / LPR, HALF = kMfmaSlots / 2;
+    static_assert(kAccRun % kMfmaSlots == 0 && 16 % kAccRun == 0 && 64 % LPR == 0, "output runs");
+    const int kk = lane % LPR, sp = kk % HALF, cl = kk / HALF;
+    const int colg = ct * 16 + cl, kb = colg >> 1, comp = colg & 1;
+    const double *res = (const double *)lds + (size_t)wv * 4 * 64 + cl;
+    // Run of the tile's slots and their offset in it.
+    const size_t zr = ((size_t)l * g.NC + zc) * (16 / kAccRun) + (h * kMfmaSlots) / kAccRun;
+    const int zoff = (h * kMfmaSlots) % kAccRun;
 #pragma unroll
-    for (int vv = 0; vv < 4; ++vv) {
-        const int ib = it * 16 + 4 * gq + vv;
-        if (ib >= g.M) continue;
-        const double *src = (const double *)lds + (size_t)wv * 4 * 64 + vv * 64 + lane;
+    for (int i = 0; i < 16 / RPI; ++i) {
+        const int row = RPI * i + lane / LPR;  // = 4 gq + vv of the results
+        const int ib = it * 16 + row;
+        if (ib >= g.M || kb >= g.K) continue;
+        const double *src = res + (row >> 2) * 16 + (row & 3) * 64;
         double2 *dst = (double2 *)(g.Ah +
-            ((((size_t)l * g.NC + zc) * g.O + (size_t)ib * g.K + kb) * 2 + comp) * 16 + h * kMfmaSlots);
-#pragma unroll
-        for (int s2 = 0; s2 < kMfmaSlots / 2; ++s2)
-            dst[s2] = double2{src[(2 * s2) * kSlotLds * 2], src[(2 * s2 + 1) * kSlotLds * 2]};
+            ((zr * g.O + (size_t)ib * g.K + kb) * 2 + comp) * kAccRun + zoff + 2 * sp);
+        *dst = double2{src[(2 * sp) * kSlotLds * 2], src[(2 * sp + 1) * kSlotLds * 2]};
     }
 }
 

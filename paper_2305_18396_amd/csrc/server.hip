@@ -159,18 +159,18 @@ __global__ void k_mask_extract(Key key, uint32_t op, const uint64_t *acc, uint64
 // ---- fused server step: product, re-randomisation, mask and reply ----------------
 
 // acc^ (reduced) plus, with re-randomisation (RR), u^ pk^ (NTT domain) for polynomials
-// [O][2][L]; RUN16: acc^ in the matrix-core product's chunked layout.  Both choices are
+// [O][2][L]; RUN: acc^ in the matrix-core product's layout (acc_run_index).  Both choices are
 // compile-time, so the reads of a pass carry no branches and are issued together.
-template <bool RR, bool RUN16>
+template <bool RR, bool RUN>
 struct LoadAccRerand {
-    const double *ah;   // [O][2][L][N], or [L][N/16][O][2][16] with RUN16
+    const double *ah;   // [O][2][L][N], or the matrix-core layout with RUN
     const double *uh;   // [O][L][N]
     const double *pkh;  // [2][L][N]
     int logn, L;
-    uint32_t O2, NC;  // 2 * O and N / 16 (RUN16 layout)
+    uint32_t O2, NR;  // 2 * O and N / kAccRun (RUN layout)
     __device__ double operator()(const PolyIx &pi, int z, double p, double pinv) const
     {
-        const size_t at = RUN16 ? run16_index(pi, z, O2, NC) : ((size_t)pi.poly << logn) + z;
+        const size_t at = RUN ? acc_run_index(pi, z, O2, NR) : ((size_t)pi.poly << logn) + z;
         double v = reduce(ah[at], p, pinv);
         if constexpr (RR) {
             const size_t o = (size_t)(pi.x >> 1), comp = (size_t)(pi.x & 1), l = (size_t)pi.l;
@@ -295,13 +295,13 @@ __global__ void k_mask_reply(Key key, uint32_t op, uint64_t *c0s, uint64_t *shar
 
 // The reply transform of every output polynomial: acc^ (+ u^ pk^), inverse transform,
 // + error, then c1 and the decoded positions of c0.
-template <bool RR, bool RUN16>
+template <bool RR, bool RUN>
 static int reply_transform(const Ctx &c, const pimm_plan_info &f, const double *ah, const double *uh,
                            const double *pkh, uint64_t *c1, uint64_t *c0s, const int8_t *e, hipStream_t s)
 {
     const int lg = c.dp.logN;
     const int L = (int)c.params.L;
-    return launch_inv_lds(c, LoadAccRerand<RR, RUN16>{ah, uh, pkh, lg, L, 2 * f.O, (uint32_t)(c.params.N / 16)},
+    return launch_inv_lds(c, LoadAccRerand<RR, RUN>{ah, uh, pkh, lg, L, 2 * f.O, (uint32_t)(c.params.N / kAccRun)},
                           ReplyOut<RR>{c1, c0s, e, FastDiv::make(f.mb), f.rb, f.nb, lg, L},
                           (int)(f.O * 2 * L), prune_factor(f.rb), s);
 }
@@ -312,7 +312,7 @@ static int reply_transform(const Ctx &c, const pimm_plan_info &f, const double *
 // re-randomisation draws and transforms, the inverse transform with the reply
 // epilogue, then the mask at the decoded positions and the server's share.
 int fused_tail(const pimm_plan *plan, const uint64_t *pk, const Key &key, uint32_t op_id,
-               double *ws, uint64_t *c1, uint64_t *c0s, uint64_t *server_share, bool run16,
+               double *ws, uint64_t *c1, uint64_t *c0s, uint64_t *server_share, bool mx_layout,
                hipStream_t s)
 {
     const Ctx &c = *plan->ctx;
@@ -336,10 +336,10 @@ int fused_tail(const pimm_plan *plan, const uint64_t *pk, const Key &key, uint32
     }
     if (!rc) {
         if (rr)
-            rc = run16 ? reply_transform<true, true>(c, f, ah, uh, pkh, c1, c0s, e, s)
+            rc = mx_layout ? reply_transform<true, true>(c, f, ah, uh, pkh, c1, c0s, e, s)
                        : reply_transform<true, false>(c, f, ah, uh, pkh, c1, c0s, e, s);
         else
-            rc = run16 ? reply_transform<false, true>(c, f, ah, uh, pkh, c1, c0s, e, s)
+            rc = mx_layout ? reply_transform<false, true>(c, f, ah, uh, pkh, c1, c0s, e, s)
                        : reply_transform<false, false>(c, f, ah, uh, pkh, c1, c0s, e, s);
     }
     if (!rc) {
@@ -505,7 +505,7 @@ int pimm_matmul(const pimm_plan *plan, const pimm_weights *w, const uint64_t *ct
                             (int)(f.I * 2 * L), s);
         if (!rc) rc = launch_mac_mfma(c, f, w->d_w_dig, ch, ah, s);
         if (!rc)
-            rc = launch_inv(c, LoadSlotsReduceRun16{ah, 2 * f.O, (uint32_t)(N / 16), (int)L},
+            rc = launch_inv(c, LoadSlotsReduceRun{ah, 2 * f.O, (uint32_t)(N / kAccRun), (int)L},
                             StoreU64{acc, lg}, (int)(f.O * 2 * L), s);
         return rc;
     }
