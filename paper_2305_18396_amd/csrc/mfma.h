@@ -15,22 +15,25 @@ uint64_t digit_cache_bytes(const Ctx &c, const pimm_plan_info &f);
 // Digit form [L][N][7][Mt][64][16 B] of the FP64 cache Wt [L][N/256][M][R][256].
 int build_weight_digits(const Ctx &c, const pimm_plan_info &f, const double *Wt, void *Wd,
                         hipStream_t s);
-// acc^ [L][N/kAccRun][O][2][kAccRun] = the slot-wise products of c^ [L][N/16][I][2][16] with the
+// acc^ [L][N/kAccRun][O][2][kAccRun] = the slot-wise products of c^ [L][N/kInRun][I][2][kInRun] with the
 // digit weight cache Wd.  Every accumulator is written once (no zeroing needed).
 int launch_mac_mfma(const Ctx &c, const pimm_plan_info &f, const void *Wd, const double *Ch,
                     double *Ah, hipStream_t s);
 
-// Input transform storer for the chunked layout: polynomial (x*2 + comp)*L + l, slot z.
-struct StoreCtRun16 {
+// Transformed inputs of the matrix-core product in runs of kInRun slots: polynomial
+// (x*2 + comp)*L + l, slot z at [L][N/kInRun][I][2][kInRun].  Input transform storer
+// (NR = N / kInRun).
+constexpr int kInRun = 8;
+struct StoreCtRun {
     double *out;
-    uint32_t I2, NC;  // 2 * I, N / 16
+    uint32_t I2, NR;  // 2 * I, N / kInRun
     int L;
     __device__ void operator()(const PolyIx &pi, int z, double v, double, double) const
     {
-        // The workgroup's base (uniform) plus run z / 16 of stride 16 I2: one 32 x 32 -> 64-bit
-        // multiply-add per element.
-        const size_t base = ((size_t)pi.l * NC * I2 + (uint32_t)pi.x) * 16 + ((uint32_t)z & 15u);
-        out[(size_t)((uint32_t)z >> 4) * (I2 * 16u) + base] = v;
+        // The workgroup's base (uniform) plus run z / kInRun of stride kInRun I2: one
+        // 32 x 32 -> 64-bit multiply-add per element.
+        const size_t base = ((size_t)pi.l * NR * I2 + (uint32_t)pi.x) * kInRun + ((uint32_t)z % kInRun);
+        out[(size_t)((uint32_t)z / kInRun) * (I2 * (uint32_t)kInRun) + base] = v;
     }
 };
 

@@ -32,9 +32,9 @@
 //
 // Layouts:
 //   digit weight cache  [L][N][7][Mt][64 lanes][16 B]   (A fragments, Mt = ceil(M/16))
-//   c^   (f64)          [L][N/16][I][2][16]             (written by the input transform: a
-//                                                        chunk of 16 slots of one polynomial
-//                                                        is one 128-byte line)
+//   c^   (f64)          [L][N/8][I][2][8]               (written by the input transform in
+//                                                        64-byte runs; a tile reads their
+//                                                        32-byte halves)
 //   acc^ (f64)          [L][N/8][O][2][8]               (read by the output transform; a
 //                                                        tile's 4 slots are half a run, so
 //                                                        its stores cover half lines and the
@@ -175,7 +175,10 @@ __global__ __launch_bounds__(kMfmaThreads, kMfmaPerCu) void k_mac_mfma(MfmaArgs 
     const int zc = (int)(lb % g.NC);
     const int l = (int)(lb / g.NC);
     const int tid = (int)threadIdx.x;
-    const size_t line0 = ((size_t)l * g.NC + zc) * g.I;  // first line of the chunk (c^)
+    // The run of c^ that holds the tile's slots, and their offset in it.
+    static_assert(kInRun % kMfmaSlots == 0 && 16 % kInRun == 0, "input runs");
+    const size_t line0 = (((size_t)l * g.NC + zc) * (16 / kInRun) + (h * kMfmaSlots) / kInRun) * g.I;
+    const int zin = (h * kMfmaSlots) % kInRun;
 
     // Inputs: thread (q, j) takes inner blocks 4q .. 4q+3 of column j for the workgroup's slots.  All
     // loads are issued before any is used (absent blocks read a valid line and are zeroed
@@ -191,7 +194,7 @@ __global__ __launch_bounds__(kMfmaThreads, kMfmaPerCu) void k_mac_mfma(MfmaArgs 
         const int jb = 4 * qq + r;
         ok[r] = jb < g.R && kbq < g.K;
         const double2 *src = (const double2 *)(g.Ch +
-            (ok[r] ? ((line0 + (size_t)jb * g.K + kbq) * 2 + compq) * 16 + h * kMfmaSlots : 0));
+            (ok[r] ? ((line0 + (size_t)jb * g.K + kbq) * 2 + compq) * kInRun + zin : 0));
 #pragma unroll
         for (int s2 = 0; s2 < kMfmaSlots / 2; ++s2) v[r][s2] = src[s2];
     }

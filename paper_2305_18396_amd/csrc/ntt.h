@@ -601,12 +601,21 @@ __global__ __launch_bounds__(ntt_threads<LOGN>()) void k_ntt_inv_lds(Load ld, Ep
     __shared__ double lds[NttPasses<LOGN, T>::LDS];
     const int poly = ntt_poly();
     const PolyIx pi = poly_ix(poly, dp.L);
+    // An epilogue with inputs of its own (Pre) reads them before the transform, so they
+    // arrive behind its work instead of after it.  Not without pruning (G = 1): the
+    // registers they take then make the compiler split the first pass's reads.
+    constexpr bool PRE = has_pre<Epi>::value && G > 1;
+    pre_t<Epi> epre;
+    if constexpr (PRE) epre = epi.template pre<LOGN, T>(pi);
     if (G > 1 && epi.sparse(pi))
         ntt_inv_block<LOGN, T, G>(ld, StoreLds{lds}, dp, poly, lds);
     else
         ntt_inv_block<LOGN, T, 1>(ld, StoreLds{lds}, dp, poly, lds);
     __syncthreads();
-    epi.template run<LOGN, T>(pi, lds, dp);
+    if constexpr (PRE)
+        epi.template run<LOGN, T>(pi, lds, dp, epre);
+    else
+        epi.template run<LOGN, T>(pi, lds, dp);
 }
 
 // The output pruning an epilogue that reads the decoded positions t * rb + rb - 1

@@ -183,56 +183,112 @@ struct LoadAccRerand {
 // The reply of output ciphertext y from its coefficient form in LDS: add the
 // re-randomisation error (RR), then write c1 (component 1, every coefficient) or
 // the unmasked c0 at the m_b n_b decoded positions k*mb*rb + i*rb + rb - 1
-// (component 0).  A thread reads all its error bytes before its first store.
+// (component 0).  The error bytes a thread needs (all 16 of a c1 polynomial, the first
+// round of 4 decoded positions of a c0 one) are read before the transform (Pre).
 template <bool RR>
-struct ReplyOut {
+struct ReplyOutBase {
     uint64_t *c1, *c0s;
     const int8_t *e;  // [O][2][N]
     FastDiv mb;
     uint32_t rb, nb;
     int logn, L;
+    static constexpr int kPer = 16;  // coefficients per thread: N / T for both ring degrees
+    static constexpr int kB = 4;     // decoded positions per round
     // Component 0 is read at the decoded positions only.
     __device__ bool sparse(const PolyIx &pi) const { return (pi.x & 1) == 0; }
-    template <int LOGN, int T>
-    __device__ void run(const PolyIx &pi, const double *lds, const DevParams &dp) const
+    __device__ uint32_t pos_of(uint32_t idx) const
     {
+        const uint32_t k = mb.div(idx), i = idx - k * mb.d;
+        return (k * mb.d + i) * rb + rb - 1;
+    }
+    template <int LOGN, int T>
+    __device__ void run_with(const PolyIx &pi, const double *lds, const DevParams &dp, const int *e16) const
+    {
+        static_assert((1 << LOGN) / T == kPer, "coefficients per thread");
         const int l = pi.l;
         const uint32_t y = (uint32_t)(pi.x >> 1), comp = (uint32_t)(pi.x & 1);
         const double p = dp.p[l], pinv = dp.pinv[l];
         const int8_t *ey = e + (((size_t)y * 2 + comp) << LOGN);
         // The transform's output (within 1.5 q_l) plus the error (|e| <= 19), reduced once.
         if (comp == 1) {
-            constexpr int PER = (1 << LOGN) / T;
             uint64_t *dst = c1 + (((size_t)y * L + l) << LOGN);
-            double ev[PER];
 #pragma unroll
-            for (int k = 0; k < PER; ++k) ev[k] = RR ? (double)ey[(int)threadIdx.x + k * T] : 0.0;
-#pragma unroll
-            for (int k = 0; k < PER; ++k) {
+            for (int k = 0; k < kPer; ++k) {
                 const int j = (int)threadIdx.x + k * T;
-                dst[j] = to_canonical(lds[lds_idx(j)] + ev[k], p, pinv);
+                dst[j] = to_canonical(lds[lds_idx(j)] + (double)e16[k], p, pinv);
             }
             return;
         }
         const uint32_t per = mb.d * nb;
         uint64_t *dst = c0s + ((size_t)y * L + l) * per;
-        constexpr int B = 4;  // positions per round: their error bytes are read together
-        for (uint32_t idx0 = threadIdx.x; idx0 < per; idx0 += B * T) {
-            uint32_t jj[B];
-            double ev[B];
+        for (uint32_t idx0 = threadIdx.x; idx0 < per; idx0 += kB * T) {
+            uint32_t jj[kB];
+            double ev[kB];
+            const bool first = idx0 == threadIdx.x;
 #pragma unroll
-            for (int b = 0; b < B; ++b) {
+            for (int b = 0; b < kB; ++b) {
                 const uint32_t idx = idx0 + b * T;
-                const uint32_t k = mb.div(idx), i = idx - k * mb.d;
-                jj[b] = (k * mb.d + i) * rb + rb - 1;
-                ev[b] = (RR && idx < per) ? (double)ey[jj[b]] : 0.0;
+                jj[b] = pos_of(idx);
+                ev[b] = first ? (double)e16[b] : ((RR && idx < per) ? (double)ey[jj[b]] : 0.0);
             }
 #pragma unroll
-            for (int b = 0; b < B; ++b) {
+            for (int b = 0; b < kB; ++b) {
                 const uint32_t idx = idx0 + b * T;
                 if (idx < per) dst[idx] = to_canonical(lds[lds_idx((int)jj[b])] + ev[b], p, pinv);
             }
         }
+    }
+};
+
+template <bool RR>
+struct ReplyOut;
+
+// With re-randomisation: the error bytes come ahead of the transform.
+template <>
+struct ReplyOut<true> : ReplyOutBase<true> {
+    struct Pre {
+        int e[kPer];
+    };
+    template <int LOGN, int T>
+    __device__ Pre pre(const PolyIx &pi) const
+    {
+        Pre pr;
+        const uint32_t y = (uint32_t)(pi.x >> 1), comp = (uint32_t)(pi.x & 1);
+        const int8_t *ey = e + (((size_t)y * 2 + comp) << LOGN);
+        if (comp == 1) {
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) pr.e[k] = ey[(int)threadIdx.x + k * T];
+        } else {
+            const uint32_t per = mb.d * nb;
+#pragma unroll
+            for (int b = 0; b < kB; ++b) {
+                const uint32_t idx = threadIdx.x + b * T;
+                pr.e[b] = idx < per ? ey[pos_of(idx)] : 0;
+            }
+        }
+        return pr;
+    }
+    template <int LOGN, int T>
+    __device__ void run(const PolyIx &pi, const double *lds, const DevParams &dp, const Pre &pr) const
+    {
+        run_with<LOGN, T>(pi, lds, dp, pr.e);
+    }
+    // The bytes read after the transform instead (still all before the first store).
+    template <int LOGN, int T>
+    __device__ void run(const PolyIx &pi, const double *lds, const DevParams &dp) const
+    {
+        const Pre pr = pre<LOGN, T>(pi);
+        run_with<LOGN, T>(pi, lds, dp, pr.e);
+    }
+};
+
+template <>
+struct ReplyOut<false> : ReplyOutBase<false> {
+    template <int LOGN, int T>
+    __device__ void run(const PolyIx &pi, const double *lds, const DevParams &dp) const
+    {
+        const int zero[kPer] = {};
+        run_with<LOGN, T>(pi, lds, dp, zero);
     }
 };
 
@@ -302,7 +358,7 @@ static int reply_transform(const Ctx &c, const pimm_plan_info &f, const double *
     const int lg = c.dp.logN;
     const int L = (int)c.params.L;
     return launch_inv_lds(c, LoadAccRerand<RR, RUN>{ah, uh, pkh, lg, L, 2 * f.O, (uint32_t)(c.params.N / kAccRun)},
-                          ReplyOut<RR>{c1, c0s, e, FastDiv::make(f.mb), f.rb, f.nb, lg, L},
+                          ReplyOut<RR>{{c1, c0s, e, FastDiv::make(f.mb), f.rb, f.nb, lg, L}},
                           (int)(f.O * 2 * L), prune_factor(f.rb), s);
 }
 
@@ -501,7 +557,7 @@ int pimm_matmul(const pimm_plan *plan, const pimm_weights *w, const uint64_t *ct
     if (plan->mac_rows == 0) {
         rc = mfma_ready(plan, w, "pimm_matmul");
         if (!rc)
-            rc = launch_fwd(c, LoadU64{ct, lg}, StoreCtRun16{ch, 2 * f.I, (uint32_t)(N / 16), (int)L},
+            rc = launch_fwd(c, LoadU64{ct, lg}, StoreCtRun{ch, 2 * f.I, (uint32_t)(N / kInRun), (int)L},
                             (int)(f.I * 2 * L), s);
         if (!rc) rc = launch_mac_mfma(c, f, w->d_w_dig, ch, ah, s);
         if (!rc)
@@ -592,7 +648,7 @@ int pimm_matmul_share(const pimm_plan *plan, const pimm_weights *w, const uint64
     if (mx) {
         rc = mfma_ready(plan, w, "pimm_matmul_share");
         if (!rc)
-            rc = launch_fwd(c, LoadU64{ct, lg}, StoreCtRun16{ch, 2 * f.I, (uint32_t)(N / 16), (int)L},
+            rc = launch_fwd(c, LoadU64{ct, lg}, StoreCtRun{ch, 2 * f.I, (uint32_t)(N / kInRun), (int)L},
                             (int)(f.I * 2 * L), s);
         if (!rc) rc = launch_mac_mfma(c, f, w->d_w_dig, ch, ah, s);
     } else {
