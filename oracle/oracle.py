@@ -88,7 +88,11 @@ def lib():
         _lib.orc_mask_extract.argtypes = [u64, u64, vp, vp, ctypes.c_uint, vp, u32, u64, u64, u64,
                                           vp, u64, vp, vp, vp, vp]
         _lib.orc_decrypt_residues.argtypes = [u64, u64, vp, vp, vp, u64, u64, u64, u64, vp, vp, vp]
-        _lib.orc_decrypt_full_residues.argtypes = [u64, u64, vp, vp, vp, u64, vp, vp]
+        _lib.orc_decrypt_full_residues.argtypes = [u64, u64, vp, vp, vp, u64, vp, ctypes.c_int, vp]
+        _lib.orc_slot_index.argtypes = [u64, u64]
+        _lib.orc_slot_index.restype = u64
+        _lib.orc_slots_to_coef.argtypes = [vp, vp, u64, u64, u64]
+        _lib.orc_coef_to_slots.argtypes = [vp, vp, u64, u64, u64]
         _lib.orc_max_threads.restype = ctypes.c_int
     return _lib
 
@@ -342,7 +346,8 @@ def keygen(params: Params, seed: bytes, with_pk: bool | None = None):
 
 
 def encrypt(params: Params, s: np.ndarray, seed: bytes, op_id: int, pt: np.ndarray) -> np.ndarray:
-    """Algorithm 1 step 2: symmetric encryption of each plaintext row.  -> [count][2][L][N]."""
+    """Algorithm 1 step 2: symmetric encryption of each plaintext row.  -> [count][2][L][N],
+    c1 (the uniform part a) in evaluation form: the uniform draws are a's slots (slot_index)."""
     pt = _u64(pt)
     count = pt.shape[0]
     ct = np.zeros((count, 2, params.L, params.N), dtype=np.uint64)
@@ -448,26 +453,63 @@ def decrypt_residues(params: Params, plan: Plan, s: np.ndarray, c1: np.ndarray,
     return x
 
 
-def decrypt_full(params: Params, s: np.ndarray, ct: np.ndarray) -> np.ndarray:
-    """Decrypt every coefficient of whole ciphertexts [count][2][L][N] -> [count][N] in Z_t."""
+def decrypt_full(params: Params, s: np.ndarray, ct: np.ndarray, query: bool = False) -> np.ndarray:
+    """Decrypt every coefficient of whole ciphertexts [count][2][L][N] -> [count][N] in Z_t.
+    query: c1 in evaluation form (a query ciphertext from encrypt); else coefficient form (a
+    product's output)."""
     ct = _u64(ct)
     count = ct.shape[0]
     x = np.zeros((count, params.N, params.L), dtype=np.uint64)
     lib().orc_decrypt_full_residues(params.N, params.L, _p(params.q_arr), _p(params.psi_arr),
                                     _p(np.ascontiguousarray(s, dtype=np.int64)), count, _p(ct),
-                                    _p(x))
+                                    1 if query else 0, _p(x))
     return crt_round(params, x)
 
 
-def noise_of(params: Params, s: np.ndarray, ct: np.ndarray, expected: np.ndarray) -> int:
+def slot_index(N: int) -> np.ndarray:
+    """k[z]: slot z of the evaluation form holds the value at psi^(2k+1)."""
+    return np.array([lib().orc_slot_index(z, N) for z in range(N)], dtype=np.uint64)
+
+
+def slots_to_coef(params: Params, S: np.ndarray) -> np.ndarray:
+    """Coefficients [..][L][N] of polynomials given by their slots [..][L][N]."""
+    S = _u64(S)
+    out = np.zeros_like(S)
+    flat_s, flat_o = S.reshape(-1, params.L, params.N), out.reshape(-1, params.L, params.N)
+    for i in range(flat_s.shape[0]):
+        for l in range(params.L):
+            src = np.ascontiguousarray(flat_s[i, l])
+            dst = np.zeros(params.N, np.uint64)
+            lib().orc_slots_to_coef(_p(src), _p(dst), params.N, int(params.q[l]), int(params.psi[l]))
+            flat_o[i, l] = dst
+    return out
+
+
+def coef_to_slots(params: Params, a: np.ndarray) -> np.ndarray:
+    """Slots [..][L][N] of polynomials given by their coefficients [..][L][N]."""
+    a = _u64(a)
+    out = np.zeros_like(a)
+    flat_a, flat_o = a.reshape(-1, params.L, params.N), out.reshape(-1, params.L, params.N)
+    for i in range(flat_a.shape[0]):
+        for l in range(params.L):
+            src = np.ascontiguousarray(flat_a[i, l])
+            dst = np.zeros(params.N, np.uint64)
+            lib().orc_coef_to_slots(_p(src), _p(dst), params.N, int(params.q[l]), int(params.psi[l]))
+            flat_o[i, l] = dst
+    return out
+
+
+def noise_of(params: Params, s: np.ndarray, ct: np.ndarray, expected: np.ndarray,
+             query: bool = False) -> int:
     """Exact decryption noise max |[c0 + c1 s]_q - Delta*m| over the coefficients of ct,
-    with m the expected plaintext [count][N] (centred representative mod q)."""
+    with m the expected plaintext [count][N] (centred representative mod q); query as for
+    decrypt_full."""
     ct = _u64(ct)
     count = ct.shape[0]
     x = np.zeros((count, params.N, params.L), dtype=np.uint64)
     lib().orc_decrypt_full_residues(params.N, params.L, _p(params.q_arr), _p(params.psi_arr),
                                     _p(np.ascontiguousarray(s, dtype=np.int64)), count, _p(ct),
-                                    _p(x))
+                                    1 if query else 0, _p(x))
     Q = params.Q
     coef = [(Q // q) * pow(Q // q, -1, q) for q in params.q]
     worst = 0

@@ -296,6 +296,39 @@ void orc_negacyclic_mul(const uint64_t *a, const uint64_t *b, uint64_t *c, uint6
     free(B);
 }
 
+/* Evaluation form of a query ciphertext's uniform part (how c1 travels): slot z
+ * of an n-coefficient polynomial holds its value at psi^(2k+1) with
+ * k = brv(16 (z mod n/16) + floor(z / (n/16))), brv reversing log2(n) bits.
+ * (n >= 16, a power of two.) */
+uint64_t orc_slot_index(uint64_t z, uint64_t n)
+{
+    uint64_t m = n / 16, e = 16 * (z % m) + z / m, k = 0;
+    for (uint64_t b = 1; b < n; b <<= 1) {
+        k = (k << 1) | (e & 1);
+        e >>= 1;
+    }
+    return k;
+}
+
+/* Coefficients of the polynomial whose slots are S (evaluation form -> coefficients). */
+void orc_slots_to_coef(const uint64_t *S, uint64_t *a, uint64_t n, uint64_t q, uint64_t psi)
+{
+    uint64_t *A = (uint64_t *)malloc(n * sizeof(uint64_t));
+    for (uint64_t z = 0; z < n; ++z) A[orc_slot_index(z, n)] = S[z] % q;
+    orc_intt_negacyclic(A, a, n, q, psi);
+    free(A);
+}
+
+/* Slots of the polynomial a (coefficients -> evaluation form). */
+void orc_coef_to_slots(const uint64_t *a, uint64_t *S, uint64_t n, uint64_t q, uint64_t psi)
+{
+    uint64_t *A = (uint64_t *)malloc(n * sizeof(uint64_t));
+    orc_ntt_negacyclic(a, A, n, q, psi);
+    for (uint64_t z = 0; z < n; ++z) S[z] = A[orc_slot_index(z, n)];
+    free(A);
+}
+
+
 /* c = a * b mod (X^n + 1, q) by the schoolbook definition:
  * c_k = sum_{i+j=k} a_i b_j - sum_{i+j=k+n} a_i b_j. */
 void orc_negacyclic_mul_schoolbook(const uint64_t *a, const uint64_t *b, uint64_t *c, uint64_t n,
@@ -345,9 +378,11 @@ void orc_keygen(uint64_t n, uint64_t L, const uint64_t *q, const uint64_t *psi,
 }
 
 /* Symmetric BFV encryption (Algorithm 1, step 2: the client encrypts b).
- * For ciphertext x (0 <= x < count), with a_l uniform from (ENC_A, l, op, x)
- * and e Gaussian from (ENC_E, 0, op, x):
- *     c1_l = a_l,   c0_l = [Delta_l * pt + e - a_l * s]_{q_l}.
+ * For ciphertext x (0 <= x < count), with e Gaussian from (ENC_E, 0, op, x) and
+ * the n uniform draws of (ENC_A, l, op, x) taken as the slots of a_l (its
+ * evaluation form, orc_slot_index; a uniform set of evaluations is a uniform
+ * polynomial):
+ *     c1_l = the slots of a_l,   c0_l = [Delta_l * pt + e - a_l * s]_{q_l}.
  * pt: [count][n] plaintext coefficients in [0, t); ct: [count][2][L][n]. */
 void orc_encrypt(uint64_t n, uint64_t L, const uint64_t *q, const uint64_t *psi,
                  const uint64_t *delta_l, const int64_t *s, const uint8_t key[32], uint32_t op,
@@ -359,13 +394,17 @@ void orc_encrypt(uint64_t n, uint64_t L, const uint64_t *q, const uint64_t *psi,
         int64_t *e = (int64_t *)malloc(n * sizeof(int64_t));
         uint64_t *sl = (uint64_t *)malloc(n * sizeof(uint64_t));
         uint64_t *as = (uint64_t *)malloc(n * sizeof(uint64_t));
+        uint64_t *ac = (uint64_t *)malloc(n * sizeof(uint64_t));
         orc_sample_poly(2, key, TAG_ENC_E, 0, op, (uint32_t)x, n, 0, 0, cdt, e);
         for (uint64_t l = 0; l < L; ++l) {
             uint64_t *c0 = ct + ((x * 2 + 0) * L + l) * n;
             uint64_t *c1 = ct + ((x * 2 + 1) * L + l) * n;
+            /* a is drawn in evaluation form (the uniform draws are its slots) and
+             * travels that way; c0 needs its coefficients. */
             orc_sample_poly(0, key, TAG_ENC_A, (uint32_t)l, op, (uint32_t)x, n, q[l], 0, cdt, c1);
+            orc_slots_to_coef(c1, ac, n, q[l], psi[l]);
             for (uint64_t j = 0; j < n; ++j) sl[j] = lift(s[j], q[l]);
-            orc_negacyclic_mul(c1, sl, as, n, q[l], psi[l]);
+            orc_negacyclic_mul(ac, sl, as, n, q[l], psi[l]);
             for (uint64_t j = 0; j < n; ++j) {
                 uint64_t m = mulm(delta_l[l], pt[x * n + j] % q[l], q[l]);
                 c0[j] = subm(addm(m, lift(e[j], q[l]), q[l]), as[j], q[l]);
@@ -374,6 +413,7 @@ void orc_encrypt(uint64_t n, uint64_t L, const uint64_t *q, const uint64_t *psi,
         free(e);
         free(sl);
         free(as);
+        free(ac);
     }
 }
 
@@ -392,13 +432,15 @@ void orc_encrypt_seeded(uint64_t n, uint64_t L, const uint64_t *q, const uint64_
         int64_t *e = (int64_t *)malloc(n * sizeof(int64_t));
         uint64_t *sl = (uint64_t *)malloc(n * sizeof(uint64_t));
         uint64_t *as = (uint64_t *)malloc(n * sizeof(uint64_t));
+        uint64_t *ac = (uint64_t *)malloc(n * sizeof(uint64_t));
         orc_sample_poly(2, e_key, TAG_ENC_E, 0, op, (uint32_t)x, n, 0, 0, cdt, e);
         for (uint64_t l = 0; l < L; ++l) {
             uint64_t *c0 = ct + ((x * 2 + 0) * L + l) * n;
             uint64_t *c1 = ct + ((x * 2 + 1) * L + l) * n;
             orc_sample_poly(0, a_key, TAG_ENC_A, (uint32_t)l, op, (uint32_t)x, n, q[l], 0, cdt, c1);
+            orc_slots_to_coef(c1, ac, n, q[l], psi[l]);
             for (uint64_t j = 0; j < n; ++j) sl[j] = lift(s[j], q[l]);
-            orc_negacyclic_mul(c1, sl, as, n, q[l], psi[l]);
+            orc_negacyclic_mul(ac, sl, as, n, q[l], psi[l]);
             for (uint64_t j = 0; j < n; ++j) {
                 uint64_t m = mulm(delta_l[l], pt[x * n + j] % q[l], q[l]);
                 c0[j] = subm(addm(m, lift(e[j], q[l]), q[l]), as[j], q[l]);
@@ -407,6 +449,7 @@ void orc_encrypt_seeded(uint64_t n, uint64_t L, const uint64_t *q, const uint64_
         free(e);
         free(sl);
         free(as);
+        free(ac);
     }
 }
 
@@ -416,8 +459,9 @@ void orc_encrypt_seeded(uint64_t n, uint64_t L, const uint64_t *q, const uint64_
  * y = ib*K + kb, component c and prime l:
  *     acc = sum_{jb < R} lift(ptA[ib*R + jb]) * ct[jb*K + kb][c][l]   (mod q_l)
  * ptA: [M*R][n] signed plaintext coefficients (lifted to q_l - |w| if negative);
- * ct: [R*K][2][L][n]; outs: the nouts output indices y to compute;
- * acc: [nouts][2][L][n]. */
+ * ct: [R*K][2][L][n] query ciphertexts (c1 in evaluation form, taken back to
+ * coefficients first); outs: the nouts output indices y to compute;
+ * acc: [nouts][2][L][n] in coefficient form. */
 void orc_ctpt_matmul(uint64_t n, uint64_t L, const uint64_t *q, const uint64_t *psi, uint64_t R,
                      uint64_t K, const int64_t *ptA, const uint64_t *ct, const uint32_t *outs,
                      uint64_t nouts, uint64_t *acc)
@@ -432,16 +476,22 @@ void orc_ctpt_matmul(uint64_t n, uint64_t L, const uint64_t *q, const uint64_t *
         uint64_t *dst = acc + ((o * 2 + c) * L + l) * n;
         uint64_t *a = (uint64_t *)malloc(n * sizeof(uint64_t));
         uint64_t *prod = (uint64_t *)malloc(n * sizeof(uint64_t));
+        uint64_t *cc = (uint64_t *)malloc(n * sizeof(uint64_t));
         memset(dst, 0, n * sizeof(uint64_t));
         for (uint64_t jb = 0; jb < R; ++jb) {
             const int64_t *pa = ptA + (ib * R + jb) * n;
             const uint64_t *src = ct + (((jb * K + kb) * 2 + c) * L + l) * n;
+            if (c == 1) {  /* the query's c1 travels in evaluation form */
+                orc_slots_to_coef(src, cc, n, q[l], psi[l]);
+                src = cc;
+            }
             for (uint64_t j = 0; j < n; ++j) a[j] = lift(pa[j], q[l]);
             orc_negacyclic_mul(a, src, prod, n, q[l], psi[l]);
             for (uint64_t j = 0; j < n; ++j) dst[j] = addm(dst[j], prod[j], q[l]);
         }
         free(a);
         free(prod);
+        free(cc);
     }
 }
 
@@ -543,21 +593,29 @@ void orc_decrypt_residues(uint64_t n, uint64_t L, const uint64_t *q, const uint6
 }
 
 /* Full decryption residues of whole ciphertexts (every coefficient):
- * x[o][j][l] = [c0 + c1*s]_{q_l}; ct: [count][2][L][n].  Used by tests of
- * encryption and of the ciphertext-plaintext product. */
+ * x[o][j][l] = [c0 + c1*s]_{q_l}; ct: [count][2][L][n], c1 in evaluation form
+ * (a query ciphertext) when c1_slots, else in coefficient form (a product's
+ * output).  Used by tests of encryption and of the ciphertext-plaintext product. */
 void orc_decrypt_full_residues(uint64_t n, uint64_t L, const uint64_t *q, const uint64_t *psi,
-                               const int64_t *s, uint64_t count, const uint64_t *ct, uint64_t *x)
+                               const int64_t *s, uint64_t count, const uint64_t *ct, int c1_slots,
+                               uint64_t *x)
 {
 #pragma omp parallel for schedule(dynamic)
     for (int64_t w = 0; w < (int64_t)(count * L); ++w) {
         uint64_t o = (uint64_t)w / L, l = (uint64_t)w % L;
         uint64_t *sl = (uint64_t *)malloc(n * sizeof(uint64_t));
         uint64_t *prod = (uint64_t *)malloc(n * sizeof(uint64_t));
+        uint64_t *c1 = (uint64_t *)malloc(n * sizeof(uint64_t));
+        if (c1_slots)
+            orc_slots_to_coef(ct + ((o * 2 + 1) * L + l) * n, c1, n, q[l], psi[l]);
+        else
+            memcpy(c1, ct + ((o * 2 + 1) * L + l) * n, n * sizeof(uint64_t));
         for (uint64_t j = 0; j < n; ++j) sl[j] = lift(s[j], q[l]);
-        orc_negacyclic_mul(ct + ((o * 2 + 1) * L + l) * n, sl, prod, n, q[l], psi[l]);
+        orc_negacyclic_mul(c1, sl, prod, n, q[l], psi[l]);
         for (uint64_t j = 0; j < n; ++j)
             x[(o * n + j) * L + l] = addm(ct[((o * 2 + 0) * L + l) * n + j], prod[j], q[l]);
         free(sl);
         free(prod);
+        free(c1);
     }
 }

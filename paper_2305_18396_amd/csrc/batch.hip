@@ -57,12 +57,26 @@ __device__ __forceinline__ int find_item(const BatchItemDev *items, int n, uint3
     return lo;
 }
 
+// Input polynomial `poly` of an item's ciphertexts [I][2][L][N]: c0 is transformed, c1
+// (already in evaluation form) is moved into the tiled layout as it is.
 template <int LOGN>
 __device__ __forceinline__ void run_in(const BatchItemDev &it, int poly, double *ws,
                                        const DevParams &dp, double *lds)
 {
-    ntt_fwd_block<LOGN, kNttThreads>(LoadU64{it.ct, LOGN}, StoreCtTiled{ws + it.chat_off, LOGN, dp.L, it.K, it.R, 1u},
-                        dp, poly, lds);
+    const StoreCtTiled st{ws + it.chat_off, LOGN, dp.L, it.K, it.R, 1u, -1};
+    const PolyIx pi = poly_ix(poly, dp.L);
+    if ((pi.x & 1) == 0) {
+        ntt_fwd_block<LOGN, kNttThreads>(LoadU64{it.ct, LOGN}, st, dp, poly, lds);
+        return;
+    }
+    const double p = dp.p[pi.l];
+    const uint64_t *src = it.ct + ((size_t)poly << LOGN);
+#pragma unroll
+    for (int k = 0; k < (1 << LOGN) / kNttThreads; ++k) {
+        const int z = (int)threadIdx.x + k * kNttThreads;
+        const double v = f64_of(src[z]);
+        st(pi, z, v > 0.5 * p ? v - p : v, p, 0.0);
+    }
 }
 
 template <int LOGN>

@@ -33,14 +33,16 @@ __global__ void k_encode_input(const uint64_t *X, uint64_t *pt, pimm_plan_info f
 
 // ---- encrypt (Algorithm 1 step 2) -----------------------------------------------
 
-// Component `comp` of [count][2][L][N] ciphertexts as [count*L] polynomials.
-struct LoadCtComp {
+// a^ s^ for polynomial x*L + l: a^ is the ciphertext's c1, drawn in evaluation form
+// (canonical residues in slot order), s^ the key's slots for prime l.
+struct LoadCtSlotsMul {
     const uint64_t *ct;
-    int logn, L, comp;
-    __device__ double operator()(const PolyIx &pi, int j, double, double) const
+    const double *sh;
+    int logn, L;
+    __device__ double operator()(const PolyIx &pi, int z, double p, double pinv) const
     {
         const size_t x = (size_t)pi.x, l = (size_t)pi.l;
-        return f64_of(ct[(((x * 2 + comp) * L + l) << logn) + j]);
+        return mulmod(f64_of(ct[(((x * 2 + 1) * L + l) << logn) + z]), sh[(l << logn) + z], p, pinv);
     }
 };
 
@@ -309,15 +311,15 @@ static int encrypt_with(const pimm_plan *plan, const pimm_sk *sk, const uint8_t 
         js.job[0] = je;
         if (!rc) rc = launch_samples(c, key, op_id, js, s);
     }
-    if (!rc)
-        rc = launch_fwd(c, LoadCtComp{ct, lg, (int)L, 1}, StoreSlots{ah, lg}, (int)(f.I * L), s);
+    // a is drawn in evaluation form (its slots are the uniform draws, c1 on the wire), so
+    // c0 = [Delta pt + e - a s] takes one inverse transform of a^ s^ and no forward one.
     if (!rc) {
         StoreEncC0 st{pt, e, ct, {0.0, 0.0, 0.0, 0.0}, lg, (int)L};
         for (size_t l = 0; l < L; ++l) {
             const uint64_t d = c.dp.delta[l], q = c.q[l];
             st.delta[l] = d > q / 2 ? -(double)(q - d) : (double)d;
         }
-        rc = launch_inv(c, LoadSlotsMul{ah, sk->d_s_hat, lg, 1}, st, (int)(f.I * L), s);
+        rc = launch_inv(c, LoadCtSlotsMul{ct, sk->d_s_hat, lg, (int)L}, st, (int)(f.I * L), s);
     }
     return rc;
 }

@@ -263,9 +263,13 @@ struct StoreCtTiled {
     double *out;
     int logn, L;
     uint32_t K, R, G;
+    // comp < 0: polynomial (x*2 + c)*L + l of the ciphertexts; else polynomial x*L + l of
+    // component comp alone.
+    int comp;
     __device__ void operator()(const PolyIx &pi, int z, double v, double, double) const
     {
-        const uint32_t xg = (uint32_t)(pi.x >> 1), c = (uint32_t)(pi.x & 1), l = (uint32_t)pi.l;
+        const uint32_t xg = comp < 0 ? (uint32_t)(pi.x >> 1) : (uint32_t)pi.x;
+        const uint32_t c = comp < 0 ? (uint32_t)(pi.x & 1) : (uint32_t)comp, l = (uint32_t)pi.l;
         const uint32_t g = xg / (K * R), x = xg - g * (K * R);
         const uint32_t jb = x / K, kb = g * K + x % K;
         const size_t chunks = (size_t)1 << (logn - 8);

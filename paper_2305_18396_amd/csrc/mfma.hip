@@ -32,9 +32,12 @@
 //
 // Layouts:
 //   digit weight cache  [L][N][7][Mt][64 lanes][16 B]   (A fragments, Mt = ceil(M/16))
-//   c^   (f64)          [L][N/8][I][2][8]               (written by the input transform in
-//                                                        64-byte runs; a tile reads their
-//                                                        32-byte halves)
+//   c0^  (f64)          [L][N/8][I][8]                  (written by the input transform of
+//                                                        c0 in 64-byte runs; a tile reads
+//                                                        their 32-byte halves)
+//   c1   (u64)          the query ciphertexts [I][2][L][N] (already in evaluation form: read
+//                                                        in place, 32 bytes per polynomial
+//                                                        and tile)
 //   acc^ (f64)          [L][N/8][O][2][8]               (read by the output transform; a
 //                                                        tile's 4 slots are half a run, so
 //                                                        its stores cover half lines and the
@@ -45,6 +48,7 @@
 namespace pimm {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 
 constexpr uint64_t kDigitBias = 0x0080808080808080ull;    // B = sum_{a<7} 128 * 256^a
 constexpr uint64_t kMagicBits = 0x4338000000000000ull;    // bits of 1.5 * 2^52
@@ -115,16 +119,18 @@ __global__ __launch_bounds__(256) void k_w_digits(const double *__restrict__ Wt,
 
 struct MfmaArgs {
     const v4i *Wd;
-    const double *Ch;
+    const double *C0h;   // c0^ [L][N/kInRun][I][kInRun]
+    const uint64_t *ct;  // the query ciphertexts [I][2][L][N], c1 in evaluation form
     double *Ah;
-    int M, R, K, I, O, Mt, CT, RG, NC, logn;
+    int M, R, K, I, O, Mt, CT, RG, NC, logn, L;
     double c64[kMaxL];  // 2^64 mod q_l, balanced
 };
 
 // The residue sum_d 256^d T_d (mod p) of result element v, exactly:
 //   P_k = T_2k + 2^8 T_2k+1 in int32 (|P_k| < 7 * 2^28 + 2^23 < 2^31);
 //   g0 = P0 + 2^16 P1, g1 = P2 + 2^16 P3, g2 = P4 + 2^16 P5 + 2^32 T12 (exact doubles,
-//   |g| < 2^48, since |T12| <= 64 * 4: the top digits of |x| <= p/2 < 2^49 are in [-2, 2]);
+//   |g| < 2^48, since |T12| <= 64 * 8: the top digit of a balanced weight, |x| <= p/2 < 2^49,
+//   is in [-2, 2] and that of an input, balanced or a canonical c1 residue below 2^50, in [-2, 4]);
 //   value = g0 + g1 2^32 + g2 2^64: the first product is a power of two, so its quotient
 //   k = rint(g1 2^32 / p) leaves fma(-k, p, g1 2^32) exact; the second is a floating-point
 //   modular product by 2^64 mod p; one reduction ends in [-p/2, p/2].
@@ -175,28 +181,33 @@ __global__ __launch_bounds__(kMfmaThreads, kMfmaPerCu) void k_mac_mfma(MfmaArgs 
     const int zc = (int)(lb % g.NC);
     const int l = (int)(lb / g.NC);
     const int tid = (int)threadIdx.x;
-    // The run of c^ that holds the tile's slots, and their offset in it.
+    // The run of c0^ that holds the tile's slots, and their offset in it.
     static_assert(kInRun % kMfmaSlots == 0 && 16 % kInRun == 0, "input runs");
     const size_t line0 = (((size_t)l * g.NC + zc) * (16 / kInRun) + (h * kMfmaSlots) / kInRun) * g.I;
     const int zin = (h * kMfmaSlots) % kInRun;
+    const int zt = zc * 16 + h * kMfmaSlots;  // the tile's first slot
 
     // Inputs: thread (q, j) takes inner blocks 4q .. 4q+3 of column j for the workgroup's slots.  All
     // loads are issued before any is used (absent blocks read a valid line and are zeroed
     // afterwards), so their latencies overlap.  The first half of the slots is split into
     // digits and its products start while the second half's loads are still arriving; the
     // second half goes to LDS before slot kMfmaSlots / 2.
+    // Column (kb, 0) reads c0^ (balanced doubles), column (kb, 1) the ciphertext's c1
+    // (canonical residues, already in evaluation form); both as raw 64-bit words here.
     const int jq = tid & 15, qq = tid >> 4;
     const int colq = ct * 16 + jq, kbq = colq >> 1, compq = colq & 1;
-    double2 v[4][kMfmaSlots / 2];
+    u64x2 v[4][kMfmaSlots / 2];
     bool ok[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int jb = 4 * qq + r;
         ok[r] = jb < g.R && kbq < g.K;
-        const double2 *src = (const double2 *)(g.Ch +
-            (ok[r] ? ((line0 + (size_t)jb * g.K + kbq) * 2 + compq) * kInRun + zin : 0));
+        const size_t x = (size_t)jb * g.K + kbq;
+        const uint64_t *src = !ok[r] ? (const uint64_t *)g.C0h
+                              : compq ? g.ct + ((((x * 2 + 1) * g.L + l) << g.logn) + zt)
+                                      : (const uint64_t *)g.C0h + (line0 + x) * kInRun + zin;
 #pragma unroll
-        for (int s2 = 0; s2 < kMfmaSlots / 2; ++s2) v[r][s2] = src[s2];
+        for (int s2 = 0; s2 < kMfmaSlots / 2; ++s2) v[r][s2] = ((const u64x2 *)src)[s2];
     }
     uint32_t *ld32 = (uint32_t *)lds;
     const int grpq = (qq >> 2) ^ ((jq >> 2) & 3);
@@ -204,7 +215,8 @@ __global__ __launch_bounds__(kMfmaThreads, kMfmaPerCu) void k_mac_mfma(MfmaArgs 
         uint64_t w[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const double x = (s & 1) ? v[r][s >> 1].y : v[r][s >> 1].x;
+            const uint64_t b = (s & 1) ? v[r][s >> 1].y : v[r][s >> 1].x;
+            const double x = compq ? f64_of(b) : __longlong_as_double((long long)b);
             w[r] = ok[r] ? digits7(x) : 0;
         }
 #pragma unroll
@@ -318,8 +330,8 @@ int build_weight_digits(const Ctx &c, const pimm_plan_info &f, const double *Wt,
     return check_hip(hipGetLastError(), "weight digits launch");
 }
 
-int launch_mac_mfma(const Ctx &c, const pimm_plan_info &f, const void *Wd, const double *Ch, double *Ah,
-                    hipStream_t s)
+int launch_mac_mfma(const Ctx &c, const pimm_plan_info &f, const void *Wd, const double *C0h,
+                    const uint64_t *ct, double *Ah, hipStream_t s)
 {
     if (!mfma_eligible(f))
         return set_error(PIMM_E_UNSUPPORTED,
@@ -327,7 +339,9 @@ int launch_mac_mfma(const Ctx &c, const pimm_plan_info &f, const void *Wd, const
                          "(plan has R = %u, K = %u)", f.R, f.K);
     MfmaArgs g{};
     g.Wd = (const v4i *)Wd;
-    g.Ch = Ch;
+    g.C0h = C0h;
+    g.ct = ct;
+    g.L = (int)c.params.L;
     g.Ah = Ah;
     g.M = (int)f.M;
     g.R = (int)f.R;

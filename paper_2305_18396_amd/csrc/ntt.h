@@ -563,6 +563,37 @@ __global__ __launch_bounds__(ntt_threads<LOGN>()) void k_ntt_fwd2(Load1 ld1, Loa
         ntt_fwd_block<LOGN, T>(ld2, st, dp, poly, lds);
 }
 
+// The forward transform of polynomial `poly` through (ld, st), with a second polynomial of
+// the same index moved as it is through (cld, cst) (an operand already in evaluation form,
+// such as the c1 of a query ciphertext beside its c0) and, as in k_ntt_fwd_zero, the
+// workgroup's share of another buffer zeroed.  The move comes first, so its reads and writes
+// are in flight while the transform runs.
+template <int LOGN, class Load, class Store, class CLoad, class CStore>
+__global__ __launch_bounds__(ntt_threads<LOGN>()) void k_ntt_fwd_move(Load ld, Store st, CLoad cld, CStore cst,
+                                                                       double *zero, size_t zero_n,
+                                                                       DevParams dp)
+{
+    constexpr int T = ntt_threads<LOGN>();
+    __shared__ double lds[NttPasses<LOGN, T>::LDS];
+    const int poly = ntt_poly();
+    const PolyIx pi = poly_ix(poly, dp.L);
+    {
+        const double p = dp.p[pi.l], pinv = dp.pinv[pi.l];
+        double v[(1 << LOGN) / T];
+#pragma unroll
+        for (int k = 0; k < (1 << LOGN) / T; ++k) v[k] = cld(pi, (int)threadIdx.x + k * T, p, pinv);
+#pragma unroll
+        for (int k = 0; k < (1 << LOGN) / T; ++k) cst(pi, (int)threadIdx.x + k * T, v[k], p, pinv);
+    }
+    ntt_fwd_block<LOGN, T>(ld, st, dp, poly, lds);
+    if (zero_n) {
+        const size_t per = (zero_n + gridDim.x - 1) / gridDim.x;
+        const size_t b = (size_t)blockIdx.x * per;
+        const size_t e = b + per < zero_n ? b + per : zero_n;
+        for (size_t i = b + threadIdx.x; i < e; i += T) zero[i] = 0.0;
+    }
+}
+
 // Forward transform that also clears its share of another buffer (the
 // product's accumulators), saving a launch: workgroup b zeroes
 // zero[b * per, (b + 1) * per), per = ceil(zero_n / gridDim.x).
@@ -631,6 +662,30 @@ struct LoadU64 {
     __device__ double operator()(const PolyIx &pi, int j, double, double) const
     {
         return f64_of(in[((size_t)pi.poly << logn) + j]);
+    }
+};
+
+// Component `comp` of [count][2][L][N] ciphertexts as [count*L] polynomials.
+struct LoadCtComp {
+    const uint64_t *ct;
+    int logn, L, comp;
+    __device__ double operator()(const PolyIx &pi, int j, double, double) const
+    {
+        const size_t x = (size_t)pi.x, l = (size_t)pi.l;
+        return f64_of(ct[(((x * 2 + comp) * L + l) << logn) + j]);
+    }
+};
+
+// A query ciphertext's c1, already in evaluation form ([count][2][L][N], canonical
+// residues in slot order), as balanced doubles: polynomial x*L + l is the c1 of input x.
+struct LoadCtSlots {
+    const uint64_t *ct;
+    int logn, L;
+    __device__ double operator()(const PolyIx &pi, int z, double p, double) const
+    {
+        const size_t x = (size_t)pi.x, l = (size_t)pi.l;
+        const double v = f64_of(ct[(((x * 2 + 1) * L + l) << logn) + z]);
+        return v > 0.5 * p ? v - p : v;
     }
 };
 
@@ -712,6 +767,21 @@ int launch_fwd2(const Ctx &c, Load1 ld1, Load2 ld2, int n1, Store st, int npoly,
     else
         hipLaunchKernelGGL((k_ntt_fwd2<13, Load1, Load2, Store>), dim3(npoly), dim3(ntt_threads<13>()), 0,
                            s, ld1, ld2, n1, st, c.dp);
+    return check_hip(hipGetLastError(), "ntt_fwd launch");
+}
+
+template <class Load, class Store, class CLoad, class CStore>
+int launch_fwd_move(const Ctx &c, Load ld, Store st, CLoad cld, CStore cst, int npoly, double *zero,
+                    size_t zero_n, hipStream_t s)
+{
+    if (npoly <= 0) return PIMM_OK;
+    ProfScope prof("ntt_fwd", s);
+    if (c.dp.logN == 12)
+        hipLaunchKernelGGL((k_ntt_fwd_move<12, Load, Store, CLoad, CStore>), dim3(npoly),
+                           dim3(ntt_threads<12>()), 0, s, ld, st, cld, cst, zero, zero_n, c.dp);
+    else
+        hipLaunchKernelGGL((k_ntt_fwd_move<13, Load, Store, CLoad, CStore>), dim3(npoly),
+                           dim3(ntt_threads<13>()), 0, s, ld, st, cld, cst, zero, zero_n, c.dp);
     return check_hip(hipGetLastError(), "ntt_fwd launch");
 }
 

@@ -47,7 +47,11 @@ void orc_decrypt_residues(uint64_t n, uint64_t L, const uint64_t *q, const uint6
                           const int64_t *s, uint64_t mb, uint64_t rb, uint64_t nb, uint64_t nouts,
                           const uint64_t *c1, const uint64_t *c0s, uint64_t *x);
 void orc_decrypt_full_residues(uint64_t n, uint64_t L, const uint64_t *q, const uint64_t *psi,
-                               const int64_t *s, uint64_t count, const uint64_t *ct, uint64_t *x);
+                               const int64_t *s, uint64_t count, const uint64_t *ct, int c1_slots,
+                               uint64_t *x);
+uint64_t orc_slot_index(uint64_t z, uint64_t n);
+void orc_slots_to_coef(const uint64_t *S, uint64_t *a, uint64_t n, uint64_t q, uint64_t psi);
+void orc_coef_to_slots(const uint64_t *a, uint64_t *S, uint64_t n, uint64_t q, uint64_t psi);
 
 static int checks = 0;
 
@@ -157,7 +161,20 @@ int main(void)
     orc_decrypt_residues(N, L, q, psi, s, MB, RB, NB, M * K, rc1, rc0, xr);
     for (int i = 0; i < M * K * MB * NB * L; ++i) CHECK(xr[i] < q[i % L]);
     uint64_t *xf = calloc((size_t)R * K * N * L, sizeof(uint64_t));
-    orc_decrypt_full_residues(N, L, q, psi, s, R * K, ct, xf);
+    orc_decrypt_full_residues(N, L, q, psi, s, R * K, ct, 1, xf);
+    /* Evaluation form: the slot map is a permutation and the two directions invert each other. */
+    {
+        uint64_t seen[N], back2[N], S[N];
+        memset(seen, 0, sizeof seen);
+        for (uint64_t z = 0; z < N; ++z) {
+            uint64_t k = orc_slot_index(z, N);
+            CHECK(k < N && !seen[k]);
+            seen[k] = 1;
+        }
+        orc_coef_to_slots(a, S, N, q[0], psi[0]);
+        orc_slots_to_coef(S, back2, N, q[0], psi[0]);
+        CHECK(memcmp(a, back2, sizeof back2) == 0);
+    }
     free(pk);
     free(pt);
     free(ct);

@@ -64,7 +64,7 @@ def test_products_of_a_group_use_distinct_streams(orc):
     I, O = plan.I, plan.O
     assert not np.array_equal(g["ct"][:I], g["ct"][I:])
     assert not np.array_equal(g["smask"][:O], g["smask"][O:])
-    dec = orc.decrypt_full(p, g["s"], g["ct"])
+    dec = orc.decrypt_full(p, g["s"], g["ct"], query=True)
     assert np.array_equal(dec, np.asarray(g["pt"], np.uint64) % np.uint64(p.t))
     assert np.array_equal(g["Y0"][0] + g["Y1"][0] & np.uint64(p.t - 1),
                           g["Y0"][1] + g["Y1"][1] & np.uint64(p.t - 1))

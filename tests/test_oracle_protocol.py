@@ -117,14 +117,14 @@ def test_encrypt_decrypt_roundtrip(orc, small_params):
     rng = np.random.default_rng(0)
     pt = rng.integers(0, p.t, (3, p.N), dtype=np.uint64)
     ct = orc.encrypt(p, s, workloads.seed("client", 1), 7, pt)
-    assert np.array_equal(orc.decrypt_full(p, s, ct), pt)
+    assert np.array_equal(orc.decrypt_full(p, s, ct, query=True), pt)
     assert ct.max() < max(p.q)
     for l, q in enumerate(p.q):
         assert ct[:, :, l].max() < q
     zero = orc.encrypt(p, s, workloads.seed("client", 1), 8, np.zeros((2, p.N), np.uint64))
-    assert not np.any(orc.decrypt_full(p, s, zero))
+    assert not np.any(orc.decrypt_full(p, s, zero, query=True))
     # Fresh noise is exactly the Gaussian error: |e| <= 19.
-    assert 0 < orc.noise_of(p, s, ct, pt) <= 19
+    assert 0 < orc.noise_of(p, s, ct, pt, query=True) <= 19
     assert np.all(np.isin(s, [-1, 0, 1]))
 
 
@@ -328,7 +328,7 @@ def test_rerandomisation_adds_an_encryption_of_zero_with_its_exact_noise(orc, N)
         orc.lib().orc_decrypt_full_residues(
             p.N, p.L, p.q_arr.ctypes.data_as(ctypes.c_void_p),
             p.psi_arr.ctypes.data_as(ctypes.c_void_p), s.ctypes.data_as(ctypes.c_void_p), 1,
-            np.ascontiguousarray(ct).ctypes.data_as(ctypes.c_void_p),
+            np.ascontiguousarray(ct).ctypes.data_as(ctypes.c_void_p), 0,
             x.ctypes.data_as(ctypes.c_void_p))
         out = []
         for j in range(p.N):

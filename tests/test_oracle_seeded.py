@@ -49,7 +49,7 @@ def test_expand_rebuilds_and_decrypts(orc, params):
     ct = orc.encrypt_seeded(params, s, workloads.seed("client", 9), a_seed, 11, pt)
     ex = orc.expand_ct(params, a_seed, 11, np.ascontiguousarray(ct[:, 0]))
     assert np.array_equal(ex, ct)
-    assert np.array_equal(orc.decrypt_full(params, s, ex), pt)
+    assert np.array_equal(orc.decrypt_full(params, s, ex, query=True), pt)
 
 
 def test_protocol_with_seeded_upload(orc):
