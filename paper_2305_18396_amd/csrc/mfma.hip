@@ -149,25 +149,26 @@ __device__ __forceinline__ double combine(const v4i *T, int v, double p, double 
     return reduce(g0 + r1 + mulmod(g2, c64, p, pinv), p, pinv);
 }
 
-constexpr int kMfmaSlots = 4;    // slots per workgroup (a quarter of a 16-slot chunk)
+constexpr int kMfmaSlots = 8;    // slots per workgroup (half a 16-slot chunk)
 constexpr int kMfmaParts = 16 / kMfmaSlots;  // workgroups per 16-slot chunk
 constexpr int kMfmaThreads = 256;  // 4 waves, one 16-row tile each
 constexpr int kSlotLds = 512;      // v4i per slot region (8 KiB)
 constexpr int kMfmaPerCu = 16 / kMfmaSlots;  // workgroups per compute unit (128 KiB of LDS)
 
-// Workgroup: prime l, slots zc*16 + h*4 .. +3, column tile ct (16 columns), row tiles
+// Workgroup: prime l, slots zc*16 + h*8 .. +7, column tile ct (16 columns), row tiles
 // rg*4 .. rg*4+3 (one per wave).  LDS holds one 8 KiB region per slot: first the slot's
 // B fragments ([digit][column][4 x 16 B], the 16-byte groups of column j rotated by
 // (j / 4) % 4 so that the 16 lanes of a group hit distinct banks), then, once every wave
 // has issued its products for the slot, the slot's results ([wave][row v][lane] doubles),
 // which the wave finally writes out with lanes remapped so that each row's 16 columns x
-// 4 slots go out as 16 contiguous 32-byte pieces of the accumulator runs (acc_run_index;
-// the sibling tile h ^ 1 writes the other halves).  32 KiB of LDS and at most 128
-// registers per lane: four workgroups (16 waves) share a compute unit, so the loads of
-// some overlap the matrix instructions of others; with 8 slots (64 KiB) only two fit.
-// Logical index (from xcd_local, so that the quarters and the column tiles of a chunk
-// run side by side on one XCD and share its L2)
-//     lb = (((l * NC + zc) * RG + rg) * CT + ct) * 4 + h.
+// 8 slots go out as one contiguous 1 KiB run of the accumulator runs (acc_run_index).
+// The inputs come as 64-byte pieces: whole runs of c0^ and 8 consecutive slots of each
+// c1 polynomial, read in place from the ciphertexts (each a different polynomial, so the
+// piece size sets how well those reads use DRAM: with 4 slots per workgroup (32 KiB, four
+// per CU) the product was 9% slower).  64 KiB of LDS: two workgroups share a compute unit.
+// Logical index (from xcd_local, so that the halves and the column tiles of a chunk run
+// side by side on one XCD and share its L2)
+//     lb = (((l * NC + zc) * RG + rg) * CT + ct) * 2 + h.
 __global__ __launch_bounds__(kMfmaThreads, kMfmaPerCu) void k_mac_mfma(MfmaArgs g, DevParams dp)
 {
     __shared__ v4i lds[kMfmaSlots * kSlotLds];
