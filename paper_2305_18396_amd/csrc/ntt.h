@@ -232,6 +232,7 @@ struct NttPasses {
     // The pass that touches global memory in slot order (the forward's last, the inverse's
     // first) and its size.
     static constexpr int PL = S::P3 > 0 ? S::P3 : S::P2;
+    using PFirst = std::conditional_t<(S::P3 > 0), D, C>;
     // LDS: the N elements (padded, lds_idx), then the twiddles of every other pass
     // (factor indices below N >> PL), copied from global memory once per transform so that
     // those passes read them from LDS.
@@ -271,6 +272,11 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Loader of the passes that read only LDS (never called).
+struct NoLoad {
+    __device__ double operator()(const PolyIx &, int, double, double) const { return 0.0; }
+};
+
 // Storer of a transform whose result stays in the workgroup's LDS (natural order,
 // lds_idx layout).
 struct StoreLds {
@@ -280,6 +286,12 @@ struct StoreLds {
         lds[lds_idx(j)] = v;
     }
 };
+
+// Storer of a forward transform whose last pass leaves its result where it read it in
+// LDS: each thread's sets stay with that thread, so an inverse transform's first pass
+// (the mirror of that pass: the same sets on the same threads) can read them there
+// without a barrier.  Slot c * NSETS + S is then at LDS element P::elem(S, c).
+struct StoreKeepLds {};
 
 // A storer whose value needs global inputs of its own (the plaintext and error words of
 // an encryption) declares `Pre`, reads them in `pre(pi, j)` and takes them back as the
@@ -352,7 +364,7 @@ __device__ __forceinline__ void fwd_pass(const Load &ld, const Store &st, const 
             P::fwd(x, S, tw, p, pinv);
 #pragma unroll
         for (int c = 0; c < P::E; ++c) {
-            if (LAST)
+            if constexpr (LAST && !std::is_same<Store, StoreKeepLds>::value)
                 store_val(st, pi, c * P::NSETS + S, reduce(x[c], p, pinv), p, pinv, pr[c]);
             else
                 lds[b0 + P::lds_off(c)] = reduce(x[c], p, pinv);
@@ -506,31 +518,39 @@ __device__ __forceinline__ void ntt_fwd_block(const Load &ld, const Store &st, c
 // G > 1 only the coefficients j with j % G == G - 1 are produced.  The first pass
 // reads its twiddles from global memory (with its inputs), the others from the
 // LDS table.
+// The passes of an inverse transform after its first one, on the LDS data that pass
+// left (visible after a barrier) with the LDS twiddle table loaded.
+template <int LOGN, int T, int G = 1, class Store>
+__device__ __forceinline__ void ntt_inv_rest(const Store &st, const DevParams &dp, const PolyIx &pi,
+                                             double *lds)
+{
+    using NP = NttPasses<LOGN, T>;
+    const int l = pi.l;
+    const double p = dp.p[l], pinv = dp.pinv[l], ninv = dp.n_inv[l];
+    const double *twl = lds + NP::DATA;
+    const NoLoad nl;
+    if constexpr (NP::S::P3 > 0) {
+        inv_pass<typename NP::C, T, false, false, G>(nl, st, pi, twl, p, pinv, ninv, lds);
+        __syncthreads();
+    }
+    inv_pass<typename NP::B, T, false, false, G>(nl, st, pi, twl, p, pinv, ninv, lds);
+    __syncthreads();
+    inv_pass<typename NP::A, T, false, true, G>(nl, st, pi, twl, p, pinv, ninv, lds);
+}
+
 template <int LOGN, int T, int G = 1, class Load, class Store>
 __device__ __forceinline__ void ntt_inv_block(const Load &ld, const Store &st, const DevParams &dp,
                                               int poly, double *lds)
 {
     using NP = NttPasses<LOGN, T>;
-    constexpr bool FOUR = NP::S::P3 > 0;
     const PolyIx pi = poly_ix(poly, dp.L);
     const int l = pi.l;
     const double p = dp.p[l], pinv = dp.pinv[l];
     const double *tw = dp.tw_inv + ((size_t)l << LOGN);
-    const double *twl = lds + NP::DATA;
-    const double ninv = dp.n_inv[l];
     load_tw_table<LOGN, T>(tw, lds);
-    if constexpr (FOUR) {
-        inv_pass<typename NP::D, T, true, false, G>(ld, st, pi, tw, p, pinv, ninv, lds);
-        __syncthreads();
-    }
-    if constexpr (FOUR)
-        inv_pass<typename NP::C, T, false, false, G>(ld, st, pi, twl, p, pinv, ninv, lds);
-    else
-        inv_pass<typename NP::C, T, true, false, G>(ld, st, pi, tw, p, pinv, ninv, lds);
+    inv_pass<typename NP::PFirst, T, true, false, G>(ld, st, pi, tw, p, pinv, dp.n_inv[l], lds);
     __syncthreads();
-    inv_pass<typename NP::B, T, false, false, G>(ld, st, pi, twl, p, pinv, ninv, lds);
-    __syncthreads();
-    inv_pass<typename NP::A, T, false, true, G>(ld, st, pi, twl, p, pinv, ninv, lds);
+    ntt_inv_rest<LOGN, T, G>(st, dp, pi, lds);
 }
 
 // Polynomial of a workgroup: workgroups are dispatched round-robin over the XCDs, so the

@@ -362,6 +362,117 @@ static int reply_transform(const Ctx &c, const pimm_plan_info &f, const double *
                           (int)(f.O * 2 * L), prune_factor(f.rb), s);
 }
 
+// The re-randomised reply of output ciphertext y at prime l by one workgroup (O L
+// workgroups; ntt_poly() = y L + l keeps a ciphertext's primes on one XCD):
+//  - the forward transform of u (one byte per coefficient, shared by the primes), whose
+//    last pass leaves each thread's slots in LDS where the inverse's first pass (the same
+//    sets on the same threads) reads them back;
+//  - the first inverse pass of both components on acc^ + u^ pk^: component 0 pruned to the
+//    few registers its decoded positions depend on, component 1 into LDS;
+//  - the rest of component 1's inverse and its epilogue (c1), then component 0's.
+// The same values as the forward transform of u to memory followed by the reply transform
+// of each component, without u^ leaving the compute unit.
+template <int LOGN, int G, bool RUN>
+__global__ __launch_bounds__(ntt_threads<LOGN>()) __attribute__((amdgpu_waves_per_eu(4))) void k_reply_rr(const int8_t *u, const double *ah,
+                                                                    const double *pkh, ReplyOut<true> epi,
+                                                                    uint32_t O2, uint32_t NR, DevParams dp)
+{
+    constexpr int T = ntt_threads<LOGN>();
+    using NP = NttPasses<LOGN, T>;
+    using P = typename NP::PFirst;
+    static_assert(P::PER_THREAD == 1 && P::E == 16 && P::STRIDE == 1, "one set of 16 adjacent slots per thread");
+    static_assert(G == 4 || G == 16, "pruned component 0");
+    __shared__ double lds[NP::LDS];
+    const int wg = ntt_poly();
+    const int L = dp.L;
+    const int y = wg / L, l = wg - y * L;
+    ntt_fwd_block<LOGN, T>(LoadI8Shared{u, LOGN, 0u}, StoreKeepLds{}, dp, wg, lds);
+    const PolyIx p0{(y * 2) * L + l, l, y * 2}, p1{(y * 2 + 1) * L + l, l, y * 2 + 1};
+    const double p = dp.p[l], pinv = dp.pinv[l];
+    const double *tw = dp.tw_inv + ((size_t)l << LOGN);
+    const int S = (int)threadIdx.x;
+    const int b0 = lds_idx(P::elem(S, 0));
+    const double *pk0 = pkh + ((size_t)l << LOGN), *pk1 = pkh + ((size_t)(L + l) << LOGN);
+    double s0[P::E / G];
+    {
+        double x[P::E];
+#pragma unroll
+        for (int c = 0; c < P::E; ++c) {
+            const int z = c * P::NSETS + S;
+            const size_t at = RUN ? acc_run_index(p0, z, O2, NR) : ((size_t)p0.poly << LOGN) + z;
+            x[c] = reduce(ah[at], p, pinv) + mulmod(lds[b0 + P::lds_off(c)], pk0[z], p, pinv);
+        }
+        P::template inv_pruned<G>(x, S, tw, p, pinv);
+#pragma unroll
+        for (int c = G - 1; c < P::E; c += G) s0[c / G] = reduce(x[c], p, pinv);
+    }
+    // One component's reads at a time (both at once would not fit two workgroups per CU).
+    __builtin_amdgcn_sched_barrier(0);
+    {
+        double x[P::E];
+#pragma unroll
+        for (int c = 0; c < P::E; ++c) {
+            const int z = c * P::NSETS + S;
+            const size_t at = RUN ? acc_run_index(p1, z, O2, NR) : ((size_t)p1.poly << LOGN) + z;
+            x[c] = reduce(ah[at], p, pinv) + mulmod(lds[b0 + P::lds_off(c)], pk1[z], p, pinv);
+        }
+        P::inv(x, S, tw, p, pinv);
+#pragma unroll
+        for (int c = 0; c < P::E; ++c) lds[b0 + P::lds_off(c)] = reduce(x[c], p, pinv);
+    }
+    // Every wave is past the forward's passes that read the LDS twiddle table.
+    __syncthreads();
+    load_tw_table<LOGN, T>(tw, lds);
+    // The error bytes of both epilogues, read ahead of component 1's other passes.
+    const ReplyOut<true>::Pre e1 = epi.template pre<LOGN, T>(p1);
+    const ReplyOut<true>::Pre e0 = epi.template pre<LOGN, T>(p0);
+    __syncthreads();
+    ntt_inv_rest<LOGN, T, 1>(StoreLds{lds}, dp, p1, lds);
+    __syncthreads();
+    epi.template run<LOGN, T>(p1, lds, dp, e1);
+    __syncthreads();
+#pragma unroll
+    for (int c = G - 1; c < P::E; c += G) lds[b0 + P::lds_off(c)] = s0[c / G];
+    __syncthreads();
+    ntt_inv_rest<LOGN, T, G>(StoreLds{lds}, dp, p0, lds);
+    __syncthreads();
+    epi.template run<LOGN, T>(p0, lds, dp, e0);
+}
+
+template <int LOGN, bool RUN>
+static void launch_reply_rr(int g, const int8_t *u, const double *ah, const double *pkh,
+                            const ReplyOut<true> &epi, uint32_t O2, uint32_t NR, int nwg, const DevParams &dp,
+                            hipStream_t s)
+{
+    if (g == 16)
+        hipLaunchKernelGGL((k_reply_rr<LOGN, 16, RUN>), dim3(nwg), dim3(ntt_threads<LOGN>()), 0, s, u, ah, pkh,
+                           epi, O2, NR, dp);
+    else
+        hipLaunchKernelGGL((k_reply_rr<LOGN, 4, RUN>), dim3(nwg), dim3(ntt_threads<LOGN>()), 0, s, u, ah, pkh,
+                           epi, O2, NR, dp);
+}
+
+// The re-randomised reply from u (bytes) and pk^ in one launch (k_reply_rr); for plans
+// whose reply needs every coefficient of c0 (no output pruning) the caller takes the
+// separate transform of u and the reply transform instead.
+template <bool RUN>
+static int reply_rr(const Ctx &c, const pimm_plan_info &f, const int8_t *u, const double *ah, const double *pkh,
+                    uint64_t *c1, uint64_t *c0s, const int8_t *e, hipStream_t s)
+{
+    const int lg = c.dp.logN;
+    const int L = (int)c.params.L;
+    const int g = prune_factor(f.rb);
+    if (g < 4) return set_error(PIMM_E_ARG, "reply_rr: the plan's reply allows no output pruning");
+    const ReplyOut<true> epi{{c1, c0s, e, FastDiv::make(f.mb), f.rb, f.nb, lg, L}};
+    const uint32_t O2 = 2 * f.O, NR = (uint32_t)(c.params.N / kAccRun);
+    ProfScope prof("ntt_inv", s);
+    if (lg == 12)
+        launch_reply_rr<12, RUN>(g, u, ah, pkh, epi, O2, NR, (int)(f.O * L), c.dp, s);
+    else
+        launch_reply_rr<13, RUN>(g, u, ah, pkh, epi, O2, NR, (int)(f.O * L), c.dp, s);
+    return check_hip(hipGetLastError(), "reply_rr launch");
+}
+
 // The query ciphertexts into the vector product's tiled layout in one launch: the forward
 // transform of c0, c1 (already in evaluation form) moved as it is, and the accumulators zeroed.
 static int ct_to_tiled(const Ctx &c, const pimm_plan_info &f, const uint64_t *ct, double *ch, double *ah,
@@ -395,15 +506,22 @@ int fused_tail(const pimm_plan *plan, const uint64_t *pk, const Key &key, uint32
     int8_t *u = (int8_t *)(uh + (size_t)f.O * L * N);
     int8_t *e = u + (size_t)f.O * N * 8;
     int rc = PIMM_OK;
+    // With output pruning the transform of u runs inside the reply's workgroups (u^ stays on
+    // chip); otherwise pk^ and u^ are transformed in one launch (adjacent in the workspace).
+    const bool in_reply = rr && prune_factor(f.rb) >= 4;
     if (rr) {
         rc = launch_samples(c, key, op_id, rerand_jobs(f.O, N, u, e), s);
-        // pk^ and u^ in one launch: they are adjacent in the workspace.
-        if (!rc)
+        if (!rc && in_reply)
+            rc = launch_fwd(c, LoadU64{pk, lg}, StoreSlots{pkh, lg}, (int)(2 * L), s);
+        else if (!rc)
             rc = launch_fwd2(c, LoadU64{pk, lg}, LoadI8Shared{u, lg, 2u}, (int)(2 * L), StoreSlots{pkh, lg},
                              (int)((2 + f.O) * L), s);
     }
     if (!rc) {
-        if (rr)
+        if (in_reply)
+            rc = mx_layout ? reply_rr<true>(c, f, u, ah, pkh, c1, c0s, e, s)
+                           : reply_rr<false>(c, f, u, ah, pkh, c1, c0s, e, s);
+        else if (rr)
             rc = mx_layout ? reply_transform<true, true>(c, f, ah, uh, pkh, c1, c0s, e, s)
                        : reply_transform<true, false>(c, f, ah, uh, pkh, c1, c0s, e, s);
         else
