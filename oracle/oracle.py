@@ -346,8 +346,9 @@ def keygen(params: Params, seed: bytes, with_pk: bool | None = None):
 
 
 def encrypt(params: Params, s: np.ndarray, seed: bytes, op_id: int, pt: np.ndarray) -> np.ndarray:
-    """Algorithm 1 step 2: symmetric encryption of each plaintext row.  -> [count][2][L][N],
-    c1 (the uniform part a) in evaluation form: the uniform draws are a's slots (slot_index)."""
+    """Algorithm 1 step 2: symmetric encryption of each plaintext row.  -> [count][2][L][N]
+    in evaluation form (slot_index): c1's slots are the uniform draws of a, c0's are those of
+    [Delta pt + e - a s]."""
     pt = _u64(pt)
     count = pt.shape[0]
     ct = np.zeros((count, 2, params.L, params.N), dtype=np.uint64)
@@ -455,7 +456,7 @@ def decrypt_residues(params: Params, plan: Plan, s: np.ndarray, c1: np.ndarray,
 
 def decrypt_full(params: Params, s: np.ndarray, ct: np.ndarray, query: bool = False) -> np.ndarray:
     """Decrypt every coefficient of whole ciphertexts [count][2][L][N] -> [count][N] in Z_t.
-    query: c1 in evaluation form (a query ciphertext from encrypt); else coefficient form (a
+    query: in evaluation form (a query ciphertext from encrypt); else coefficient form (a
     product's output)."""
     ct = _u64(ct)
     count = ct.shape[0]

@@ -296,7 +296,7 @@ void orc_negacyclic_mul(const uint64_t *a, const uint64_t *b, uint64_t *c, uint6
     free(B);
 }
 
-/* Evaluation form of a query ciphertext's uniform part (how c1 travels): slot z
+/* Evaluation form of a query ciphertext (how both of its components travel): slot z
  * of an n-coefficient polynomial holds its value at psi^(2k+1) with
  * k = brv(16 (z mod n/16) + floor(z / (n/16))), brv reversing log2(n) bits.
  * (n >= 16, a power of two.) */
@@ -382,7 +382,9 @@ void orc_keygen(uint64_t n, uint64_t L, const uint64_t *q, const uint64_t *psi,
  * the n uniform draws of (ENC_A, l, op, x) taken as the slots of a_l (its
  * evaluation form, orc_slot_index; a uniform set of evaluations is a uniform
  * polynomial):
- *     c1_l = the slots of a_l,   c0_l = [Delta_l * pt + e - a_l * s]_{q_l}.
+ *     c1_l = the slots of a_l,   c0_l = the slots of [Delta_l * pt + e - a_l * s]_{q_l}.
+ * The whole ciphertext travels in evaluation form (the slot form is a ring
+ * isomorphism, so it is the same ciphertext): the server's product is slot-wise.
  * pt: [count][n] plaintext coefficients in [0, t); ct: [count][2][L][n]. */
 void orc_encrypt(uint64_t n, uint64_t L, const uint64_t *q, const uint64_t *psi,
                  const uint64_t *delta_l, const int64_t *s, const uint8_t key[32], uint32_t op,
@@ -400,15 +402,16 @@ void orc_encrypt(uint64_t n, uint64_t L, const uint64_t *q, const uint64_t *psi,
             uint64_t *c0 = ct + ((x * 2 + 0) * L + l) * n;
             uint64_t *c1 = ct + ((x * 2 + 1) * L + l) * n;
             /* a is drawn in evaluation form (the uniform draws are its slots) and
-             * travels that way; c0 needs its coefficients. */
+             * travels that way; c0 is computed from coefficients, then sent as slots. */
             orc_sample_poly(0, key, TAG_ENC_A, (uint32_t)l, op, (uint32_t)x, n, q[l], 0, cdt, c1);
             orc_slots_to_coef(c1, ac, n, q[l], psi[l]);
             for (uint64_t j = 0; j < n; ++j) sl[j] = lift(s[j], q[l]);
             orc_negacyclic_mul(ac, sl, as, n, q[l], psi[l]);
             for (uint64_t j = 0; j < n; ++j) {
                 uint64_t m = mulm(delta_l[l], pt[x * n + j] % q[l], q[l]);
-                c0[j] = subm(addm(m, lift(e[j], q[l]), q[l]), as[j], q[l]);
+                ac[j] = subm(addm(m, lift(e[j], q[l]), q[l]), as[j], q[l]);
             }
+            orc_coef_to_slots(ac, c0, n, q[l], psi[l]);
         }
         free(e);
         free(sl);
@@ -443,8 +446,9 @@ void orc_encrypt_seeded(uint64_t n, uint64_t L, const uint64_t *q, const uint64_
             orc_negacyclic_mul(ac, sl, as, n, q[l], psi[l]);
             for (uint64_t j = 0; j < n; ++j) {
                 uint64_t m = mulm(delta_l[l], pt[x * n + j] % q[l], q[l]);
-                c0[j] = subm(addm(m, lift(e[j], q[l]), q[l]), as[j], q[l]);
+                ac[j] = subm(addm(m, lift(e[j], q[l]), q[l]), as[j], q[l]);
             }
+            orc_coef_to_slots(ac, c0, n, q[l], psi[l]);
         }
         free(e);
         free(sl);
@@ -459,7 +463,7 @@ void orc_encrypt_seeded(uint64_t n, uint64_t L, const uint64_t *q, const uint64_
  * y = ib*K + kb, component c and prime l:
  *     acc = sum_{jb < R} lift(ptA[ib*R + jb]) * ct[jb*K + kb][c][l]   (mod q_l)
  * ptA: [M*R][n] signed plaintext coefficients (lifted to q_l - |w| if negative);
- * ct: [R*K][2][L][n] query ciphertexts (c1 in evaluation form, taken back to
+ * ct: [R*K][2][L][n] query ciphertexts (in evaluation form, taken back to
  * coefficients first); outs: the nouts output indices y to compute;
  * acc: [nouts][2][L][n] in coefficient form. */
 void orc_ctpt_matmul(uint64_t n, uint64_t L, const uint64_t *q, const uint64_t *psi, uint64_t R,
@@ -481,10 +485,8 @@ void orc_ctpt_matmul(uint64_t n, uint64_t L, const uint64_t *q, const uint64_t *
         for (uint64_t jb = 0; jb < R; ++jb) {
             const int64_t *pa = ptA + (ib * R + jb) * n;
             const uint64_t *src = ct + (((jb * K + kb) * 2 + c) * L + l) * n;
-            if (c == 1) {  /* the query's c1 travels in evaluation form */
-                orc_slots_to_coef(src, cc, n, q[l], psi[l]);
-                src = cc;
-            }
+            orc_slots_to_coef(src, cc, n, q[l], psi[l]);  /* queries travel as slots */
+            src = cc;
             for (uint64_t j = 0; j < n; ++j) a[j] = lift(pa[j], q[l]);
             orc_negacyclic_mul(a, src, prod, n, q[l], psi[l]);
             for (uint64_t j = 0; j < n; ++j) dst[j] = addm(dst[j], prod[j], q[l]);
@@ -593,11 +595,11 @@ void orc_decrypt_residues(uint64_t n, uint64_t L, const uint64_t *q, const uint6
 }
 
 /* Full decryption residues of whole ciphertexts (every coefficient):
- * x[o][j][l] = [c0 + c1*s]_{q_l}; ct: [count][2][L][n], c1 in evaluation form
- * (a query ciphertext) when c1_slots, else in coefficient form (a product's
- * output).  Used by tests of encryption and of the ciphertext-plaintext product. */
+ * x[o][j][l] = [c0 + c1*s]_{q_l}; ct: [count][2][L][n], in evaluation form (a
+ * query ciphertext) when slots, else in coefficient form (a product's output).
+ * Used by tests of encryption and of the ciphertext-plaintext product. */
 void orc_decrypt_full_residues(uint64_t n, uint64_t L, const uint64_t *q, const uint64_t *psi,
-                               const int64_t *s, uint64_t count, const uint64_t *ct, int c1_slots,
+                               const int64_t *s, uint64_t count, const uint64_t *ct, int slots,
                                uint64_t *x)
 {
 #pragma omp parallel for schedule(dynamic)
@@ -605,17 +607,22 @@ void orc_decrypt_full_residues(uint64_t n, uint64_t L, const uint64_t *q, const 
         uint64_t o = (uint64_t)w / L, l = (uint64_t)w % L;
         uint64_t *sl = (uint64_t *)malloc(n * sizeof(uint64_t));
         uint64_t *prod = (uint64_t *)malloc(n * sizeof(uint64_t));
+        uint64_t *c0 = (uint64_t *)malloc(n * sizeof(uint64_t));
         uint64_t *c1 = (uint64_t *)malloc(n * sizeof(uint64_t));
-        if (c1_slots)
-            orc_slots_to_coef(ct + ((o * 2 + 1) * L + l) * n, c1, n, q[l], psi[l]);
-        else
-            memcpy(c1, ct + ((o * 2 + 1) * L + l) * n, n * sizeof(uint64_t));
+        const uint64_t *in0 = ct + ((o * 2 + 0) * L + l) * n, *in1 = ct + ((o * 2 + 1) * L + l) * n;
+        if (slots) {
+            orc_slots_to_coef(in0, c0, n, q[l], psi[l]);
+            orc_slots_to_coef(in1, c1, n, q[l], psi[l]);
+        } else {
+            memcpy(c0, in0, n * sizeof(uint64_t));
+            memcpy(c1, in1, n * sizeof(uint64_t));
+        }
         for (uint64_t j = 0; j < n; ++j) sl[j] = lift(s[j], q[l]);
         orc_negacyclic_mul(c1, sl, prod, n, q[l], psi[l]);
-        for (uint64_t j = 0; j < n; ++j)
-            x[(o * n + j) * L + l] = addm(ct[((o * 2 + 0) * L + l) * n + j], prod[j], q[l]);
+        for (uint64_t j = 0; j < n; ++j) x[(o * n + j) * L + l] = addm(c0[j], prod[j], q[l]);
         free(sl);
         free(prod);
+        free(c0);
         free(c1);
     }
 }

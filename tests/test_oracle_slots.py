@@ -9,7 +9,8 @@ computations:
 - the slot form is a ring isomorphism: the slots of a negacyclic product (schoolbook) are the
   slot-wise products, and the slots of a sum are the slot-wise sums;
 - a fresh encryption, whose c1 is the draws taken as slots, decrypts to its plaintext and its
-  c1 is exactly the uniform draws of its stream.
+  c1 is exactly the uniform draws of its stream; its c0, read as slots, is exactly
+  Delta pt + e - a s with e the Gaussian draws of its stream and a s a schoolbook product.
 """
 import ctypes
 
@@ -110,3 +111,23 @@ def test_fresh_encryption_in_evaluation_form(orc):
     # and the coefficient form of c1 is what the slots describe
     c1c = orc.slots_to_coef(p, ct[:, 1])
     assert np.array_equal(orc.coef_to_slots(p, c1c), ct[:, 1])
+    # c0 travels as slots too: its coefficients are Delta pt + e - a s, with e the stream's
+    # Gaussian draws and a s by schoolbook (no transform on this side)
+    c0c = orc.slots_to_coef(p, ct[:, 0])
+    assert not np.array_equal(c0c, ct[:, 0])
+    cdt = np.ascontiguousarray(p.cdt_arr)
+    for x in range(2):
+        e = np.zeros(p.N, np.int64)
+        orc.lib().orc_sample_poly(2, key.ctypes.data_as(ctypes.c_void_p), orc.TAG_ENC_E, 0, 3, x, p.N, 0, 0,
+                                  cdt.ctypes.data_as(ctypes.c_void_p), e.ctypes.data_as(ctypes.c_void_p))
+        for l in range(p.L):
+            q = int(p.q[l])
+            sl = np.array([int(v) % q for v in s], np.uint64)
+            a = np.ascontiguousarray(c1c[x, l])
+            prod = np.zeros(p.N, np.uint64)
+            orc.lib().orc_negacyclic_mul_schoolbook(a.ctypes.data_as(ctypes.c_void_p),
+                                                    sl.ctypes.data_as(ctypes.c_void_p),
+                                                    prod.ctypes.data_as(ctypes.c_void_p), p.N, q)
+            delta = (p.Q // p.t) % q
+            want = [(delta * int(pt[x, j]) + int(e[j]) - int(prod[j])) % q for j in range(p.N)]
+            assert [int(v) for v in c0c[x, l]] == want
