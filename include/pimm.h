@@ -98,8 +98,8 @@ typedef struct {
  * output ciphertexts (index y = ib*K + kb), Wb = M*R weight blocks, P = M*R*K
  * block products.  Byte sizes are of the caller-owned buffers:
  *   pt        [I][N]          uint64  encoded client plaintexts
- *   ct        [I][2][L][N]    uint64  input ciphertexts: c0 in coefficient form, c1 in
- *                                     evaluation form (see pimm_encrypt)
+ *   ct        [I][2][L][N]    uint64  input ciphertexts, both components in evaluation
+ *                                     form (see pimm_encrypt)
  *   acc       [O][2][L][N]    uint64  products before masking, coefficient form
  *   c1        [O][L][N]       uint64  reply, full c1
  *   c0s       [O][L][mb*nb]   uint64  reply, c0 at the decoded positions only,
@@ -230,20 +230,23 @@ int pimm_sk_destroy(pimm_sk *sk);
  * X: [n][r] values < 2^l (device). */
 int pimm_encode_input(const pimm_plan *plan, const uint64_t *X, uint64_t *pt, void *stream);
 
-/* Algorithm 1 step 2: symmetric BFV encryption of every pt row x:
- * c0_l = [Delta_l pt + e - a_l s]_{q_l} (e Gaussian, tag 5, op_id, x),
- * Delta = floor(q / t), where a_l is uniform mod q_l and is drawn, and sent, in
- * evaluation form: c1_l[z] = draw z of the stream (tag 4, prime l, op_id, x) is
- * a_l's value at psi_l^(2k+1), k = brv(16 (z mod N/16) + floor(z / (N/16))) with brv
- * reversing log2 N bits and psi_l the primitive 2N-th root g^((q_l - 1) / 2N) mod q_l
- * for the smallest g >= 2 that gives psi_l^N = -1.  A uniform set of
- * evaluations is a uniform polynomial, the server needs a's evaluations anyway, and
- * neither party transforms a.  ct: [I][2][L][N] (device). */
+/* Algorithm 1 step 2: symmetric BFV encryption of every pt row x, sent in evaluation
+ * form (slot z of a polynomial holds its value at psi_l^(2k+1),
+ * k = brv(16 (z mod N/16) + floor(z / (N/16))) with brv reversing log2 N bits and psi_l
+ * the primitive 2N-th root g^((q_l - 1) / 2N) mod q_l for the smallest g >= 2 that gives
+ * psi_l^N = -1):
+ *   c1_l = the slots of a_l: c1_l[z] = draw z of the stream (tag 4, prime l, op_id, x)
+ *          (a_l uniform mod q_l, drawn as its slots: a uniform set of evaluations is a
+ *          uniform polynomial, and neither party transforms a);
+ *   c0_l = the slots of [Delta_l pt + e - a_l s]_{q_l} (e Gaussian, tag 5, op_id, x),
+ *          Delta = floor(q / t).
+ * The slot form is a ring isomorphism, so this is the BFV ciphertext itself; the server's
+ * product is slot-wise and takes it as it comes.  ct: [I][2][L][N] (device). */
 int pimm_encrypt(const pimm_plan *plan, const pimm_sk *sk, const uint8_t seed[32], uint32_t op_id,
                  const uint64_t *pt, uint64_t *ct, void *ws, size_t ws_bytes, void *stream);
 
-/* Seed-compressed upload, a wire-format variant of Algorithm 1 step 2.  c1 = a (in
- * evaluation form, as in pimm_encrypt) is public, so it can come from a public seed:
+/* Seed-compressed upload, a wire-format variant of Algorithm 1 step 2.  c1 = a (its
+ * slots, as in pimm_encrypt) is public, so it can come from a public seed:
  * pimm_encrypt_seeded draws a_l from
  * the stream of a_seed (tag 4) and e from `seed` (tag 5), and the client sends
  * c0 ([I][L][N], half the ciphertext bytes) with the 32-byte a_seed; the server

@@ -3,7 +3,7 @@
 // A batch is a list of (plan, weight cache, input ciphertexts, accumulator)
 // items of any shapes and sequence lengths on one context.  Its work is the
 // union of three kinds of units:
-//   in   forward NTT of one input polynomial      (sum over items of I*2*L)
+//   in   one input polynomial (already in evaluation form) into the tiled layout (sum over items of I*2*L)
 //   mac  one slot group x row-tile group x column tile (RT row tiles per group);
 //        under the phased schedule the items that share a weight cache line up
 //        their column blocks, and a column tile may span items, so every weight
@@ -17,7 +17,7 @@
 //               list of units of every item;
 //   PERSISTENT  one launch of a resident grid that takes units from an atomic
 //               counter in dependency order (in, then mac, then out).  A mac
-//               unit waits until the 2R input NTTs of each column block of its
+//               unit waits until the 2R input moves of each column block of its
 //               column tile and prime are done; an out unit waits until the
 //               mac units of its (row-tile group, column tile, prime) are
 //               done.  Every unit it waits for was taken
@@ -57,26 +57,22 @@ __device__ __forceinline__ int find_item(const BatchItemDev *items, int n, uint3
     return lo;
 }
 
-// Input polynomial `poly` of an item's ciphertexts [I][2][L][N]: c0 is transformed, c1
-// (already in evaluation form) is moved into the tiled layout as it is.
+// Input polynomial `poly` of an item's ciphertexts [I][2][L][N], already in evaluation form,
+// moved into the tiled layout as balanced doubles.
 template <int LOGN>
 __device__ __forceinline__ void run_in(const BatchItemDev &it, int poly, double *ws,
-                                       const DevParams &dp, double *lds)
+                                       const DevParams &dp, double *)
 {
     const StoreCtTiled st{ws + it.chat_off, LOGN, dp.L, it.K, it.R, 1u, -1};
     const PolyIx pi = poly_ix(poly, dp.L);
-    if ((pi.x & 1) == 0) {
-        ntt_fwd_block<LOGN, kNttThreads>(LoadU64{it.ct, LOGN}, st, dp, poly, lds);
-        return;
-    }
     const double p = dp.p[pi.l];
     const uint64_t *src = it.ct + ((size_t)poly << LOGN);
+    double v[(1 << LOGN) / kNttThreads];
 #pragma unroll
-    for (int k = 0; k < (1 << LOGN) / kNttThreads; ++k) {
-        const int z = (int)threadIdx.x + k * kNttThreads;
-        const double v = f64_of(src[z]);
-        st(pi, z, v > 0.5 * p ? v - p : v, p, 0.0);
-    }
+    for (int k = 0; k < (1 << LOGN) / kNttThreads; ++k) v[k] = f64_of(src[(int)threadIdx.x + k * kNttThreads]);
+#pragma unroll
+    for (int k = 0; k < (1 << LOGN) / kNttThreads; ++k)
+        st(pi, (int)threadIdx.x + k * kNttThreads, v[k] > 0.5 * p ? v[k] - p : v[k], p, 0.0);
 }
 
 template <int LOGN>
@@ -126,10 +122,9 @@ template <int LOGN>
 __global__ __launch_bounds__(kNttThreads) void k_batch_in(const BatchItemDev *items, int n,
                                                           double *ws, DevParams dp)
 {
-    __shared__ double lds[NttPasses<LOGN, kNttThreads>::LDS];
     const uint32_t u = blockIdx.x;
     const BatchItemDev &it = items[find_item(items, n, u, 0)];
-    run_in<LOGN>(it, (int)(u - it.in0), ws, dp, lds);
+    run_in<LOGN>(it, (int)(u - it.in0), ws, dp, nullptr);
 }
 
 // The columns of one weight group (see BatchGroupDev): column j is block kb of
@@ -262,7 +257,7 @@ __global__ __launch_bounds__(kNttThreads) void k_batch_fused(const BatchItemDev 
             const uint32_t v = u - n_in;
             const BatchItemDev &it = items[find_item(items, n, v, 1)];
             const MacCoord c = mac_coord(it, v - it.mac0, chunks, mac_rt(G, KB));
-            // Every input NTT of the column tile's blocks for this prime.
+            // Every input move of the column tile's blocks for this prime.
             const int left = (int)it.K - c.kbt * KB;
             const uint32_t cols = (uint32_t)(left < KB ? left : KB);
             if (threadIdx.x == 0)

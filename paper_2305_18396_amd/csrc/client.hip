@@ -33,48 +33,45 @@ __global__ void k_encode_input(const uint64_t *X, uint64_t *pt, pimm_plan_info f
 
 // ---- encrypt (Algorithm 1 step 2) -----------------------------------------------
 
-// a^ s^ for polynomial x*L + l: a^ is the ciphertext's c1, drawn in evaluation form
-// (canonical residues in slot order), s^ the key's slots for prime l.
-struct LoadCtSlotsMul {
-    const uint64_t *ct;
-    const double *sh;
-    int logn, L;
-    __device__ double operator()(const PolyIx &pi, int z, double p, double pinv) const
+// Delta_l pt + e for polynomial x*L + l: the coefficients whose forward transform is the
+// message part of c0's slots.  Delta_l balanced (|.| <= q_l/2) times pt < t, plus |e| <= 19:
+// within 0.6 q_l.  Delta_l travels by value inside the functor (kernel arguments are the only
+// host data a kernel may read).
+struct LoadEncMsg {
+    const uint64_t *pt;  // [I][N], values < t
+    const int8_t *e;     // [I][N]
+    double delta[kMaxL];
+    int logn;
+    __device__ double operator()(const PolyIx &pi, int j, double p, double pinv) const
     {
-        const size_t x = (size_t)pi.x, l = (size_t)pi.l;
-        return mulmod(f64_of(ct[(((x * 2 + 1) * L + l) << logn) + z]), sh[(l << logn) + z], p, pinv);
+        const size_t at = ((size_t)pi.x << logn) + j;
+        return mulmod(delta[pi.l], f64_of(pt[at]), p, pinv) + (double)e[at];
     }
 };
 
-// c0 = [Delta_l pt + e - a s]_{q_l} from the inverse NTT of a^ s^, in balanced
-// doubles: Delta_l pt (|.| <= 0.6 q_l), e (|e| <= 19) and a s (|.| <= 0.6 q_l) add
-// to well under 2^52, and one reduction gives the canonical residue.  Delta_l
-// travels by value inside the functor, balanced (kernel arguments are the only
-// host data a kernel may read).
+// c0's slots [Delta_l pt + e]^ - a^ s^ (mod q_l): the transform's output (balanced) minus a^ s^
+// (a^ the ciphertext's c1 slot, canonical; s^ the key's slot, balanced; the product within
+// 0.7 q_l), one reduction to the canonical residue.  a^ is read ahead of the transform's last
+// pass (Pre: the c0 stores could alias it); the key's doubles cannot alias the stores, so
+// their reads are free to move ahead of them.
 struct StoreEncC0 {
-    const uint64_t *pt;  // [I][N], values < t
-    const int8_t *e;     // [I][N]
-    uint64_t *ct;        // [I][2][L][N]
-    double delta[kMaxL];
+    uint64_t *ct;      // [I][2][L][N]
+    const double *sh;  // [L][N]
     int logn, L;
-    // The plaintext and error words, read ahead of the transform's last pass.
     struct Pre {
-        uint64_t m;
-        int e;
+        uint64_t a;
     };
-    __device__ Pre pre(const PolyIx &pi, int j) const
+    __device__ Pre pre(const PolyIx &pi, int z) const
     {
-        const size_t at = ((size_t)pi.x << logn) + j;
-        return Pre{pt[at], (int)e[at]};
+        const size_t x = (size_t)pi.x, l = (size_t)pi.l;
+        return Pre{ct[(((x * 2 + 1) * L + l) << logn) + z]};
     }
-    __device__ void operator()(const PolyIx &pi, int j, double v, double p, double pinv,
+    __device__ void operator()(const PolyIx &pi, int z, double v, double p, double pinv,
                                const Pre &pr) const
     {
-        const size_t x = (size_t)pi.x;
-        const int l = pi.l;
-        const double m = mulmod(delta[l], f64_of(pr.m), p, pinv);
-        const double c0 = m + (double)pr.e - v;
-        ct[(((x * 2) * L + l) << logn) + j] = to_canonical(c0, p, pinv);
+        const size_t x = (size_t)pi.x, l = (size_t)pi.l;
+        const double as = mulmod(f64_of(pr.a), sh[(l << logn) + z], p, pinv);
+        ct[(((x * 2) * L + l) << logn) + z] = to_canonical(v - as, p, pinv);
     }
 };
 
@@ -311,15 +308,15 @@ static int encrypt_with(const pimm_plan *plan, const pimm_sk *sk, const uint8_t 
         js.job[0] = je;
         if (!rc) rc = launch_samples(c, key, op_id, js, s);
     }
-    // a is drawn in evaluation form (its slots are the uniform draws, c1 on the wire), so
-    // c0 = [Delta pt + e - a s] takes one inverse transform of a^ s^ and no forward one.
+    // The ciphertext travels in evaluation form: a is drawn as its slots (c1 as it is), and
+    // c0's slots are the forward transform of Delta pt + e minus a^ s^.
     if (!rc) {
-        StoreEncC0 st{pt, e, ct, {0.0, 0.0, 0.0, 0.0}, lg, (int)L};
+        LoadEncMsg ld{pt, e, {0.0, 0.0, 0.0, 0.0}, lg};
         for (size_t l = 0; l < L; ++l) {
             const uint64_t d = c.dp.delta[l], q = c.q[l];
-            st.delta[l] = d > q / 2 ? -(double)(q - d) : (double)d;
+            ld.delta[l] = d > q / 2 ? -(double)(q - d) : (double)d;
         }
-        rc = launch_inv(c, LoadCtSlotsMul{ct, sk->d_s_hat, lg, (int)L}, st, (int)(f.I * L), s);
+        rc = launch_fwd(c, ld, StoreEncC0{ct, sk->d_s_hat, lg, (int)L}, (int)(f.I * L), s);
     }
     return rc;
 }

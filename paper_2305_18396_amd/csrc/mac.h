@@ -8,7 +8,7 @@
 // NTT-form operands are stored chunk-contiguous, so that a thread's stream over
 // the inner blocks is sequential in memory:
 //     W^   [L][chunks][M][R][256]        (weight cache)
-//     c^   [L][chunks][K][R][2][256]     (transformed inputs)
+//     c^   [L][chunks][K][R][2][256]     (the inputs, in evaluation form)
 //     acc^ [O][2][L][N], O = M*K         (accumulators, read by the inverse NTT)
 // A tile is (prime l, chunk zc, column block kb, rows ib0 .. ib0+G-1); a
 // thread owns one slot of the tile and G output rows, streams G weight words
@@ -35,7 +35,7 @@ __device__ __forceinline__ size_t c_tile_base(const MacShape &s, int l, int zc, 
 }
 
 // Column blocks of the product as seen by one tile: column `col` has its input
-// words (transformed ciphertext, both components) and its accumulators.  For a
+// words (the ciphertext in evaluation form, both components) and its accumulators.  For a
 // single product the columns are its K column blocks; a batch may also line up
 // the columns of several products that share one weight cache.
 struct ColsOne {

@@ -15,29 +15,11 @@ uint64_t digit_cache_bytes(const Ctx &c, const pimm_plan_info &f);
 // Digit form [L][N][7][Mt][64][16 B] of the FP64 cache Wt [L][N/256][M][R][256].
 int build_weight_digits(const Ctx &c, const pimm_plan_info &f, const double *Wt, void *Wd,
                         hipStream_t s);
-// acc^ [L][N/kAccRun][O][2][kAccRun] = the slot-wise products of the inputs (c0^
-// [L][N/kInRun][I][kInRun]; c1 read from the query ciphertexts ct [I][2][L][N], in evaluation
-// form) with the digit weight cache Wd.  Every accumulator is written once (no zeroing needed).
-int launch_mac_mfma(const Ctx &c, const pimm_plan_info &f, const void *Wd, const double *C0h,
-                    const uint64_t *ct, double *Ah, hipStream_t s);
-
-// Transformed c0 of the matrix-core product's inputs in runs of kInRun slots: input x,
-// slot z at [L][N/kInRun][I][kInRun] (c1 arrives in evaluation form and the product reads it
-// from the ciphertexts themselves).  Input transform storer for polynomials x*L + l
-// (NR = N / kInRun).
-constexpr int kInRun = 8;
-struct StoreC0Run {
-    double *out;
-    uint32_t I, NR;  // inputs, N / kInRun
-    int L;
-    __device__ void operator()(const PolyIx &pi, int z, double v, double, double) const
-    {
-        // The workgroup's base (uniform) plus run z / kInRun of stride kInRun I: one
-        // 32 x 32 -> 64-bit multiply-add per element.
-        const size_t base = ((size_t)pi.l * NR * I + (uint32_t)pi.x) * kInRun + ((uint32_t)z % kInRun);
-        out[(size_t)((uint32_t)z / kInRun) * (I * (uint32_t)kInRun) + base] = v;
-    }
-};
+// acc^ [L][N/kAccRun][O][2][kAccRun] = the slot-wise products of the query ciphertexts ct
+// [I][2][L][N] (in evaluation form, read in place) with the digit weight cache Wd.  Every
+// accumulator is written once (no zeroing needed).
+int launch_mac_mfma(const Ctx &c, const pimm_plan_info &f, const void *Wd, const uint64_t *ct, double *Ah,
+                    hipStream_t s);
 
 // Accumulators of the matrix-core product in runs of the kAccRun slots one workgroup
 // computes: polynomial (o*2 + comp)*L + l, slot z at [L][N/kAccRun][O][2][kAccRun] (a

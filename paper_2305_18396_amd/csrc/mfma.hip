@@ -8,8 +8,9 @@
 // the exact int8 matrix instructions of CDNA4 do it much faster than the FP64
 // vector unit:
 //
-//   * every balanced residue x (|x| < 2^49) is split into seven signed 8-bit
-//     digits, x = sum_{a<7} d_a 256^a, d_a in [-128, 127];
+//   * every residue x (a balanced weight, |x| < 2^49, or a canonical input below
+//     2^50) is split into seven signed 8-bit digits, x = sum_{a<7} d_a 256^a,
+//     d_a in [-128, 127];
 //   * sum_jb W c = sum_{d<13} 256^d T_d with T_d = sum_{a+b=d} sum_jb dW_a dc_b,
 //     each T_d an exact int32 (|T_d| <= 7 * 64 * 2^14 < 2^23): the 49 digit pairs
 //     are int8 matrix products (v_mfma_i32_16x16x64_i8, the inner dimension = the
@@ -32,16 +33,12 @@
 //
 // Layouts:
 //   digit weight cache  [L][N][7][Mt][64 lanes][16 B]   (A fragments, Mt = ceil(M/16))
-//   c0^  (f64)          [L][N/8][I][8]                  (written by the input transform of
-//                                                        c0 in 64-byte runs; a tile reads
-//                                                        their 32-byte halves)
-//   c1   (u64)          the query ciphertexts [I][2][L][N] (already in evaluation form: read
-//                                                        in place, 32 bytes per polynomial
-//                                                        and tile)
+//   c0, c1 (u64)        the query ciphertexts [I][2][L][N] (in evaluation form: read in
+//                                                        place, 64 bytes per polynomial and
+//                                                        tile)
 //   acc^ (f64)          [L][N/8][O][2][8]               (read by the output transform; a
-//                                                        tile's 4 slots are half a run, so
-//                                                        its stores cover half lines and the
-//                                                        transform's reads 64-byte runs)
+//                                                        tile's 8 slots are one run, so its
+//                                                        stores cover whole 64-byte runs)
 #include "common.h"
 #include "mfma.h"
 
@@ -119,8 +116,7 @@ __global__ __launch_bounds__(256) void k_w_digits(const double *__restrict__ Wt,
 
 struct MfmaArgs {
     const v4i *Wd;
-    const double *C0h;   // c0^ [L][N/kInRun][I][kInRun]
-    const uint64_t *ct;  // the query ciphertexts [I][2][L][N], c1 in evaluation form
+    const uint64_t *ct;  // the query ciphertexts [I][2][L][N], in evaluation form
     double *Ah;
     int M, R, K, I, O, Mt, CT, RG, NC, logn, L;
     double c64[kMaxL];  // 2^64 mod q_l, balanced
@@ -130,7 +126,7 @@ struct MfmaArgs {
 //   P_k = T_2k + 2^8 T_2k+1 in int32 (|P_k| < 7 * 2^28 + 2^23 < 2^31);
 //   g0 = P0 + 2^16 P1, g1 = P2 + 2^16 P3, g2 = P4 + 2^16 P5 + 2^32 T12 (exact doubles,
 //   |g| < 2^48, since |T12| <= 64 * 8: the top digit of a balanced weight, |x| <= p/2 < 2^49,
-//   is in [-2, 2] and that of an input, balanced or a canonical c1 residue below 2^50, in [-2, 4]);
+//   is in [-2, 2] and that of an input, a canonical residue below 2^50, in [-2, 4]);
 //   value = g0 + g1 2^32 + g2 2^64: the first product is a power of two, so its quotient
 //   k = rint(g1 2^32 / p) leaves fma(-k, p, g1 2^32) exact; the second is a floating-point
 //   modular product by 2^64 mod p; one reduction ends in [-p/2, p/2].
@@ -182,10 +178,6 @@ __global__ __launch_bounds__(kMfmaThreads, kMfmaPerCu) void k_mac_mfma(MfmaArgs 
     const int zc = (int)(lb % g.NC);
     const int l = (int)(lb / g.NC);
     const int tid = (int)threadIdx.x;
-    // The run of c0^ that holds the tile's slots, and their offset in it.
-    static_assert(kInRun % kMfmaSlots == 0 && 16 % kInRun == 0, "input runs");
-    const size_t line0 = (((size_t)l * g.NC + zc) * (16 / kInRun) + (h * kMfmaSlots) / kInRun) * g.I;
-    const int zin = (h * kMfmaSlots) % kInRun;
     const int zt = zc * 16 + h * kMfmaSlots;  // the tile's first slot
 
     // Inputs: thread (q, j) takes inner blocks 4q .. 4q+3 of column j for the workgroup's slots.  All
@@ -193,8 +185,8 @@ __global__ __launch_bounds__(kMfmaThreads, kMfmaPerCu) void k_mac_mfma(MfmaArgs 
     // afterwards), so their latencies overlap.  The first half of the slots is split into
     // digits and its products start while the second half's loads are still arriving; the
     // second half goes to LDS before slot kMfmaSlots / 2.
-    // Column (kb, 0) reads c0^ (balanced doubles), column (kb, 1) the ciphertext's c1
-    // (canonical residues, already in evaluation form); both as raw 64-bit words here.
+    // Column (kb, c) reads component c of the query ciphertexts in place (canonical residues
+    // in slot order).
     const int jq = tid & 15, qq = tid >> 4;
     const int colq = ct * 16 + jq, kbq = colq >> 1, compq = colq & 1;
     u64x2 v[4][kMfmaSlots / 2];
@@ -204,9 +196,7 @@ __global__ __launch_bounds__(kMfmaThreads, kMfmaPerCu) void k_mac_mfma(MfmaArgs 
         const int jb = 4 * qq + r;
         ok[r] = jb < g.R && kbq < g.K;
         const size_t x = (size_t)jb * g.K + kbq;
-        const uint64_t *src = !ok[r] ? (const uint64_t *)g.C0h
-                              : compq ? g.ct + ((((x * 2 + 1) * g.L + l) << g.logn) + zt)
-                                      : (const uint64_t *)g.C0h + (line0 + x) * kInRun + zin;
+        const uint64_t *src = !ok[r] ? g.ct : g.ct + ((((x * 2 + compq) * g.L + l) << g.logn) + zt);
 #pragma unroll
         for (int s2 = 0; s2 < kMfmaSlots / 2; ++s2) v[r][s2] = ((const u64x2 *)src)[s2];
     }
@@ -217,8 +207,7 @@ __global__ __launch_bounds__(kMfmaThreads, kMfmaPerCu) void k_mac_mfma(MfmaArgs 
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const uint64_t b = (s & 1) ? v[r][s >> 1].y : v[r][s >> 1].x;
-            const double x = compq ? f64_of(b) : __longlong_as_double((long long)b);
-            w[r] = ok[r] ? digits7(x) : 0;
+            w[r] = ok[r] ? digits7(f64_of(b)) : 0;
         }
 #pragma unroll
         for (int b = 0; b < 7; ++b)
@@ -331,8 +320,8 @@ int build_weight_digits(const Ctx &c, const pimm_plan_info &f, const double *Wt,
     return check_hip(hipGetLastError(), "weight digits launch");
 }
 
-int launch_mac_mfma(const Ctx &c, const pimm_plan_info &f, const void *Wd, const double *C0h,
-                    const uint64_t *ct, double *Ah, hipStream_t s)
+int launch_mac_mfma(const Ctx &c, const pimm_plan_info &f, const void *Wd, const uint64_t *ct, double *Ah,
+                    hipStream_t s)
 {
     if (!mfma_eligible(f))
         return set_error(PIMM_E_UNSUPPORTED,
@@ -340,7 +329,6 @@ int launch_mac_mfma(const Ctx &c, const pimm_plan_info &f, const void *Wd, const
                          "(plan has R = %u, K = %u)", f.R, f.K);
     MfmaArgs g{};
     g.Wd = (const v4i *)Wd;
-    g.C0h = C0h;
     g.ct = ct;
     g.L = (int)c.params.L;
     g.Ah = Ah;

@@ -3,7 +3,7 @@
 // loops that must not call the allocator, harnesses that forbid it).
 //
 // pimm_matmul_share needs a workspace of fused_workspace_bytes(plan) for the
-// transformed inputs, the accumulators in NTT form and the re-randomisation
+// inputs in the product's layout, the accumulators in NTT form and the re-randomisation
 // terms.  pimm_matmul_share_noalloc takes that workspace from `scratch`, an
 // array in the code object's static device data: every device the library
 // runs on holds one copy of it (kNoallocScratchBytes) from the loading of the

@@ -583,29 +583,21 @@ __global__ __launch_bounds__(ntt_threads<LOGN>()) void k_ntt_fwd2(Load1 ld1, Loa
         ntt_fwd_block<LOGN, T>(ld2, st, dp, poly, lds);
 }
 
-// The forward transform of polynomial `poly` through (ld, st), with a second polynomial of
-// the same index moved as it is through (cld, cst) (an operand already in evaluation form,
-// such as the c1 of a query ciphertext beside its c0) and, as in k_ntt_fwd_zero, the
-// workgroup's share of another buffer zeroed.  The move comes first, so its reads and writes
-// are in flight while the transform runs.
-template <int LOGN, class Load, class Store, class CLoad, class CStore>
-__global__ __launch_bounds__(ntt_threads<LOGN>()) void k_ntt_fwd_move(Load ld, Store st, CLoad cld, CStore cst,
-                                                                       double *zero, size_t zero_n,
-                                                                       DevParams dp)
+// Polynomial `poly`, already in evaluation form (a query ciphertext's component), moved into
+// another layout through (ld, st), and, as in k_ntt_fwd_zero, the workgroup's share of another
+// buffer zeroed.  Every read of a thread is issued before its first write.
+template <int LOGN, class Load, class Store>
+__global__ __launch_bounds__(ntt_threads<LOGN>()) void k_move(Load ld, Store st, double *zero, size_t zero_n,
+                                                               DevParams dp)
 {
     constexpr int T = ntt_threads<LOGN>();
-    __shared__ double lds[NttPasses<LOGN, T>::LDS];
-    const int poly = ntt_poly();
-    const PolyIx pi = poly_ix(poly, dp.L);
-    {
-        const double p = dp.p[pi.l], pinv = dp.pinv[pi.l];
-        double v[(1 << LOGN) / T];
+    const PolyIx pi = poly_ix(ntt_poly(), dp.L);
+    const double p = dp.p[pi.l], pinv = dp.pinv[pi.l];
+    double v[(1 << LOGN) / T];
 #pragma unroll
-        for (int k = 0; k < (1 << LOGN) / T; ++k) v[k] = cld(pi, (int)threadIdx.x + k * T, p, pinv);
+    for (int k = 0; k < (1 << LOGN) / T; ++k) v[k] = ld(pi, (int)threadIdx.x + k * T, p, pinv);
 #pragma unroll
-        for (int k = 0; k < (1 << LOGN) / T; ++k) cst(pi, (int)threadIdx.x + k * T, v[k], p, pinv);
-    }
-    ntt_fwd_block<LOGN, T>(ld, st, dp, poly, lds);
+    for (int k = 0; k < (1 << LOGN) / T; ++k) st(pi, (int)threadIdx.x + k * T, v[k], p, pinv);
     if (zero_n) {
         const size_t per = (zero_n + gridDim.x - 1) / gridDim.x;
         const size_t b = (size_t)blockIdx.x * per;
@@ -685,26 +677,14 @@ struct LoadU64 {
     }
 };
 
-// Component `comp` of [count][2][L][N] ciphertexts as [count*L] polynomials.
-struct LoadCtComp {
-    const uint64_t *ct;
-    int logn, L, comp;
-    __device__ double operator()(const PolyIx &pi, int j, double, double) const
-    {
-        const size_t x = (size_t)pi.x, l = (size_t)pi.l;
-        return f64_of(ct[(((x * 2 + comp) * L + l) << logn) + j]);
-    }
-};
-
-// A query ciphertext's c1, already in evaluation form ([count][2][L][N], canonical
-// residues in slot order), as balanced doubles: polynomial x*L + l is the c1 of input x.
-struct LoadCtSlots {
-    const uint64_t *ct;
-    int logn, L;
+// Canonical residues in slot order ([npoly][N], such as the query ciphertexts [I][2][L][N])
+// as balanced doubles.
+struct LoadSlotsBalanced {
+    const uint64_t *in;
+    int logn;
     __device__ double operator()(const PolyIx &pi, int z, double p, double) const
     {
-        const size_t x = (size_t)pi.x, l = (size_t)pi.l;
-        const double v = f64_of(ct[(((x * 2 + 1) * L + l) << logn) + z]);
+        const double v = f64_of(in[((size_t)pi.poly << logn) + z]);
         return v > 0.5 * p ? v - p : v;
     }
 };
@@ -790,19 +770,18 @@ int launch_fwd2(const Ctx &c, Load1 ld1, Load2 ld2, int n1, Store st, int npoly,
     return check_hip(hipGetLastError(), "ntt_fwd launch");
 }
 
-template <class Load, class Store, class CLoad, class CStore>
-int launch_fwd_move(const Ctx &c, Load ld, Store st, CLoad cld, CStore cst, int npoly, double *zero,
-                    size_t zero_n, hipStream_t s)
+template <class Load, class Store>
+int launch_move(const Ctx &c, Load ld, Store st, int npoly, double *zero, size_t zero_n, hipStream_t s)
 {
     if (npoly <= 0) return PIMM_OK;
     ProfScope prof("ntt_fwd", s);
     if (c.dp.logN == 12)
-        hipLaunchKernelGGL((k_ntt_fwd_move<12, Load, Store, CLoad, CStore>), dim3(npoly),
-                           dim3(ntt_threads<12>()), 0, s, ld, st, cld, cst, zero, zero_n, c.dp);
+        hipLaunchKernelGGL((k_move<12, Load, Store>), dim3(npoly), dim3(ntt_threads<12>()), 0, s, ld, st, zero,
+                           zero_n, c.dp);
     else
-        hipLaunchKernelGGL((k_ntt_fwd_move<13, Load, Store, CLoad, CStore>), dim3(npoly),
-                           dim3(ntt_threads<13>()), 0, s, ld, st, cld, cst, zero, zero_n, c.dp);
-    return check_hip(hipGetLastError(), "ntt_fwd launch");
+        hipLaunchKernelGGL((k_move<13, Load, Store>), dim3(npoly), dim3(ntt_threads<13>()), 0, s, ld, st, zero,
+                           zero_n, c.dp);
+    return check_hip(hipGetLastError(), "move launch");
 }
 
 template <class Load, class Store>

@@ -473,16 +473,15 @@ static int reply_rr(const Ctx &c, const pimm_plan_info &f, const int8_t *u, cons
     return check_hip(hipGetLastError(), "reply_rr launch");
 }
 
-// The query ciphertexts into the vector product's tiled layout in one launch: the forward
-// transform of c0, c1 (already in evaluation form) moved as it is, and the accumulators zeroed.
+// The query ciphertexts (already in evaluation form) into the vector product's tiled layout
+// as balanced doubles, and the accumulators zeroed, in one launch.
 static int ct_to_tiled(const Ctx &c, const pimm_plan_info &f, const uint64_t *ct, double *ch, double *ah,
                        hipStream_t s)
 {
     const int lg = c.dp.logN, L = (int)c.params.L;
     const size_t N = c.params.N;
-    return launch_fwd_move(c, LoadCtComp{ct, lg, L, 0}, StoreCtTiled{ch, lg, L, f.K, f.R, f.groups, 0},
-                           LoadCtSlots{ct, lg, L}, StoreCtTiled{ch, lg, L, f.K, f.R, f.groups, 1},
-                           (int)(f.I * L), ah, (size_t)f.O * 2 * L * N, s);
+    return launch_move(c, LoadSlotsBalanced{ct, lg}, StoreCtTiled{ch, lg, L, f.K, f.R, f.groups, -1},
+                       (int)(f.I * 2 * L), ah, (size_t)f.O * 2 * L * N, s);
 }
 
 // The fused step after the product, on the workspace laid out as
@@ -686,11 +685,8 @@ int pimm_matmul(const pimm_plan *plan, const pimm_weights *w, const uint64_t *ct
     int rc = PIMM_OK;
     if (plan->mac_rows == 0) {
         rc = mfma_ready(plan, w, "pimm_matmul");
-        // c0 transformed; the product reads c1, already in evaluation form, in place.
-        if (!rc)
-            rc = launch_fwd(c, LoadCtComp{ct, lg, (int)L, 0}, StoreC0Run{ch, f.I, (uint32_t)(N / kInRun), (int)L},
-                            (int)(f.I * L), s);
-        if (!rc) rc = launch_mac_mfma(c, f, w->d_w_dig, ch, ct, ah, s);
+        // The product reads the query ciphertexts, already in evaluation form, in place.
+        if (!rc) rc = launch_mac_mfma(c, f, w->d_w_dig, ct, ah, s);
         if (!rc)
             rc = launch_inv(c, LoadSlotsReduceRun{ah, 2 * f.O, (uint32_t)(N / kAccRun), (int)L},
                             StoreU64{acc, lg}, (int)(f.O * 2 * L), s);
@@ -777,11 +773,8 @@ int pimm_matmul_share(const pimm_plan *plan, const pimm_weights *w, const uint64
     int rc = PIMM_OK;
     if (mx) {
         rc = mfma_ready(plan, w, "pimm_matmul_share");
-        // c0 transformed; the product reads c1, already in evaluation form, in place.
-        if (!rc)
-            rc = launch_fwd(c, LoadCtComp{ct, lg, (int)L, 0}, StoreC0Run{ch, f.I, (uint32_t)(N / kInRun), (int)L},
-                            (int)(f.I * L), s);
-        if (!rc) rc = launch_mac_mfma(c, f, w->d_w_dig, ch, ct, ah, s);
+        // The product reads the query ciphertexts, already in evaluation form, in place.
+        if (!rc) rc = launch_mac_mfma(c, f, w->d_w_dig, ct, ah, s);
     } else {
         rc = ct_to_tiled(c, f, ct, ch, ah, s);
         if (!rc)
