@@ -100,6 +100,61 @@ struct DecodedOut {
     }
 };
 
+// (c1 s) at the decoded positions of reply polynomial y*L + l, by one workgroup: the forward
+// transform of c1 leaves each thread's slots in LDS, where the inverse's first pass (the mirror
+// of the forward's last: the same sets on the same threads) reads them back times s^ without a
+// barrier; that pass is pruned to the registers the decoded positions depend on (G > 1), the
+// other passes follow, and the epilogue reads the decoded positions.  The same values as the
+// forward transform to memory followed by k_ntt_inv_lds with LoadSlotsMul, without c1^ leaving
+// the compute unit.
+template <int LOGN, int G>
+__global__ __launch_bounds__(ntt_threads<LOGN>()) void k_decrypt_cs(const uint64_t *c1, const double *sh,
+                                                                      DecodedOut epi, DevParams dp)
+{
+    constexpr int T = ntt_threads<LOGN>();
+    using NP = NttPasses<LOGN, T>;
+    using P = typename NP::PFirst;
+    static_assert(P::PER_THREAD == 1 && P::E == 16 && P::STRIDE == 1, "one set of 16 adjacent slots per thread");
+    __shared__ double lds[NP::LDS];
+    const int poly = ntt_poly();
+    const PolyIx pi = poly_ix(poly, dp.L);
+    ntt_fwd_block<LOGN, T>(LoadU64{c1, LOGN}, StoreKeepLds{}, dp, poly, lds);
+    const int l = pi.l;
+    const double p = dp.p[l], pinv = dp.pinv[l];
+    const double *tw = dp.tw_inv + ((size_t)l << LOGN);
+    const double *sl = sh + ((size_t)l << LOGN);
+    const int S = (int)threadIdx.x;
+    const int b0 = lds_idx(P::elem(S, 0));
+    double x[P::E];
+#pragma unroll
+    for (int c = 0; c < P::E; ++c) x[c] = mulmod(lds[b0 + P::lds_off(c)], sl[c * P::NSETS + S], p, pinv);
+    if constexpr (G > 1)
+        P::template inv_pruned<G>(x, S, tw, p, pinv);
+    else
+        P::inv(x, S, tw, p, pinv);
+#pragma unroll
+    for (int c = G - 1; c < P::E; c += G) lds[b0 + P::lds_off(c)] = reduce(x[c], p, pinv);
+    // Every wave is past the forward's passes that read the LDS twiddle table.
+    __syncthreads();
+    load_tw_table<LOGN, T>(tw, lds);
+    __syncthreads();
+    ntt_inv_rest<LOGN, T, G>(StoreLds{lds}, dp, pi, lds);
+    __syncthreads();
+    epi.template run<LOGN, T>(pi, lds, dp);
+}
+
+template <int LOGN>
+static void launch_decrypt_cs(int g, const uint64_t *c1, const double *sh, const DecodedOut &epi, int npoly,
+                              const DevParams &dp, hipStream_t s)
+{
+    if (g == 16)
+        hipLaunchKernelGGL((k_decrypt_cs<LOGN, 16>), dim3(npoly), dim3(ntt_threads<LOGN>()), 0, s, c1, sh, epi, dp);
+    else if (g == 4)
+        hipLaunchKernelGGL((k_decrypt_cs<LOGN, 4>), dim3(npoly), dim3(ntt_threads<LOGN>()), 0, s, c1, sh, epi, dp);
+    else
+        hipLaunchKernelGGL((k_decrypt_cs<LOGN, 1>), dim3(npoly), dim3(ntt_threads<LOGN>()), 0, s, c1, sh, epi, dp);
+}
+
 // Multi-limb helpers (little-endian uint64 limbs, W limbs).
 constexpr int W = kMaxL + 1;
 
@@ -228,18 +283,22 @@ int decrypt_reply(const Ctx &c, const pimm_plan_info &f, const pimm_sk *sk, cons
                   const uint64_t *c0s, uint64_t *client_share, void *ws, size_t ws_bytes,
                   hipStream_t s, const char *who)
 {
-    const size_t N = c.dp.N, L = c.dp.L;
+    const size_t L = c.dp.L;
     const size_t per = (size_t)f.mb * f.nb;
-    const size_t need = (size_t)f.O * L * N * 8 + (size_t)f.O * L * per * 8;
+    const size_t need = (size_t)f.O * L * per * 8;
     if (!ws || ws_bytes < need) return set_error(PIMM_E_WORKSPACE, "%s: workspace too small", who);
     const int lg = c.dp.logN;
-    double *ch = (double *)ws;
-    uint64_t *cs = (uint64_t *)(ch + (size_t)f.O * L * N);
-    int rc = launch_fwd(c, LoadU64{c1, lg}, StoreSlots{ch, lg}, (int)(f.O * L), s);
-    if (!rc)
-        rc = launch_inv_lds(c, LoadSlotsMul{ch, sk->d_s_hat, lg, 1},
-                            DecodedOut{cs, FastDiv::make(f.mb), f.rb, f.nb}, (int)(f.O * L),
-                            prune_factor(f.rb), s);
+    uint64_t *cs = (uint64_t *)ws;
+    int rc;
+    {
+        const DecodedOut epi{cs, FastDiv::make(f.mb), f.rb, f.nb};
+        ProfScope prof("ntt_inv", s);
+        if (lg == 12)
+            launch_decrypt_cs<12>(prune_factor(f.rb), c1, sk->d_s_hat, epi, (int)(f.O * L), c.dp, s);
+        else
+            launch_decrypt_cs<13>(prune_factor(f.rb), c1, sk->d_s_hat, epi, (int)(f.O * L), c.dp, s);
+        rc = check_hip(hipGetLastError(), "decrypt launch");
+    }
     if (!rc) {
         const size_t total = (size_t)f.O * per;
         const int threads = 256;
@@ -334,7 +393,7 @@ int pimm_encrypt_seeded(const pimm_plan *plan, const pimm_sk *sk, const uint8_t 
     return encrypt_with(plan, sk, seed, a_seed, op_id, pt, ct, ws, ws_bytes, stream);
 }
 
-// Workspace: c1^ [O][L][N] doubles, then cs [O][L][mb*nb] uint64.
+// Workspace: cs [O][L][mb*nb] uint64 (the residues of c1 s at the decoded positions).
 int pimm_decrypt(const pimm_plan *plan, const pimm_sk *sk, const uint64_t *c1, const uint64_t *c0s,
                  uint64_t *client_share, void *ws, size_t ws_bytes, void *stream)
 {

@@ -280,7 +280,7 @@ static void fill_info(const Ctx &c, pimm_plan_info &f)
     const uint64_t enc = (uint64_t)f.I * N * 8 * (L + 1);
     const uint64_t mm = ((uint64_t)f.I + f.O) * 2 * L * N * 8;
     const uint64_t msk = 2 * L * N * 8 + (uint64_t)f.O * L * N * 8 + (uint64_t)f.O * 3 * N * 8;
-    const uint64_t dec = (uint64_t)f.O * L * N * 8 + (uint64_t)f.O * L * f.mb * f.nb * 8;
+    const uint64_t dec = (uint64_t)f.O * L * f.mb * f.nb * 8;
     uint64_t ws = enc;
     const uint64_t fused = fused_workspace_bytes(c, f);
     if (fused > ws) ws = fused;
