@@ -466,8 +466,7 @@ def bench_stack(args):
         w, X = layers[k][i]
         plan, b = plans[i], bufs[i]
         op = (t * args.stack_layers + k) * 4 + i
-        pimm.encode_input(plan, X, b["pt"])
-        pimm.encrypt(plan, sk, cseed, op, b["pt"], b["ct"])
+        pimm.encrypt_input(plan, sk, cseed, op, X, b["ct"])  # Alg. 1 steps 1 and 2 in one pass
         pimm.matmul_share(plan, w, pk, sseed, op, b["ct"], b["c1"], b["c0s"], b["y1"])
         if switched:
             # The reply crosses the wire with its last prime dropped.
@@ -527,8 +526,8 @@ def bench_stack(args):
     slot_rate = slot_per_launch / mac_avg_s if cnt else 0.0
     schedules = [p.tuning() for p in plans]
     if all(sch == (0, 0, 0) for sch in schedules):
-        # Matrix-core product: the algorithmic bytes are the transformed inputs (FP64), the
-        # digit form of the weight fragments (7 bytes a residue, padded to 16 rows x 64 inner
+        # Matrix-core product: the algorithmic bytes are the query ciphertexts (both components,
+        # read in place in evaluation form, 8 bytes a residue), the digit form of the weight fragments (7 bytes a residue, padded to 16 rows x 64 inner
         # blocks) and the accumulators (FP64), each once; the int8 work is 49 digit-pair
         # products of 2 x 16 x 16 x 64 operations per tile, slot and prime.
         byts, ops = [], []
@@ -1027,8 +1026,7 @@ def bench_layer(args):
     def step(k):
         for st in state:
             p = st["plan"]
-            pimm.encode_input(p, st["X"], st["pt"])
-            pimm.encrypt(p, sk, cseed, k * 8 + st["op"], st["pt"], st["ct"], st["ws"])
+            pimm.encrypt_input(p, sk, cseed, k * 8 + st["op"], st["X"], st["ct"], st["ws"])
             pimm.matmul_share(p, st["w"], pk, sseed, k * 8 + st["op"], st["ct"], st["c1"],
                               st["c0s"], st["y1"], st["ws"])
             if switched:

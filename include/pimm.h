@@ -245,6 +245,14 @@ int pimm_encode_input(const pimm_plan *plan, const uint64_t *X, uint64_t *pt, vo
 int pimm_encrypt(const pimm_plan *plan, const pimm_sk *sk, const uint8_t seed[32], uint32_t op_id,
                  const uint64_t *pt, uint64_t *ct, void *ws, size_t ws_bytes, void *stream);
 
+/* Algorithm 1 steps 1 and 2 in one pass: pi_B of X (as pimm_encode_input) encoded
+ * inside the encryption (as pimm_encrypt), without the plaintexts in memory.  The
+ * ciphertexts are exactly those of pimm_encode_input followed by pimm_encrypt with the
+ * same seed and op_id.  X: [n][r] values < 2^l (device; [G][n][r] for a grouped plan),
+ * ct: [I][2][L][N] (device); the workspace of pimm_encrypt. */
+int pimm_encrypt_input(const pimm_plan *plan, const pimm_sk *sk, const uint8_t seed[32], uint32_t op_id,
+                       const uint64_t *X, uint64_t *ct, void *ws, size_t ws_bytes, void *stream);
+
 /* Seed-compressed upload, a wire-format variant of Algorithm 1 step 2.  c1 = a (its
  * slots, as in pimm_encrypt) is public, so it can come from a public seed:
  * pimm_encrypt_seeded draws a_l from

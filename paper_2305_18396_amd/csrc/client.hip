@@ -49,6 +49,29 @@ struct LoadEncMsg {
     }
 };
 
+// Delta_l pi_B(X) + e for polynomial x*L + l: the encoding of Algorithm 1 step 1 done in the
+// encryption's loader, coefficient by coefficient (the values k_encode_input writes): input
+// x = (g R + jb) K + kb of product g holds X_g[kb nb + k][jb rb + j] at coefficient k D + j
+// (k < nb, j < rb, D = mb rb), zero elsewhere.
+struct LoadEncX {
+    const uint64_t *X;  // [G][n][r], values < 2^l
+    const int8_t *e;    // [I][N]
+    double delta[kMaxL];
+    FastDiv D, I1, K;   // mb rb, R K, K
+    uint32_t rb, nb, n, r;
+    int logn;
+    __device__ double operator()(const PolyIx &pi, int j, double p, double pinv) const
+    {
+        const uint32_t xg = (uint32_t)pi.x, g = I1.div(xg), x = xg - g * I1.d;
+        const uint32_t jb = K.div(x), kb = x - jb * K.d;
+        const uint32_t k = D.div((uint32_t)j), jj = (uint32_t)j - k * D.d;
+        const uint32_t row = kb * nb + k, col = jb * rb + jj;
+        const uint64_t v = (k < nb && jj < rb && row < n && col < r)
+                               ? X[((size_t)g * n + row) * r + col] : 0;
+        return mulmod(delta[pi.l], f64_of(v), p, pinv) + (double)e[((size_t)pi.x << logn) + j];
+    }
+};
+
 // c0's slots [Delta_l pt + e]^ - a^ s^ (mod q_l): the transform's output (balanced) minus a^ s^
 // (a^ the ciphertext's c1 slot, canonical; s^ the key's slot, balanced; the product within
 // 0.7 q_l), one reduction to the canonical residue.  a^ is read ahead of the transform's last
@@ -331,11 +354,12 @@ int pimm_encode_input(const pimm_plan *plan, const uint64_t *X, uint64_t *pt, vo
 // Workspace: a^ [I][L][N] doubles, then e [I][N] (one byte each, in an int64-sized region).
 // Symmetric encryption with e drawn from `seed` and a from `a_seed` (the same
 // seed for pimm_encrypt).
+// The encryption of the plaintexts pt, or (X set) of pi_B(X) encoded on the fly.
 static int encrypt_with(const pimm_plan *plan, const pimm_sk *sk, const uint8_t seed[32],
-                        const uint8_t a_seed[32], uint32_t op_id, const uint64_t *pt, uint64_t *ct,
-                        void *ws, size_t ws_bytes, void *stream)
+                        const uint8_t a_seed[32], uint32_t op_id, const uint64_t *pt, const uint64_t *X,
+                        uint64_t *ct, void *ws, size_t ws_bytes, void *stream)
 {
-    if (!plan || !sk || !seed || !a_seed || !pt || !ct)
+    if (!plan || !sk || !seed || !a_seed || !(pt || X) || !ct)
         return set_error(PIMM_E_ARG, "pimm_encrypt: NULL argument");
     const Ctx &c = *plan->ctx;
     if (sk->ctx != plan->ctx) return set_error(PIMM_E_ARG, "pimm_encrypt: key of another context");
@@ -370,12 +394,22 @@ static int encrypt_with(const pimm_plan *plan, const pimm_sk *sk, const uint8_t 
     // The ciphertext travels in evaluation form: a is drawn as its slots (c1 as it is), and
     // c0's slots are the forward transform of Delta pt + e minus a^ s^.
     if (!rc) {
-        LoadEncMsg ld{pt, e, {0.0, 0.0, 0.0, 0.0}, lg};
+        double delta[kMaxL] = {0.0, 0.0, 0.0, 0.0};
         for (size_t l = 0; l < L; ++l) {
             const uint64_t d = c.dp.delta[l], q = c.q[l];
-            ld.delta[l] = d > q / 2 ? -(double)(q - d) : (double)d;
+            delta[l] = d > q / 2 ? -(double)(q - d) : (double)d;
         }
-        rc = launch_fwd(c, ld, StoreEncC0{ct, sk->d_s_hat, lg, (int)L}, (int)(f.I * L), s);
+        const StoreEncC0 st{ct, sk->d_s_hat, lg, (int)L};
+        if (X) {
+            LoadEncX ld{X, e, {0.0, 0.0, 0.0, 0.0}, FastDiv::make(f.mb * f.rb), FastDiv::make(f.R * f.K),
+                        FastDiv::make(f.K), f.rb, f.nb, f.n, f.r, lg};
+            memcpy(ld.delta, delta, sizeof(delta));
+            rc = launch_fwd(c, ld, st, (int)(f.I * L), s);
+        } else {
+            LoadEncMsg ld{pt, e, {0.0, 0.0, 0.0, 0.0}, lg};
+            memcpy(ld.delta, delta, sizeof(delta));
+            rc = launch_fwd(c, ld, st, (int)(f.I * L), s);
+        }
     }
     return rc;
 }
@@ -383,14 +417,22 @@ static int encrypt_with(const pimm_plan *plan, const pimm_sk *sk, const uint8_t 
 int pimm_encrypt(const pimm_plan *plan, const pimm_sk *sk, const uint8_t seed[32], uint32_t op_id,
                  const uint64_t *pt, uint64_t *ct, void *ws, size_t ws_bytes, void *stream)
 {
-    return encrypt_with(plan, sk, seed, seed, op_id, pt, ct, ws, ws_bytes, stream);
+    return encrypt_with(plan, sk, seed, seed, op_id, pt, nullptr, ct, ws, ws_bytes, stream);
+}
+
+int pimm_encrypt_input(const pimm_plan *plan, const pimm_sk *sk, const uint8_t seed[32], uint32_t op_id,
+                       const uint64_t *X, uint64_t *ct, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!X) return set_error(PIMM_E_ARG, "pimm_encrypt_input: NULL argument");
+    return encrypt_with(plan, sk, seed, seed, op_id, nullptr, X, ct, ws, ws_bytes, stream);
 }
 
 int pimm_encrypt_seeded(const pimm_plan *plan, const pimm_sk *sk, const uint8_t seed[32],
                         const uint8_t a_seed[32], uint32_t op_id, const uint64_t *pt, uint64_t *ct,
                         void *ws, size_t ws_bytes, void *stream)
 {
-    return encrypt_with(plan, sk, seed, a_seed, op_id, pt, ct, ws, ws_bytes, stream);
+    if (!pt) return set_error(PIMM_E_ARG, "pimm_encrypt_seeded: NULL argument");
+    return encrypt_with(plan, sk, seed, a_seed, op_id, pt, nullptr, ct, ws, ws_bytes, stream);
 }
 
 // Workspace: cs [O][L][mb*nb] uint64 (the residues of c1 s at the decoded positions).

@@ -34,7 +34,8 @@ EXPORTS = [
     "pimm_params_primes", "pimm_cdt", "pimm_plan_rule", "pimm_noise_ok", "pimm_switch_ok",
     "pimm_plan_create", "pimm_plan_create_grouped", "pimm_plan_destroy", "pimm_plan_query", "pimm_plan_set_tuning",
     "pimm_plan_get_tuning", "pimm_plan_autotune", "pimm_plan_select", "pimm_batch_autotune",
-    "pimm_keygen", "pimm_sk_destroy", "pimm_encode_input", "pimm_encrypt", "pimm_decrypt",
+    "pimm_keygen", "pimm_sk_destroy", "pimm_encode_input", "pimm_encrypt", "pimm_encrypt_input",
+    "pimm_decrypt",
     "pimm_weights_create", "pimm_weights_destroy", "pimm_matmul", "pimm_mask_share",
     "pimm_matmul_share", "pimm_matmul_share_noalloc",
     "pimm_fc_complete",
@@ -119,6 +120,7 @@ def lib():
         "pimm_sk_destroy": [vp],
         "pimm_encode_input": [vp, vp, vp, vp],
         "pimm_encrypt": [vp, vp, vp, u32, vp, vp, vp, ctypes.c_size_t, vp],
+        "pimm_encrypt_input": [vp, vp, vp, u32, vp, vp, vp, ctypes.c_size_t, vp],
         "pimm_decrypt": [vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp],
         "pimm_weights_create": [vp, vp, vp, vp],
         "pimm_weights_destroy": [vp],
@@ -440,6 +442,18 @@ def encrypt(plan: Plan, sk: SecretKey, seed: bytes, op_id: int, pt: torch.Tensor
     ws = plan.workspace() if ws is None else ws
     _check(lib().pimm_encrypt(plan.h, sk.h, _seed(seed), op_id, _ptr(pt), _ptr(ct), _ptr(ws),
                               ws.numel() * 8, _stream(stream)))
+    return ct
+
+
+def encrypt_input(plan: Plan, sk: SecretKey, seed: bytes, op_id: int, X: torch.Tensor,
+                  ct: torch.Tensor | None = None, ws: torch.Tensor | None = None, stream=None):
+    """pimm_encrypt_input: encode_input and encrypt in one pass (X [n][r], or [G][n][r])."""
+    f, c = plan.info, plan.ctx
+    if ct is None:
+        ct = torch.empty((f.I, 2, c.L, c.N), dtype=torch.int64, device=c.device)
+    ws = plan.workspace() if ws is None else ws
+    _check(lib().pimm_encrypt_input(plan.h, sk.h, _seed(seed), op_id, _ptr(X), _ptr(ct), _ptr(ws),
+                                    ws.numel() * 8, _stream(stream)))
     return ct
 
 

@@ -77,10 +77,12 @@ def test_grouped_bitexact(orc, name):
     sk, pk = pimm.keygen(ctx, cseed)
     pt = pimm.encode_input(plan, pimm.to_device_u64(np.stack(Xs)))
     ct = pimm.encrypt(plan, sk, cseed, tag, pt)
+    ct_in = pimm.encrypt_input(plan, sk, cseed, tag, pimm.to_device_u64(np.stack(Xs)))
     w = pimm.Weights(plan, pimm.to_device_u64(np.stack(Ws).astype(np.int64)))
     pimm.sync()
     assert np.array_equal(u64(pt), ref["pt"])
     assert np.array_equal(u64(ct), ref["ct"])
+    assert np.array_equal(u64(ct_in), ref["ct"]), "encrypt_input"
     for tile in ((4, 1, 1), (8, 1, 1), (16, 1, 1)):
         plan.set_tuning(*tile)
         acc = pimm.matmul(plan, w, ct)

@@ -148,13 +148,14 @@ def run_both(orc, N, L, ell, f, rr, X, W, plan_kw, tag, tuning=None):
     Xd, Wd = pimm.to_device_u64(X), pimm.to_device_u64(W.astype(np.int64))
     pt = pimm.encode_input(plan, Xd)
     ct = pimm.encrypt(plan, sk, cseed, tag, pt)
+    ct_in = pimm.encrypt_input(plan, sk, cseed, tag, Xd)  # steps 1 and 2 in one pass
     w = pimm.Weights(plan, Wd)
     acc = pimm.matmul(plan, w, ct)
     acc0 = u64(acc).copy()
     c1, c0s, y1 = pimm.mask_share(plan, pk, sseed, tag, acc)
     y0 = pimm.decrypt(plan, sk, c1, c0s)
     pimm.sync()
-    gpu = dict(pk=None if pk is None else u64(pk), pt=u64(pt), ct=u64(ct), acc=acc0,
+    gpu = dict(pk=None if pk is None else u64(pk), pt=u64(pt), ct=u64(ct), ct_in=u64(ct_in), acc=acc0,
                acc_rr=u64(acc), c1=u64(c1), c0s=u64(c0s), Y1=u64(y1), Y0=u64(y0))
     ref = orc.pi_matmul(pyp, oplan, X, W, cseed, sseed, op_id=tag)
     return gpu, ref, pyp
@@ -187,6 +188,8 @@ def test_protocol_bitexact(orc, name):
     for k in ("pt", "ct", "acc", "acc_rr", "c1", "c0s", "Y1", "Y0"):
         want = ref[k].view(np.uint64) if ref[k].dtype != np.uint64 else ref[k]
         assert np.array_equal(gpu[k], want), k
+    # pimm_encrypt_input (encoding inside the encryption) gives the oracle's ciphertexts too
+    assert np.array_equal(gpu["ct_in"], ref["ct"].view(np.uint64)), "ct of encrypt_input"
     Y = (gpu["Y0"] + gpu["Y1"]) & np.uint64(pyp.t - 1)
     assert np.array_equal(Y, xw_mod(X, W, c["ell"]))
 

@@ -164,14 +164,16 @@ def test_probe_rejects_bad_arguments():
 
 
 def test_new_entry_points_reject_null_arguments():
-    """The FC completion, the seed-compressed upload and the in-place weight update check their
-    pointers before touching a device."""
+    """The FC completion, the seed-compressed upload, the encoding encryption and the in-place
+    weight update check their pointers before touching a device."""
     import ctypes
     lib = pimm.lib()
     seed = ctypes.create_string_buffer(32)
     assert lib.pimm_fc_complete(None, None, None, None, None, None, 0, None) == -1
     assert b"pimm_fc_complete" in lib.pimm_last_error()
     assert lib.pimm_encrypt_seeded(None, None, seed, seed, 0, None, None, None, 0, None) == -1
+    assert lib.pimm_encrypt_input(None, None, seed, 0, None, None, None, 0, None) == -1
+    assert b"pimm_encrypt_input" in lib.pimm_last_error()
     assert lib.pimm_ct_expand(None, seed, 0, None, None, None) == -1
     assert b"pimm_ct_expand" in lib.pimm_last_error()
     assert lib.pimm_weights_update(None, None, 0, None) == -1
