@@ -62,13 +62,18 @@ struct LoadEncX {
     int logn;
     __device__ double operator()(const PolyIx &pi, int j, double p, double pinv) const
     {
+        // The input's block of X (the same for every element of the workgroup): rows kb nb ..,
+        // columns jb rb .., kmax x jmax of them inside X.
         const uint32_t xg = (uint32_t)pi.x, g = I1.div(xg), x = xg - g * I1.d;
         const uint32_t jb = K.div(x), kb = x - jb * K.d;
+        const uint32_t kmax = min(nb, n - kb * nb), jmax = min(rb, r - jb * rb);
+        const uint64_t *Xb = X + ((size_t)g * n + kb * nb) * r + jb * rb;
         const uint32_t k = D.div((uint32_t)j), jj = (uint32_t)j - k * D.d;
-        const uint32_t row = kb * nb + k, col = jb * rb + jj;
-        const uint64_t v = (k < nb && jj < rb && row < n && col < r)
-                               ? X[((size_t)g * n + row) * r + col] : 0;
-        return mulmod(delta[pi.l], f64_of(v), p, pinv) + (double)e[((size_t)pi.x << logn) + j];
+        // Every element reads (X[0] where it holds no input) and selects: a load under a
+        // branch would wait for its data before the next element's load is issued.
+        const bool in = k < kmax && jj < jmax;
+        const uint64_t xv = in ? Xb[(size_t)k * r + jj] : X[0];
+        return mulmod(delta[pi.l], f64_of(in ? xv : 0), p, pinv) + (double)e[((size_t)pi.x << logn) + j];
     }
 };
 

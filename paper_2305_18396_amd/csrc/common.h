@@ -150,15 +150,16 @@ __device__ __forceinline__ uint64_t mul_mod(uint64_t a, uint64_t b, double p, do
     return to_canonical(mulmod(f64_of(a), f64_of(b), p, pinv), p, pinv);
 }
 
-// n / d for n * d < 2^32 by one multiply-high: M = ceil(2^32 / d) (d = 1 is kept apart,
-// its M would not fit in 32 bits).
+// n / d for n * d < 2^32 by one multiply-high: M = ceil(2^32 / d).  d = 1 (whose M would not
+// fit in 32 bits) takes M = 0 and adds n through the mask `one`, so there is no branch: a branch
+// in an unrolled loop of loads would make each load wait for the previous one's data.
 struct FastDiv {
-    uint32_t d, M;
+    uint32_t d, M, one;
     static FastDiv make(uint32_t d)
     {
-        return FastDiv{d, d == 1 ? 0u : (uint32_t)(((1ull << 32) + d - 1) / d)};
+        return FastDiv{d, d == 1 ? 0u : (uint32_t)(((1ull << 32) + d - 1) / d), d == 1 ? 0xffffffffu : 0u};
     }
-    __device__ __forceinline__ uint32_t div(uint32_t n) const { return d == 1 ? n : __umulhi(n, M); }
+    __device__ __forceinline__ uint32_t div(uint32_t n) const { return __umulhi(n, M) + (n & one); }
     __device__ __forceinline__ uint32_t mod(uint32_t n) const { return n - div(n) * d; }
 };
 

@@ -345,6 +345,25 @@ __device__ __forceinline__ void fwd_pass(const Load &ld, const Store &st, const 
                                          const double *tw, double p, double pinv, double *lds,
                                          const double *w = nullptr)
 {
+    if constexpr (FIRST && !LAST && P::PER_THREAD > 1) {
+        // The first pass with several sets per thread reads every element of all of them
+        // before any butterfly, so the reads are in flight together whatever the loader's
+        // arithmetic (the compiler does not always move a later set's reads ahead by itself).
+        double xs[P::PER_THREAD][P::E];
+#pragma unroll
+        for (int k = 0; k < P::PER_THREAD; ++k)
+#pragma unroll
+            for (int c = 0; c < P::E; ++c) xs[k][c] = ld(pi, P::elem((int)threadIdx.x + k * T, c), p, pinv);
+#pragma unroll
+        for (int k = 0; k < P::PER_THREAD; ++k) {
+            const int S = (int)threadIdx.x + k * T;
+            const int b0 = lds_idx(P::elem(S, 0));
+            P::fwd(xs[k], S, tw, p, pinv);
+#pragma unroll
+            for (int c = 0; c < P::E; ++c) lds[b0 + P::lds_off(c)] = reduce(xs[k][c], p, pinv);
+        }
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < P::PER_THREAD; ++k) {
         const int S = (int)threadIdx.x + k * T;
