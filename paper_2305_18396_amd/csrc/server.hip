@@ -260,10 +260,13 @@ struct ReplyOut<true> : ReplyOutBase<true> {
             for (int k = 0; k < kPer; ++k) pr.e[k] = ey[(int)threadIdx.x + k * T];
         } else {
             const uint32_t per = mb.d * nb;
+            // Every lane reads (position 0 past the end) and selects: a read under a branch
+            // would wait for every read issued before it.
 #pragma unroll
             for (int b = 0; b < kB; ++b) {
                 const uint32_t idx = threadIdx.x + b * T;
-                pr.e[b] = idx < per ? ey[pos_of(idx)] : 0;
+                const int v = ey[idx < per ? pos_of(idx) : 0u];
+                pr.e[b] = idx < per ? v : 0;
             }
         }
         return pr;
