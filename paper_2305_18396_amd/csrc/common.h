@@ -218,6 +218,21 @@ __device__ __forceinline__ int64_t gauss_of(uint64_t v, const uint64_t *cdt)
     return (v >> 63) ? -mag : mag;
 }
 
+// The same value with the table in LDS, padded to 32 entries with all-ones words (above any
+// 63-bit u): the count of entries <= u by a five-step binary search (the table ascends)
+// instead of 19 compares.
+constexpr int kCdtPad = 32;
+static_assert(kCdtLen <= kCdtPad, "CDT table padding");
+__device__ __forceinline__ int64_t gauss_of_lds(uint64_t v, const uint64_t *cdt32)
+{
+    const uint64_t u = v & 0x7fffffffffffffffull;
+    int pos = 0;
+#pragma unroll
+    for (int step = kCdtPad / 2; step >= 1; step >>= 1) pos += (cdt32[pos + step - 1] <= u) ? step : 0;
+    const int64_t mag = pos;
+    return (v >> 63) ? -mag : mag;
+}
+
 __device__ __forceinline__ uint64_t mask_of(uint64_t v, int ell)
 {
     return ell >= 64 ? v : (v & ((1ull << ell) - 1));

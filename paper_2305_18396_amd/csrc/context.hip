@@ -439,7 +439,7 @@ void switched_params(const Ctx &c, DevParams &d, double *qd_inv)
 // values (int64), 2 eight Gaussian values (int64), 3 eight Z_{2^l} values (uint64).
 template <int KIND>
 __device__ __forceinline__ void sample_block(const Key &key, uint32_t op, const SampleJob &jb,
-                                             uint32_t gid, const DevParams &dp)
+                                             uint32_t gid, const DevParams &dp, const uint64_t *cdt32)
 {
     constexpr int per = 8;
     // gid = (o * nprime + li) * (N / 8) + b; the host keeps every job below 2^31 threads.
@@ -484,14 +484,14 @@ __device__ __forceinline__ void sample_block(const Key &key, uint32_t op, const 
     } else if (KIND == 2) {
         int64_t *dst = (int64_t *)jb.out + base;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) dst[i] = gauss_of(word64(w, i), dp.cdt);
+        for (int i = 0; i < 8; ++i) dst[i] = gauss_of_lds(word64(w, i), cdt32);
     } else if (KIND == kSampleTernary8 || KIND == kSampleGauss8) {
         // The same values as kinds 1 and 2 (|value| <= 19), one byte each.
         uint64_t packed = 0;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int64_t v = KIND == kSampleTernary8 ? ternary_of(word64(w, i))
-                                                      : gauss_of(word64(w, i), dp.cdt);
+                                                      : gauss_of_lds(word64(w, i), cdt32);
             packed |= (uint64_t)(uint8_t)(int8_t)v << (8 * i);
         }
         *(uint64_t *)((int8_t *)jb.out + base) = packed;
@@ -506,6 +506,14 @@ __device__ __forceinline__ void sample_block(const Key &key, uint32_t op, const 
 // one launch: workgroups [first_k, first_k + blocks_k) serve job k.
 __global__ __launch_bounds__(256) void k_sample(Key key, uint32_t op, SampleJobs js, DevParams dp)
 {
+    // The Gaussian table in LDS for gauss_of_lds (every workgroup, whatever its job's kind:
+    // the barrier must be reached by all of its threads).
+    __shared__ uint64_t cdt32[kCdtPad];
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < kCdtPad; ++k) cdt32[k] = k < kCdtLen ? dp.cdt[k] : ~0ull;
+    }
+    __syncthreads();
     uint32_t b = blockIdx.x;
     int k = 0;
     while (k + 1 < js.n && b >= js.job[k].blocks) {
@@ -515,12 +523,12 @@ __global__ __launch_bounds__(256) void k_sample(Key key, uint32_t op, SampleJobs
     const SampleJob &jb = js.job[k];
     const uint32_t gid = b * blockDim.x + threadIdx.x;
     switch (jb.kind) {
-    case 0: sample_block<0>(key, op, jb, gid, dp); break;
-    case 1: sample_block<1>(key, op, jb, gid, dp); break;
-    case 2: sample_block<2>(key, op, jb, gid, dp); break;
-    case kSampleTernary8: sample_block<kSampleTernary8>(key, op, jb, gid, dp); break;
-    case kSampleGauss8: sample_block<kSampleGauss8>(key, op, jb, gid, dp); break;
-    default: sample_block<3>(key, op, jb, gid, dp); break;
+    case 0: sample_block<0>(key, op, jb, gid, dp, cdt32); break;
+    case 1: sample_block<1>(key, op, jb, gid, dp, cdt32); break;
+    case 2: sample_block<2>(key, op, jb, gid, dp, cdt32); break;
+    case kSampleTernary8: sample_block<kSampleTernary8>(key, op, jb, gid, dp, cdt32); break;
+    case kSampleGauss8: sample_block<kSampleGauss8>(key, op, jb, gid, dp, cdt32); break;
+    default: sample_block<3>(key, op, jb, gid, dp, cdt32); break;
     }
 }
 
