@@ -306,10 +306,11 @@ __device__ __forceinline__ void mask_one(uint64_t *c0s, uint64_t *share, uint32_
 {
     const uint32_t per = f.mb * f.nb;
     uint64_t *dst = c0s + (size_t)y * dp.L * per + idx;
+    // Every prime's word is read (prime 0's again past L) before the first store, without a
+    // branch around the reads.
     uint64_t cur[kMaxL];
 #pragma unroll
-    for (int l = 0; l < kMaxL; ++l)
-        if (l < dp.L) cur[l] = dst[(size_t)l * per];
+    for (int l = 0; l < kMaxL; ++l) cur[l] = dst[(size_t)(l < dp.L ? l : 0) * per];
 #pragma unroll
     for (int l = 0; l < kMaxL; ++l)
         if (l < dp.L)
