@@ -375,7 +375,9 @@ static int reply_transform(const Ctx &c, const pimm_plan_info &f, const double *
 //    few registers its decoded positions depend on, component 1 into LDS;
 //  - the rest of component 1's inverse and its epilogue (c1), then component 0's.
 // The same values as the forward transform of u to memory followed by the reply transform
-// of each component, without u^ leaving the compute unit.
+// of each component, without u^ leaving the compute unit.  Four waves per SIMD (at most 128
+// registers) keep two 512-thread workgroups on a compute unit, as their LDS allows; left to
+// itself the compiler takes 130 registers and one workgroup.
 template <int LOGN, int G, bool RUN>
 __global__ __launch_bounds__(ntt_threads<LOGN>()) __attribute__((amdgpu_waves_per_eu(4))) void k_reply_rr(const int8_t *u, const double *ah,
                                                                     const double *pkh, ReplyOut<true> epi,
